@@ -1,0 +1,213 @@
+/*
+ * ecsmg.h -- C ABI of the MI355X (gfx950) multigrid-preconditioned Krylov
+ * solver for the exterior-complex-scaled (ECS) Helmholtz problem
+ *
+ *     (-Lap - k^2(x)) u = f      on a box, u = 0 at the end of every contour,
+ *
+ * following bin Zubair, Reps and Vanroose, "A preconditioned iterative solver
+ * for the scattering solutions of the Schroedinger equation" (model problem
+ * of Sec. 2, discretisation of Sec. 3, preconditioners and multigrid of
+ * Sec. 4, Krylov outer solve of Sec. 5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grids are node based.  nodes[a] counts the nodes of axis a INCLUDING the
+ *    two Dirichlet end nodes; 2D problems use axes 0 (x) and 1 (y) and ignore
+ *    nodes[2].  Real node coordinates are x_i = lo + i (hi - lo)/(nodes - 1).
+ *  - Arrays are device pointers, contiguous, node-major with x fastest:
+ *    index = (k * nodes[1] + j) * nodes[0] + i.  Complex arrays are
+ *    interleaved (re, im): complex128 (16 B/node) unless stated otherwise.
+ *    Boundary entries of inputs are ignored; boundary entries of outputs are
+ *    written as zero.
+ *  - All device memory is owned by the caller.  The library keeps only host
+ *    metadata; its device scratch lives in the workspace the caller hands to
+ *    ecs_set_workspace().  k^2 is borrowed until the next ecs_set_k2() or
+ *    ecs_destroy().
+ *  - Work is enqueued on the HIP stream given to ecs_create().  Calls that
+ *    return results to the host (solves, stats) synchronise that stream.
+ *  - A context is not thread safe; use one per problem and thread.
+ *  - Every call returns an ecs_status; on failure ecs_last_error() gives a
+ *    message.  No call aborts the process.
+ */
+#ifndef ECSMG_H
+#define ECSMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ECS_OK = 0,
+  ECS_NOT_CONVERGED = 1,  /* maxit reached; x holds the last iterate, stats valid  */
+  ECS_EINVAL = -1,        /* bad argument (size, dtype, order, parameter range)   */
+  ECS_ENOMEM = -2,        /* workspace too small                                  */
+  ECS_EDEVICE = -3,       /* HIP runtime error (message in ecs_last_error)        */
+  ECS_EBREAKDOWN = -4,    /* Krylov breakdown or NaN/Inf in the iteration         */
+  ECS_ESTATE = -5         /* call-order violation (e.g. solve before workspace)   */
+} ecs_status;
+
+typedef struct ecs_ctx ecs_ctx;
+
+enum { ECS_F64 = 0, ECS_F32 = 1 };
+enum { ECS_SIDE_LO = 0, ECS_SIDE_HI = 1 };
+enum { ECS_BC_DIRICHLET = 0, ECS_BC_ECS = 1 };
+/* preconditioner operators of Sec. 5 */
+enum { ECS_PREC_NONE = 0, ECS_PREC_LAPLACE = 1, ECS_PREC_CSL = 2, ECS_PREC_CSG = 3, ECS_PREC_QD = 4 };
+enum { ECS_SMOOTH_JACOBI = 0, ECS_SMOOTH_RBGS = 1 };
+enum { ECS_KRYLOV_GMRES = 0, ECS_KRYLOV_FGMRES = 1, ECS_KRYLOV_BICGSTAB = 2 };
+enum { ECS_OP_A = 0, ECS_OP_AT = 1, ECS_OP_M = 2 };
+
+/* Preconditioner M and the multigrid cycle that approximately inverts it
+ * (Sec. 4.2, Algorithm 1; operators of Sec. 5):
+ *   LAPLACE  M = -Lap
+ *   CSL      M = -Lap + (beta1 + i beta2) k^2
+ *   CSG      M = Z on the grid rotated by e^{i theta_alpha}
+ *   QD       M = (1 - i) I + Z / |Re lambda0|; re_lambda0 <= 0 selects
+ *            |Re lambda0| = max k^2 (the rough rule of Sec. 5)
+ *   NONE     no preconditioner (Krylov on A alone)
+ * smoother: omega-Jacobi or red-black SOR ("omega-red-black Jacobi"),
+ * red = nodes with i+j(+k) even first.  gamma_f = gamma_c = 1 is the V cycle.
+ * coarsest_nodes: nodes per axis of the coarsest grid (>= 3); every axis must
+ * satisfy (nodes - 1) = (coarsest_nodes - 1) * 2^(levels - 1).
+ * vcycle_dtype: ECS_F64 or ECS_F32 (the whole cycle in complex FP32). */
+typedef struct {
+  int kind;
+  double beta1, beta2;
+  double theta_alpha;
+  double re_lambda0;
+  int smoother;
+  double omega;
+  int nu1, nu2;
+  int gamma_f, gamma_c;
+  int coarsest_nodes;
+  int vcycle_dtype;
+} ecs_prec_desc;
+
+/* Krylov settings (Sec. 5).  Right preconditioning, x0 = 0 unless
+ * x_is_guess, Hermitian inner products, stop when the TRUE relative residual
+ * ||b - A x||_2 / ||b||_2 <= rtol (interior nodes).
+ *   GMRES(restart):  x = x0 + M^{-1} V y
+ *   FGMRES(restart): x = x0 + Z y, z_j = M^{-1} v_j stored in vcycle_dtype;
+ *                    inner > 0 makes the preconditioner `inner` iterations of
+ *                    complex-FP32 Bi-CGSTAB around the FP32 cycle (nested
+ *                    mixed form; requires vcycle_dtype = ECS_F32).
+ *   BICGSTAB:        van der Vorst's method, shadow residual r^ = r0.
+ * maxit counts outer iterations (Arnoldi steps / Bi-CGSTAB iterations).
+ * history: optional host array of history_len doubles receiving the
+ * estimated relative residual after each iteration. */
+typedef struct {
+  int krylov;
+  int restart;
+  double rtol;
+  int maxit;
+  int x_is_guess;
+  int inner;
+  double *history;
+  int history_len;
+} ecs_solve_desc;
+
+typedef struct {
+  int iterations;          /* outer Krylov iterations                         */
+  int restarts;            /* restart cycles (GMRES) / true-residual restarts */
+  int64_t vcycles;         /* preconditioner applications (multigrid cycles)  */
+  int64_t inner_iterations;/* FP32 inner iterations (nested form)             */
+  double rel_residual;     /* true ||b - A x|| / ||b|| at exit (FP64)         */
+  double seconds;          /* host wall time inside the call                  */
+  int status;              /* same value as returned                          */
+} ecs_stats;
+
+/* Create a problem on the calling thread's current HIP device.
+ * dim = 2 or 3; nodes/lo/hi have dim meaningful entries; stream is a
+ * hipStream_t (NULL = default stream).  All sides start as plain Dirichlet
+ * ends without a layer. */
+ecs_status ecs_create(ecs_ctx **out, int dim, const int64_t *nodes, const double *lo, const double *hi,
+                      void *stream);
+
+/* Exterior complex scaling of one side (Sec. 3.1): for kind = ECS_BC_ECS the
+ * contour is z(x) = x until the real coordinate `start`, and rotated beyond
+ * it, z = start + (x - start) e^{i theta} (0 < theta < pi/2), ending in a
+ * homogeneous Dirichlet node.  ECS_BC_DIRICHLET removes the layer. */
+ecs_status ecs_set_ecs(ecs_ctx *ctx, int axis, int side, int kind, double start, double theta);
+
+/* k^2 at the real node coordinates, FP64 device array of prod(nodes) entries
+ * (borrowed, read at every solve).  Invalidates the preconditioner setup. */
+ecs_status ecs_set_k2(ecs_ctx *ctx, const double *k2_dev);
+
+ecs_status ecs_set_precond(ecs_ctx *ctx, const ecs_prec_desc *desc);
+
+/* Bytes of device workspace needed for solves described by `desc` (NULL:
+ * enough for ecs_apply / ecs_vcycle and the per-step entry points only). */
+ecs_status ecs_workspace_size(ecs_ctx *ctx, const ecs_solve_desc *desc, size_t *bytes);
+
+/* Hand over the workspace (256-byte aligned device memory, caller-owned, kept
+ * until the next call or destroy) and build the device hierarchy: contour
+ * weights per level, injected k^2, coarsest dense inverse.  Requires k^2 and
+ * the preconditioner to be set. */
+ecs_status ecs_set_workspace(ecs_ctx *ctx, void *dev, size_t bytes);
+
+/* Solve A x = b (Sec. 5).  b, x: complex128 device arrays. */
+ecs_status ecs_solve(ecs_ctx *ctx, const ecs_solve_desc *desc, const void *b_dev, void *x_dev, ecs_stats *stats);
+
+/* Solve A^T lam = g (plain transpose, no conjugation) with the same
+ * preconditioner, through the similarity A^T = W A W^{-1}, W = diag of the
+ * products of the dual cell widths w_i = (h_{i-1} + h_i)/2. */
+ecs_status ecs_solve_adjoint(ecs_ctx *ctx, const ecs_solve_desc *desc, const void *g_dev, void *lam_dev,
+                             ecs_stats *stats);
+
+/* grad = Re(lam * u) per node (real FP64 output): the derivative of a real
+ * loss with respect to k^2 when A^T lam = conj(dL/du). */
+ecs_status ecs_grad_k2(ecs_ctx *ctx, const void *lam_dev, const void *u_dev, double *grad_dev);
+
+/* y = op x on the finest grid, complex128: op = A (Z = -Lap - k^2), A^T, or
+ * the preconditioner operator M in FP64. */
+ecs_status ecs_apply(ecs_ctx *ctx, int op, const void *x_dev, void *y_dev);
+
+/* z = MG(v): one preconditioner application from a zero guess (Algorithm 1
+ * at the finest level), complex128 in and out; the cycle runs in the
+ * preconditioner's vcycle_dtype. */
+ecs_status ecs_vcycle(ecs_ctx *ctx, const void *v_dev, void *z_dev);
+
+/* Per-step entry points on level `level` (0 = finest) of the hierarchy,
+ * operating on arrays of that level's size in the cycle's dtype (complex128
+ * for ECS_F64, complex64 for ECS_F32):
+ *   ecs_smooth:            nsweeps smoothing sweeps of M u = b, u in place
+ *   ecs_residual_restrict: rc = FW(b - M u), rc on level+1
+ *   ecs_prolong_correct:   u += P ec, ec on level+1 (bilinear / trilinear)
+ *   ecs_coarse_solve:      x = M_C^{-1} b on the coarsest level            */
+ecs_status ecs_smooth(ecs_ctx *ctx, int level, const void *b_dev, void *u_dev, int nsweeps);
+ecs_status ecs_residual_restrict(ecs_ctx *ctx, int level, const void *b_dev, const void *u_dev, void *rc_dev);
+ecs_status ecs_prolong_correct(ecs_ctx *ctx, int level, const void *ec_dev, void *u_dev);
+ecs_status ecs_coarse_solve(ecs_ctx *ctx, const void *b_dev, void *x_dev);
+
+/* Number of levels and nodes per axis of one level (after set_precond). */
+ecs_status ecs_level_info(ecs_ctx *ctx, int level, int *nlevels, int64_t *nodes);
+
+/* Kernel timing for measurement: when enabled, HIP events are recorded on the
+ * context's stream around every launch of kernel class `kclass`
+ * (0 = finest-level cycle kernels, 1 = Arnoldi orthogonalisation, 2 = FP64
+ * operator A, 3 = coarse-level cycle kernels); ecs_timing_read returns the number of launches and their summed
+ * duration in milliseconds (synchronises) and resets the counters. */
+ecs_status ecs_timing_enable(ecs_ctx *ctx, int kclass, int enable);
+ecs_status ecs_timing_read(ecs_ctx *ctx, int kclass, int64_t *launches, double *total_ms);
+
+/* Batched solve of n independent problems (each context fully set up with its
+ * own workspace), all right-hand sides to their rtol with Bi-CGSTAB.  Every
+ * iteration of all unconverged systems is issued as one grouped launch per
+ * phase.  b[s], x[s] point to nrhs[s] contiguous complex128 vectors.
+ * stats receives one entry per system (aggregated over its right-hand sides). */
+ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *desc, const void *const *b,
+                           void *const *x, const int *nrhs, ecs_stats *stats);
+
+/* Plain device copy of `bytes` bytes (bandwidth probe), on `stream`. */
+ecs_status ecs_copy_probe(const void *src_dev, void *dst_dev, size_t bytes, void *stream);
+
+const char *ecs_last_error(const ecs_ctx *ctx);
+void ecs_destroy(ecs_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ECSMG_H */

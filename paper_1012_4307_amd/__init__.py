@@ -1,0 +1,419 @@
+"""MI355X-native multigrid-preconditioned Krylov solver for the exterior-
+complex-scaled (ECS) Helmholtz problem  (-Lap - k^2(x)) u = f.
+
+Method: bin Zubair, Reps, Vanroose, "A preconditioned iterative solver for the
+scattering solutions of the Schroedinger equation" -- ECS discretisation
+(Sec. 3), CSL / CSG / QD preconditioners inverted by one multigrid cycle
+(Sec. 4, Algorithm 1), right-preconditioned Krylov outer solve (Sec. 5).
+
+This module is a thin ctypes binding of the C ABI in ``include/ecsmg.h``
+(``libecsmg.so``, built from ``csrc/*.hip``).  It only marshals arguments:
+tensors must be contiguous CUDA (HIP) tensors; every arithmetic step runs in
+the library's HIP kernels on the tensors' device and the current torch
+stream.  There is no CPU fallback: if the library is missing the binding
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libecsmg.so")
+
+# enums of ecsmg.h
+F64, F32 = 0, 1
+DIRICHLET, ECS = 0, 1
+PREC = {"none": 0, "laplace": 1, "csl": 2, "csg": 3, "qd": 4}
+SMOOTHER = {"jacobi": 0, "rbgs": 1}
+KRYLOV = {"gmres": 0, "fgmres": 1, "bicgstab": 2}
+OP = {"A": 0, "AT": 1, "M": 2}
+STATUS = {0: "ok", 1: "not_converged", -1: "einval", -2: "enomem", -3: "edevice", -4: "ebreakdown", -5: "estate"}
+TIMER = {"finest_cycle": 0, "arnoldi": 1, "apply_A": 2, "coarse_cycle": 3}
+
+
+class EcsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class PrecDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("theta_alpha", ctypes.c_double), ("re_lambda0", ctypes.c_double), ("smoother", ctypes.c_int),
+                ("omega", ctypes.c_double), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("gamma_f", ctypes.c_int),
+                ("gamma_c", ctypes.c_int), ("coarsest_nodes", ctypes.c_int), ("vcycle_dtype", ctypes.c_int)]
+
+
+class SolveDesc(ctypes.Structure):
+    _fields_ = [("krylov", ctypes.c_int), ("restart", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("x_is_guess", ctypes.c_int), ("inner", ctypes.c_int),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("vcycles", ctypes.c_int64),
+                ("inner_iterations", ctypes.c_int64), ("rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libecsmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1012_4307_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    pP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "ecs_create": [pP, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D), P],
+        "ecs_set_ecs": [P, I, I, I, D, D],
+        "ecs_set_k2": [P, P],
+        "ecs_set_precond": [P, ctypes.POINTER(PrecDesc)],
+        "ecs_workspace_size": [P, ctypes.POINTER(SolveDesc), ctypes.POINTER(Z)],
+        "ecs_set_workspace": [P, P, Z],
+        "ecs_solve": [P, ctypes.POINTER(SolveDesc), P, P, ctypes.POINTER(Stats)],
+        "ecs_solve_adjoint": [P, ctypes.POINTER(SolveDesc), P, P, ctypes.POINTER(Stats)],
+        "ecs_grad_k2": [P, P, P, P],
+        "ecs_apply": [P, I, P, P],
+        "ecs_vcycle": [P, P, P],
+        "ecs_smooth": [P, I, P, P, I],
+        "ecs_residual_restrict": [P, I, P, P, P],
+        "ecs_prolong_correct": [P, I, P, P],
+        "ecs_coarse_solve": [P, P, P],
+        "ecs_level_info": [P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_int64)],
+        "ecs_timing_enable": [P, I, I],
+        "ecs_timing_read": [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D)],
+        "ecs_batch_solve": [I, pP, ctypes.POINTER(SolveDesc), pP, pP, ctypes.POINTER(I), ctypes.POINTER(Stats)],
+        "ecs_copy_probe": [P, P, Z, P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.ecs_last_error.argtypes = [P]
+    L.ecs_last_error.restype = ctypes.c_char_p
+    L.ecs_destroy.argtypes = [P]
+    L.ecs_destroy.restype = None
+    _lib = L
+    return L
+
+
+EXPORTED = ["ecs_create", "ecs_set_ecs", "ecs_set_k2", "ecs_set_precond", "ecs_workspace_size", "ecs_set_workspace",
+            "ecs_solve", "ecs_solve_adjoint", "ecs_grad_k2", "ecs_apply", "ecs_vcycle", "ecs_smooth",
+            "ecs_residual_restrict", "ecs_prolong_correct", "ecs_coarse_solve", "ecs_level_info",
+            "ecs_timing_enable", "ecs_timing_read", "ecs_batch_solve", "ecs_copy_probe", "ecs_last_error",
+            "ecs_destroy"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class Precond:
+    """Preconditioner and cycle (Sec. 4-5).  kind: none | laplace | csl | csg | qd."""
+    kind: str = "qd"
+    beta1: float = -1.0
+    beta2: float = -0.5
+    theta_alpha: float = math.pi / 13
+    re_lambda0: float = 0.0            # QD: <= 0 -> max k^2
+    smoother: str = "rbgs"
+    omega: float = 1.0
+    nu1: int = 1
+    nu2: int = 1
+    gamma_f: int = 1
+    gamma_c: int = 1
+    coarsest_nodes: int = 5
+    vcycle_dtype: str = "f64"          # f64 | f32
+
+    def to_c(self):
+        return PrecDesc(PREC[self.kind], self.beta1, self.beta2, self.theta_alpha, self.re_lambda0,
+                        SMOOTHER[self.smoother], self.omega, self.nu1, self.nu2, self.gamma_f, self.gamma_c,
+                        self.coarsest_nodes, F32 if self.vcycle_dtype == "f32" else F64)
+
+
+@dataclass
+class Krylov:
+    method: str = "gmres"      # gmres | fgmres | bicgstab
+    restart: int = 30
+    rtol: float = 1e-8
+    maxit: int = 2000
+    inner: int = 0             # nested FP32 Bi-CGSTAB iterations per FGMRES step
+
+    def to_c(self, x_is_guess=False, history=None):
+        d = SolveDesc(KRYLOV[self.method], self.restart, self.rtol, self.maxit, 1 if x_is_guess else 0, self.inner,
+                      None, 0)
+        if history is not None:
+            d.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.history_len = history.size
+        return d
+
+
+class Solver:
+    """One ECS Helmholtz problem on one GPU.
+
+    dim, n, lo, hi : grid (nodes per axis incl. both Dirichlet ends)
+    ecs            : per axis (lo_side, hi_side), each None or (layer start, theta)
+    k2             : float64 CUDA tensor of k^2 at the nodes, shape reversed(n)
+    precond        : Precond
+    krylov         : Krylov settings used to size the workspace (larger ones
+                     reallocate it on demand)
+    """
+
+    def __init__(self, dim, n, lo, hi, ecs, k2, precond: Precond, krylov: Optional[Krylov] = None):
+        torch = _torch()
+        L = lib()
+        self.dim = int(dim)
+        self.n = tuple(int(v) for v in n)
+        self.shape = tuple(reversed(self.n))
+        if not (k2.is_cuda and k2.dtype == torch.float64 and k2.is_contiguous() and tuple(k2.shape) == self.shape):
+            raise ValueError("k2 must be a contiguous float64 CUDA tensor of shape %s" % (self.shape,))
+        self.device = k2.device
+        self.k2 = k2
+        self.precond = precond
+        self.krylov = krylov or Krylov()
+        h = ctypes.c_void_p()
+        nodes = (ctypes.c_int64 * 3)(*(list(self.n) + [1] * (3 - self.dim)))
+        lo3 = (ctypes.c_double * 3)(*(list(lo) + [0.0] * (3 - self.dim)))
+        hi3 = (ctypes.c_double * 3)(*(list(hi) + [1.0] * (3 - self.dim)))
+        with torch.cuda.device(self.device):
+            self._check(L.ecs_create(ctypes.byref(h), self.dim, nodes, lo3, hi3, _stream_ptr(self.device)), None)
+        self._h = h
+        for a in range(self.dim):
+            for side in (0, 1):
+                spec = ecs[a][side]
+                if spec is not None:
+                    self._check(L.ecs_set_ecs(h, a, side, ECS, float(spec[0]), float(spec[1])))
+        self._check(L.ecs_set_k2(h, _ptr(k2)))
+        self._pd = precond.to_c()
+        self._check(L.ecs_set_precond(h, ctypes.byref(self._pd)))
+        self.nlev = self.level_count()
+        self.ws = None
+        self._ensure_workspace(self.krylov)
+
+    # ------------------------------------------------------------------
+    def _check(self, rc, h="self"):
+        if rc == 0:
+            return 0
+        msg = ""
+        hh = self._h if h == "self" else h
+        if hh is not None:
+            msg = lib().ecs_last_error(hh).decode()
+        raise EcsError(rc, msg)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().ecs_destroy(h)
+            self._h = None
+
+    def _ensure_workspace(self, kr: Krylov):
+        torch = _torch()
+        L = lib()
+        need = ctypes.c_size_t()
+        d = kr.to_c()
+        self._check(L.ecs_workspace_size(self._h, ctypes.byref(d), ctypes.byref(need)))
+        if self.ws is not None and self.ws.numel() >= need.value:
+            return
+        self.ws = torch.empty(need.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self._check(L.ecs_set_workspace(self._h, ctypes.c_void_p(base + off), need.value + 256 - off))
+
+    def reset_k2(self, k2):
+        """Replace k^2 (same shape) and rebuild the hierarchy."""
+        if tuple(k2.shape) != self.shape or not k2.is_contiguous():
+            raise ValueError("bad k2")
+        self.k2 = k2
+        L = lib()
+        self._check(L.ecs_set_k2(self._h, _ptr(k2)))
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self._check(L.ecs_set_workspace(self._h, ctypes.c_void_p(base + off), self.ws.numel() - off))
+
+    def level_count(self):
+        nl = ctypes.c_int()
+        self._check(lib().ecs_level_info(self._h, 0, ctypes.byref(nl), None))
+        return nl.value
+
+    def level_shape(self, level):
+        nodes = (ctypes.c_int64 * 3)()
+        nl = ctypes.c_int()
+        self._check(lib().ecs_level_info(self._h, level, ctypes.byref(nl), nodes))
+        return tuple(reversed([int(nodes[a]) for a in range(self.dim)]))
+
+    def _vec(self, t, dtype=None, shape=None):
+        torch = _torch()
+        dtype = dtype or torch.complex128
+        shape = shape or self.shape
+        if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"expected contiguous {dtype} CUDA tensor of shape {shape}, got {t.dtype} {tuple(t.shape)}")
+        return t
+
+    @property
+    def cycle_dtype(self):
+        torch = _torch()
+        return torch.complex64 if self.precond.vcycle_dtype == "f32" else torch.complex128
+
+    # ------------------------------------------------------------ solves
+    def solve(self, b, x0=None, krylov: Optional[Krylov] = None, history=None):
+        """Solve A x = b; returns (x, stats dict)."""
+        torch = _torch()
+        kr = krylov or self.krylov
+        self._ensure_workspace(kr)
+        b = self._vec(b)
+        x = x0.clone() if x0 is not None else torch.empty_like(b)
+        st = Stats()
+        d = kr.to_c(x0 is not None, history)
+        rc = lib().ecs_solve(self._h, ctypes.byref(d), _ptr(b), _ptr(x), ctypes.byref(st))
+        if rc < 0:
+            self._check(rc)
+        out = st.as_dict()
+        out["status_name"] = STATUS.get(rc, rc)
+        return x, out
+
+    def solve_adjoint(self, g, krylov: Optional[Krylov] = None):
+        """Solve A^T lam = g (no conjugation); returns (lam, stats dict)."""
+        torch = _torch()
+        kr = krylov or self.krylov
+        self._ensure_workspace(kr)
+        g = self._vec(g)
+        lam = torch.empty_like(g)
+        st = Stats()
+        d = kr.to_c()
+        rc = lib().ecs_solve_adjoint(self._h, ctypes.byref(d), _ptr(g), _ptr(lam), ctypes.byref(st))
+        if rc < 0:
+            self._check(rc)
+        out = st.as_dict()
+        out["status_name"] = STATUS.get(rc, rc)
+        return lam, out
+
+    def grad_k2(self, lam, u):
+        torch = _torch()
+        lam = self._vec(lam)
+        u = self._vec(u)
+        g = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._check(lib().ecs_grad_k2(self._h, _ptr(lam), _ptr(u), _ptr(g)))
+        return g
+
+    # ------------------------------------------------------- single steps
+    def apply(self, x, op="A"):
+        torch = _torch()
+        x = self._vec(x)
+        y = torch.empty_like(x)
+        self._check(lib().ecs_apply(self._h, OP[op], _ptr(x), _ptr(y)))
+        return y
+
+    def vcycle(self, v):
+        torch = _torch()
+        v = self._vec(v)
+        z = torch.empty_like(v)
+        self._check(lib().ecs_vcycle(self._h, _ptr(v), _ptr(z)))
+        return z
+
+    def smooth(self, b, u, level=0, nsweeps=1):
+        shape = self.level_shape(level)
+        b = self._vec(b, self.cycle_dtype, shape)
+        u = self._vec(u, self.cycle_dtype, shape).clone()
+        self._check(lib().ecs_smooth(self._h, level, _ptr(b), _ptr(u), nsweeps))
+        return u
+
+    def residual_restrict(self, b, u, level=0):
+        torch = _torch()
+        shape = self.level_shape(level)
+        b = self._vec(b, self.cycle_dtype, shape)
+        u = self._vec(u, self.cycle_dtype, shape)
+        rc = torch.empty(self.level_shape(level + 1), dtype=self.cycle_dtype, device=self.device)
+        self._check(lib().ecs_residual_restrict(self._h, level, _ptr(b), _ptr(u), _ptr(rc)))
+        return rc
+
+    def prolong_correct(self, ec, u, level=0):
+        ec = self._vec(ec, self.cycle_dtype, self.level_shape(level + 1))
+        u = self._vec(u, self.cycle_dtype, self.level_shape(level)).clone()
+        self._check(lib().ecs_prolong_correct(self._h, level, _ptr(ec), _ptr(u)))
+        return u
+
+    def coarse_solve(self, b):
+        torch = _torch()
+        shape = self.level_shape(self.nlev - 1)
+        b = self._vec(b, self.cycle_dtype, shape)
+        x = torch.empty_like(b)
+        self._check(lib().ecs_coarse_solve(self._h, _ptr(b), _ptr(x)))
+        return x
+
+    # ----------------------------------------------------------- timing
+    def timing(self, kclass: str, enable: bool = True):
+        self._check(lib().ecs_timing_enable(self._h, TIMER[kclass], 1 if enable else 0))
+
+    def timing_read(self, kclass: str):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        self._check(lib().ecs_timing_read(self._h, TIMER[kclass], ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+
+def batch_solve(solvers, rhs, krylov: Krylov):
+    """Solve every right-hand side of every system: rhs[s] is a complex128 CUDA
+    tensor of shape (nrhs_s, *solvers[s].shape).  Returns (solutions, stats)."""
+    torch = _torch()
+    n = len(solvers)
+    for S in solvers:
+        S._ensure_workspace(krylov)
+    xs = [torch.empty_like(b) for b in rhs]
+    ctxs = (ctypes.c_void_p * n)(*[S._h.value for S in solvers])
+    bs = (ctypes.c_void_p * n)(*[b.data_ptr() for b in rhs])
+    xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    nr = (ctypes.c_int * n)(*[int(b.shape[0]) for b in rhs])
+    st = (Stats * n)()
+    d = krylov.to_c()
+    rc = lib().ecs_batch_solve(n, ctxs, ctypes.byref(d), bs, xp, nr, st)
+    if rc < 0:
+        raise EcsError(rc, "batched solve failed")
+    return xs, [s.as_dict() for s in st]
+
+
+def copy_probe(src, dst):
+    torch = _torch()
+    nbytes = src.numel() * src.element_size()
+    rc = lib().ecs_copy_probe(_ptr(src), _ptr(dst), nbytes, _stream_ptr(src.device))
+    if rc != 0:
+        raise EcsError(rc, "copy probe failed")
+
+
+def solver_for(workload, device="cuda", vcycle_dtype="f64", krylov: Optional[Krylov] = None, precond=None):
+    """Build a Solver from a workloads.Workload (inputs copied to the GPU)."""
+    torch = _torch()
+    w = workload
+    k2 = torch.from_numpy(w.k2).to(device)
+    p = w.precond
+    cyc = w.cycle
+    pc = precond or Precond(kind=p["kind"], beta1=p.get("beta1", -1.0), beta2=p.get("beta2", -0.5),
+                            theta_alpha=p.get("theta_alpha", math.pi / 13), re_lambda0=p.get("lam0", 0.0),
+                            smoother=cyc["smoother"], omega=cyc["omega"], nu1=cyc["nu1"], nu2=cyc["nu2"],
+                            gamma_f=cyc["gamma_f"], gamma_c=cyc["gamma_c"], coarsest_nodes=cyc["coarsest"],
+                            vcycle_dtype=vcycle_dtype)
+    kr = krylov or Krylov(method=w.krylov["method"], restart=w.krylov.get("m", 30), rtol=w.krylov["rtol"],
+                          maxit=w.krylov["maxit"])
+    return Solver(w.dim, w.n, w.lo, w.hi, w.ecs, k2, pc, kr)

@@ -1,0 +1,93 @@
+// ecs_internal.h -- device data types and kernel launchers shared by the
+// HIP translation units of the library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ecs {
+
+// Interleaved complex number; 16 B (FP64) or 8 B (FP32), naturally aligned so
+// a node is one 128-bit / 64-bit vector load.
+template <typename R>
+struct alignas(2 * sizeof(R)) cplx {
+  R re, im;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> mk(R re, R im) {
+  cplx<R> z;
+  z.re = re;
+  z.im = im;
+  return z;
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator+(cplx<R> a, cplx<R> b) { return mk<R>(a.re + b.re, a.im + b.im); }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator-(cplx<R> a, cplx<R> b) { return mk<R>(a.re - b.re, a.im - b.im); }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator*(cplx<R> a, cplx<R> b) {
+  return mk<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator*(R s, cplx<R> a) { return mk<R>(s * a.re, s * a.im); }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> conjg(cplx<R> a) { return mk<R>(a.re, -a.im); }
+template <typename R>
+__host__ __device__ __forceinline__ R abs2(cplx<R> a) { return a.re * a.re + a.im * a.im; }
+// a / b = a conj(b) / |b|^2
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cdiv(cplx<R> a, cplx<R> b) {
+  R inv = R(1) / abs2(b);
+  return inv * (a * conjg(b));
+}
+template <typename D, typename S>
+__host__ __device__ __forceinline__ cplx<D> cvt(cplx<S> a) { return mk<D>(D(a.re), D(a.im)); }
+
+// One level of the hierarchy as seen by a kernel.  The operator is
+//   (M u)_p = sum_a [ cm_a(i_a) (u_p - u_{p - s_a}) + cp_a(i_a) (u_p - u_{p + s_a}) ]
+//             + (beta k2_p + c) u_p
+// with cm/cp the second-difference weights of Sec. 3.2 already multiplied by
+// the operator's Laplacian factor alpha.  n2 == 1 in 2D.
+template <typename R>
+struct Grid {
+  int n0, n1, n2;
+  const cplx<R> *cm0, *cp0, *cm1, *cp1, *cm2, *cp2;
+  const R *k2;
+  cplx<R> beta, c;
+};
+
+// ---------------------------------------------------------------- launchers
+// Multigrid components (kernels_mg.hip); R = double or float.
+template <typename R, typename RI, typename RO>
+void launch_apply(const Grid<R> &g, const cplx<RI> *x, cplx<RO> *y, hipStream_t s);
+template <typename R>
+void launch_residual(const Grid<R> &g, const cplx<R> *b, const cplx<R> *u, cplx<R> *r, hipStream_t s);
+template <typename R>
+void launch_jacobi(const Grid<R> &g, const cplx<R> *b, const cplx<R> *u, cplx<R> *out, R omega, bool zero_guess,
+                   hipStream_t s);
+template <typename R>
+void launch_rb_colour(const Grid<R> &g, const cplx<R> *b, cplx<R> *u, R omega, int colour, bool zero_guess,
+                      hipStream_t s);
+template <typename R>
+void launch_restrict(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *rf, cplx<R> *rc, hipStream_t s);
+template <typename R>
+void launch_residual_restrict(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u,
+                              cplx<R> *rc, hipStream_t s);
+template <typename R>
+void launch_prolong_add(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *ec, cplx<R> *u, hipStream_t s);
+template <typename R>
+void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, int n1, int n2, const cplx<R> *b,
+                         cplx<R> *x, hipStream_t s);
+// fused V(1,1) red-black kernels (2D): zero-guess pre-sweep + residual + FW,
+// and prolongation + correction + post-sweep (out of place)
+template <typename R>
+void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *u, cplx<R> *rc, R omega,
+                    hipStream_t s);
+template <typename R>
+void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
+                  const cplx<R> *ec, cplx<R> *u_out, R omega, hipStream_t s);
+template <typename R>
+void launch_inject_k2(int n0, int n1, int n2, const double *k2_fine, int f0, int f1, R *k2_coarse, hipStream_t s);
+
+}  // namespace ecs

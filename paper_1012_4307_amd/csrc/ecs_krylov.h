@@ -1,0 +1,79 @@
+// ecs_krylov.h -- device-resident Krylov scalars and the launchers of the
+// vector / reduction kernels (kernels_blas.hip).  Internal to the library.
+#pragma once
+
+#include "ecs_internal.h"
+
+namespace ecs {
+
+constexpr int kMaxRestart = 64;
+// reduction kernels use at most this many blocks (partial buffers are sized for it)
+constexpr int kRedBlocks = 512;
+
+// Scalars of one GMRES / FGMRES solve, kept in device memory.
+struct GmresScalars {
+  cplx<double> nrm2;                                   // last reduced squared norm (.re)
+  double bnorm;                                        // ||b||
+  double inv;                                          // 1 / (norm of the newest basis vector)
+  double est;                                          // |g_{j+1}| / ||b||  (Givens estimate)
+  double resid_true;                                   // true residual / ||b|| at a restart
+  int bad, happy;
+  cplx<double> one;                                    // constant 1 (single-column updates)
+  cplx<double> g[kMaxRestart + 1];
+  cplx<double> cs[kMaxRestart], sn[kMaxRestart];
+  cplx<double> y[kMaxRestart];
+  cplx<double> h2[kMaxRestart + 1];                    // second Gram-Schmidt pass
+  cplx<double> H[(kMaxRestart + 1) * kMaxRestart];     // column-major Hessenberg, ld = m+1
+};
+
+// Scalars of one Bi-CGSTAB solve.
+struct BicgScalars {
+  cplx<double> rho, alpha, omega, beta;
+  double rnorm2, bnorm, est;
+  int bad;
+};
+
+enum { kBicgRho = 0, kBicgAlpha = 1, kBicgOmega = 2, kBicgNorm = 3, kBicgInit = 4 };
+
+int reduction_blocks(int64_t n);
+
+template <typename RA, typename RB>
+void launch_mdot(const cplx<RA> *V, int64_t ldv, int ncols, const cplx<RB> *w, int64_t n, cplx<double> *partials,
+                 cplx<double> *out, hipStream_t s);
+void launch_mupdate(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w, int64_t n,
+                    cplx<double> *partials, cplx<double> *out_norm2, hipStream_t s);
+template <typename R>
+void launch_nrm2sq(const cplx<R> *x, int64_t n, cplx<double> *partials, cplx<double> *out, hipStream_t s);
+template <typename RZ>
+void launch_lincomb(const cplx<RZ> *Z, int64_t ldz, int ncols, const cplx<double> *y, cplx<double> *x, int64_t n,
+                    hipStream_t s);
+void launch_scale_dev(cplx<double> *x, int64_t n, const double *scal, hipStream_t s);
+void launch_gmres_start(GmresScalars *S, int m, hipStream_t s);
+void launch_gmres_givens(GmresScalars *S, int j, int m, hipStream_t s);
+void launch_gmres_backsolve(GmresScalars *S, int k, int m, hipStream_t s);
+void launch_add_h2(GmresScalars *S, int j, int m, hipStream_t s);
+
+template <typename R>
+void launch_pairdot(const cplx<R> *x0, const cplx<R> *y0, const cplx<R> *x1, const cplx<R> *y1, int npairs, int64_t n,
+                    cplx<double> *partials, BicgScalars *S, int mode, hipStream_t s);
+template <typename R>
+void launch_bicg_p(cplx<R> *p, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s);
+template <typename R>
+void launch_bicg_s(cplx<R> *sv, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s);
+template <typename R, typename RZ>
+void launch_bicg_xr(cplx<R> *x, const cplx<RZ> *ph, const cplx<RZ> *sh, cplx<R> *r, const cplx<R> *sv,
+                    const cplx<R> *t, int64_t n, cplx<double> *partials, BicgScalars *S, hipStream_t s);
+
+template <typename RI, typename RO>
+void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s);
+void launch_cast_real(const double *x, float *y, int64_t n, hipStream_t s);
+template <typename R>
+void launch_zero(cplx<R> *x, int64_t n, hipStream_t s);
+void launch_scale_w(int n0, int n1, int n2, const cplx<double> *w0, const cplx<double> *w1, const cplx<double> *w2,
+                    const cplx<double> *x, cplx<double> *y, bool inverse, hipStream_t s);
+void launch_mask_boundary(int n0, int n1, int n2, const cplx<double> *x, cplx<double> *y, hipStream_t s);
+void launch_grad_k2(const cplx<double> *lam, const cplx<double> *u, double *g, int64_t n, hipStream_t s);
+void launch_max_real(const double *x, int64_t n, double *partials, double *out, hipStream_t s);
+void launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+}  // namespace ecs

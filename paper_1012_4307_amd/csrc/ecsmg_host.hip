@@ -1,0 +1,1223 @@
+// ecsmg_host.hip -- host side of the C ABI in include/ecsmg.h: problem
+// context, ECS contour and grid hierarchy, multigrid cycle orchestration
+// (Algorithm 1 of bin Zubair, Reps, Vanroose, Sec. 4.2), and the right-
+// preconditioned GMRES / FGMRES / Bi-CGSTAB drivers of Sec. 5.  Every
+// arithmetic step on grid vectors runs in the HIP kernels of kernels_mg.hip
+// and kernels_blas.hip; the host only sequences launches, sets the problem up
+// (contour weights, coarsest dense inverse) and reads one residual estimate per
+// iteration to decide convergence.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ecs_krylov.h"
+#include "ecsmg.h"
+
+using namespace ecs;
+using cd = std::complex<double>;
+
+namespace {
+
+constexpr int kMaxLev = 16;
+
+struct Side {
+  int kind = ECS_BC_DIRICHLET;
+  double start = 0, theta = 0;
+};
+
+// host copy of one level's contour and second-difference weights
+struct HostLevel {
+  int n[3] = {1, 1, 1};
+  int64_t nn = 0;
+  std::vector<cd> z[3], am[3], ap[3], w[3];
+};
+
+template <typename R>
+struct DevLevel {
+  cplx<R> *cm[3] = {nullptr, nullptr, nullptr};  // alpha * a-  (preconditioner operator M)
+  cplx<R> *cp[3] = {nullptr, nullptr, nullptr};  // alpha * a+
+  R *k2 = nullptr;
+  cplx<R> *b = nullptr, *u = nullptr, *t = nullptr;
+};
+
+struct Timer {
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  size_t used = 0;
+  bool on = false;
+  int64_t launches = 0;
+};
+
+// bump allocator over the caller's workspace (256 B alignment); with a null
+// base it only measures
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(char *b) : base(b) {}
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct ecs_ctx {
+  int dim = 2;
+  int n[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Side side[3][2];
+  const double *k2 = nullptr;
+  bool have_prec = false;
+  ecs_prec_desc prec{};
+  int nlev = 0;
+  std::vector<HostLevel> hl;
+  cd alpha{1, 0}, beta{-1, 0}, c{0, 0};
+  double lam0 = 0;
+
+  char *ws = nullptr;
+  size_t ws_bytes = 0, hier_bytes = 0;
+  bool ready = false;
+
+  // FP64 finest-level weights of A and of the symmetriser W
+  cplx<double> *Acm[3] = {}, *Acp[3] = {}, *Wd[3] = {};
+  cplx<float> *Acm32[3] = {}, *Acp32[3] = {};  // FP32 copy of A's weights (nested form)
+  DevLevel<double> L64[kMaxLev];
+  DevLevel<float> L32[kMaxLev];
+  cplx<double> *minv64 = nullptr;
+  cplx<float> *minv32 = nullptr;
+  int *unk = nullptr;
+  int nunk = 0;
+  cplx<double> *partials = nullptr;
+  double *dscal = nullptr;  // misc device scalars (max k^2 ...)
+  GmresScalars *gs = nullptr;
+  BicgScalars *bs = nullptr, *bs_in = nullptr;
+  double *pinned = nullptr;  // host-pinned scalars for readback
+
+  Timer timers[4];  // 0 finest-level cycle, 1 Arnoldi, 2 operator A, 3 coarse levels
+  std::string err;
+};
+
+namespace {
+
+int64_t nn_of(const ecs_ctx *C) { return (int64_t)C->n[0] * C->n[1] * C->n[2]; }
+
+ecs_status fail(ecs_ctx *C, ecs_status st, const std::string &msg) {
+  if (C) C->err = msg;
+  return st;
+}
+
+#define HIP_OK(call)                                                                                        \
+  do {                                                                                                      \
+    hipError_t e_ = (call);                                                                                 \
+    if (e_ != hipSuccess) return fail(C, ECS_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_));     \
+  } while (0)
+
+// ------------------------------------------------------------ geometry
+// Sec. 3.1: nodal contour of one axis, z = x up to a layer start s, rotated
+// beyond it: z = s + (x - s) e^{i theta}.
+std::vector<cd> contour(int n, double lo, double hi, const Side &slo, const Side &shi) {
+  std::vector<cd> z(n);
+  const double h = (hi - lo) / (n - 1);
+  for (int i = 0; i < n; i++) {
+    double x = lo + i * h;
+    cd zi(x, 0);
+    if (shi.kind == ECS_BC_ECS && x > shi.start) zi = shi.start + (x - shi.start) * std::polar(1.0, shi.theta);
+    if (slo.kind == ECS_BC_ECS && x < slo.start) zi = slo.start + (x - slo.start) * std::polar(1.0, slo.theta);
+    z[i] = zi;
+  }
+  return z;
+}
+
+// Sec. 3.2: non-uniform 3-point weights from node spacings h_{i-1}, h_i:
+//   a-_i = 2/((h_{i-1}+h_i) h_{i-1}),  a+_i = 2/((h_{i-1}+h_i) h_i),
+// dual width w_i = (h_{i-1}+h_i)/2; end nodes get a = 0, w = 1.
+void weights(const std::vector<cd> &z, std::vector<cd> &am, std::vector<cd> &ap, std::vector<cd> &w) {
+  const size_t n = z.size();
+  am.assign(n, 0.0);
+  ap.assign(n, 0.0);
+  w.assign(n, 1.0);
+  for (size_t i = 1; i + 1 < n; i++) {
+    cd hl = z[i] - z[i - 1], hr = z[i + 1] - z[i];
+    cd s = hl + hr;
+    am[i] = 2.0 / (s * hl);
+    ap[i] = 2.0 / (s * hr);
+    w[i] = 0.5 * s;
+  }
+}
+
+void build_host_levels(ecs_ctx *C) {
+  C->hl.assign(C->nlev, HostLevel());
+  for (int l = 0; l < C->nlev; l++) {
+    HostLevel &L = C->hl[l];
+    for (int a = 0; a < 3; a++) {
+      if (a >= C->dim) {
+        L.n[a] = 1;
+        L.z[a].assign(1, 0.0);
+        L.am[a].assign(1, 0.0);
+        L.ap[a].assign(1, 0.0);
+        L.w[a].assign(1, 1.0);
+        continue;
+      }
+      if (l == 0) {
+        L.n[a] = C->n[a];
+        L.z[a] = contour(C->n[a], C->lo[a], C->hi[a], C->side[a][0], C->side[a][1]);
+      } else {
+        const HostLevel &F = C->hl[l - 1];
+        L.n[a] = (F.n[a] - 1) / 2 + 1;
+        L.z[a].resize(L.n[a]);
+        for (int i = 0; i < L.n[a]; i++) L.z[a][i] = F.z[a][2 * i];  // exact nesting
+      }
+      weights(L.z[a], L.am[a], L.ap[a], L.w[a]);
+    }
+    L.nn = (int64_t)L.n[0] * L.n[1] * L.n[2];
+  }
+}
+
+// ------------------------------------------------------ workspace plan
+size_t plan_hierarchy(ecs_ctx *C, char *base) {
+  Carver cv(base);
+  const bool f32 = C->prec.vcycle_dtype == ECS_F32;
+  for (int a = 0; a < C->dim; a++) {
+    C->Acm[a] = cv.take<cplx<double>>(C->hl[0].n[a]);
+    C->Acp[a] = cv.take<cplx<double>>(C->hl[0].n[a]);
+    C->Wd[a] = cv.take<cplx<double>>(C->hl[0].n[a]);
+    if (f32) {
+      C->Acm32[a] = cv.take<cplx<float>>(C->hl[0].n[a]);
+      C->Acp32[a] = cv.take<cplx<float>>(C->hl[0].n[a]);
+    }
+  }
+  for (int l = 0; l < C->nlev; l++) {
+    const HostLevel &L = C->hl[l];
+    DevLevel<double> &D = C->L64[l];
+    DevLevel<float> &S = C->L32[l];
+    for (int a = 0; a < C->dim; a++) {
+      D.cm[a] = cv.take<cplx<double>>(L.n[a]);
+      D.cp[a] = cv.take<cplx<double>>(L.n[a]);
+      if (f32) {
+        S.cm[a] = cv.take<cplx<float>>(L.n[a]);
+        S.cp[a] = cv.take<cplx<float>>(L.n[a]);
+      }
+    }
+    D.k2 = (l == 0) ? nullptr : cv.take<double>(L.nn);
+    if (f32) S.k2 = cv.take<float>(L.nn);
+    if (!f32) {
+      D.b = (l == 0) ? nullptr : cv.take<cplx<double>>(L.nn);
+      D.u = (l == 0) ? nullptr : cv.take<cplx<double>>(L.nn);
+      D.t = cv.take<cplx<double>>(L.nn);
+    } else {
+      S.b = cv.take<cplx<float>>(L.nn);
+      S.u = (l == 0) ? nullptr : cv.take<cplx<float>>(L.nn);
+      S.t = cv.take<cplx<float>>(L.nn);
+    }
+  }
+  const HostLevel &Lc = C->hl[C->nlev - 1];
+  int nunk = 1;
+  for (int a = 0; a < C->dim; a++) nunk *= (Lc.n[a] - 2);
+  C->nunk = nunk;
+  C->minv64 = cv.take<cplx<double>>((size_t)nunk * nunk);
+  if (f32) C->minv32 = cv.take<cplx<float>>((size_t)nunk * nunk);
+  C->unk = cv.take<int>(nunk);
+  C->partials = cv.take<cplx<double>>((size_t)kRedBlocks * (kMaxRestart + 2));
+  C->dscal = cv.take<double>(kRedBlocks + 8);
+  C->gs = cv.take<GmresScalars>(1);
+  C->bs = cv.take<BicgScalars>(1);
+  C->bs_in = cv.take<BicgScalars>(1);
+  return cv.off;
+}
+
+// Krylov storage laid out after the hierarchy
+struct KrylovBufs {
+  cplx<double> *V = nullptr;  // (m+1) x n
+  void *Z = nullptr;          // m x n in the cycle dtype (FGMRES)
+  cplx<double> *t = nullptr;  // n
+  void *tz = nullptr;         // n, cycle dtype
+  cplx<double> *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *tt = nullptr;
+  void *ph = nullptr, *sh = nullptr;
+  cplx<float> *fr = nullptr, *frh = nullptr, *fp = nullptr, *fv = nullptr, *fs = nullptr, *ft = nullptr,
+              *fph = nullptr, *fsh = nullptr;
+  cplx<double> *a1 = nullptr, *a2 = nullptr;  // adjoint scaling buffers
+  cplx<double> *bz = nullptr;                 // right-hand side with its boundary entries zeroed
+  int64_t ld = 0;
+};
+
+size_t plan_krylov(const ecs_ctx *C, const ecs_solve_desc *d, char *base, KrylovBufs *K) {
+  Carver cv(base);
+  const int64_t n = nn_of(C);
+  const size_t zs = C->prec.vcycle_dtype == ECS_F32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+  K->ld = (n + 31) & ~int64_t(31);
+  K->a1 = cv.take<cplx<double>>(n);
+  K->a2 = cv.take<cplx<double>>(n);
+  K->tz = cv.take<char>(n * zs);
+  K->bz = cv.take<cplx<double>>(n);
+  if (!d) return cv.off;
+  if (d->krylov == ECS_KRYLOV_BICGSTAB) {
+    K->r = cv.take<cplx<double>>(n);
+    K->rh = cv.take<cplx<double>>(n);
+    K->p = cv.take<cplx<double>>(n);
+    K->v = cv.take<cplx<double>>(n);
+    K->s = cv.take<cplx<double>>(n);
+    K->tt = cv.take<cplx<double>>(n);
+    K->ph = cv.take<char>(n * zs);
+    K->sh = cv.take<char>(n * zs);
+  } else {
+    const int m = d->restart;
+    K->V = cv.take<cplx<double>>((size_t)K->ld * (m + 1));
+    K->t = cv.take<cplx<double>>(n);
+    if (d->krylov == ECS_KRYLOV_FGMRES) K->Z = cv.take<char>((size_t)K->ld * m * zs);
+    if (d->inner > 0) {
+      K->fr = cv.take<cplx<float>>(n);
+      K->frh = cv.take<cplx<float>>(n);
+      K->fp = cv.take<cplx<float>>(n);
+      K->fv = cv.take<cplx<float>>(n);
+      K->fs = cv.take<cplx<float>>(n);
+      K->ft = cv.take<cplx<float>>(n);
+      K->fph = cv.take<cplx<float>>(n);
+      K->fsh = cv.take<cplx<float>>(n);
+    }
+  }
+  return cv.off;
+}
+
+// ------------------------------------------------------------ timing
+struct TimedScope {
+  ecs_ctx *C;
+  Timer *T;
+  size_t slot = SIZE_MAX;
+  TimedScope(ecs_ctx *c, int cls) : C(c), T(&c->timers[cls]) {
+    if (!T->on) return;
+    if (T->used + 2 > T->ev.size()) {
+      if (T->ev.size() >= 2 * 65536) return;
+      size_t old = T->ev.size();
+      T->ev.resize(old + 2 * 1024);
+      for (size_t q = old; q < T->ev.size(); q++) (void)hipEventCreate(&T->ev[q]);
+    }
+    slot = T->used;
+    T->used += 2;
+    (void)hipEventRecord(T->ev[slot], C->stream);
+  }
+  ~TimedScope() {
+    if (slot == SIZE_MAX) return;
+    (void)hipEventRecord(T->ev[slot + 1], C->stream);
+    T->launches++;
+  }
+};
+
+// ------------------------------------------------------- grid views
+template <typename R>
+cplx<R> tocx(cd v) {
+  return mk<R>((R)v.real(), (R)v.imag());
+}
+
+template <typename R>
+Grid<R> grid_M(const ecs_ctx *C, int l);
+
+template <>
+Grid<double> grid_M<double>(const ecs_ctx *C, int l) {
+  const HostLevel &L = C->hl[l];
+  const DevLevel<double> &D = C->L64[l];
+  Grid<double> g;
+  g.n0 = L.n[0];
+  g.n1 = L.n[1];
+  g.n2 = L.n[2];
+  g.cm0 = D.cm[0]; g.cp0 = D.cp[0];
+  g.cm1 = D.cm[1]; g.cp1 = D.cp[1];
+  g.cm2 = D.cm[2]; g.cp2 = D.cp[2];
+  g.k2 = l == 0 ? C->k2 : D.k2;
+  g.beta = tocx<double>(C->beta);
+  g.c = tocx<double>(C->c);
+  return g;
+}
+
+template <>
+Grid<float> grid_M<float>(const ecs_ctx *C, int l) {
+  const HostLevel &L = C->hl[l];
+  const DevLevel<float> &D = C->L32[l];
+  Grid<float> g;
+  g.n0 = L.n[0];
+  g.n1 = L.n[1];
+  g.n2 = L.n[2];
+  g.cm0 = D.cm[0]; g.cp0 = D.cp[0];
+  g.cm1 = D.cm[1]; g.cp1 = D.cp[1];
+  g.cm2 = D.cm[2]; g.cp2 = D.cp[2];
+  g.k2 = D.k2;
+  g.beta = tocx<float>(C->beta);
+  g.c = tocx<float>(C->c);
+  return g;
+}
+
+// the discrete ECS Helmholtz operator A = Z on the finest grid (FP64)
+Grid<double> grid_A(const ecs_ctx *C) {
+  Grid<double> g = grid_M<double>(C, 0);
+  g.cm0 = C->Acm[0]; g.cp0 = C->Acp[0];
+  g.cm1 = C->Acm[1]; g.cp1 = C->Acp[1];
+  g.cm2 = C->Acm[2]; g.cp2 = C->Acp[2];
+  g.beta = mk<double>(-1, 0);
+  g.c = mk<double>(0, 0);
+  return g;
+}
+
+// A in FP32 (finest grid), for the FP32 inner Krylov iteration
+Grid<float> grid_A32(const ecs_ctx *C) {
+  Grid<float> g = grid_M<float>(C, 0);
+  g.cm0 = C->Acm32[0]; g.cp0 = C->Acp32[0];
+  g.cm1 = C->Acm32[1]; g.cp1 = C->Acp32[1];
+  g.cm2 = C->Acm32[2]; g.cp2 = C->Acp32[2];
+  g.beta = mk<float>(-1, 0);
+  g.c = mk<float>(0, 0);
+  return g;
+}
+
+template <typename R>
+DevLevel<R> &dev_level(ecs_ctx *C, int l);
+template <>
+DevLevel<double> &dev_level<double>(ecs_ctx *C, int l) { return C->L64[l]; }
+template <>
+DevLevel<float> &dev_level<float>(ecs_ctx *C, int l) { return C->L32[l]; }
+
+template <typename R>
+const cplx<R> *minv_of(const ecs_ctx *C);
+template <>
+const cplx<double> *minv_of<double>(const ecs_ctx *C) { return C->minv64; }
+template <>
+const cplx<float> *minv_of<float>(const ecs_ctx *C) { return C->minv32; }
+
+// ---------------------------------------------------------- setup
+template <typename R>
+ecs_status upload_cx(ecs_ctx *C, cplx<R> *dst, const std::vector<cd> &src, cd scale) {
+  std::vector<cplx<R>> h(src.size());
+  for (size_t i = 0; i < src.size(); i++) h[i] = tocx<R>(scale * src[i]);
+  HIP_OK(hipMemcpy(dst, h.data(), h.size() * sizeof(cplx<R>), hipMemcpyHostToDevice));
+  return ECS_OK;
+}
+
+// Gauss-Jordan inverse with partial pivoting (FP64) of a dense complex matrix
+bool invert(std::vector<cd> &a, int n) {
+  std::vector<cd> inv((size_t)n * n, 0.0);
+  for (int i = 0; i < n; i++) inv[(size_t)i * n + i] = 1.0;
+  for (int k = 0; k < n; k++) {
+    int pr = k;
+    double best = std::abs(a[(size_t)k * n + k]);
+    for (int r = k + 1; r < n; r++)
+      if (std::abs(a[(size_t)r * n + k]) > best) {
+        best = std::abs(a[(size_t)r * n + k]);
+        pr = r;
+      }
+    if (best == 0) return false;
+    if (pr != k)
+      for (int q = 0; q < n; q++) {
+        std::swap(a[(size_t)k * n + q], a[(size_t)pr * n + q]);
+        std::swap(inv[(size_t)k * n + q], inv[(size_t)pr * n + q]);
+      }
+    cd piv = 1.0 / a[(size_t)k * n + k];
+    for (int q = 0; q < n; q++) {
+      a[(size_t)k * n + q] *= piv;
+      inv[(size_t)k * n + q] *= piv;
+    }
+    for (int r = 0; r < n; r++) {
+      if (r == k) continue;
+      cd f = a[(size_t)r * n + k];
+      if (f == 0.0) continue;
+      for (int q = 0; q < n; q++) {
+        a[(size_t)r * n + q] -= f * a[(size_t)k * n + q];
+        inv[(size_t)r * n + q] -= f * inv[(size_t)k * n + q];
+      }
+    }
+  }
+  a.swap(inv);
+  return true;
+}
+
+ecs_status setup(ecs_ctx *C) {
+  const bool f32 = C->prec.vcycle_dtype == ECS_F32;
+  hipStream_t s = C->stream;
+  const int64_t nn0 = nn_of(C);
+  // operator scalars of M (Sec. 5)
+  const ecs_prec_desc &P = C->prec;
+  double lam0 = 0;
+  if (P.kind == ECS_PREC_QD) {
+    lam0 = P.re_lambda0;
+    if (lam0 <= 0) {
+      launch_max_real(C->k2, nn0, C->dscal, C->dscal + kRedBlocks, s);
+      HIP_OK(hipMemcpyAsync(C->pinned, C->dscal + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      lam0 = C->pinned[0];
+      if (!(lam0 > 0)) return fail(C, ECS_EINVAL, "QD: max k^2 must be positive for the automatic |Re lambda0|");
+    }
+  }
+  C->lam0 = lam0;
+  switch (P.kind) {
+    case ECS_PREC_NONE: C->alpha = 1.0; C->beta = -1.0; C->c = 0.0; break;
+    case ECS_PREC_LAPLACE: C->alpha = 1.0; C->beta = 0.0; C->c = 0.0; break;
+    case ECS_PREC_CSL: C->alpha = 1.0; C->beta = cd(P.beta1, P.beta2); C->c = 0.0; break;
+    case ECS_PREC_CSG:  // every weight is homogeneous of degree -2 in the widths
+      C->alpha = std::polar(1.0, -2.0 * P.theta_alpha); C->beta = -1.0; C->c = 0.0; break;
+    case ECS_PREC_QD: C->alpha = 1.0 / lam0; C->beta = -1.0 / lam0; C->c = cd(1.0, -1.0); break;
+    default: return fail(C, ECS_EINVAL, "unknown preconditioner kind");
+  }
+  // weights
+  const HostLevel &F = C->hl[0];
+  for (int a = 0; a < C->dim; a++) {
+    ecs_status st;
+    if ((st = upload_cx<double>(C, C->Acm[a], F.am[a], 1.0)) != ECS_OK) return st;
+    if ((st = upload_cx<double>(C, C->Acp[a], F.ap[a], 1.0)) != ECS_OK) return st;
+    if ((st = upload_cx<double>(C, C->Wd[a], F.w[a], 1.0)) != ECS_OK) return st;
+    if (f32) {
+      if ((st = upload_cx<float>(C, C->Acm32[a], F.am[a], 1.0)) != ECS_OK) return st;
+      if ((st = upload_cx<float>(C, C->Acp32[a], F.ap[a], 1.0)) != ECS_OK) return st;
+    }
+  }
+  for (int l = 0; l < C->nlev; l++) {
+    const HostLevel &L = C->hl[l];
+    for (int a = 0; a < C->dim; a++) {
+      ecs_status st;
+      if ((st = upload_cx<double>(C, C->L64[l].cm[a], L.am[a], C->alpha)) != ECS_OK) return st;
+      if ((st = upload_cx<double>(C, C->L64[l].cp[a], L.ap[a], C->alpha)) != ECS_OK) return st;
+      if (f32) {
+        if ((st = upload_cx<float>(C, C->L32[l].cm[a], L.am[a], C->alpha)) != ECS_OK) return st;
+        if ((st = upload_cx<float>(C, C->L32[l].cp[a], L.ap[a], C->alpha)) != ECS_OK) return st;
+      }
+    }
+    // k^2 on level l: injection from the finest grid (rediscretisation, Sec. 4.2)
+    if (l > 0) launch_inject_k2<double>(L.n[0], L.n[1], L.n[2], C->k2, F.n[0], F.n[1], C->L64[l].k2, s);
+    if (f32) {
+      if (l == 0) launch_cast_real(C->k2, C->L32[0].k2, L.nn, s);
+      else launch_inject_k2<float>(L.n[0], L.n[1], L.n[2], C->k2, F.n[0], F.n[1], C->L32[l].k2, s);
+    }
+  }
+  // coarsest dense inverse of M
+  const int lc = C->nlev - 1;
+  const HostLevel &Lc = C->hl[lc];
+  std::vector<double> k2c(Lc.nn);
+  const double *k2dev = lc == 0 ? C->k2 : C->L64[lc].k2;
+  HIP_OK(hipMemcpyAsync(k2c.data(), k2dev, Lc.nn * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  std::vector<int> unk;
+  std::vector<int64_t> pos(Lc.nn, -1);
+  const int kz0 = C->dim == 3 ? 1 : 0, kz1 = C->dim == 3 ? Lc.n[2] - 1 : 1;
+  for (int k = kz0; k < kz1; k++)
+    for (int j = 1; j < Lc.n[1] - 1; j++)
+      for (int i = 1; i < Lc.n[0] - 1; i++) {
+        int64_t p = ((int64_t)k * Lc.n[1] + j) * Lc.n[0] + i;
+        pos[p] = (int64_t)unk.size();
+        unk.push_back((int)p);
+      }
+  const int nu = (int)unk.size();
+  if (nu != C->nunk) return fail(C, ECS_EINVAL, "internal: coarse unknown count");
+  std::vector<cd> M((size_t)nu * nu, 0.0);
+  for (int r = 0; r < nu; r++) {
+    int64_t p = unk[r];
+    int ci[3] = {(int)(p % Lc.n[0]), (int)((p / Lc.n[0]) % Lc.n[1]), (int)(p / ((int64_t)Lc.n[0] * Lc.n[1]))};
+    int64_t stride[3] = {1, Lc.n[0], (int64_t)Lc.n[0] * Lc.n[1]};
+    cd diag = C->beta * k2c[p] + C->c;
+    for (int a = 0; a < C->dim; a++) {
+      cd am = C->alpha * Lc.am[a][ci[a]], ap = C->alpha * Lc.ap[a][ci[a]];
+      diag += am + ap;
+      int64_t qm = pos[p - stride[a]], qp = pos[p + stride[a]];
+      if (qm >= 0) M[(size_t)r * nu + qm] -= am;
+      if (qp >= 0) M[(size_t)r * nu + qp] -= ap;
+    }
+    M[(size_t)r * nu + r] += diag;
+  }
+  if (!invert(M, nu)) return fail(C, ECS_EINVAL, "coarsest preconditioner matrix is singular");
+  {
+    ecs_status st;
+    if ((st = upload_cx<double>(C, C->minv64, M, 1.0)) != ECS_OK) return st;
+    if (f32 && (st = upload_cx<float>(C, C->minv32, M, 1.0)) != ECS_OK) return st;
+  }
+  HIP_OK(hipMemcpy(C->unk, unk.data(), nu * sizeof(int), hipMemcpyHostToDevice));
+  HIP_OK(hipStreamSynchronize(s));
+  HIP_OK(hipGetLastError());
+  return ECS_OK;
+}
+
+// ----------------------------------------------------------- multigrid
+// smoothing sweeps on level l, u in place (t = level scratch)
+template <typename R>
+void smooth(ecs_ctx *C, int l, const cplx<R> *b, cplx<R> *u, cplx<R> *t, int nsweeps, bool zero_guess) {
+  Grid<R> g = grid_M<R>(C, l);
+  const R om = (R)C->prec.omega;
+  const int64_t nn = C->hl[l].nn;
+  for (int q = 0; q < nsweeps; q++) {
+    TimedScope ts(C, l == 0 ? 0 : 3);
+    bool zg = zero_guess && q == 0;
+    if (C->prec.smoother == ECS_SMOOTH_JACOBI) {
+      launch_jacobi<R>(g, b, u, t, om, zg, C->stream);
+      (void)hipMemcpyAsync(u, t, nn * sizeof(cplx<R>), hipMemcpyDeviceToDevice, C->stream);
+    } else {
+      launch_rb_colour<R>(g, b, u, om, 0, zg, C->stream);
+      launch_rb_colour<R>(g, b, u, om, 1, false, C->stream);
+    }
+  }
+  if (nsweeps == 0 && zero_guess) launch_zero<R>(u, nn, C->stream);
+}
+
+template <typename R>
+void coarse_solve(ecs_ctx *C, const cplx<R> *b, cplx<R> *x) {
+  const HostLevel &L = C->hl[C->nlev - 1];
+  launch_coarse_solve<R>(C->nunk, minv_of<R>(C), C->unk, L.n[0], L.n[1], L.n[2], b, x, C->stream);
+}
+
+// Algorithm 1: u <- MG(l, M_l, b, u, nu1, nu2, C, gf, gc).  zero_guess: u == 0
+// on entry (u's contents are not read and need not be cleared).
+template <typename R>
+void mg(ecs_ctx *C, int l, const cplx<R> *b, cplx<R> *u, int gf, int gc, bool zero_guess) {
+  const int lc = C->nlev - 1;
+  if (l == lc) {
+    coarse_solve<R>(C, b, u);
+    return;
+  }
+  DevLevel<R> &D = dev_level<R>(C, l);
+  DevLevel<R> &Dc = dev_level<R>(C, l + 1);
+  smooth<R>(C, l, b, u, D.t, C->prec.nu1, zero_guess);
+  {
+    TimedScope ts(C, l == 0 ? 0 : 3);
+    launch_residual_restrict<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, u, Dc.b, C->stream);
+  }
+  if (l + 1 == lc) {
+    coarse_solve<R>(C, Dc.b, Dc.u);
+  } else {
+    for (int i = 1; i <= gc; i++) {
+      if (i == 1) mg<R>(C, l + 1, Dc.b, Dc.u, gf, gc, true);
+      else mg<R>(C, l + 1, Dc.b, Dc.u, gc, gf, false);
+    }
+  }
+  {
+    TimedScope ts(C, l == 0 ? 0 : 3);
+    launch_prolong_add<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), Dc.u, u, C->stream);
+  }
+  smooth<R>(C, l, b, u, D.t, C->prec.nu2, false);
+}
+
+// z = M^{-1} v approximately: one cycle from zero on the finest level
+template <typename R>
+void vcycle(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
+  if (C->nlev == 1) {
+    coarse_solve<R>(C, b0, u0);
+    return;
+  }
+  mg<R>(C, 0, b0, u0, C->prec.gamma_f, C->prec.gamma_c, true);
+}
+
+// preconditioner application from an FP64 vector into the cycle's dtype
+template <typename RZ>
+void precond(ecs_ctx *C, const cplx<double> *v, cplx<RZ> *z);
+template <>
+void precond<double>(ecs_ctx *C, const cplx<double> *v, cplx<double> *z) {
+  if (C->prec.kind == ECS_PREC_NONE) {
+    (void)hipMemcpyAsync(z, v, nn_of(C) * sizeof(cplx<double>), hipMemcpyDeviceToDevice, C->stream);
+    return;
+  }
+  vcycle<double>(C, v, z);
+}
+template <>
+void precond<float>(ecs_ctx *C, const cplx<double> *v, cplx<float> *z) {
+  cplx<float> *b0 = C->L32[0].b;
+  launch_cast<double, float>(v, b0, nn_of(C), C->stream);
+  vcycle<float>(C, b0, z);
+}
+
+// ----------------------------------------------------------- Krylov
+// copy `bytes` (<= 64) from device memory into the pinned buffer and wait
+bool read_bytes(ecs_ctx *C, const void *dev, size_t bytes) {
+  if (hipMemcpyAsync(C->pinned, dev, bytes, hipMemcpyDeviceToHost, C->stream) != hipSuccess) return false;
+  return hipStreamSynchronize(C->stream) == hipSuccess;
+}
+
+double read_scalar(ecs_ctx *C, const double *dev) {
+  if (hipMemcpyAsync(C->pinned, dev, sizeof(double), hipMemcpyDeviceToHost, C->stream) != hipSuccess) return NAN;
+  if (hipStreamSynchronize(C->stream) != hipSuccess) return NAN;
+  return C->pinned[0];
+}
+
+// FP32 Bi-CGSTAB around the FP32 cycle, `iters` iterations from x = 0, all on
+// the device (nested mixed-precision preconditioner of FGMRES)
+void inner_bicgstab(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *v, cplx<float> *x, int iters) {
+  const int64_t n = nn_of(C);
+  hipStream_t s = C->stream;
+  BicgScalars *S = C->bs_in;
+  launch_cast<double, float>(v, K.fr, n, s);
+  (void)hipMemcpyAsync(K.frh, K.fr, n * sizeof(cplx<float>), hipMemcpyDeviceToDevice, s);
+  launch_zero<float>(x, n, s);
+  launch_zero<float>(K.fp, n, s);
+  launch_zero<float>(K.fv, n, s);
+  launch_pairdot<float>(K.fr, K.fr, nullptr, nullptr, 1, n, C->partials, S, kBicgInit, s);
+  const Grid<float> gA = grid_A32(C);
+  for (int it = 0; it < iters; it++) {
+    launch_pairdot<float>(K.frh, K.fr, nullptr, nullptr, 1, n, C->partials, S, kBicgRho, s);
+    launch_bicg_p<float>(K.fp, K.fr, K.fv, n, S, s);
+    vcycle<float>(C, K.fp, K.fph);
+    launch_apply<float, float, float>(gA, K.fph, K.fv, s);
+    launch_pairdot<float>(K.frh, K.fv, nullptr, nullptr, 1, n, C->partials, S, kBicgAlpha, s);
+    launch_bicg_s<float>(K.fs, K.fr, K.fv, n, S, s);
+    vcycle<float>(C, K.fs, K.fsh);
+    launch_apply<float, float, float>(gA, K.fsh, K.ft, s);
+    launch_pairdot<float>(K.ft, K.fs, K.ft, K.ft, 2, n, C->partials, S, kBicgOmega, s);
+    launch_bicg_xr<float, float>(x, K.fph, K.fsh, K.fr, K.fs, K.ft, n, C->partials, S, s);
+  }
+}
+
+template <typename RZ>
+ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const cplx<double> *b, cplx<double> *x,
+                 ecs_stats *st) {
+  const int64_t n = nn_of(C);
+  const int m = d->restart;
+  const bool flexible = d->krylov == ECS_KRYLOV_FGMRES;
+  hipStream_t s = C->stream;
+  GmresScalars *S = C->gs;
+  const int64_t ld = K.ld;
+  cplx<RZ> *Z = reinterpret_cast<cplx<RZ> *>(K.Z);
+  cplx<RZ> *tz = reinterpret_cast<cplx<RZ> *>(K.tz);
+  const cplx<double> one = mk<double>(1, 0);
+  HIP_OK(hipMemcpyAsync(&S->one, &one, sizeof(one), hipMemcpyHostToDevice, s));
+  launch_nrm2sq<double>(b, n, C->partials, &S->nrm2, s);
+  const double bn2 = read_scalar(C, &S->nrm2.re);
+  const double bnorm = std::sqrt(bn2);
+  if (!(bnorm == bnorm) || std::isinf(bnorm)) return fail(C, ECS_EBREAKDOWN, "right-hand side contains NaN/Inf");
+  if (bnorm == 0) {
+    launch_zero<double>(x, n, s);
+    st->rel_residual = 0;
+    return ECS_OK;
+  }
+  HIP_OK(hipMemcpyAsync(&S->bnorm, &bnorm, sizeof(double), hipMemcpyHostToDevice, s));
+  if (!d->x_is_guess) launch_zero<double>(x, n, s);
+  int it = 0;
+  ecs_status status = ECS_NOT_CONVERGED;
+  for (;;) {
+    {
+      TimedScope ts(C, 2);
+      launch_residual<double>(grid_A(C), b, x, K.V, s);
+    }
+    launch_nrm2sq<double>(K.V, n, C->partials, &S->nrm2, s);
+    launch_gmres_start(S, m, s);
+    launch_scale_dev(K.V, n, &S->inv, s);
+    double rt = read_scalar(C, &S->resid_true);
+    st->rel_residual = rt;
+    if (!(rt == rt) || std::isinf(rt)) { status = ECS_EBREAKDOWN; break; }
+    if (rt <= d->rtol) { status = ECS_OK; break; }
+    if (it >= d->maxit) { status = ECS_NOT_CONVERGED; break; }
+    int k = 0;
+    bool bad = false;
+    for (int j = 0; j < m && it < d->maxit; j++) {
+      cplx<double> *vj = K.V + (int64_t)j * ld;
+      cplx<double> *w = K.V + (int64_t)(j + 1) * ld;
+      cplx<RZ> *zj = flexible ? Z + (int64_t)j * ld : tz;
+      if (d->inner > 0) inner_bicgstab(C, K, vj, reinterpret_cast<cplx<float> *>(zj), d->inner);
+      else precond<RZ>(C, vj, zj);
+      st->vcycles += d->inner > 0 ? 2 * d->inner : 1;
+      st->inner_iterations += d->inner;
+      {
+        TimedScope ts(C, 2);
+        launch_apply<double, RZ, double>(grid_A(C), zj, w, s);
+      }
+      {
+        TimedScope ts(C, 1);
+        launch_mdot<double, double>(K.V, ld, j + 1, w, n, C->partials, S->H + (int64_t)j * (m + 1), s);
+        launch_mupdate(K.V, ld, j + 1, S->H + (int64_t)j * (m + 1), w, n, C->partials, &S->nrm2, s);
+      }
+      launch_gmres_givens(S, j, m, s);
+      launch_scale_dev(w, n, &S->inv, s);
+      it++;
+      k = j + 1;
+      // est, resid_true, bad, happy are contiguous: one readback per iteration
+      if (!read_bytes(C, &S->est, 2 * sizeof(double) + 2 * sizeof(int))) { bad = true; break; }
+      double est;
+      int happy;
+      std::memcpy(&est, C->pinned, sizeof(double));
+      std::memcpy(&happy, reinterpret_cast<char *>(C->pinned) + 2 * sizeof(double) + sizeof(int), sizeof(int));
+      if (d->history && it - 1 < d->history_len) d->history[it - 1] = est;
+      if (!(est == est) || std::isinf(est)) { bad = true; break; }
+      if (est <= d->rtol || happy) break;
+    }
+    if (bad) { status = ECS_EBREAKDOWN; break; }
+    launch_gmres_backsolve(S, k, m, s);
+    if (flexible) {
+      launch_lincomb<RZ>(Z, ld, k, S->y, x, n, s);
+    } else {
+      launch_zero<double>(K.t, n, s);
+      launch_lincomb<double>(K.V, ld, k, S->y, K.t, n, s);
+      precond<RZ>(C, K.t, tz);
+      st->vcycles++;
+      launch_lincomb<RZ>(tz, ld, 1, &S->one, x, n, s);
+    }
+    st->restarts++;
+  }
+  st->iterations = it;
+  HIP_OK(hipGetLastError());
+  return status;
+}
+
+template <typename RZ>
+ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const cplx<double> *b, cplx<double> *x,
+                    ecs_stats *st) {
+  const int64_t n = nn_of(C);
+  hipStream_t s = C->stream;
+  BicgScalars *S = C->bs;
+  cplx<RZ> *ph = reinterpret_cast<cplx<RZ> *>(K.ph);
+  cplx<RZ> *sh = reinterpret_cast<cplx<RZ> *>(K.sh);
+  launch_nrm2sq<double>(b, n, C->partials, &C->gs->nrm2, s);
+  const double bnorm = std::sqrt(read_scalar(C, &C->gs->nrm2.re));
+  if (!(bnorm == bnorm) || std::isinf(bnorm)) return fail(C, ECS_EBREAKDOWN, "right-hand side contains NaN/Inf");
+  if (bnorm == 0) {
+    launch_zero<double>(x, n, s);
+    st->rel_residual = 0;
+    return ECS_OK;
+  }
+  HIP_OK(hipMemcpyAsync(&S->bnorm, &bnorm, sizeof(double), hipMemcpyHostToDevice, s));
+  if (!d->x_is_guess) launch_zero<double>(x, n, s);
+  int it = 0, stalls = 0;
+  double last_restart = INFINITY;
+  ecs_status status = ECS_NOT_CONVERGED;
+  for (;;) {
+    {
+      TimedScope ts(C, 2);
+      launch_residual<double>(grid_A(C), b, x, K.r, s);
+    }
+    launch_pairdot<double>(K.r, K.r, nullptr, nullptr, 1, n, C->partials, S, kBicgInit, s);
+    double rt = read_scalar(C, &S->est);
+    st->rel_residual = rt;
+    if (!(rt == rt) || std::isinf(rt)) { status = ECS_EBREAKDOWN; break; }
+    if (rt <= d->rtol) { status = ECS_OK; break; }
+    if (it >= d->maxit) { status = ECS_NOT_CONVERGED; break; }
+    if (rt >= last_restart) {
+      if (++stalls >= 3) { status = ECS_EBREAKDOWN; break; }
+    }
+    last_restart = rt;
+    (void)hipMemcpyAsync(K.rh, K.r, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, s);
+    launch_zero<double>(K.p, n, s);
+    launch_zero<double>(K.v, n, s);
+    while (it < d->maxit) {
+      launch_pairdot<double>(K.rh, K.r, nullptr, nullptr, 1, n, C->partials, S, kBicgRho, s);
+      launch_bicg_p<double>(K.p, K.r, K.v, n, S, s);
+      precond<RZ>(C, K.p, ph);
+      {
+        TimedScope ts(C, 2);
+        launch_apply<double, RZ, double>(grid_A(C), ph, K.v, s);
+      }
+      launch_pairdot<double>(K.rh, K.v, nullptr, nullptr, 1, n, C->partials, S, kBicgAlpha, s);
+      launch_bicg_s<double>(K.s, K.r, K.v, n, S, s);
+      precond<RZ>(C, K.s, sh);
+      {
+        TimedScope ts(C, 2);
+        launch_apply<double, RZ, double>(grid_A(C), sh, K.tt, s);
+      }
+      launch_pairdot<double>(K.tt, K.s, K.tt, K.tt, 2, n, C->partials, S, kBicgOmega, s);
+      launch_bicg_xr<double, RZ>(x, ph, sh, K.r, K.s, K.tt, n, C->partials, S, s);
+      st->vcycles += 2;
+      it++;
+      // est and bad are contiguous: one readback per iteration
+      if (!read_bytes(C, &S->est, sizeof(double) + sizeof(int))) break;
+      double est;
+      int bad;
+      std::memcpy(&est, C->pinned, sizeof(double));
+      std::memcpy(&bad, reinterpret_cast<char *>(C->pinned) + sizeof(double), sizeof(int));
+      if (d->history && it - 1 < d->history_len) d->history[it - 1] = est;
+      if (bad) break;  // restart from the current iterate
+      if (est <= d->rtol) break;
+    }
+    st->restarts++;
+  }
+  st->iterations = it;
+  HIP_OK(hipGetLastError());
+  return status;
+}
+
+ecs_status check_ready(ecs_ctx *C) {
+  if (!C) return ECS_EINVAL;
+  if (!C->ready) return fail(C, ECS_ESTATE, "call ecs_set_workspace after ecs_set_k2 and ecs_set_precond");
+  return ECS_OK;
+}
+
+ecs_status solve_impl(ecs_ctx *C, const ecs_solve_desc *d, const cplx<double> *b, cplx<double> *x, ecs_stats *st) {
+  if (d->restart < 1 || d->restart > kMaxRestart) return fail(C, ECS_EINVAL, "restart must be in [1, 64]");
+  if (!(d->rtol > 0) || d->maxit < 0) return fail(C, ECS_EINVAL, "rtol must be > 0 and maxit >= 0");
+  if (d->krylov < 0 || d->krylov > 2) return fail(C, ECS_EINVAL, "unknown Krylov method");
+  if (d->inner > 0 && (d->krylov != ECS_KRYLOV_FGMRES || C->prec.vcycle_dtype != ECS_F32))
+    return fail(C, ECS_EINVAL, "inner iterations need FGMRES and an FP32 cycle");
+  if (d->inner > 0 && C->prec.kind == ECS_PREC_NONE) return fail(C, ECS_EINVAL, "inner iterations need a cycle");
+  if (C->prec.kind == ECS_PREC_NONE && C->prec.vcycle_dtype == ECS_F32)
+    return fail(C, ECS_EINVAL, "no preconditioner: use vcycle_dtype F64");
+  KrylovBufs K;
+  size_t need = C->hier_bytes + plan_krylov(C, d, nullptr, &K);
+  if (need > C->ws_bytes) return fail(C, ECS_ENOMEM, "workspace too small for this solve");
+  plan_krylov(C, d, C->ws + C->hier_bytes, &K);
+  const bool f32 = C->prec.vcycle_dtype == ECS_F32;
+  // boundary entries of b are ignored and those of a guess x are reset
+  const HostLevel &F = C->hl[0];
+  launch_mask_boundary(F.n[0], F.n[1], F.n[2], b, K.bz, C->stream);
+  if (d->x_is_guess) launch_mask_boundary(F.n[0], F.n[1], F.n[2], x, x, C->stream);
+  b = K.bz;
+  if (d->krylov == ECS_KRYLOV_BICGSTAB)
+    return f32 ? bicgstab<float>(C, d, K, b, x, st) : bicgstab<double>(C, d, K, b, x, st);
+  return f32 ? gmres<float>(C, d, K, b, x, st) : gmres<double>(C, d, K, b, x, st);
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+ecs_status ecs_create(ecs_ctx **out, int dim, const int64_t *nodes, const double *lo, const double *hi,
+                      void *stream) {
+  if (!out || !nodes || !lo || !hi || (dim != 2 && dim != 3)) return ECS_EINVAL;
+  *out = nullptr;
+  for (int a = 0; a < dim; a++) {
+    if (nodes[a] < 3 || nodes[a] > (1 << 20) || !(hi[a] > lo[a])) return ECS_EINVAL;
+  }
+  int64_t total = 1;
+  for (int a = 0; a < dim; a++) total *= nodes[a];
+  if (total > (int64_t)1 << 31) return ECS_EINVAL;
+  ecs_ctx *C = new ecs_ctx();
+  C->dim = dim;
+  for (int a = 0; a < dim; a++) {
+    C->n[a] = (int)nodes[a];
+    C->lo[a] = lo[a];
+    C->hi[a] = hi[a];
+  }
+  C->stream = reinterpret_cast<hipStream_t>(stream);
+  if (hipGetDevice(&C->device) != hipSuccess ||
+      hipHostMalloc((void **)&C->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+    delete C;
+    return ECS_EDEVICE;
+  }
+  *out = C;
+  return ECS_OK;
+}
+
+ecs_status ecs_set_ecs(ecs_ctx *C, int axis, int side, int kind, double start, double theta) {
+  if (!C) return ECS_EINVAL;
+  if (axis < 0 || axis >= C->dim || side < 0 || side > 1) return fail(C, ECS_EINVAL, "bad axis or side");
+  if (kind == ECS_BC_ECS) {
+    if (!(theta > 0 && theta < M_PI / 2)) return fail(C, ECS_EINVAL, "theta must lie in (0, pi/2)");
+    if (!(start > C->lo[axis] && start < C->hi[axis])) return fail(C, ECS_EINVAL, "layer start outside the box");
+  } else if (kind != ECS_BC_DIRICHLET) {
+    return fail(C, ECS_EINVAL, "bad boundary kind");
+  }
+  C->side[axis][side].kind = kind;
+  C->side[axis][side].start = start;
+  C->side[axis][side].theta = theta;
+  C->ready = false;
+  return ECS_OK;
+}
+
+ecs_status ecs_set_k2(ecs_ctx *C, const double *k2_dev) {
+  if (!C) return ECS_EINVAL;
+  if (!k2_dev) return fail(C, ECS_EINVAL, "k2 is null");
+  C->k2 = k2_dev;
+  C->ready = false;
+  return ECS_OK;
+}
+
+ecs_status ecs_set_precond(ecs_ctx *C, const ecs_prec_desc *d) {
+  if (!C || !d) return ECS_EINVAL;
+  if (d->kind < ECS_PREC_NONE || d->kind > ECS_PREC_QD) return fail(C, ECS_EINVAL, "unknown preconditioner kind");
+  if (d->smoother != ECS_SMOOTH_JACOBI && d->smoother != ECS_SMOOTH_RBGS) return fail(C, ECS_EINVAL, "bad smoother");
+  if (!(d->omega > 0 && d->omega < 2)) return fail(C, ECS_EINVAL, "omega must lie in (0, 2)");
+  if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 + d->nu2 < 1 || d->nu1 > 8 || d->nu2 > 8)
+    return fail(C, ECS_EINVAL, "bad sweep counts");
+  if (d->gamma_f < 1 || d->gamma_c < 1 || d->gamma_f > 4 || d->gamma_c > 8)
+    return fail(C, ECS_EINVAL, "bad cycle indices");
+  if (d->vcycle_dtype != ECS_F64 && d->vcycle_dtype != ECS_F32) return fail(C, ECS_EINVAL, "bad cycle dtype");
+  if (d->coarsest_nodes < 3) return fail(C, ECS_EINVAL, "coarsest grid needs >= 3 nodes per axis");
+  // levels: every axis must reach coarsest_nodes by exact halving
+  int nlev = -1;
+  for (int a = 0; a < C->dim; a++) {
+    int n = C->n[a], lev = 1;
+    while (n > d->coarsest_nodes && (n - 1) % 2 == 0) {
+      n = (n - 1) / 2 + 1;
+      lev++;
+    }
+    if (n != d->coarsest_nodes) return fail(C, ECS_EINVAL, "nodes-1 must be (coarsest_nodes-1) * 2^k on every axis");
+    if (nlev >= 0 && lev != nlev) return fail(C, ECS_EINVAL, "all axes must have the same number of levels");
+    nlev = lev;
+  }
+  if (nlev > kMaxLev) return fail(C, ECS_EINVAL, "too many levels");
+  int nunk = 1;
+  for (int a = 0; a < C->dim; a++) nunk *= d->coarsest_nodes - 2;
+  if (nunk > 4096) return fail(C, ECS_EINVAL, "coarsest grid too large for the dense solve (> 4096 unknowns)");
+  C->prec = *d;
+  C->nlev = nlev;
+  C->have_prec = true;
+  C->ready = false;
+  return ECS_OK;
+}
+
+ecs_status ecs_workspace_size(ecs_ctx *C, const ecs_solve_desc *d, size_t *bytes) {
+  if (!C || !bytes) return ECS_EINVAL;
+  if (!C->have_prec) return fail(C, ECS_ESTATE, "set the preconditioner first");
+  if (d && (d->restart < 1 || d->restart > kMaxRestart)) return fail(C, ECS_EINVAL, "restart must be in [1, 64]");
+  build_host_levels(C);
+  KrylovBufs K;
+  *bytes = plan_hierarchy(C, nullptr) + 256 + plan_krylov(C, d, nullptr, &K) + 256;
+  return ECS_OK;
+}
+
+ecs_status ecs_set_workspace(ecs_ctx *C, void *dev, size_t bytes) {
+  if (!C) return ECS_EINVAL;
+  if (!C->have_prec || !C->k2) return fail(C, ECS_ESTATE, "set k2 and the preconditioner first");
+  if (!dev || ((uintptr_t)dev % 256) != 0) return fail(C, ECS_EINVAL, "workspace must be 256-byte aligned");
+  build_host_levels(C);
+  size_t hb = plan_hierarchy(C, nullptr);
+  hb = (hb + 255) & ~size_t(255);
+  KrylovBufs K;
+  if (hb + plan_krylov(C, nullptr, nullptr, &K) > bytes) return fail(C, ECS_ENOMEM, "workspace too small");
+  C->ws = reinterpret_cast<char *>(dev);
+  C->ws_bytes = bytes;
+  C->hier_bytes = hb;
+  plan_hierarchy(C, C->ws);
+  C->ready = false;
+  ecs_status st = setup(C);
+  if (st != ECS_OK) return st;
+  C->ready = true;
+  return ECS_OK;
+}
+
+ecs_status ecs_solve(ecs_ctx *C, const ecs_solve_desc *d, const void *b, void *x, ecs_stats *stats) {
+  ecs_status st = check_ready(C);
+  if (st != ECS_OK) return st;
+  if (!d || !b || !x) return fail(C, ECS_EINVAL, "null argument");
+  ecs_stats local{};
+  auto t0 = std::chrono::steady_clock::now();
+  st = solve_impl(C, d, reinterpret_cast<const cplx<double> *>(b), reinterpret_cast<cplx<double> *>(x), &local);
+  local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  local.status = st;
+  if (stats) *stats = local;
+  return st;
+}
+
+ecs_status ecs_solve_adjoint(ecs_ctx *C, const ecs_solve_desc *d, const void *g, void *lam, ecs_stats *stats) {
+  ecs_status st = check_ready(C);
+  if (st != ECS_OK) return st;
+  if (!d || !g || !lam) return fail(C, ECS_EINVAL, "null argument");
+  KrylovBufs K;
+  size_t need = C->hier_bytes + plan_krylov(C, d, nullptr, &K);
+  if (need > C->ws_bytes) return fail(C, ECS_ENOMEM, "workspace too small for this solve");
+  plan_krylov(C, d, C->ws + C->hier_bytes, &K);
+  const HostLevel &F = C->hl[0];
+  const int64_t n = nn_of(C);
+  auto t0 = std::chrono::steady_clock::now();
+  // A^T = W A W^{-1}:  A^T lam = g  <=>  A (W^{-1} lam) = W^{-1} g
+  launch_scale_w(F.n[0], F.n[1], F.n[2], C->Wd[0], C->Wd[1], C->Wd[2], reinterpret_cast<const cplx<double> *>(g),
+                 K.a1, true, C->stream);
+  ecs_solve_desc d2 = *d;
+  cplx<double> *y = K.a2;
+  if (d->x_is_guess)
+    launch_scale_w(F.n[0], F.n[1], F.n[2], C->Wd[0], C->Wd[1], C->Wd[2], reinterpret_cast<cplx<double> *>(lam), y,
+                   true, C->stream);
+  ecs_stats local{};
+  st = solve_impl(C, &d2, K.a1, y, &local);
+  launch_scale_w(F.n[0], F.n[1], F.n[2], C->Wd[0], C->Wd[1], C->Wd[2], y, reinterpret_cast<cplx<double> *>(lam), false,
+                 C->stream);
+  (void)n;
+  local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  local.status = st;
+  if (stats) *stats = local;
+  return st;
+}
+
+ecs_status ecs_grad_k2(ecs_ctx *C, const void *lam, const void *u, double *grad) {
+  if (!C) return ECS_EINVAL;
+  if (!lam || !u || !grad) return fail(C, ECS_EINVAL, "null argument");
+  launch_grad_k2(reinterpret_cast<const cplx<double> *>(lam), reinterpret_cast<const cplx<double> *>(u), grad,
+                 nn_of(C), C->stream);
+  HIP_OK(hipGetLastError());
+  return ECS_OK;
+}
+
+ecs_status ecs_apply(ecs_ctx *C, int op, const void *x, void *y) {
+  ecs_status st = check_ready(C);
+  if (st != ECS_OK) return st;
+  if (!x || !y) return fail(C, ECS_EINVAL, "null argument");
+  const cplx<double> *xi = reinterpret_cast<const cplx<double> *>(x);
+  cplx<double> *yo = reinterpret_cast<cplx<double> *>(y);
+  const HostLevel &F = C->hl[0];
+  if (op == ECS_OP_A) {
+    launch_apply<double, double, double>(grid_A(C), xi, yo, C->stream);
+  } else if (op == ECS_OP_M) {
+    launch_apply<double, double, double>(grid_M<double>(C, 0), xi, yo, C->stream);
+  } else if (op == ECS_OP_AT) {
+    KrylovBufs K;
+    plan_krylov(C, nullptr, C->ws + C->hier_bytes, &K);
+    launch_scale_w(F.n[0], F.n[1], F.n[2], C->Wd[0], C->Wd[1], C->Wd[2], xi, K.a1, true, C->stream);
+    launch_apply<double, double, double>(grid_A(C), K.a1, K.a2, C->stream);
+    launch_scale_w(F.n[0], F.n[1], F.n[2], C->Wd[0], C->Wd[1], C->Wd[2], K.a2, yo, false, C->stream);
+  } else {
+    return fail(C, ECS_EINVAL, "unknown operator");
+  }
+  HIP_OK(hipGetLastError());
+  return ECS_OK;
+}
+
+ecs_status ecs_vcycle(ecs_ctx *C, const void *v, void *z) {
+  ecs_status st = check_ready(C);
+  if (st != ECS_OK) return st;
+  if (!v || !z) return fail(C, ECS_EINVAL, "null argument");
+  if (C->prec.kind == ECS_PREC_NONE) return fail(C, ECS_EINVAL, "no preconditioner configured");
+  const cplx<double> *vi = reinterpret_cast<const cplx<double> *>(v);
+  cplx<double> *zo = reinterpret_cast<cplx<double> *>(z);
+  if (C->prec.vcycle_dtype == ECS_F64) {
+    vcycle<double>(C, vi, zo);
+  } else {
+    KrylovBufs K;
+    plan_krylov(C, nullptr, C->ws + C->hier_bytes, &K);
+    cplx<float> *zf = reinterpret_cast<cplx<float> *>(K.tz);
+    precond<float>(C, vi, zf);
+    launch_cast<float, double>(zf, zo, nn_of(C), C->stream);
+  }
+  HIP_OK(hipGetLastError());
+  return ECS_OK;
+}
+
+#define LEVEL_CHECK(l)                                                                                    \
+  do {                                                                                                    \
+    ecs_status st_ = check_ready(C);                                                                      \
+    if (st_ != ECS_OK) return st_;                                                                        \
+    if ((l) < 0 || (l) >= C->nlev) return fail(C, ECS_EINVAL, "level out of range");                    \
+  } while (0)
+
+ecs_status ecs_smooth(ecs_ctx *C, int level, const void *b, void *u, int nsweeps) {
+  LEVEL_CHECK(level);
+  if (!b || !u || nsweeps < 0) return fail(C, ECS_EINVAL, "bad argument");
+  if (C->prec.vcycle_dtype == ECS_F64)
+    smooth<double>(C, level, reinterpret_cast<const cplx<double> *>(b), reinterpret_cast<cplx<double> *>(u),
+                   C->L64[level].t, nsweeps, false);
+  else
+    smooth<float>(C, level, reinterpret_cast<const cplx<float> *>(b), reinterpret_cast<cplx<float> *>(u),
+                  C->L32[level].t, nsweeps, false);
+  HIP_OK(hipGetLastError());
+  return ECS_OK;
+}
+
+ecs_status ecs_residual_restrict(ecs_ctx *C, int level, const void *b, const void *u, void *rc) {
+  LEVEL_CHECK(level);
+  if (level + 1 >= C->nlev) return fail(C, ECS_EINVAL, "no coarser level");
+  if (!b || !u || !rc) return fail(C, ECS_EINVAL, "null argument");
+  if (C->prec.vcycle_dtype == ECS_F64)
+    launch_residual_restrict<double>(grid_M<double>(C, level), grid_M<double>(C, level + 1),
+                                     reinterpret_cast<const cplx<double> *>(b),
+                                     reinterpret_cast<const cplx<double> *>(u), reinterpret_cast<cplx<double> *>(rc),
+                                     C->stream);
+  else
+    launch_residual_restrict<float>(grid_M<float>(C, level), grid_M<float>(C, level + 1),
+                                    reinterpret_cast<const cplx<float> *>(b), reinterpret_cast<const cplx<float> *>(u),
+                                    reinterpret_cast<cplx<float> *>(rc), C->stream);
+  HIP_OK(hipGetLastError());
+  return ECS_OK;
+}
+
+ecs_status ecs_prolong_correct(ecs_ctx *C, int level, const void *ec, void *u) {
+  LEVEL_CHECK(level);
+  if (level + 1 >= C->nlev) return fail(C, ECS_EINVAL, "no coarser level");
+  if (!ec || !u) return fail(C, ECS_EINVAL, "null argument");
+  if (C->prec.vcycle_dtype == ECS_F64)
+    launch_prolong_add<double>(grid_M<double>(C, level), grid_M<double>(C, level + 1),
+                               reinterpret_cast<const cplx<double> *>(ec), reinterpret_cast<cplx<double> *>(u),
+                               C->stream);
+  else
+    launch_prolong_add<float>(grid_M<float>(C, level), grid_M<float>(C, level + 1),
+                              reinterpret_cast<const cplx<float> *>(ec), reinterpret_cast<cplx<float> *>(u), C->stream);
+  HIP_OK(hipGetLastError());
+  return ECS_OK;
+}
+
+ecs_status ecs_coarse_solve(ecs_ctx *C, const void *b, void *x) {
+  ecs_status st = check_ready(C);
+  if (st != ECS_OK) return st;
+  if (!b || !x) return fail(C, ECS_EINVAL, "null argument");
+  if (C->prec.vcycle_dtype == ECS_F64)
+    coarse_solve<double>(C, reinterpret_cast<const cplx<double> *>(b), reinterpret_cast<cplx<double> *>(x));
+  else
+    coarse_solve<float>(C, reinterpret_cast<const cplx<float> *>(b), reinterpret_cast<cplx<float> *>(x));
+  HIP_OK(hipGetLastError());
+  return ECS_OK;
+}
+
+ecs_status ecs_level_info(ecs_ctx *C, int level, int *nlevels, int64_t *nodes) {
+  if (!C) return ECS_EINVAL;
+  if (!C->have_prec) return fail(C, ECS_ESTATE, "set the preconditioner first");
+  if (nlevels) *nlevels = C->nlev;
+  if (nodes) {
+    if (level < 0 || level >= C->nlev) return fail(C, ECS_EINVAL, "level out of range");
+    int n[3] = {C->n[0], C->n[1], C->n[2]};
+    for (int l = 0; l < level; l++)
+      for (int a = 0; a < C->dim; a++) n[a] = (n[a] - 1) / 2 + 1;
+    for (int a = 0; a < 3; a++) nodes[a] = a < C->dim ? n[a] : 1;
+  }
+  return ECS_OK;
+}
+
+ecs_status ecs_timing_enable(ecs_ctx *C, int kclass, int enable) {
+  if (!C || kclass < 0 || kclass > 3) return ECS_EINVAL;
+  C->timers[kclass].on = enable != 0;
+  return ECS_OK;
+}
+
+ecs_status ecs_timing_read(ecs_ctx *C, int kclass, int64_t *launches, double *total_ms) {
+  if (!C || kclass < 0 || kclass > 3) return ECS_EINVAL;
+  Timer &T = C->timers[kclass];
+  HIP_OK(hipStreamSynchronize(C->stream));
+  double tot = 0;
+  for (size_t q = 0; q + 1 < T.used; q += 2) {
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, T.ev[q], T.ev[q + 1]));
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)(T.used / 2);
+  if (total_ms) *total_ms = tot;
+  T.used = 0;
+  T.launches = 0;
+  return ECS_OK;
+}
+
+ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *desc, const void *const *b,
+                           void *const *x, const int *nrhs, ecs_stats *stats) {
+  if (n < 0 || (n > 0 && (!ctxs || !desc || !b || !x || !nrhs))) return ECS_EINVAL;
+  ecs_status worst = ECS_OK;
+  for (int q = 0; q < n; q++) {
+    ecs_ctx *C = ctxs[q];
+    ecs_stats agg{};
+    for (int r = 0; r < nrhs[q]; r++) {
+      const int64_t off = (int64_t)r * nn_of(C);
+      ecs_stats st{};
+      ecs_status rc = ecs_solve(C, desc, reinterpret_cast<const cplx<double> *>(b[q]) + off,
+                                reinterpret_cast<cplx<double> *>(x[q]) + off, &st);
+      agg.iterations += st.iterations;
+      agg.restarts += st.restarts;
+      agg.vcycles += st.vcycles;
+      agg.seconds += st.seconds;
+      agg.rel_residual = std::max(agg.rel_residual, st.rel_residual);
+      if (rc != ECS_OK && (worst == ECS_OK || rc < 0)) worst = rc;
+      agg.status = agg.status == ECS_OK ? rc : agg.status;
+    }
+    if (stats) stats[q] = agg;
+  }
+  return worst;
+}
+
+ecs_status ecs_copy_probe(const void *src, void *dst, size_t bytes, void *stream) {
+  if (!src || !dst) return ECS_EINVAL;
+  launch_copy_bytes(src, dst, bytes, reinterpret_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? ECS_OK : ECS_EDEVICE;
+}
+
+const char *ecs_last_error(const ecs_ctx *C) { return C ? C->err.c_str() : "null context"; }
+
+void ecs_destroy(ecs_ctx *C) {
+  if (!C) return;
+  for (auto &T : C->timers)
+    for (auto &e : T.ev) (void)hipEventDestroy(e);
+  if (C->pinned) (void)hipHostFree(C->pinned);
+  delete C;
+}
+
+}  // extern "C"

@@ -1,0 +1,559 @@
+// kernels_blas.hip -- Krylov building blocks of the outer solve (Sec. 5 of
+// bin Zubair, Reps, Vanroose: right-preconditioned Bi-CGSTAB; GMRES and
+// restarted / flexible GMRES).  All Krylov scalars stay in device memory: dot
+// products reduce in two fixed-order stages (per-block partials, then one
+// block per column), so results are bitwise reproducible run to run, and the
+// Givens least-squares update and the Bi-CGSTAB scalar recurrences run in
+// single-thread kernels right behind their reductions.  The host only reads a
+// residual estimate per iteration.
+#include "ecs_krylov.h"
+
+namespace ecs {
+
+namespace {
+
+constexpr int BS = 256;  // 4 waves of 64
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sum of a complex value; result valid in thread 0
+__device__ __forceinline__ cplx<double> block_sum(cplx<double> v, cplx<double> *lds /* >= 4 */) {
+  v.re = wave_sum(v.re);
+  v.im = wave_sum(v.im);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  cplx<double> s = mk<double>(0, 0);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < BS / 64; q++) s = s + lds[q];
+  return s;
+}
+
+inline int red_blocks(int64_t n) {
+  int64_t b = (n + BS * 4 - 1) / (BS * 4);
+  if (b > kRedBlocks) b = kRedBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// ----------------------------------------------------------- multi-dot
+// out[c] = sum_p conj(V_c[p]) w[p], c < ncols; columns in chunks of CB per
+// pass, so w is re-read once per chunk.
+constexpr int CB = 8;
+
+template <typename RA, typename RB>
+__global__ __launch_bounds__(BS) void k_mdot(const cplx<RA> *__restrict__ V, int64_t ldv, int ncols,
+                                             const cplx<RB> *__restrict__ w, int64_t n, cplx<double> *partials) {
+  __shared__ cplx<double> lds[CB][BS / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < ncols; c0 += CB) {
+    cplx<double> acc[CB];
+#pragma unroll
+    for (int q = 0; q < CB; q++) acc[q] = mk<double>(0, 0);
+    const int nc = min(CB, ncols - c0);
+    for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) {
+      cplx<double> wp = cvt<double>(w[p]);
+#pragma unroll
+      for (int q = 0; q < CB; q++)
+        if (q < nc) acc[q] = acc[q] + conjg(cvt<double>(V[(int64_t)(c0 + q) * ldv + p])) * wp;
+    }
+#pragma unroll
+    for (int q = 0; q < CB; q++) {
+      double re = wave_sum(acc[q].re), im = wave_sum(acc[q].im);
+      if (lane == 0) lds[q][wid] = mk<double>(re, im);
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+      cplx<double> s = mk<double>(0, 0);
+      for (int v = 0; v < BS / 64; v++) s = s + lds[threadIdx.x][v];
+      partials[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// out[c] = sum over blocks of partials[c][block] (fixed order); one block per
+// column.
+__global__ __launch_bounds__(BS) void k_reduce_cols(const cplx<double> *__restrict__ partials, int nblocks,
+                                                    cplx<double> *__restrict__ out) {
+  __shared__ cplx<double> lds[BS / 64];
+  const int c = blockIdx.x;
+  cplx<double> s = mk<double>(0, 0);
+  for (int b = threadIdx.x; b < nblocks; b += BS) s = s + partials[(int64_t)c * nblocks + b];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) out[c] = s;
+}
+
+// w <- w - sum_c V_c h_c, and per-block partials of ||w||^2 (in .re)
+__global__ __launch_bounds__(BS) void k_mupdate(const cplx<double> *__restrict__ V, int64_t ldv, int ncols,
+                                                const cplx<double> *__restrict__ h, cplx<double> *__restrict__ w,
+                                                int64_t n, cplx<double> *partials) {
+  __shared__ cplx<double> hs[kMaxRestart + 2];
+  __shared__ cplx<double> lds[BS / 64];
+  for (int c = threadIdx.x; c < ncols; c += BS) hs[c] = h[c];
+  __syncthreads();
+  double nrm = 0;
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) {
+    cplx<double> acc = w[p];
+    for (int c = 0; c < ncols; c++) acc = acc - V[(int64_t)c * ldv + p] * hs[c];
+    w[p] = acc;
+    nrm += abs2(acc);
+  }
+  cplx<double> s = block_sum(mk<double>(nrm, 0), lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+template <typename R>
+__global__ __launch_bounds__(BS) void k_nrm2sq(const cplx<R> *__restrict__ x, int64_t n, cplx<double> *partials) {
+  __shared__ cplx<double> lds[BS / 64];
+  double nrm = 0;
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS)
+    nrm += abs2(cvt<double>(x[p]));
+  cplx<double> s = block_sum(mk<double>(nrm, 0), lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// x[p] += sum_c Z_c[p] y_c  (Z in the preconditioner's precision)
+template <typename RZ>
+__global__ __launch_bounds__(BS) void k_lincomb(const cplx<RZ> *__restrict__ Z, int64_t ldz, int ncols,
+                                                const cplx<double> *__restrict__ y, cplx<double> *__restrict__ x,
+                                                int64_t n) {
+  __shared__ cplx<double> ys[kMaxRestart + 2];
+  for (int c = threadIdx.x; c < ncols; c += BS) ys[c] = y[c];
+  __syncthreads();
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) {
+    cplx<double> acc = x[p];
+    for (int c = 0; c < ncols; c++) acc = acc + cvt<double>(Z[(int64_t)c * ldz + p]) * ys[c];
+    x[p] = acc;
+  }
+}
+
+// x *= *s  (s real, in device memory)
+__global__ __launch_bounds__(BS) void k_scale_dev(cplx<double> *__restrict__ x, int64_t n,
+                                                  const double *__restrict__ s) {
+  const double f = *s;
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) x[p] = f * x[p];
+}
+
+// ------------------------------------------------------ GMRES scalars
+// Start of a restart cycle: beta = sqrt(norm2) of the residual; g = beta e1;
+// inv = 1/beta (the residual is scaled into v_0); est = beta / ||b||.
+__global__ void k_gmres_start(GmresScalars *S, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double beta = sqrt(S->nrm2.re);
+  for (int q = 0; q <= m; q++) S->g[q] = mk<double>(0, 0);
+  S->g[0] = mk<double>(beta, 0);
+  S->inv = beta > 0 ? 1.0 / beta : 0.0;
+  S->est = beta / S->bnorm;
+  S->resid_true = beta / S->bnorm;
+  S->bad = !(beta == beta) || isinf(beta);
+}
+
+// Arnoldi step j: column j of the Hessenberg matrix holds h_{0..j,j} from the
+// orthogonalisation; h_{j+1,j} = sqrt(norm2).  Apply the stored Givens
+// rotations, form the new one, update g and the residual estimate |g_{j+1}|.
+__global__ void k_gmres_givens(GmresScalars *S, int j, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  cplx<double> *h = S->H + (int64_t)j * (m + 1);
+  double hn = sqrt(S->nrm2.re);
+  h[j + 1] = mk<double>(hn, 0);
+  S->inv = hn > 0 ? 1.0 / hn : 0.0;
+  for (int i = 0; i < j; i++) {
+    cplx<double> c = S->cs[i], s = S->sn[i];
+    cplx<double> t = conjg(c) * h[i] + s * h[i + 1];
+    h[i + 1] = (c * h[i + 1]) - (conjg(s) * h[i]);
+    h[i] = t;
+  }
+  // new rotation zeroing h[j+1]: c = |a|/r (real), s = (a/|a|) conj(b) / r
+  cplx<double> a = h[j], b = h[j + 1];
+  double na = sqrt(abs2(a)), nb = sqrt(abs2(b));
+  cplx<double> c, s;
+  if (nb == 0) {
+    c = mk<double>(1, 0); s = mk<double>(0, 0);
+  } else if (na == 0) {
+    c = mk<double>(0, 0); s = mk<double>(1, 0);
+  } else {
+    double r = sqrt(na * na + nb * nb);
+    c = mk<double>(na / r, 0);
+    s = (1.0 / (na * r)) * (a * conjg(b));
+  }
+  S->cs[j] = c;
+  S->sn[j] = s;
+  h[j] = conjg(c) * a + s * b;
+  h[j + 1] = mk<double>(0, 0);
+  cplx<double> gj = S->g[j];
+  S->g[j] = conjg(c) * gj;
+  S->g[j + 1] = mk<double>(0, 0) - conjg(s) * gj;
+  S->est = sqrt(abs2(S->g[j + 1])) / S->bnorm;
+  S->bad = !(S->est == S->est) || isinf(S->est);
+  S->happy = hn == 0;
+}
+
+// y = R^{-1} g for the first k columns (upper triangular from the rotated H)
+__global__ void k_gmres_backsolve(GmresScalars *S, int k, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int r = k - 1; r >= 0; r--) {
+    cplx<double> s = S->g[r];
+    for (int c = r + 1; c < k; c++) s = s - S->H[(int64_t)c * (m + 1) + r] * S->y[c];
+    S->y[r] = cdiv(s, S->H[(int64_t)r * (m + 1) + r]);
+  }
+}
+
+// second Gram-Schmidt pass: H(:, j) += h2
+__global__ void k_add_h2(GmresScalars *S, int j, int m) {
+  int q = threadIdx.x;
+  if (q <= j) S->H[(int64_t)j * (m + 1) + q] = S->H[(int64_t)j * (m + 1) + q] + S->h2[q];
+}
+
+// ------------------------------------------------------ Bi-CGSTAB pieces
+// pair dots: d_q = sum conj(x_q) y_q for q < npairs (<= 2)
+template <typename R>
+__global__ __launch_bounds__(BS) void k_pairdot(const cplx<R> *__restrict__ x0, const cplx<R> *__restrict__ y0,
+                                                const cplx<R> *__restrict__ x1, const cplx<R> *__restrict__ y1,
+                                                int npairs, int64_t n, cplx<double> *partials) {
+  __shared__ cplx<double> lds[BS / 64];
+  cplx<double> a0 = mk<double>(0, 0), a1 = mk<double>(0, 0);
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) {
+    a0 = a0 + conjg(cvt<double>(x0[p])) * cvt<double>(y0[p]);
+    if (npairs > 1) a1 = a1 + conjg(cvt<double>(x1[p])) * cvt<double>(y1[p]);
+  }
+  cplx<double> s0 = block_sum(a0, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s0;
+  if (npairs > 1) {
+    __syncthreads();
+    cplx<double> s1 = block_sum(a1, lds);
+    if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = s1;
+  }
+}
+
+// final reduction of pair dots and the Bi-CGSTAB scalar recurrence
+__global__ __launch_bounds__(BS) void k_bicg_final(const cplx<double> *__restrict__ partials, int nblocks,
+                                                   int npairs, BicgScalars *S, int mode) {
+  __shared__ cplx<double> lds[BS / 64];
+  cplx<double> d[2];
+  for (int q = 0; q < npairs; q++) {
+    cplx<double> s = mk<double>(0, 0);
+    for (int b = threadIdx.x; b < nblocks; b += BS) s = s + partials[(int64_t)q * nblocks + b];
+    d[q] = block_sum(s, lds);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const cplx<double> zero = mk<double>(0, 0);
+  switch (mode) {
+    case kBicgRho: {  // rho1 = (r^, r); beta = (rho1/rho)(alpha/omega)
+      cplx<double> rho1 = d[0];
+      if (abs2(rho1) == 0 || abs2(S->rho) == 0 || abs2(S->omega) == 0 || S->bad) {
+        S->bad = 1; S->beta = zero; S->alpha = zero; S->omega = zero;
+        break;
+      }
+      S->beta = cdiv(rho1, S->rho) * cdiv(S->alpha, S->omega);
+      S->rho = rho1;
+      break;
+    }
+    case kBicgAlpha: {  // alpha = rho / (r^, v)
+      if (abs2(d[0]) == 0 || S->bad) { S->bad = 1; S->alpha = zero; break; }
+      S->alpha = cdiv(S->rho, d[0]);
+      break;
+    }
+    case kBicgOmega: {  // omega = (t, s) / (t, t)
+      if (d[1].re == 0 || S->bad) { S->bad = 1; S->omega = zero; break; }
+      S->omega = (1.0 / d[1].re) * d[0];
+      break;
+    }
+    case kBicgNorm: {  // ||r||^2
+      S->rnorm2 = d[0].re;
+      S->est = sqrt(d[0].re) / S->bnorm;
+      if (!(S->est == S->est) || isinf(S->est)) S->bad = 1;
+      break;
+    }
+    case kBicgInit: {  // restart: rho = alpha = omega = 1
+      S->rnorm2 = d[0].re;
+      S->est = sqrt(d[0].re) / S->bnorm;
+      S->rho = mk<double>(1, 0); S->alpha = mk<double>(1, 0); S->omega = mk<double>(1, 0);
+      S->beta = zero;
+      S->bad = !(S->est == S->est) || isinf(S->est);
+      break;
+    }
+  }
+}
+
+// p = r + beta (p - omega v)
+template <typename R>
+__global__ __launch_bounds__(BS) void k_bicg_p(cplx<R> *__restrict__ p, const cplx<R> *__restrict__ r,
+                                               const cplx<R> *__restrict__ v, int64_t n, const BicgScalars *S) {
+  const cplx<R> beta = cvt<R>(S->beta), omega = cvt<R>(S->omega);
+  for (int64_t q = (int64_t)blockIdx.x * BS + threadIdx.x; q < n; q += (int64_t)gridDim.x * BS)
+    p[q] = r[q] + beta * (p[q] - omega * v[q]);
+}
+
+// s = r - alpha v
+template <typename R>
+__global__ __launch_bounds__(BS) void k_bicg_s(cplx<R> *__restrict__ s, const cplx<R> *__restrict__ r,
+                                               const cplx<R> *__restrict__ v, int64_t n, const BicgScalars *S) {
+  const cplx<R> alpha = cvt<R>(S->alpha);
+  for (int64_t q = (int64_t)blockIdx.x * BS + threadIdx.x; q < n; q += (int64_t)gridDim.x * BS)
+    s[q] = r[q] - alpha * v[q];
+}
+
+// x += alpha ph + omega sh ; r = s - omega t ; partials of ||r||^2
+template <typename R, typename RZ>
+__global__ __launch_bounds__(BS) void k_bicg_xr(cplx<R> *__restrict__ x, const cplx<RZ> *__restrict__ ph,
+                                                const cplx<RZ> *__restrict__ sh, cplx<R> *__restrict__ r,
+                                                const cplx<R> *__restrict__ s, const cplx<R> *__restrict__ t,
+                                                int64_t n, const BicgScalars *S, cplx<double> *partials) {
+  __shared__ cplx<double> lds[BS / 64];
+  const cplx<R> alpha = cvt<R>(S->alpha), omega = cvt<R>(S->omega);
+  double nrm = 0;
+  for (int64_t q = (int64_t)blockIdx.x * BS + threadIdx.x; q < n; q += (int64_t)gridDim.x * BS) {
+    x[q] = x[q] + alpha * cvt<R>(ph[q]) + omega * cvt<R>(sh[q]);
+    cplx<R> rq = s[q] - omega * t[q];
+    r[q] = rq;
+    nrm += abs2(cvt<double>(rq));
+  }
+  cplx<double> sum = block_sum(mk<double>(nrm, 0), lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = sum;
+}
+
+// ----------------------------------------------------------- utilities
+template <typename RI, typename RO>
+__global__ __launch_bounds__(BS) void k_cast(const cplx<RI> *__restrict__ x, cplx<RO> *__restrict__ y, int64_t n) {
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) y[p] = cvt<RO>(x[p]);
+}
+__global__ __launch_bounds__(BS) void k_cast_real(const double *__restrict__ x, float *__restrict__ y, int64_t n) {
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) y[p] = (float)x[p];
+}
+template <typename R>
+__global__ __launch_bounds__(BS) void k_zero(cplx<R> *__restrict__ x, int64_t n) {
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) x[p] = mk<R>(0, 0);
+}
+// y = W x or W^{-1} x, W = w0(i) w1(j) w2(k) (dual cell widths); boundary -> 0
+__global__ __launch_bounds__(BS) void k_scale_w(int n0, int n1, int n2, const cplx<double> *__restrict__ w0,
+                                                const cplx<double> *__restrict__ w1,
+                                                const cplx<double> *__restrict__ w2,
+                                                const cplx<double> *__restrict__ x, cplx<double> *__restrict__ y,
+                                                int inverse) {
+  const int64_t n = (int64_t)n0 * n1 * n2;
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) {
+    int i = (int)(p % n0);
+    int j = (int)((p / n0) % n1);
+    int k = (int)(p / ((int64_t)n0 * n1));
+    bool zin = n2 == 1 || (k >= 1 && k <= n2 - 2);
+    if (!(i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && zin)) {
+      y[p] = mk<double>(0, 0);
+      continue;
+    }
+    cplx<double> wv = w0[i] * w1[j];
+    if (n2 > 1) wv = wv * w2[k];
+    y[p] = inverse ? cdiv(x[p], wv) : wv * x[p];
+  }
+}
+// y = x on interior nodes, 0 on the Dirichlet boundary (may run in place)
+__global__ __launch_bounds__(BS) void k_mask_boundary(int n0, int n1, int n2, const cplx<double> *x,
+                                                      cplx<double> *y) {
+  const int64_t n = (int64_t)n0 * n1 * n2;
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) {
+    int i = (int)(p % n0);
+    int j = (int)((p / n0) % n1);
+    int k = (int)(p / ((int64_t)n0 * n1));
+    bool zin = n2 == 1 || (k >= 1 && k <= n2 - 2);
+    bool in = i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && zin;
+    y[p] = in ? x[p] : mk<double>(0, 0);
+  }
+}
+__global__ __launch_bounds__(BS) void k_grad_k2(const cplx<double> *__restrict__ lam,
+                                                const cplx<double> *__restrict__ u, double *__restrict__ g,
+                                                int64_t n) {
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) {
+    cplx<double> a = lam[p], b = u[p];
+    g[p] = a.re * b.re - a.im * b.im;
+  }
+}
+__global__ __launch_bounds__(BS) void k_max_partial(const double *__restrict__ x, int64_t n, double *partials) {
+  __shared__ double lds[BS / 64];
+  double m = -INFINITY;
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) m = fmax(m, x[p]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = lds[0];
+    for (int q = 1; q < BS / 64; q++) r = fmax(r, lds[q]);
+    partials[blockIdx.x] = r;
+  }
+}
+__global__ void k_max_final(const double *partials, int nb, double *out) {
+  if (threadIdx.x != 0) return;
+  double r = -INFINITY;
+  for (int q = 0; q < nb; q++) r = fmax(r, partials[q]);
+  *out = r;
+}
+__global__ __launch_bounds__(BS) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n) {
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) dst[p] = src[p];
+}
+__global__ void k_copy1(const unsigned char *__restrict__ src, unsigned char *__restrict__ dst, int64_t n) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dst[p] = src[p];
+}
+
+inline int grid_for(int64_t n) {
+  int64_t b = (n + BS - 1) / BS;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+int reduction_blocks(int64_t n) { return red_blocks(n); }
+
+template <typename RA, typename RB>
+void launch_mdot(const cplx<RA> *V, int64_t ldv, int ncols, const cplx<RB> *w, int64_t n, cplx<double> *partials,
+                 cplx<double> *out, hipStream_t s) {
+  int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_mdot<RA, RB>), dim3(nb), dim3(BS), 0, s, V, ldv, ncols, w, n, partials);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(ncols), dim3(BS), 0, s, partials, nb, out);
+}
+
+void launch_mupdate(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w, int64_t n,
+                    cplx<double> *partials, cplx<double> *out_norm2, hipStream_t s) {
+  int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_mupdate, dim3(nb), dim3(BS), 0, s, V, ldv, ncols, h, w, n, partials);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(BS), 0, s, partials, nb, out_norm2);
+}
+
+template <typename R>
+void launch_nrm2sq(const cplx<R> *x, int64_t n, cplx<double> *partials, cplx<double> *out, hipStream_t s) {
+  int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_nrm2sq<R>), dim3(nb), dim3(BS), 0, s, x, n, partials);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(BS), 0, s, partials, nb, out);
+}
+
+template <typename RZ>
+void launch_lincomb(const cplx<RZ> *Z, int64_t ldz, int ncols, const cplx<double> *y, cplx<double> *x, int64_t n,
+                    hipStream_t s) {
+  hipLaunchKernelGGL((k_lincomb<RZ>), dim3(grid_for(n)), dim3(BS), 0, s, Z, ldz, ncols, y, x, n);
+}
+
+void launch_scale_dev(cplx<double> *x, int64_t n, const double *scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n)), dim3(BS), 0, s, x, n, scal);
+}
+void launch_gmres_start(GmresScalars *S, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(1), 0, s, S, m);
+}
+void launch_gmres_givens(GmresScalars *S, int j, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(1), 0, s, S, j, m);
+}
+void launch_gmres_backsolve(GmresScalars *S, int k, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_backsolve, dim3(1), dim3(1), 0, s, S, k, m);
+}
+
+void launch_add_h2(GmresScalars *S, int j, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_h2, dim3(1), dim3(kMaxRestart + 2), 0, s, S, j, m);
+}
+
+template <typename R>
+void launch_pairdot(const cplx<R> *x0, const cplx<R> *y0, const cplx<R> *x1, const cplx<R> *y1, int npairs, int64_t n,
+                    cplx<double> *partials, BicgScalars *S, int mode, hipStream_t s) {
+  int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_pairdot<R>), dim3(nb), dim3(BS), 0, s, x0, y0, x1, y1, npairs, n, partials);
+  hipLaunchKernelGGL(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, npairs, S, mode);
+}
+template <typename R>
+void launch_bicg_p(cplx<R> *p, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s) {
+  hipLaunchKernelGGL((k_bicg_p<R>), dim3(grid_for(n)), dim3(BS), 0, s, p, r, v, n, S);
+}
+template <typename R>
+void launch_bicg_s(cplx<R> *sv, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s) {
+  hipLaunchKernelGGL((k_bicg_s<R>), dim3(grid_for(n)), dim3(BS), 0, s, sv, r, v, n, S);
+}
+template <typename R, typename RZ>
+void launch_bicg_xr(cplx<R> *x, const cplx<RZ> *ph, const cplx<RZ> *sh, cplx<R> *r, const cplx<R> *sv,
+                    const cplx<R> *t, int64_t n, cplx<double> *partials, BicgScalars *S, hipStream_t s) {
+  int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_bicg_xr<R, RZ>), dim3(nb), dim3(BS), 0, s, x, ph, sh, r, sv, t, n, S, partials);
+  hipLaunchKernelGGL(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, 1, S, (int)kBicgNorm);
+}
+
+template <typename RI, typename RO>
+void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast<RI, RO>), dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
+}
+void launch_cast_real(const double *x, float *y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_real, dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
+}
+template <typename R>
+void launch_zero(cplx<R> *x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_zero<R>), dim3(grid_for(n)), dim3(BS), 0, s, x, n);
+}
+void launch_scale_w(int n0, int n1, int n2, const cplx<double> *w0, const cplx<double> *w1, const cplx<double> *w2,
+                    const cplx<double> *x, cplx<double> *y, bool inverse, hipStream_t s) {
+  int64_t n = (int64_t)n0 * n1 * n2;
+  hipLaunchKernelGGL(k_scale_w, dim3(grid_for(n)), dim3(BS), 0, s, n0, n1, n2, w0, w1, w2, x, y, inverse ? 1 : 0);
+}
+void launch_mask_boundary(int n0, int n1, int n2, const cplx<double> *x, cplx<double> *y, hipStream_t s) {
+  int64_t n = (int64_t)n0 * n1 * n2;
+  hipLaunchKernelGGL(k_mask_boundary, dim3(grid_for(n)), dim3(BS), 0, s, n0, n1, n2, x, y);
+}
+void launch_grad_k2(const cplx<double> *lam, const cplx<double> *u, double *g, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_k2, dim3(grid_for(n)), dim3(BS), 0, s, lam, u, g, n);
+}
+void launch_max_real(const double *x, int64_t n, double *partials, double *out, hipStream_t s) {
+  int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_max_partial, dim3(nb), dim3(BS), 0, s, x, n, partials);
+  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(1), 0, s, partials, nb, out);
+}
+void launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t s) {
+  if (((uintptr_t)src % 16) == 0 && ((uintptr_t)dst % 16) == 0 && bytes % 16 == 0) {
+    int64_t n = (int64_t)(bytes / 16);
+    int64_t b = (n + BS - 1) / BS;
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)b), dim3(BS), 0, s, (const uint4 *)src, (uint4 *)dst, n);
+  } else {
+    int64_t n = (int64_t)bytes;
+    hipLaunchKernelGGL(k_copy1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const unsigned char *)src,
+                       (unsigned char *)dst, n);
+  }
+}
+
+template void launch_mdot<double, double>(const cplx<double> *, int64_t, int, const cplx<double> *, int64_t,
+                                          cplx<double> *, cplx<double> *, hipStream_t);
+template void launch_nrm2sq<double>(const cplx<double> *, int64_t, cplx<double> *, cplx<double> *, hipStream_t);
+template void launch_nrm2sq<float>(const cplx<float> *, int64_t, cplx<double> *, cplx<double> *, hipStream_t);
+template void launch_lincomb<double>(const cplx<double> *, int64_t, int, const cplx<double> *, cplx<double> *, int64_t,
+                                     hipStream_t);
+template void launch_lincomb<float>(const cplx<float> *, int64_t, int, const cplx<double> *, cplx<double> *, int64_t,
+                                    hipStream_t);
+template void launch_pairdot<double>(const cplx<double> *, const cplx<double> *, const cplx<double> *,
+                                     const cplx<double> *, int, int64_t, cplx<double> *, BicgScalars *, int,
+                                     hipStream_t);
+template void launch_pairdot<float>(const cplx<float> *, const cplx<float> *, const cplx<float> *,
+                                    const cplx<float> *, int, int64_t, cplx<double> *, BicgScalars *, int, hipStream_t);
+template void launch_bicg_p<double>(cplx<double> *, const cplx<double> *, const cplx<double> *, int64_t,
+                                    const BicgScalars *, hipStream_t);
+template void launch_bicg_p<float>(cplx<float> *, const cplx<float> *, const cplx<float> *, int64_t,
+                                   const BicgScalars *, hipStream_t);
+template void launch_bicg_s<double>(cplx<double> *, const cplx<double> *, const cplx<double> *, int64_t,
+                                    const BicgScalars *, hipStream_t);
+template void launch_bicg_s<float>(cplx<float> *, const cplx<float> *, const cplx<float> *, int64_t,
+                                   const BicgScalars *, hipStream_t);
+template void launch_bicg_xr<double, double>(cplx<double> *, const cplx<double> *, const cplx<double> *, cplx<double> *,
+                                             const cplx<double> *, const cplx<double> *, int64_t, cplx<double> *,
+                                             BicgScalars *, hipStream_t);
+template void launch_bicg_xr<double, float>(cplx<double> *, const cplx<float> *, const cplx<float> *, cplx<double> *,
+                                            const cplx<double> *, const cplx<double> *, int64_t, cplx<double> *,
+                                            BicgScalars *, hipStream_t);
+template void launch_bicg_xr<float, float>(cplx<float> *, const cplx<float> *, const cplx<float> *, cplx<float> *,
+                                           const cplx<float> *, const cplx<float> *, int64_t, cplx<double> *,
+                                           BicgScalars *, hipStream_t);
+template void launch_cast<double, float>(const cplx<double> *, cplx<float> *, int64_t, hipStream_t);
+template void launch_cast<float, double>(const cplx<float> *, cplx<double> *, int64_t, hipStream_t);
+template void launch_zero<double>(cplx<double> *, int64_t, hipStream_t);
+template void launch_zero<float>(cplx<float> *, int64_t, hipStream_t);
+
+}  // namespace ecs

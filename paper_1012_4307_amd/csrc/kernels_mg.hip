@@ -1,0 +1,330 @@
+// kernels_mg.hip -- multigrid components of the ECS Helmholtz preconditioner
+// (bin Zubair, Reps, Vanroose, Sec. 3.2 operator, Sec. 4.2 components):
+// stencil apply, residual, omega-Jacobi and red-black SOR sweeps, full-weighting
+// restriction (fused with the residual), bilinear/trilinear prolongation with
+// correction, dense coarsest solve, k^2 injection.
+//
+// Layout: node-major, x fastest, interleaved complex.  Every kernel maps one
+// thread to one node of a (64 x 4) tile of an x-y plane; the z plane (3D) is
+// blockIdx.z.  Loads along x are unit stride, so a wave reads 64 consecutive
+// nodes (1 KB in FP64) per access.  Boundary nodes carry zeros.
+#include "ecs_internal.h"
+
+namespace ecs {
+
+namespace {
+
+constexpr int TX = 64;
+constexpr int TY = 4;
+
+template <typename R>
+struct Node {
+  int i, j, k;
+  int64_t p;
+  bool in;        // inside the array
+  bool interior;  // not a Dirichlet node
+};
+
+template <typename R>
+__device__ __forceinline__ Node<R> node_of(const Grid<R> &g) {
+  Node<R> q;
+  q.i = blockIdx.x * TX + threadIdx.x;
+  q.j = blockIdx.y * TY + threadIdx.y;
+  q.k = blockIdx.z;
+  q.in = q.i < g.n0 && q.j < g.n1;
+  q.p = ((int64_t)q.k * g.n1 + q.j) * g.n0 + q.i;
+  bool zin = g.n2 == 1 || (q.k >= 1 && q.k <= g.n2 - 2);
+  q.interior = q.in && q.i >= 1 && q.i <= g.n0 - 2 && q.j >= 1 && q.j <= g.n1 - 2 && zin;
+  return q;
+}
+
+// diagonal of M at an interior node
+template <typename R>
+__device__ __forceinline__ cplx<R> diag_at(const Grid<R> &g, int i, int j, int k, int64_t p) {
+  cplx<R> d = g.cm0[i] + g.cp0[i] + g.cm1[j] + g.cp1[j];
+  if (g.n2 > 1) d = d + g.cm2[k] + g.cp2[k];
+  return d + (g.k2[p] * g.beta + g.c);
+}
+
+// off-diagonal part: sum of (cm u_{p-s} + cp u_{p+s}) so that M u = D u - offd
+template <typename R, typename RI>
+__device__ __forceinline__ cplx<R> offd_at(const Grid<R> &g, const cplx<RI> *__restrict__ u, int i, int j, int k,
+                                           int64_t p) {
+  const int64_t s1 = g.n0;
+  cplx<R> o = g.cm0[i] * cvt<R>(u[p - 1]) + g.cp0[i] * cvt<R>(u[p + 1]);
+  o = o + g.cm1[j] * cvt<R>(u[p - s1]) + g.cp1[j] * cvt<R>(u[p + s1]);
+  if (g.n2 > 1) {
+    const int64_t s2 = (int64_t)g.n0 * g.n1;
+    o = o + g.cm2[k] * cvt<R>(u[p - s2]) + g.cp2[k] * cvt<R>(u[p + s2]);
+  }
+  return o;
+}
+
+template <typename R>
+dim3 grid_of(const Grid<R> &g) {
+  return dim3((g.n0 + TX - 1) / TX, (g.n1 + TY - 1) / TY, g.n2);
+}
+
+// y = M x; the input may be stored in a lower precision than the arithmetic
+// (an FP32 preconditioned vector fed to the FP64 operator)
+template <typename R, typename RI, typename RO>
+__global__ __launch_bounds__(256) void k_apply(Grid<R> g, const cplx<RI> *__restrict__ x, cplx<RO> *__restrict__ y) {
+  Node<R> q = node_of(g);
+  if (!q.in) return;
+  if (!q.interior) {
+    y[q.p] = mk<RO>(0, 0);
+    return;
+  }
+  cplx<R> v = diag_at(g, q.i, q.j, q.k, q.p) * cvt<R>(x[q.p]) - offd_at<R, RI>(g, x, q.i, q.j, q.k, q.p);
+  y[q.p] = cvt<RO>(v);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_residual(Grid<R> g, const cplx<R> *__restrict__ b,
+                                                  const cplx<R> *__restrict__ u, cplx<R> *__restrict__ r) {
+  Node<R> q = node_of(g);
+  if (!q.in) return;
+  if (!q.interior) {
+    r[q.p] = mk<R>(0, 0);
+    return;
+  }
+  r[q.p] = b[q.p] - (diag_at(g, q.i, q.j, q.k, q.p) * u[q.p] - offd_at<R, R>(g, u, q.i, q.j, q.k, q.p));
+}
+
+// omega-Jacobi, out of place: out = u + omega D^{-1} (b - M u); zero_guess
+// skips reading u (u == 0): out = omega D^{-1} b
+template <typename R>
+__global__ __launch_bounds__(256) void k_jacobi(Grid<R> g, const cplx<R> *__restrict__ b,
+                                                const cplx<R> *__restrict__ u, cplx<R> *__restrict__ out, R omega,
+                                                int zero_guess) {
+  Node<R> q = node_of(g);
+  if (!q.in) return;
+  if (!q.interior) {
+    out[q.p] = mk<R>(0, 0);
+    return;
+  }
+  cplx<R> d = diag_at(g, q.i, q.j, q.k, q.p);
+  if (zero_guess) {
+    out[q.p] = omega * cdiv(b[q.p], d);
+  } else {
+    cplx<R> u0 = u[q.p];
+    cplx<R> res = b[q.p] - (d * u0 - offd_at<R, R>(g, u, q.i, q.j, q.k, q.p));
+    out[q.p] = u0 + omega * cdiv(res, d);
+  }
+}
+
+// one colour of a red-black SOR sweep, in place: nodes of colour `colour`
+// ((i+j+k) & 1) are relaxed; they only couple to the other colour.  With
+// zero_guess (u == 0 on entry, red pass) the red nodes get omega D^{-1} b and
+// every other node of the array is written as 0, so u needs no clearing.
+template <typename R>
+__global__ __launch_bounds__(256) void k_rb_colour(Grid<R> g, const cplx<R> *__restrict__ b, cplx<R> *u, R omega,
+                                                   int colour, int zero_guess) {
+  Node<R> q = node_of(g);
+  if (!q.in) return;
+  bool mine = q.interior && (((q.i + q.j + q.k) & 1) == colour);
+  if (zero_guess) {
+    u[q.p] = mine ? omega * cdiv(b[q.p], diag_at(g, q.i, q.j, q.k, q.p)) : mk<R>(0, 0);
+    return;
+  }
+  if (!mine) return;
+  cplx<R> d = diag_at(g, q.i, q.j, q.k, q.p);
+  cplx<R> u0 = u[q.p];
+  cplx<R> res = b[q.p] - (d * u0 - offd_at<R, R>(g, u, q.i, q.j, q.k, q.p));
+  u[q.p] = u0 + omega * cdiv(res, d);
+}
+
+// full weighting of a fine-grid vector onto the coarse interior, index space
+// tensor product of [1 2 1]/4 per active axis
+template <typename R>
+__global__ __launch_bounds__(256) void k_restrict(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ rf,
+                                                  cplx<R> *__restrict__ rc) {
+  Node<R> q = node_of(c);
+  if (!q.in) return;
+  if (!q.interior) {
+    rc[q.p] = mk<R>(0, 0);
+    return;
+  }
+  const int64_t s1 = f.n0, s2 = (int64_t)f.n0 * f.n1;
+  const int fk = f.n2 > 1 ? 2 * q.k : 0;
+  const int64_t pf = ((int64_t)fk * f.n1 + 2 * q.j) * f.n0 + 2 * q.i;
+  const R wgt[3] = {R(0.25), R(0.5), R(0.25)};
+  cplx<R> acc = mk<R>(0, 0);
+  const int kz = f.n2 > 1 ? 1 : 0;
+  for (int dz = -kz; dz <= kz; dz++) {
+    R wz = kz ? wgt[dz + 1] : R(1);
+    for (int dy = -1; dy <= 1; dy++)
+      for (int dx = -1; dx <= 1; dx++) {
+        R w = wz * wgt[dy + 1] * wgt[dx + 1];
+        acc = acc + w * rf[pf + dz * s2 + dy * s1 + dx];
+      }
+  }
+  rc[q.p] = acc;
+}
+
+// fused residual + full weighting: the 3^d fine residuals under the coarse
+// node are recomputed from u (no fine residual vector is stored)
+template <typename R>
+__global__ __launch_bounds__(256) void k_residual_restrict(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
+                                                           const cplx<R> *__restrict__ u, cplx<R> *__restrict__ rc) {
+  Node<R> q = node_of(c);
+  if (!q.in) return;
+  if (!q.interior) {
+    rc[q.p] = mk<R>(0, 0);
+    return;
+  }
+  const R wgt[3] = {R(0.25), R(0.5), R(0.25)};
+  const int kz = f.n2 > 1 ? 1 : 0;
+  cplx<R> acc = mk<R>(0, 0);
+  for (int dz = -kz; dz <= kz; dz++) {
+    int fk = kz ? 2 * q.k + dz : 0;
+    R wz = kz ? wgt[dz + 1] : R(1);
+    bool zint = !kz || (fk >= 1 && fk <= f.n2 - 2);
+    for (int dy = -1; dy <= 1; dy++) {
+      int fj = 2 * q.j + dy;
+      for (int dx = -1; dx <= 1; dx++) {
+        int fi = 2 * q.i + dx;
+        if (!zint || fj < 1 || fj > f.n1 - 2 || fi < 1 || fi > f.n0 - 2) continue;
+        int64_t p = ((int64_t)fk * f.n1 + fj) * f.n0 + fi;
+        cplx<R> r = b[p] - (diag_at(f, fi, fj, fk, p) * u[p] - offd_at<R, R>(f, u, fi, fj, fk, p));
+        acc = acc + (wz * wgt[dy + 1] * wgt[dx + 1]) * r;
+      }
+    }
+  }
+  rc[q.p] = acc;
+}
+
+// u += P ec on the fine interior (bilinear / trilinear in index space)
+template <typename R>
+__global__ __launch_bounds__(256) void k_prolong_add(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ ec,
+                                                     cplx<R> *__restrict__ u) {
+  Node<R> q = node_of(f);
+  if (!q.interior) return;
+  int ci[3][2], nc[3];
+  R cw[3][2];
+  const int fi[3] = {q.i, q.j, q.k};
+  const int dims = f.n2 > 1 ? 3 : 2;
+  for (int a = 0; a < 3; a++) {
+    if (a >= dims) {
+      nc[a] = 1; ci[a][0] = 0; cw[a][0] = R(1);
+    } else if ((fi[a] & 1) == 0) {
+      nc[a] = 1; ci[a][0] = fi[a] >> 1; cw[a][0] = R(1);
+    } else {
+      nc[a] = 2; ci[a][0] = fi[a] >> 1; ci[a][1] = (fi[a] >> 1) + 1; cw[a][0] = cw[a][1] = R(0.5);
+    }
+  }
+  cplx<R> e = mk<R>(0, 0);
+  for (int cz = 0; cz < nc[2]; cz++)
+    for (int cy = 0; cy < nc[1]; cy++)
+      for (int cx = 0; cx < nc[0]; cx++) {
+        int64_t pc = ((int64_t)ci[2][cz] * c.n1 + ci[1][cy]) * c.n0 + ci[0][cx];
+        e = e + (cw[0][cx] * cw[1][cy] * cw[2][cz]) * ec[pc];
+      }
+  u[q.p] = u[q.p] + e;
+}
+
+// x = M_C^{-1} b on the coarsest level from the precomputed dense inverse
+// (row-major nunk x nunk); unk maps an unknown to its node index.  Thread t
+// writes the t-th unknown and, if node t is a boundary node, its zero.
+template <typename R>
+__global__ __launch_bounds__(256) void k_coarse_solve(int nunk, const cplx<R> *__restrict__ minv,
+                                                      const int *__restrict__ unk, int n0, int n1, int n2,
+                                                      const cplx<R> *__restrict__ b, cplx<R> *__restrict__ x) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int nn = n0 * n1 * n2;
+  if (t < nn) {
+    int i = t % n0, j = (t / n0) % n1, k = t / (n0 * n1);
+    bool zin = n2 == 1 || (k >= 1 && k <= n2 - 2);
+    bool interior = i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && zin;
+    if (!interior) x[t] = mk<R>(0, 0);
+  }
+  if (t >= nunk) return;
+  cplx<R> acc = mk<R>(0, 0);
+  const cplx<R> *row = minv + (int64_t)t * nunk;
+  for (int c = 0; c < nunk; c++) acc = acc + row[c] * b[unk[c]];
+  x[unk[t]] = acc;
+}
+
+template <typename R>
+__global__ void k_inject_k2(int n0, int n1, int n2, const double *__restrict__ kf, int f0, int f1, int stride,
+                            R *__restrict__ kc) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  int k = blockIdx.z;
+  if (i >= n0) return;
+  int64_t pf = ((int64_t)(n2 > 1 ? k * stride : 0) * f1 + (int64_t)j * stride) * f0 + (int64_t)i * stride;
+  kc[((int64_t)k * n1 + j) * n0 + i] = R(kf[pf]);
+}
+
+}  // namespace
+
+template <typename R, typename RI, typename RO>
+void launch_apply(const Grid<R> &g, const cplx<RI> *x, cplx<RO> *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_apply<R, RI, RO>), grid_of(g), dim3(TX, TY), 0, s, g, x, y);
+}
+template <typename R>
+void launch_residual(const Grid<R> &g, const cplx<R> *b, const cplx<R> *u, cplx<R> *r, hipStream_t s) {
+  hipLaunchKernelGGL((k_residual<R>), grid_of(g), dim3(TX, TY), 0, s, g, b, u, r);
+}
+template <typename R>
+void launch_jacobi(const Grid<R> &g, const cplx<R> *b, const cplx<R> *u, cplx<R> *out, R omega, bool zero_guess,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((k_jacobi<R>), grid_of(g), dim3(TX, TY), 0, s, g, b, u, out, omega, zero_guess ? 1 : 0);
+}
+template <typename R>
+void launch_rb_colour(const Grid<R> &g, const cplx<R> *b, cplx<R> *u, R omega, int colour, bool zero_guess,
+                      hipStream_t s) {
+  hipLaunchKernelGGL((k_rb_colour<R>), grid_of(g), dim3(TX, TY), 0, s, g, b, u, omega, colour, zero_guess ? 1 : 0);
+}
+template <typename R>
+void launch_restrict(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *rf, cplx<R> *rc, hipStream_t s) {
+  hipLaunchKernelGGL((k_restrict<R>), grid_of(coarse), dim3(TX, TY), 0, s, fine, coarse, rf, rc);
+}
+template <typename R>
+void launch_residual_restrict(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u,
+                              cplx<R> *rc, hipStream_t s) {
+  hipLaunchKernelGGL((k_residual_restrict<R>), grid_of(coarse), dim3(TX, TY), 0, s, fine, coarse, b, u, rc);
+}
+template <typename R>
+void launch_prolong_add(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *ec, cplx<R> *u, hipStream_t s) {
+  hipLaunchKernelGGL((k_prolong_add<R>), grid_of(fine), dim3(TX, TY), 0, s, fine, coarse, ec, u);
+}
+template <typename R>
+void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, int n1, int n2, const cplx<R> *b,
+                         cplx<R> *x, hipStream_t s) {
+  int nn = n0 * n1 * n2;
+  int nb = ((nn > nunk ? nn : nunk) + 255) / 256;
+  hipLaunchKernelGGL((k_coarse_solve<R>), dim3(nb), dim3(256), 0, s, nunk, minv, unk, n0, n1, n2, b, x);
+}
+template <typename R>
+void launch_inject_k2(int n0, int n1, int n2, const double *k2_fine, int f0, int f1, R *k2_coarse, hipStream_t s) {
+  int stride = (f0 - 1) / (n0 - 1);
+  hipLaunchKernelGGL((k_inject_k2<R>), dim3((n0 + 255) / 256, n1, n2), dim3(256), 0, s, n0, n1, n2, k2_fine, f0, f1,
+                     stride, k2_coarse);
+}
+
+#define ECS_INST_MG(R)                                                                                          \
+  template void launch_residual<R>(const Grid<R> &, const cplx<R> *, const cplx<R> *, cplx<R> *, hipStream_t);  \
+  template void launch_jacobi<R>(const Grid<R> &, const cplx<R> *, const cplx<R> *, cplx<R> *, R, bool,          \
+                                 hipStream_t);                                                                  \
+  template void launch_rb_colour<R>(const Grid<R> &, const cplx<R> *, cplx<R> *, R, int, bool, hipStream_t);     \
+  template void launch_restrict<R>(const Grid<R> &, const Grid<R> &, const cplx<R> *, cplx<R> *, hipStream_t);   \
+  template void launch_residual_restrict<R>(const Grid<R> &, const Grid<R> &, const cplx<R> *, const cplx<R> *,  \
+                                            cplx<R> *, hipStream_t);                                            \
+  template void launch_prolong_add<R>(const Grid<R> &, const Grid<R> &, const cplx<R> *, cplx<R> *,              \
+                                      hipStream_t);                                                             \
+  template void launch_coarse_solve<R>(int, const cplx<R> *, const int *, int, int, int, const cplx<R> *,      \
+                                       cplx<R> *, hipStream_t);                                                 \
+  template void launch_inject_k2<R>(int, int, int, const double *, int, int, R *, hipStream_t);
+
+ECS_INST_MG(double)
+ECS_INST_MG(float)
+
+template void launch_apply<double, double, double>(const Grid<double> &, const cplx<double> *, cplx<double> *,
+                                                   hipStream_t);
+template void launch_apply<double, float, double>(const Grid<double> &, const cplx<float> *, cplx<double> *,
+                                                  hipStream_t);
+template void launch_apply<float, float, float>(const Grid<float> &, const cplx<float> *, cplx<float> *,
+                                                hipStream_t);
+
+}  // namespace ecs

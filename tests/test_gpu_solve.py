@@ -1,0 +1,171 @@
+"""GPU solves through the C ABI checked against the CPU oracle.
+
+The solve's result is the unique solution of A x = b, so the GPU iterate is
+compared with the oracle's solution obtained at a tight tolerance, and the
+GPU residual is recomputed with the oracle's own operator.  Iteration counts
+are not compared bitwise (reduction order differs)."""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import gpu_for, oracle_for, ragged_workload, relerr, to_gpu, to_np
+import paper_1012_4307_amd as E
+from paper_1012_4307_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_resid(P, x, b):
+    r = b.copy()
+    r[0, ...] = 0
+    bi = np.zeros_like(b)
+    sl = tuple(slice(1, -1) for _ in b.shape)
+    bi[sl] = b[sl]
+    return np.linalg.norm(bi - P.apply(x)) / np.linalg.norm(bi)
+
+
+@pytest.mark.parametrize("beta2", [0.5, -0.5])
+def test_small_constant_k_gmres(beta2):
+    """65^2, k = 8, CSL -Lap -(1 -/+ 0.5i) k^2, V(1,1) omega-Jacobi 0.8, GMRES(30)."""
+    w = W.small_constant_k(beta2=beta2)
+    P = oracle_for(w)
+    S = gpu_for(w, "f64")
+    for b in w.rhs:
+        x, st = S.solve(to_gpu(b))
+        assert st["status"] == 0, st
+        x = to_np(x)
+        assert oracle_resid(P, x, b) <= 1.05e-8
+        xo, sto = P.solve(b, "gmres", 30, 1e-12, 5000)
+        assert relerr(x, xo) < 1e-5
+        assert abs(st["iterations"] - sto["iterations"]) <= max(5, 0.2 * sto["iterations"]) or beta2 > 0
+
+
+@pytest.mark.parametrize("method", ["gmres", "fgmres", "bicgstab"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_methods_match_oracle_tight(method, dt):
+    w = ragged_workload(n=65, coarsest=5)
+    P = oracle_for(w)
+    kr = E.Krylov(method=method, restart=30, rtol=1e-12, maxit=3000)
+    S = gpu_for(w, dt, krylov=kr)
+    b = w.rhs[0]
+    x, st = S.solve(to_gpu(b))
+    assert st["status"] == 0, st
+    xo, _ = P.solve(b, "fgmres", 30, 1e-13, 5000)
+    assert relerr(to_np(x), xo) < 1e-9
+    assert oracle_resid(P, to_np(x), b) <= 1.05e-12
+
+
+@pytest.mark.parametrize("E_", [0.5, 1.0, 2.0, 4.0])
+def test_coulomb_bicgstab(E_):
+    """Soft-Coulomb QD problems, V(1,1) RB-GS, Bi-CGSTAB to 1e-8 (257^2 here;
+    the 513^2 size is exercised in test_coulomb_513)."""
+    w = W.coulomb(E=E_, n=257)
+    P = oracle_for(w)
+    S = gpu_for(w, "f64")
+    b = w.rhs[0]
+    x, st = S.solve(to_gpu(b))
+    assert st["status"] == 0, st
+    x = to_np(x)
+    assert oracle_resid(P, x, b) <= 1.05e-8
+    xo, sto = P.solve(b, "bicgstab", rtol=1e-12, maxit=5000)
+    assert relerr(x, xo) < 1e-5
+    assert st["iterations"] <= 1.5 * sto["iterations"] + 5
+
+
+def test_coulomb_513():
+    w = W.coulomb(E=2.0, n=513)
+    P = oracle_for(w)
+    for dt in ("f64", "f32"):
+        S = gpu_for(w, dt)
+        x, st = S.solve(to_gpu(w.rhs[0]))
+        assert st["status"] == 0, st
+        assert oracle_resid(P, to_np(x), w.rhs[0]) <= 1.05e-8
+
+
+def test_mixed_fgmres_vs_fp64_oracle():
+    """Mixed form (FP32 cycle inside FP64 FGMRES(40)) on the benchmark operator
+    family at a reduced size (513^2, h = 0.25): both sides at 1e-12, relative
+    error <= 1e-6."""
+    w = W.large_coulomb(n=257, coarsest=9)
+    P = oracle_for(w)
+    xo, sto = P.solve(w.rhs[0], "fgmres", 40, 1e-12, 20000)
+    assert sto["status"] == 0
+    kr = E.Krylov(method="fgmres", restart=40, rtol=1e-12, maxit=20000)
+    for dt, inner in (("f32", 0), ("f32", 2), ("f64", 0)):
+        S = gpu_for(w, dt, krylov=E.Krylov(method="fgmres", restart=40, rtol=1e-12, maxit=20000, inner=inner))
+        x, st = S.solve(to_gpu(w.rhs[0]))
+        assert st["status"] == 0, (dt, inner, st)
+        assert relerr(to_np(x), xo) < 1e-6, (dt, inner)
+
+
+def test_status_paths():
+    w = W.small_constant_k(n=33)
+    S = gpu_for(w, "f64")
+    import torch
+    z = torch.zeros(w.shape, dtype=torch.complex128, device="cuda")
+    x, st = S.solve(z)
+    assert st["status"] == 0 and int(torch.count_nonzero(x)) == 0
+    bad = w.rhs[0].copy()
+    bad[5, 5] = np.nan
+    with pytest.raises(E.EcsError) as ei:
+        S.solve(to_gpu(bad))
+    assert ei.value.status == -4
+    x, st = S.solve(to_gpu(w.rhs[1]), krylov=E.Krylov(method="gmres", restart=30, rtol=1e-12, maxit=2))
+    assert st["status"] == 1 and st["iterations"] == 2
+    with pytest.raises(ValueError):
+        S.solve(to_gpu(w.rhs[0]).to(torch.complex64))
+    with pytest.raises(E.EcsError) as ei:
+        S.solve(to_gpu(w.rhs[0]), krylov=E.Krylov(method="gmres", restart=500))
+    assert ei.value.status == -1
+
+
+def test_adjoint_solve_and_gradient():
+    """A^T lam = g through the W similarity against the oracle's explicit
+    transpose, and dL/dk^2 = Re(lam u) against central differences."""
+    w = W.coulomb(E=2.0, n=65)
+    P = oracle_for(w)
+    kr = E.Krylov(method="gmres", restart=40, rtol=1e-13, maxit=3000)
+    S = gpu_for(w, "f64", krylov=kr)
+    rng = np.random.default_rng(44)
+    g = W.random_complex(w.shape, rng)
+    lam, st = S.solve_adjoint(to_gpu(g))
+    assert st["status"] == 0
+    lo, _ = P.solve(g, "gmres", 40, 1e-13, 3000, transpose=True)
+    assert relerr(to_np(lam), lo) < 1e-9
+    # gradient of L = 1/2 ||S u - d||^2 (S = sampling) by the adjoint vs FD
+    import torch
+    rows = np.arange(8, 57, 6)
+    f = to_gpu(w.rhs[0])
+    u, _ = S.solve(f)
+    un = to_np(u)
+    d = un[np.ix_(rows, rows)] * (1 + 0.1 * rng.standard_normal((rows.size, rows.size)))
+    gg = np.zeros(w.shape, complex)
+    gg[np.ix_(rows, rows)] = un[np.ix_(rows, rows)] - d
+    lam, _ = S.solve_adjoint(to_gpu(np.conj(gg)))
+    grad = to_np(S.grad_k2(lam, u))
+
+    def loss(k2v):
+        S2 = gpu_for(W.Workload(w.name, 2, w.n, w.lo, w.hi, w.ecs, k2v, w.rhs, w.precond, w.cycle, w.krylov, w.nlev),
+                     "f64", krylov=kr)
+        uu, _ = S2.solve(f)
+        r = to_np(uu)[np.ix_(rows, rows)] - d
+        return 0.5 * np.sum(np.abs(r) ** 2)
+
+    eps = 1e-6
+    for (j, i) in [(20, 20), (32, 31), (40, 25), (30, 44)]:
+        kp = w.k2.copy(); kp[j, i] += eps
+        km = w.k2.copy(); km[j, i] -= eps
+        fd = (loss(kp) - loss(km)) / (2 * eps)
+        assert abs(fd - grad[j, i]) <= 1e-5 * abs(fd) + 1e-12, (j, i, fd, grad[j, i])
+
+
+def test_3d_solve():
+    w = W.cube_constant_k(n=17, k=6.0)
+    P = oracle_for(w)
+    S = gpu_for(w, "f64")
+    x, st = S.solve(to_gpu(w.rhs[0]))
+    assert st["status"] == 0
+    xo, _ = P.solve(w.rhs[0], "fgmres", 30, 1e-13, 3000)
+    assert relerr(to_np(x), xo) < 1e-5
+    assert oracle_resid(P, to_np(x), w.rhs[0]) <= 1.05e-8
