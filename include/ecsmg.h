@@ -186,12 +186,18 @@ ecs_status ecs_coarse_solve(ecs_ctx *ctx, const void *b_dev, void *x_dev);
 ecs_status ecs_level_info(ecs_ctx *ctx, int level, int *nlevels, int64_t *nodes);
 
 /* Kernel timing for measurement: when enabled, HIP events are recorded on the
- * context's stream around every launch of kernel class `kclass`
- * (0 = finest-level cycle kernels, 1 = Arnoldi orthogonalisation, 2 = FP64
- * operator A, 3 = coarse-level cycle kernels); ecs_timing_read returns the number of launches and their summed
- * duration in milliseconds (synchronises) and resets the counters. */
+ * context's stream around every launch of kernel class `kclass`:
+ *   0 finest-level smoothing sweep      5 finest-level residual + restriction
+ *   1 Arnoldi multi-dot (partials)      6 finest-level prolongation + correction
+ *   2 FP64 operator A (matvec)          7 finest-level fused down kernel
+ *   3 coarse-level cycle kernels        8 finest-level fused up kernel
+ *   4 Arnoldi orthogonal update
+ * ecs_timing_read synchronises the stream and returns the number of timed
+ * launches, their summed duration in ms and their summed algorithmic bytes
+ * (the minimum HBM traffic of each launch: every input read once, every
+ * output written once), then resets the class. */
 ecs_status ecs_timing_enable(ecs_ctx *ctx, int kclass, int enable);
-ecs_status ecs_timing_read(ecs_ctx *ctx, int kclass, int64_t *launches, double *total_ms);
+ecs_status ecs_timing_read(ecs_ctx *ctx, int kclass, int64_t *launches, double *total_ms, double *algo_bytes);
 
 /* Batched solve of n independent problems (each context fully set up with its
  * own workspace), all right-hand sides to their rtol with Bi-CGSTAB.  Every

@@ -32,7 +32,8 @@ SMOOTHER = {"jacobi": 0, "rbgs": 1}
 KRYLOV = {"gmres": 0, "fgmres": 1, "bicgstab": 2}
 OP = {"A": 0, "AT": 1, "M": 2}
 STATUS = {0: "ok", 1: "not_converged", -1: "einval", -2: "enomem", -3: "edevice", -4: "ebreakdown", -5: "estate"}
-TIMER = {"finest_cycle": 0, "arnoldi": 1, "apply_A": 2, "coarse_cycle": 3}
+TIMER = {"smooth": 0, "mdot": 1, "apply_A": 2, "coarse": 3, "mupdate": 4, "restrict": 5, "prolong": 6, "down": 7,
+         "up": 8}
 
 
 class EcsError(RuntimeError):
@@ -94,7 +95,7 @@ def lib():
         "ecs_coarse_solve": [P, P, P],
         "ecs_level_info": [P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_int64)],
         "ecs_timing_enable": [P, I, I],
-        "ecs_timing_read": [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D)],
+        "ecs_timing_read": [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D)],
         "ecs_batch_solve": [I, pP, ctypes.POINTER(SolveDesc), pP, pP, ctypes.POINTER(I), ctypes.POINTER(Stats)],
         "ecs_copy_probe": [P, P, Z, P],
     }
@@ -368,10 +369,13 @@ class Solver:
         self._check(lib().ecs_timing_enable(self._h, TIMER[kclass], 1 if enable else 0))
 
     def timing_read(self, kclass: str):
+        """(launches, total ms, algorithmic bytes) of one kernel class since the last read."""
         n = ctypes.c_int64()
         ms = ctypes.c_double()
-        self._check(lib().ecs_timing_read(self._h, TIMER[kclass], ctypes.byref(n), ctypes.byref(ms)))
-        return n.value, ms.value
+        by = ctypes.c_double()
+        self._check(lib().ecs_timing_read(self._h, TIMER[kclass], ctypes.byref(n), ctypes.byref(ms),
+                                          ctypes.byref(by)))
+        return n.value, ms.value, by.value
 
 
 def batch_solve(solvers, rhs, krylov: Krylov):

@@ -37,11 +37,15 @@ enum { kBicgRho = 0, kBicgAlpha = 1, kBicgOmega = 2, kBicgNorm = 3, kBicgInit = 
 
 int reduction_blocks(int64_t n);
 
+// multi-dot partials: partials[c][block] = block's share of sum_p conj(V_c[p]) w[p]
 template <typename RA, typename RB>
-void launch_mdot(const cplx<RA> *V, int64_t ldv, int ncols, const cplx<RB> *w, int64_t n, cplx<double> *partials,
-                 cplx<double> *out, hipStream_t s);
-void launch_mupdate(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w, int64_t n,
-                    cplx<double> *partials, cplx<double> *out_norm2, hipStream_t s);
+void launch_mdot_partial(const cplx<RA> *V, int64_t ldv, int ncols, const cplx<RB> *w, int64_t n,
+                         cplx<double> *partials, hipStream_t s);
+// out[c] = fixed-order sum of partials[c][*] (block count derived from n)
+void launch_reduce_cols(const cplx<double> *partials, int64_t n, int ncols, cplx<double> *out, hipStream_t s);
+// w <- w - sum_c V_c h_c ; partials[block] = block's share of ||w||^2
+void launch_mupdate_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w,
+                            int64_t n, cplx<double> *partials, hipStream_t s);
 template <typename R>
 void launch_nrm2sq(const cplx<R> *x, int64_t n, cplx<double> *partials, cplx<double> *out, hipStream_t s);
 template <typename RZ>

@@ -49,8 +49,12 @@ struct Timer {
   std::vector<hipEvent_t> ev;  // start/stop pairs
   size_t used = 0;
   bool on = false;
-  int64_t launches = 0;
+  double bytes = 0;            // algorithmic bytes of the timed launches
 };
+
+// timing classes (see ecs_timing_enable in ecsmg.h)
+enum { kTSmooth = 0, kTMdot = 1, kTApply = 2, kTCoarse = 3, kTMupdate = 4, kTRestrict = 5, kTProlong = 6,
+       kTDown = 7, kTUp = 8, kTClasses = 9 };
 
 // bump allocator over the caller's workspace (256 B alignment); with a null
 // base it only measures
@@ -103,7 +107,7 @@ struct ecs_ctx {
   BicgScalars *bs = nullptr, *bs_in = nullptr;
   double *pinned = nullptr;  // host-pinned scalars for readback
 
-  Timer timers[4];  // 0 finest-level cycle, 1 Arnoldi, 2 operator A, 3 coarse levels
+  Timer timers[kTClasses];
   std::string err;
 };
 
@@ -184,8 +188,7 @@ void build_host_levels(ecs_ctx *C) {
 }
 
 // ------------------------------------------------------ workspace plan
-size_t plan_hierarchy(ecs_ctx *C, char *base) {
-  Carver cv(base);
+size_t plan_layout(ecs_ctx *C, Carver &cv) {
   const bool f32 = C->prec.vcycle_dtype == ECS_F32;
   for (int a = 0; a < C->dim; a++) {
     C->Acm[a] = cv.take<cplx<double>>(C->hl[0].n[a]);
@@ -233,6 +236,22 @@ size_t plan_hierarchy(ecs_ctx *C, char *base) {
   C->bs = cv.take<BicgScalars>(1);
   C->bs_in = cv.take<BicgScalars>(1);
   return cv.off;
+}
+
+// Lays out the hierarchy in the workspace.  With a null base only the size
+// is measured and the context's device pointers are left untouched.
+size_t plan_hierarchy(ecs_ctx *C, char *base) {
+  if (!base) {
+    ecs_ctx probe;
+    probe.dim = C->dim;
+    probe.nlev = C->nlev;
+    probe.prec = C->prec;
+    probe.hl = C->hl;
+    Carver cv(nullptr);
+    return plan_layout(&probe, cv);
+  }
+  Carver cv(base);
+  return plan_layout(C, cv);
 }
 
 // Krylov storage laid out after the hierarchy
@@ -293,8 +312,9 @@ struct TimedScope {
   ecs_ctx *C;
   Timer *T;
   size_t slot = SIZE_MAX;
-  TimedScope(ecs_ctx *c, int cls) : C(c), T(&c->timers[cls]) {
+  TimedScope(ecs_ctx *c, int cls, double bytes) : C(c), T(&c->timers[cls]) {
     if (!T->on) return;
+    T->bytes += bytes;
     if (T->used + 2 > T->ev.size()) {
       if (T->ev.size() >= 2 * 65536) return;
       size_t old = T->ev.size();
@@ -308,7 +328,6 @@ struct TimedScope {
   ~TimedScope() {
     if (slot == SIZE_MAX) return;
     (void)hipEventRecord(T->ev[slot + 1], C->stream);
-    T->launches++;
   }
 };
 
@@ -548,8 +567,9 @@ void smooth(ecs_ctx *C, int l, const cplx<R> *b, cplx<R> *u, cplx<R> *t, int nsw
   const R om = (R)C->prec.omega;
   const int64_t nn = C->hl[l].nn;
   for (int q = 0; q < nsweeps; q++) {
-    TimedScope ts(C, l == 0 ? 0 : 3);
     bool zg = zero_guess && q == 0;
+    // algorithmic bytes of one sweep: read u, b, k^2, write u (a zero guess skips u)
+    TimedScope ts(C, l == 0 ? kTSmooth : kTCoarse, (double)nn * sizeof(R) * (zg ? 5 : 7));
     if (C->prec.smoother == ECS_SMOOTH_JACOBI) {
       launch_jacobi<R>(g, b, u, t, om, zg, C->stream);
       (void)hipMemcpyAsync(u, t, nn * sizeof(cplx<R>), hipMemcpyDeviceToDevice, C->stream);
@@ -580,7 +600,9 @@ void mg(ecs_ctx *C, int l, const cplx<R> *b, cplx<R> *u, int gf, int gc, bool ze
   DevLevel<R> &Dc = dev_level<R>(C, l + 1);
   smooth<R>(C, l, b, u, D.t, C->prec.nu1, zero_guess);
   {
-    TimedScope ts(C, l == 0 ? 0 : 3);
+    // read b, u, k^2, write the coarse residual
+    const double per = 5.0 + 2.0 / (C->dim == 3 ? 8 : 4);
+    TimedScope ts(C, l == 0 ? kTRestrict : kTCoarse, (double)C->hl[l].nn * sizeof(R) * per);
     launch_residual_restrict<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, u, Dc.b, C->stream);
   }
   if (l + 1 == lc) {
@@ -592,10 +614,48 @@ void mg(ecs_ctx *C, int l, const cplx<R> *b, cplx<R> *u, int gf, int gc, bool ze
     }
   }
   {
-    TimedScope ts(C, l == 0 ? 0 : 3);
+    // read u and the coarse correction, write u
+    const double per = 4.0 + 2.0 / (C->dim == 3 ? 8 : 4);
+    TimedScope ts(C, l == 0 ? kTProlong : kTCoarse, (double)C->hl[l].nn * sizeof(R) * per);
     launch_prolong_add<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), Dc.u, u, C->stream);
   }
   smooth<R>(C, l, b, u, D.t, C->prec.nu2, false);
+}
+
+// V(1,1) red-black in 2D (the QD set-up of Sec. 4.2) runs on the fused
+// kernels: one down and one up kernel per level.
+bool fused_vcycle(const ecs_ctx *C) {
+  const ecs_prec_desc &P = C->prec;
+  return C->dim == 2 && P.smoother == ECS_SMOOTH_RBGS && P.nu1 == 1 && P.nu2 == 1 && P.gamma_f == 1 &&
+         P.gamma_c == 1 && C->nlev > 1;
+}
+
+template <typename R>
+void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
+  const int lc = C->nlev - 1;
+  const R om = (R)C->prec.omega;
+  for (int l = 0; l < lc; l++) {
+    DevLevel<R> &D = dev_level<R>(C, l);
+    DevLevel<R> &Dc = dev_level<R>(C, l + 1);
+    const cplx<R> *b = l == 0 ? b0 : D.b;
+    // reads b, k^2; writes u and the coarse residual
+    TimedScope ts(C, l == 0 ? kTDown : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 5.5);
+    launch_down_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.b, om, C->stream);
+  }
+  {
+    DevLevel<R> &Dc = dev_level<R>(C, lc);
+    TimedScope ts(C, kTCoarse, 0.0);
+    coarse_solve<R>(C, Dc.b, Dc.u);
+  }
+  for (int l = lc - 1; l >= 0; l--) {
+    DevLevel<R> &D = dev_level<R>(C, l);
+    DevLevel<R> &Dc = dev_level<R>(C, l + 1);
+    const cplx<R> *b = l == 0 ? b0 : D.b;
+    cplx<R> *out = l == 0 ? u0 : D.u;
+    // reads u, the coarse correction, b, k^2; writes u
+    TimedScope ts(C, l == 0 ? kTUp : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 7.5);
+    launch_up_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.u, out, om, C->stream);
+  }
 }
 
 // z = M^{-1} v approximately: one cycle from zero on the finest level
@@ -603,6 +663,10 @@ template <typename R>
 void vcycle(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
   if (C->nlev == 1) {
     coarse_solve<R>(C, b0, u0);
+    return;
+  }
+  if (fused_vcycle(C)) {
+    vcycle_fused<R>(C, b0, u0);
     return;
   }
   mg<R>(C, 0, b0, u0, C->prec.gamma_f, C->prec.gamma_c, true);
@@ -689,12 +753,16 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
     return ECS_OK;
   }
   HIP_OK(hipMemcpyAsync(&S->bnorm, &bnorm, sizeof(double), hipMemcpyHostToDevice, s));
+  if (d->inner > 0) {  // the inner iteration has no stopping test: unit reference norm
+    const double unit = 1.0;
+    HIP_OK(hipMemcpyAsync(&C->bs_in->bnorm, &unit, sizeof(double), hipMemcpyHostToDevice, s));
+  }
   if (!d->x_is_guess) launch_zero<double>(x, n, s);
   int it = 0;
   ecs_status status = ECS_NOT_CONVERGED;
   for (;;) {
     {
-      TimedScope ts(C, 2);
+      TimedScope ts(C, kTApply, (double)n * 56);
       launch_residual<double>(grid_A(C), b, x, K.V, s);
     }
     launch_nrm2sq<double>(K.V, n, C->partials, &S->nrm2, s);
@@ -702,7 +770,10 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
     launch_scale_dev(K.V, n, &S->inv, s);
     double rt = read_scalar(C, &S->resid_true);
     st->rel_residual = rt;
-    if (!(rt == rt) || std::isinf(rt)) { status = ECS_EBREAKDOWN; break; }
+    if (!(rt == rt) || std::isinf(rt)) {
+      status = fail(C, ECS_EBREAKDOWN, "GMRES: residual is NaN/Inf");
+      break;
+    }
     if (rt <= d->rtol) { status = ECS_OK; break; }
     if (it >= d->maxit) { status = ECS_NOT_CONVERGED; break; }
     int k = 0;
@@ -716,14 +787,19 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
       st->vcycles += d->inner > 0 ? 2 * d->inner : 1;
       st->inner_iterations += d->inner;
       {
-        TimedScope ts(C, 2);
+        TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 24));
         launch_apply<double, RZ, double>(grid_A(C), zj, w, s);
       }
       {
-        TimedScope ts(C, 1);
-        launch_mdot<double, double>(K.V, ld, j + 1, w, n, C->partials, S->H + (int64_t)j * (m + 1), s);
-        launch_mupdate(K.V, ld, j + 1, S->H + (int64_t)j * (m + 1), w, n, C->partials, &S->nrm2, s);
+        TimedScope ts(C, kTMdot, (double)n * 16 * (j + 2));  // read v_0..v_j and w
+        launch_mdot_partial<double, double>(K.V, ld, j + 1, w, n, C->partials, s);
       }
+      launch_reduce_cols(C->partials, n, j + 1, S->H + (int64_t)j * (m + 1), s);
+      {
+        TimedScope ts(C, kTMupdate, (double)n * 16 * (j + 3));  // read v_0..v_j, w; write w
+        launch_mupdate_partial(K.V, ld, j + 1, S->H + (int64_t)j * (m + 1), w, n, C->partials, s);
+      }
+      launch_reduce_cols(C->partials, n, 1, &S->nrm2, s);
       launch_gmres_givens(S, j, m, s);
       launch_scale_dev(w, n, &S->inv, s);
       it++;
@@ -738,7 +814,10 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
       if (!(est == est) || std::isinf(est)) { bad = true; break; }
       if (est <= d->rtol || happy) break;
     }
-    if (bad) { status = ECS_EBREAKDOWN; break; }
+    if (bad) {
+      status = fail(C, ECS_EBREAKDOWN, "GMRES: Givens residual estimate is NaN/Inf");
+      break;
+    }
     launch_gmres_backsolve(S, k, m, s);
     if (flexible) {
       launch_lincomb<RZ>(Z, ld, k, S->y, x, n, s);
@@ -779,17 +858,23 @@ ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, co
   ecs_status status = ECS_NOT_CONVERGED;
   for (;;) {
     {
-      TimedScope ts(C, 2);
+      TimedScope ts(C, kTApply, (double)n * 56);
       launch_residual<double>(grid_A(C), b, x, K.r, s);
     }
     launch_pairdot<double>(K.r, K.r, nullptr, nullptr, 1, n, C->partials, S, kBicgInit, s);
     double rt = read_scalar(C, &S->est);
     st->rel_residual = rt;
-    if (!(rt == rt) || std::isinf(rt)) { status = ECS_EBREAKDOWN; break; }
+    if (!(rt == rt) || std::isinf(rt)) {
+      status = fail(C, ECS_EBREAKDOWN, "Bi-CGSTAB: residual is NaN/Inf");
+      break;
+    }
     if (rt <= d->rtol) { status = ECS_OK; break; }
     if (it >= d->maxit) { status = ECS_NOT_CONVERGED; break; }
     if (rt >= last_restart) {
-      if (++stalls >= 3) { status = ECS_EBREAKDOWN; break; }
+      if (++stalls >= 3) {
+        status = fail(C, ECS_EBREAKDOWN, "Bi-CGSTAB: no progress over three restarts");
+        break;
+      }
     }
     last_restart = rt;
     (void)hipMemcpyAsync(K.rh, K.r, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, s);
@@ -800,14 +885,14 @@ ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, co
       launch_bicg_p<double>(K.p, K.r, K.v, n, S, s);
       precond<RZ>(C, K.p, ph);
       {
-        TimedScope ts(C, 2);
+        TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 24));
         launch_apply<double, RZ, double>(grid_A(C), ph, K.v, s);
       }
       launch_pairdot<double>(K.rh, K.v, nullptr, nullptr, 1, n, C->partials, S, kBicgAlpha, s);
       launch_bicg_s<double>(K.s, K.r, K.v, n, S, s);
       precond<RZ>(C, K.s, sh);
       {
-        TimedScope ts(C, 2);
+        TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 24));
         launch_apply<double, RZ, double>(grid_A(C), sh, K.tt, s);
       }
       launch_pairdot<double>(K.tt, K.s, K.tt, K.tt, 2, n, C->partials, S, kBicgOmega, s);
@@ -1157,13 +1242,13 @@ ecs_status ecs_level_info(ecs_ctx *C, int level, int *nlevels, int64_t *nodes) {
 }
 
 ecs_status ecs_timing_enable(ecs_ctx *C, int kclass, int enable) {
-  if (!C || kclass < 0 || kclass > 3) return ECS_EINVAL;
+  if (!C || kclass < 0 || kclass >= kTClasses) return ECS_EINVAL;
   C->timers[kclass].on = enable != 0;
   return ECS_OK;
 }
 
-ecs_status ecs_timing_read(ecs_ctx *C, int kclass, int64_t *launches, double *total_ms) {
-  if (!C || kclass < 0 || kclass > 3) return ECS_EINVAL;
+ecs_status ecs_timing_read(ecs_ctx *C, int kclass, int64_t *launches, double *total_ms, double *algo_bytes) {
+  if (!C || kclass < 0 || kclass >= kTClasses) return ECS_EINVAL;
   Timer &T = C->timers[kclass];
   HIP_OK(hipStreamSynchronize(C->stream));
   double tot = 0;
@@ -1174,8 +1259,9 @@ ecs_status ecs_timing_read(ecs_ctx *C, int kclass, int64_t *launches, double *to
   }
   if (launches) *launches = (int64_t)(T.used / 2);
   if (total_ms) *total_ms = tot;
+  if (algo_bytes) *algo_bytes = T.bytes;
   T.used = 0;
-  T.launches = 0;
+  T.bytes = 0;
   return ECS_OK;
 }
 

@@ -200,7 +200,10 @@ __global__ void k_gmres_backsolve(GmresScalars *S, int k, int m) {
   for (int r = k - 1; r >= 0; r--) {
     cplx<double> s = S->g[r];
     for (int c = r + 1; c < k; c++) s = s - S->H[(int64_t)c * (m + 1) + r] * S->y[c];
-    S->y[r] = cdiv(s, S->H[(int64_t)r * (m + 1) + r]);
+    const cplx<double> d = S->H[(int64_t)r * (m + 1) + r];
+    // a zero pivot only arises when the preconditioned vector vanished (w = 0);
+    // that direction then carries no information and gets a zero coefficient
+    S->y[r] = abs2(d) > 0 ? cdiv(s, d) : mk<double>(0, 0);
   }
 }
 
@@ -413,18 +416,18 @@ inline int grid_for(int64_t n) {
 int reduction_blocks(int64_t n) { return red_blocks(n); }
 
 template <typename RA, typename RB>
-void launch_mdot(const cplx<RA> *V, int64_t ldv, int ncols, const cplx<RB> *w, int64_t n, cplx<double> *partials,
-                 cplx<double> *out, hipStream_t s) {
-  int nb = red_blocks(n);
-  hipLaunchKernelGGL((k_mdot<RA, RB>), dim3(nb), dim3(BS), 0, s, V, ldv, ncols, w, n, partials);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(ncols), dim3(BS), 0, s, partials, nb, out);
+void launch_mdot_partial(const cplx<RA> *V, int64_t ldv, int ncols, const cplx<RB> *w, int64_t n,
+                         cplx<double> *partials, hipStream_t s) {
+  hipLaunchKernelGGL((k_mdot<RA, RB>), dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, w, n, partials);
 }
 
-void launch_mupdate(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w, int64_t n,
-                    cplx<double> *partials, cplx<double> *out_norm2, hipStream_t s) {
-  int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_mupdate, dim3(nb), dim3(BS), 0, s, V, ldv, ncols, h, w, n, partials);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(BS), 0, s, partials, nb, out_norm2);
+void launch_reduce_cols(const cplx<double> *partials, int64_t n, int ncols, cplx<double> *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_cols, dim3(ncols), dim3(BS), 0, s, partials, red_blocks(n), out);
+}
+
+void launch_mupdate_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w,
+                            int64_t n, cplx<double> *partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_mupdate, dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, h, w, n, partials);
 }
 
 template <typename R>
@@ -521,8 +524,8 @@ void launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t s) 
   }
 }
 
-template void launch_mdot<double, double>(const cplx<double> *, int64_t, int, const cplx<double> *, int64_t,
-                                          cplx<double> *, cplx<double> *, hipStream_t);
+template void launch_mdot_partial<double, double>(const cplx<double> *, int64_t, int, const cplx<double> *, int64_t,
+                                                  cplx<double> *, hipStream_t);
 template void launch_nrm2sq<double>(const cplx<double> *, int64_t, cplx<double> *, cplx<double> *, hipStream_t);
 template void launch_nrm2sq<float>(const cplx<float> *, int64_t, cplx<double> *, cplx<double> *, hipStream_t);
 template void launch_lincomb<double>(const cplx<double> *, int64_t, int, const cplx<double> *, cplx<double> *, int64_t,

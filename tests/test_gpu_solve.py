@@ -36,9 +36,11 @@ def test_small_constant_k_gmres(beta2):
         assert st["status"] == 0, st
         x = to_np(x)
         assert oracle_resid(P, x, b) <= 1.05e-8
-        xo, sto = P.solve(b, "gmres", 30, 1e-12, 5000)
+        xo, _ = P.solve(b, "gmres", 30, 1e-12, 5000)
         assert relerr(x, xo) < 1e-5
-        assert abs(st["iterations"] - sto["iterations"]) <= max(5, 0.2 * sto["iterations"]) or beta2 > 0
+        # same method, same tolerance: iteration counts agree up to rounding effects
+        _, sto = P.solve(b, "gmres", 30, 1e-8, 5000)
+        assert abs(st["iterations"] - sto["iterations"]) <= max(3, 0.1 * sto["iterations"])
 
 
 @pytest.mark.parametrize("method", ["gmres", "fgmres", "bicgstab"])
@@ -97,6 +99,7 @@ def test_mixed_fgmres_vs_fp64_oracle():
         x, st = S.solve(to_gpu(w.rhs[0]))
         assert st["status"] == 0, (dt, inner, st)
         assert relerr(to_np(x), xo) < 1e-6, (dt, inner)
+        assert st["rel_residual"] <= 1e-12
 
 
 def test_status_paths():
