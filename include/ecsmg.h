@@ -199,6 +199,11 @@ ecs_status ecs_level_info(ecs_ctx *ctx, int level, int *nlevels, int64_t *nodes)
 ecs_status ecs_timing_enable(ecs_ctx *ctx, int kclass, int enable);
 ecs_status ecs_timing_read(ecs_ctx *ctx, int kclass, int64_t *launches, double *total_ms, double *algo_bytes);
 
+/* Replay the V(1,1) red-black cycle from captured HIP graphs (default on):
+ * the cycle is recorded once per (input, output) buffer pair and replayed
+ * with one launch.  0 launches every kernel eagerly (same results). */
+ecs_status ecs_set_graphs(ecs_ctx *ctx, int enable);
+
 /* Batched solve of n independent problems (each context fully set up with its
  * own workspace), all right-hand sides to their rtol with Bi-CGSTAB.  Every
  * iteration of all unconverged systems is issued as one grouped launch per

@@ -98,6 +98,7 @@ def lib():
         "ecs_timing_read": [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D)],
         "ecs_batch_solve": [I, pP, ctypes.POINTER(SolveDesc), pP, pP, ctypes.POINTER(I), ctypes.POINTER(Stats)],
         "ecs_copy_probe": [P, P, Z, P],
+        "ecs_set_graphs": [P, I],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -115,7 +116,7 @@ EXPORTED = ["ecs_create", "ecs_set_ecs", "ecs_set_k2", "ecs_set_precond", "ecs_w
             "ecs_solve", "ecs_solve_adjoint", "ecs_grad_k2", "ecs_apply", "ecs_vcycle", "ecs_smooth",
             "ecs_residual_restrict", "ecs_prolong_correct", "ecs_coarse_solve", "ecs_level_info",
             "ecs_timing_enable", "ecs_timing_read", "ecs_batch_solve", "ecs_copy_probe", "ecs_last_error",
-            "ecs_destroy"]
+            "ecs_destroy", "ecs_set_graphs"]
 
 
 def _torch():
@@ -363,6 +364,10 @@ class Solver:
         x = torch.empty_like(b)
         self._check(lib().ecs_coarse_solve(self._h, _ptr(b), _ptr(x)))
         return x
+
+    def set_graphs(self, enable: bool):
+        """Replay the V(1,1) red-black cycle from captured HIP graphs (default)."""
+        self._check(lib().ecs_set_graphs(self._h, 1 if enable else 0))
 
     # ----------------------------------------------------------- timing
     def timing(self, kclass: str, enable: bool = True):

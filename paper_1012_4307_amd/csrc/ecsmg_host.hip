@@ -109,6 +109,18 @@ struct ecs_ctx {
 
   Timer timers[kTClasses];
   std::string err;
+
+  // replayable V-cycles: one instantiated graph per (input, output, dtype),
+  // captured on a private stream and launched on `stream`
+  struct GraphEntry {
+    const void *b;
+    void *u;
+    int real_bytes;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t capture = nullptr;
+  bool use_graphs = true;
 };
 
 namespace {
@@ -658,6 +670,42 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
   }
 }
 
+void drop_graphs(ecs_ctx *C) {
+  for (auto &g : C->graphs) (void)hipGraphExecDestroy(g.exec);
+  C->graphs.clear();
+}
+
+// The fused cycle is ~2 launches per level; below ~257^2 nodes a level is a
+// few microseconds of work, so host launch overhead would dominate.  The
+// whole cycle is captured once per (input, output) pair and replayed as one
+// graph launch.  Per-kernel timing needs eager launches, so graphs are
+// bypassed while any cycle timer is on.
+template <typename R>
+bool vcycle_graph(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
+  if (!C->use_graphs || C->timers[kTDown].on || C->timers[kTUp].on || C->timers[kTCoarse].on) return false;
+  for (auto &g : C->graphs)
+    if (g.b == b0 && g.u == u0 && g.real_bytes == (int)sizeof(R))
+      return hipGraphLaunch(g.exec, C->stream) == hipSuccess;
+  if (!C->capture && hipStreamCreateWithFlags(&C->capture, hipStreamNonBlocking) != hipSuccess) {
+    C->capture = nullptr;
+    return false;
+  }
+  if (C->graphs.size() >= 256) drop_graphs(C);
+  if (hipStreamBeginCapture(C->capture, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
+  hipStream_t user = C->stream;
+  C->stream = C->capture;
+  vcycle_fused<R>(C, b0, u0);
+  C->stream = user;
+  hipGraph_t graph = nullptr;
+  if (hipStreamEndCapture(C->capture, &graph) != hipSuccess || !graph) return false;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return false;
+  C->graphs.push_back({b0, u0, (int)sizeof(R), exec});
+  return hipGraphLaunch(exec, C->stream) == hipSuccess;
+}
+
 // z = M^{-1} v approximately: one cycle from zero on the finest level
 template <typename R>
 void vcycle(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
@@ -666,7 +714,7 @@ void vcycle(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
     return;
   }
   if (fused_vcycle(C)) {
-    vcycle_fused<R>(C, b0, u0);
+    if (!vcycle_graph<R>(C, b0, u0)) vcycle_fused<R>(C, b0, u0);
     return;
   }
   mg<R>(C, 0, b0, u0, C->prec.gamma_f, C->prec.gamma_c, true);
@@ -1056,6 +1104,7 @@ ecs_status ecs_set_workspace(ecs_ctx *C, void *dev, size_t bytes) {
   hb = (hb + 255) & ~size_t(255);
   KrylovBufs K;
   if (hb + plan_krylov(C, nullptr, nullptr, &K) > bytes) return fail(C, ECS_ENOMEM, "workspace too small");
+  drop_graphs(C);
   C->ws = reinterpret_cast<char *>(dev);
   C->ws_bytes = bytes;
   C->hier_bytes = hb;
@@ -1290,6 +1339,13 @@ ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *de
   return worst;
 }
 
+ecs_status ecs_set_graphs(ecs_ctx *C, int enable) {
+  if (!C) return ECS_EINVAL;
+  C->use_graphs = enable != 0;
+  if (!C->use_graphs) drop_graphs(C);
+  return ECS_OK;
+}
+
 ecs_status ecs_copy_probe(const void *src, void *dst, size_t bytes, void *stream) {
   if (!src || !dst) return ECS_EINVAL;
   launch_copy_bytes(src, dst, bytes, reinterpret_cast<hipStream_t>(stream));
@@ -1300,6 +1356,8 @@ const char *ecs_last_error(const ecs_ctx *C) { return C ? C->err.c_str() : "null
 
 void ecs_destroy(ecs_ctx *C) {
   if (!C) return;
+  drop_graphs(C);
+  if (C->capture) (void)hipStreamDestroy(C->capture);
   for (auto &T : C->timers)
     for (auto &e : T.ev) (void)hipEventDestroy(e);
   if (C->pinned) (void)hipHostFree(C->pinned);

@@ -35,45 +35,53 @@ __device__ __forceinline__ cplx<double> block_sum(cplx<double> v, cplx<double> *
 }
 
 inline int red_blocks(int64_t n) {
-  int64_t b = (n + BS * 4 - 1) / (BS * 4);
+  int64_t b = (n + BS * 16 - 1) / (BS * 16);
   if (b > kRedBlocks) b = kRedBlocks;
   if (b < 1) b = 1;
   return (int)b;
 }
 
 // ----------------------------------------------------------- multi-dot
-// out[c] = sum_p conj(V_c[p]) w[p], c < ncols; columns in chunks of CB per
-// pass, so w is re-read once per chunk.
-constexpr int CB = 8;
+// out[c] = sum_p conj(V_c[p]) w[p], c < ncols.  A block walks tiles of
+// BS * EPT nodes; each thread keeps its EPT entries of w in registers, so w is
+// read once, and every column costs EPT independent loads per thread followed
+// by one wave reduction whose result lane 0 adds to the wave's LDS
+// accumulator.  Fixed order throughout: bitwise reproducible.
+constexpr int EPT = 16;
 
 template <typename RA, typename RB>
 __global__ __launch_bounds__(BS) void k_mdot(const cplx<RA> *__restrict__ V, int64_t ldv, int ncols,
                                              const cplx<RB> *__restrict__ w, int64_t n, cplx<double> *partials) {
-  __shared__ cplx<double> lds[CB][BS / 64];
+  __shared__ cplx<double> acc[BS / 64][kMaxRestart + 2];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int c0 = 0; c0 < ncols; c0 += CB) {
-    cplx<double> acc[CB];
+  for (int c = threadIdx.x; c < (BS / 64) * (kMaxRestart + 2); c += BS) acc[c / (kMaxRestart + 2)][c % (kMaxRestart + 2)] = mk<double>(0, 0);
+  __syncthreads();
+  const int64_t tile = (int64_t)BS * EPT;
+  for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
+    cplx<double> wv[EPT];
 #pragma unroll
-    for (int q = 0; q < CB; q++) acc[q] = mk<double>(0, 0);
-    const int nc = min(CB, ncols - c0);
-    for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) {
-      cplx<double> wp = cvt<double>(w[p]);
-#pragma unroll
-      for (int q = 0; q < CB; q++)
-        if (q < nc) acc[q] = acc[q] + conjg(cvt<double>(V[(int64_t)(c0 + q) * ldv + p])) * wp;
+    for (int e = 0; e < EPT; e++) {
+      const int64_t p = base + e * BS + threadIdx.x;
+      wv[e] = p < n ? cvt<double>(w[p]) : mk<double>(0, 0);
     }
-#pragma unroll
-    for (int q = 0; q < CB; q++) {
-      double re = wave_sum(acc[q].re), im = wave_sum(acc[q].im);
-      if (lane == 0) lds[q][wid] = mk<double>(re, im);
-    }
-    __syncthreads();
-    if (threadIdx.x < nc) {
+    for (int c = 0; c < ncols; c++) {
+      const cplx<RA> *vc = V + (int64_t)c * ldv;
       cplx<double> s = mk<double>(0, 0);
-      for (int v = 0; v < BS / 64; v++) s = s + lds[threadIdx.x][v];
-      partials[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        const int64_t p = base + e * BS + threadIdx.x;
+        if (p < n) s = s + conjg(cvt<double>(vc[p])) * wv[e];
+      }
+      s.re = wave_sum(s.re);
+      s.im = wave_sum(s.im);
+      if (lane == 0) acc[wid][c] = acc[wid][c] + s;
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncols; c += BS) {
+    cplx<double> t = mk<double>(0, 0);
+    for (int q = 0; q < BS / 64; q++) t = t + acc[q][c];
+    partials[(int64_t)c * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -89,7 +97,8 @@ __global__ __launch_bounds__(BS) void k_reduce_cols(const cplx<double> *__restri
   if (threadIdx.x == 0) out[c] = s;
 }
 
-// w <- w - sum_c V_c h_c, and per-block partials of ||w||^2 (in .re)
+// w <- w - sum_c V_c h_c, and per-block partials of ||w||^2 (in .re); same
+// tiling as the multi-dot (w in registers, EPT independent loads per column)
 __global__ __launch_bounds__(BS) void k_mupdate(const cplx<double> *__restrict__ V, int64_t ldv, int ncols,
                                                 const cplx<double> *__restrict__ h, cplx<double> *__restrict__ w,
                                                 int64_t n, cplx<double> *partials) {
@@ -98,11 +107,31 @@ __global__ __launch_bounds__(BS) void k_mupdate(const cplx<double> *__restrict__
   for (int c = threadIdx.x; c < ncols; c += BS) hs[c] = h[c];
   __syncthreads();
   double nrm = 0;
-  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) {
-    cplx<double> acc = w[p];
-    for (int c = 0; c < ncols; c++) acc = acc - V[(int64_t)c * ldv + p] * hs[c];
-    w[p] = acc;
-    nrm += abs2(acc);
+  const int64_t tile = (int64_t)BS * EPT;
+  for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
+    cplx<double> wv[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const int64_t p = base + e * BS + threadIdx.x;
+      wv[e] = p < n ? w[p] : mk<double>(0, 0);
+    }
+    for (int c = 0; c < ncols; c++) {
+      const cplx<double> *vc = V + (int64_t)c * ldv;
+      const cplx<double> hc = hs[c];
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        const int64_t p = base + e * BS + threadIdx.x;
+        if (p < n) wv[e] = wv[e] - vc[p] * hc;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const int64_t p = base + e * BS + threadIdx.x;
+      if (p < n) {
+        w[p] = wv[e];
+        nrm += abs2(wv[e]);
+      }
+    }
   }
   cplx<double> s = block_sum(mk<double>(nrm, 0), lds);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
