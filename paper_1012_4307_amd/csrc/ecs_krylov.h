@@ -8,7 +8,7 @@ namespace ecs {
 
 constexpr int kMaxRestart = 64;
 // reduction kernels use at most this many blocks (partial buffers are sized for it)
-constexpr int kRedBlocks = 512;
+constexpr int kRedBlocks = 2048;
 
 // Scalars of one GMRES / FGMRES solve, kept in device memory.
 struct GmresScalars {

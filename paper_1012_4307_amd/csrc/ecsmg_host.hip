@@ -561,9 +561,13 @@ ecs_status setup(ecs_ctx *C) {
   }
   if (!invert(M, nu)) return fail(C, ECS_EINVAL, "coarsest preconditioner matrix is singular");
   {
+    // the solve kernel reads the inverse column by column (transposed layout)
+    std::vector<cd> MT((size_t)nu * nu);
+    for (int r = 0; r < nu; r++)
+      for (int q = 0; q < nu; q++) MT[(size_t)q * nu + r] = M[(size_t)r * nu + q];
     ecs_status st;
-    if ((st = upload_cx<double>(C, C->minv64, M, 1.0)) != ECS_OK) return st;
-    if (f32 && (st = upload_cx<float>(C, C->minv32, M, 1.0)) != ECS_OK) return st;
+    if ((st = upload_cx<double>(C, C->minv64, MT, 1.0)) != ECS_OK) return st;
+    if (f32 && (st = upload_cx<float>(C, C->minv32, MT, 1.0)) != ECS_OK) return st;
   }
   HIP_OK(hipMemcpy(C->unk, unk.data(), nu * sizeof(int), hipMemcpyHostToDevice));
   HIP_OK(hipStreamSynchronize(s));
@@ -1077,7 +1081,7 @@ ecs_status ecs_set_precond(ecs_ctx *C, const ecs_prec_desc *d) {
   if (nlev > kMaxLev) return fail(C, ECS_EINVAL, "too many levels");
   int nunk = 1;
   for (int a = 0; a < C->dim; a++) nunk *= d->coarsest_nodes - 2;
-  if (nunk > 4096) return fail(C, ECS_EINVAL, "coarsest grid too large for the dense solve (> 4096 unknowns)");
+  if (nunk > 2048) return fail(C, ECS_EINVAL, "coarsest grid too large for the dense solve (> 2048 unknowns)");
   C->prec = *d;
   C->nlev = nlev;
   C->have_prec = true;

@@ -35,7 +35,7 @@ __device__ __forceinline__ cplx<double> block_sum(cplx<double> v, cplx<double> *
 }
 
 inline int red_blocks(int64_t n) {
-  int64_t b = (n + BS * 16 - 1) / (BS * 16);
+  int64_t b = (n + BS * 4 - 1) / (BS * 4);
   if (b > kRedBlocks) b = kRedBlocks;
   if (b < 1) b = 1;
   return (int)b;
@@ -43,18 +43,21 @@ inline int red_blocks(int64_t n) {
 
 // ----------------------------------------------------------- multi-dot
 // out[c] = sum_p conj(V_c[p]) w[p], c < ncols.  A block walks tiles of
-// BS * EPT nodes; each thread keeps its EPT entries of w in registers, so w is
-// read once, and every column costs EPT independent loads per thread followed
-// by one wave reduction whose result lane 0 adds to the wave's LDS
-// accumulator.  Fixed order throughout: bitwise reproducible.
-constexpr int EPT = 16;
+// BS * EPT nodes; each thread keeps its EPT entries of w in registers (w is
+// read once) and treats the columns in groups of CG, so CG * EPT independent
+// loads are in flight per thread.  Each column's tile sum is wave-reduced and
+// lane 0 adds it to the wave's LDS accumulator; fixed order throughout, so
+// the result is bitwise reproducible.
+constexpr int EPT = 4;
+constexpr int CG = 4;
 
 template <typename RA, typename RB>
 __global__ __launch_bounds__(BS) void k_mdot(const cplx<RA> *__restrict__ V, int64_t ldv, int ncols,
                                              const cplx<RB> *__restrict__ w, int64_t n, cplx<double> *partials) {
-  __shared__ cplx<double> acc[BS / 64][kMaxRestart + 2];
+  constexpr int LDA = kMaxRestart + 2;
+  __shared__ cplx<double> acc[BS / 64][LDA];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int c = threadIdx.x; c < (BS / 64) * (kMaxRestart + 2); c += BS) acc[c / (kMaxRestart + 2)][c % (kMaxRestart + 2)] = mk<double>(0, 0);
+  for (int c = threadIdx.x; c < (BS / 64) * LDA; c += BS) acc[c / LDA][c % LDA] = mk<double>(0, 0);
   __syncthreads();
   const int64_t tile = (int64_t)BS * EPT;
   for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
@@ -64,17 +67,27 @@ __global__ __launch_bounds__(BS) void k_mdot(const cplx<RA> *__restrict__ V, int
       const int64_t p = base + e * BS + threadIdx.x;
       wv[e] = p < n ? cvt<double>(w[p]) : mk<double>(0, 0);
     }
-    for (int c = 0; c < ncols; c++) {
-      const cplx<RA> *vc = V + (int64_t)c * ldv;
-      cplx<double> s = mk<double>(0, 0);
+    for (int c0 = 0; c0 < ncols; c0 += CG) {
+      cplx<double> sg[CG];
 #pragma unroll
-      for (int e = 0; e < EPT; e++) {
-        const int64_t p = base + e * BS + threadIdx.x;
-        if (p < n) s = s + conjg(cvt<double>(vc[p])) * wv[e];
+      for (int g = 0; g < CG; g++) {
+        sg[g] = mk<double>(0, 0);
+        if (c0 + g < ncols) {
+          const cplx<RA> *vc = V + (int64_t)(c0 + g) * ldv;
+#pragma unroll
+          for (int e = 0; e < EPT; e++) {
+            const int64_t p = base + e * BS + threadIdx.x;
+            if (p < n) sg[g] = sg[g] + conjg(cvt<double>(vc[p])) * wv[e];
+          }
+        }
       }
-      s.re = wave_sum(s.re);
-      s.im = wave_sum(s.im);
-      if (lane == 0) acc[wid][c] = acc[wid][c] + s;
+#pragma unroll
+      for (int g = 0; g < CG; g++) {
+        if (c0 + g < ncols) {
+          double re = wave_sum(sg[g].re), im = wave_sum(sg[g].im);
+          if (lane == 0) acc[wid][c0 + g] = acc[wid][c0 + g] + mk<double>(re, im);
+        }
+      }
     }
   }
   __syncthreads();
@@ -98,7 +111,7 @@ __global__ __launch_bounds__(BS) void k_reduce_cols(const cplx<double> *__restri
 }
 
 // w <- w - sum_c V_c h_c, and per-block partials of ||w||^2 (in .re); same
-// tiling as the multi-dot (w in registers, EPT independent loads per column)
+// tiling as the multi-dot
 __global__ __launch_bounds__(BS) void k_mupdate(const cplx<double> *__restrict__ V, int64_t ldv, int ncols,
                                                 const cplx<double> *__restrict__ h, cplx<double> *__restrict__ w,
                                                 int64_t n, cplx<double> *partials) {
@@ -115,13 +128,18 @@ __global__ __launch_bounds__(BS) void k_mupdate(const cplx<double> *__restrict__
       const int64_t p = base + e * BS + threadIdx.x;
       wv[e] = p < n ? w[p] : mk<double>(0, 0);
     }
-    for (int c = 0; c < ncols; c++) {
-      const cplx<double> *vc = V + (int64_t)c * ldv;
-      const cplx<double> hc = hs[c];
+    for (int c0 = 0; c0 < ncols; c0 += CG) {
 #pragma unroll
-      for (int e = 0; e < EPT; e++) {
-        const int64_t p = base + e * BS + threadIdx.x;
-        if (p < n) wv[e] = wv[e] - vc[p] * hc;
+      for (int g = 0; g < CG; g++) {
+        if (c0 + g < ncols) {
+          const cplx<double> *vc = V + (int64_t)(c0 + g) * ldv;
+          const cplx<double> hc = hs[c0 + g];
+#pragma unroll
+          for (int e = 0; e < EPT; e++) {
+            const int64_t p = base + e * BS + threadIdx.x;
+            if (p < n) wv[e] = wv[e] - vc[p] * hc;
+          }
+        }
       }
     }
 #pragma unroll

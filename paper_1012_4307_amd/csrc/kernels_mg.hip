@@ -223,26 +223,31 @@ __global__ __launch_bounds__(256) void k_prolong_add(Grid<R> f, Grid<R> c, const
   u[q.p] = u[q.p] + e;
 }
 
-// x = M_C^{-1} b on the coarsest level from the precomputed dense inverse
-// (row-major nunk x nunk); unk maps an unknown to its node index.  Thread t
-// writes the t-th unknown and, if node t is a boundary node, its zero.
+// x = M_C^{-1} b on the coarsest level from the precomputed dense inverse,
+// stored transposed (minvT[c * nunk + r] = Minv[r][c]) so that the threads of
+// a wave read consecutive entries; b's unknowns are first staged in LDS.
+// Thread t writes the t-th unknown and, if node t is a boundary node, its zero.
+// One block of 1024 threads (nunk <= 2048 unknowns).
 template <typename R>
-__global__ __launch_bounds__(256) void k_coarse_solve(int nunk, const cplx<R> *__restrict__ minv,
-                                                      const int *__restrict__ unk, int n0, int n1, int n2,
-                                                      const cplx<R> *__restrict__ b, cplx<R> *__restrict__ x) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int nn = n0 * n1 * n2;
-  if (t < nn) {
-    int i = t % n0, j = (t / n0) % n1, k = t / (n0 * n1);
-    bool zin = n2 == 1 || (k >= 1 && k <= n2 - 2);
-    bool interior = i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && zin;
+__global__ __launch_bounds__(1024) void k_coarse_solve(int nunk, const cplx<R> *__restrict__ minvT,
+                                                       const int *__restrict__ unk, int n0, int n1, int n2,
+                                                       const cplx<R> *__restrict__ b, cplx<R> *__restrict__ x) {
+  __shared__ cplx<R> sb[2048];
+  const int nn = n0 * n1 * n2;
+  for (int t = threadIdx.x; t < nunk; t += blockDim.x) sb[t] = b[unk[t]];
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+    const int i = t % n0, j = (t / n0) % n1, k = t / (n0 * n1);
+    const bool zin = n2 == 1 || (k >= 1 && k <= n2 - 2);
+    const bool interior = i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && zin;
     if (!interior) x[t] = mk<R>(0, 0);
   }
-  if (t >= nunk) return;
-  cplx<R> acc = mk<R>(0, 0);
-  const cplx<R> *row = minv + (int64_t)t * nunk;
-  for (int c = 0; c < nunk; c++) acc = acc + row[c] * b[unk[c]];
-  x[unk[t]] = acc;
+  __syncthreads();
+  for (int r = threadIdx.x; r < nunk; r += blockDim.x) {
+    cplx<R> acc = mk<R>(0, 0);
+#pragma unroll 8
+    for (int c = 0; c < nunk; c++) acc = acc + minvT[(int64_t)c * nunk + r] * sb[c];
+    x[unk[r]] = acc;
+  }
 }
 
 template <typename R>
@@ -292,9 +297,7 @@ void launch_prolong_add(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R
 template <typename R>
 void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, int n1, int n2, const cplx<R> *b,
                          cplx<R> *x, hipStream_t s) {
-  int nn = n0 * n1 * n2;
-  int nb = ((nn > nunk ? nn : nunk) + 255) / 256;
-  hipLaunchKernelGGL((k_coarse_solve<R>), dim3(nb), dim3(256), 0, s, nunk, minv, unk, n0, n1, n2, b, x);
+  hipLaunchKernelGGL((k_coarse_solve<R>), dim3(1), dim3(1024), 0, s, nunk, minv, unk, n0, n1, n2, b, x);
 }
 template <typename R>
 void launch_inject_k2(int n0, int n1, int n2, const double *k2_fine, int f0, int f1, R *k2_coarse, hipStream_t s) {

@@ -29,173 +29,247 @@ __device__ __forceinline__ cplx<R> zero_c() {
   return mk<R>(0, 0);
 }
 
+// Both kernels first issue every global load of the block (register arrays
+// of PER entries per thread, unrolled, so all are in flight together) and
+// stage the tile's 1D weights in LDS.  A thread keeps the values of its own
+// nodes (b, the inverse diagonal, its iterate) in registers across the phases;
+// only the iterate and the residual, which neighbours read, go through LDS.
+//
+// With M u = D u - o(u), o the off-diagonal part, a red-black sweep relaxes
+// u_p <- (1 - w) u_p + w (b_p + o_p) / D_p.  From a zero guess the residual
+// after the sweep is (1 - w) b + o at red nodes (o from the relaxed black
+// neighbours) and (1 - w)(b + o) at black nodes (o from the red ones), so the
+// diagonal is never multiplied back.
+
+template <typename R>
+__device__ __forceinline__ cplx<R> inv_c(cplx<R> d) {
+  const R s = R(1) / abs2(d);
+  return mk<R>(d.re * s, -d.im * s);
+}
+
 // ----------------------------------------------------------------- down
-// Block tile: CX x CY coarse nodes starting at (I0, J0); owned fine nodes are
-// [2 I0, 2 I0 + 2 CX) x [2 J0, 2 J0 + 2 CY).  Staged region: fine x in
-// [2 I0 - 3, 2 I0 + 2 CX + 1], y likewise (halo 3 on the low side, 2 on the
-// high side; the residual of the FW stencil at the tile's last coarse node
-// reaches 2 I0 + 2 CX - 1, its relaxed neighbourhood 2 I0 + 2 CX, and the red
-// values that feed it 2 I0 + 2 CX + 1).
-template <typename R, int CX, int CY>
+// One lane per tile column (64 lanes = the tile width, so the x index, the x
+// weights and the x bounds test are per-thread constants), the 4 waves of the
+// block take every fourth tile row.  Block tile: CX = 29 coarse columns x CY
+// coarse rows from (I0, J0); owned fine nodes [2 I0, 2 I0 + 58) x
+// [2 J0, 2 J0 + 2 CY).  Staged fine region: columns 2 I0 - 3 + [0, 63) (lane
+// 63 idles), rows 2 J0 - 3 + [0, 2 CY + 5): halo 3 below, 2 above, because
+// the FW stencil of the tile's coarse nodes reads residuals one node out, a
+// residual reads the relaxed iterate one further out, and a relaxed black node
+// reads red values one further still.
+template <typename R, int CY>
 __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
                                                 cplx<R> *__restrict__ u_out, cplx<R> *__restrict__ rc, R omega) {
-  constexpr int WX = 2 * CX + 5, WY = 2 * CY + 5;
-  constexpr int NR = WX * WY;
-  __shared__ cplx<R> sb[NR];   // b, then the residual
-  __shared__ cplx<R> sd[NR];   // diagonal of M
-  __shared__ cplx<R> su[NR];   // relaxed iterate
+  constexpr int CX = 29;
+  constexpr int WX = 2 * CX + 5;          // 63 used columns
+  constexpr int WY = 2 * CY + 5;
+  constexpr int RPW = (WY + 3) / 4;       // rows per wave
+  __shared__ cplx<R> su[WY][64];          // relaxed iterate
+  __shared__ cplx<R> sr[WY][64];          // residual
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int I0 = blockIdx.x * CX, J0 = blockIdx.y * CY;
   const int gx0 = 2 * I0 - 3, gy0 = 2 * J0 - 3;
   const int n0 = f.n0, n1 = f.n1;
+  const R om1 = R(1) - omega;
+  const int i = gx0 + lane;
+  const bool xin = lane < WX && i >= 1 && i <= n0 - 2;
+  const cplx<R> cxm = xin ? f.cm0[i] : zero_c<R>();
+  const cplx<R> cxp = xin ? f.cp0[i] : zero_c<R>();
 
-  // stage b and the diagonal; mark the red iterate omega b / D
-  for (int q = threadIdx.x; q < NR; q += NT) {
-    const int lx = q % WX, ly = q / WX;
-    const int i = gx0 + lx, j = gy0 + ly;
-    cplx<R> bv = zero_c<R>(), dv = mk<R>(1, 0), uv = zero_c<R>();
-    if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
+  cplx<R> bv[RPW], iv[RPW], cym[RPW], cyp[RPW];
+  R kv[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; r++) {
+    const int ly = wv + 4 * r;
+    const int j = gy0 + ly;
+    const bool yin = ly < WY && j >= 1 && j <= n1 - 2;
+    bv[r] = zero_c<R>();
+    kv[r] = R(0);
+    cym[r] = yin ? f.cm1[j] : zero_c<R>();
+    cyp[r] = yin ? f.cp1[j] : zero_c<R>();
+    if (xin && yin) {
       const int64_t p = (int64_t)j * n0 + i;
-      bv = b[p];
-      dv = f.cm0[i] + f.cp0[i] + f.cm1[j] + f.cp1[j] + (f.k2[p] * f.beta + f.c);
-      if (((i + j) & 1) == 0) uv = omega * cdiv(bv, dv);
+      bv[r] = b[p];
+      kv[r] = f.k2[p];
     }
-    sb[q] = bv;
-    sd[q] = dv;
-    su[q] = uv;
+  }
+  // inverse diagonal; red iterate omega b / D (zero guess), black 0
+#pragma unroll
+  for (int r = 0; r < RPW; r++) {
+    const int ly = wv + 4 * r;
+    if (ly >= WY) break;
+    const int j = gy0 + ly;
+    const bool in = xin && j >= 1 && j <= n1 - 2;
+    iv[r] = in ? inv_c(cxm + cxp + cym[r] + cyp[r] + (kv[r] * f.beta + f.c)) : zero_c<R>();
+    su[ly][lane] = (in && ((i + j) & 1) == 0) ? omega * (bv[r] * iv[r]) : zero_c<R>();
   }
   __syncthreads();
-  // black relaxation from the red values (zero guess: u_b = omega (b + offd) / D)
-  for (int q = threadIdx.x; q < NR; q += NT) {
-    const int lx = q % WX, ly = q / WX;
-    const int i = gx0 + lx, j = gy0 + ly;
-    if (lx < 1 || lx > WX - 2 || ly < 1 || ly > WY - 2) continue;
-    if (i < 1 || i > n0 - 2 || j < 1 || j > n1 - 2 || ((i + j) & 1) == 0) continue;
-    cplx<R> o = f.cm0[i] * su[q - 1] + f.cp0[i] * su[q + 1] + f.cm1[j] * su[q - WX] + f.cp1[j] * su[q + WX];
-    su[q] = omega * cdiv(sb[q] + o, sd[q]);
+  // black relaxation; black residual (1 - w)(b + o)
+  const bool xmid = lane >= 1 && lane <= WX - 2;
+#pragma unroll
+  for (int r = 0; r < RPW; r++) {
+    const int ly = wv + 4 * r;
+    if (ly >= WY) break;
+    const int j = gy0 + ly;
+    if (!xmid || ly < 1 || ly > WY - 2 || !xin || j < 1 || j > n1 - 2 || ((i + j) & 1) == 0) continue;
+    const cplx<R> tb = bv[r] + (cxm * su[ly][lane - 1] + cxp * su[ly][lane + 1] + cym[r] * su[ly - 1][lane] +
+                                cyp[r] * su[ly + 1][lane]);
+    su[ly][lane] = omega * (tb * iv[r]);
+    sr[ly][lane] = om1 * tb;
   }
   __syncthreads();
-  // residual r = b - M u on the interior (stored over b), 0 elsewhere; write u
-  for (int q = threadIdx.x; q < NR; q += NT) {
-    const int lx = q % WX, ly = q / WX;
-    const int i = gx0 + lx, j = gy0 + ly;
-    if (lx < 1 || lx > WX - 2 || ly < 1 || ly > WY - 2) continue;
-    cplx<R> r = zero_c<R>();
-    if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
-      cplx<R> o = f.cm0[i] * su[q - 1] + f.cp0[i] * su[q + 1] + f.cm1[j] * su[q - WX] + f.cp1[j] * su[q + WX];
-      r = sb[q] - (sd[q] * su[q] - o);
+  // red residual (1 - w) b + o, zero off the interior; write the owned iterate
+#pragma unroll
+  for (int r = 0; r < RPW; r++) {
+    const int ly = wv + 4 * r;
+    if (ly >= WY) break;
+    const int j = gy0 + ly;
+    if (!xmid || ly < 1 || ly > WY - 2) continue;
+    const bool in = xin && j >= 1 && j <= n1 - 2;
+    if (!in) {
+      sr[ly][lane] = zero_c<R>();
+    } else if (((i + j) & 1) == 0) {
+      sr[ly][lane] = om1 * bv[r] + (cxm * su[ly][lane - 1] + cxp * su[ly][lane + 1] + cym[r] * su[ly - 1][lane] +
+                                    cyp[r] * su[ly + 1][lane]);
     }
-    // owned fine nodes: local [3, 3 + 2 CX) x [3, 3 + 2 CY)
-    if (lx >= 3 && lx < 3 + 2 * CX && ly >= 3 && ly < 3 + 2 * CY && i < n0 && j < n1)
-      u_out[(int64_t)j * n0 + i] = su[q];
-    sb[q] = r;  // each thread overwrites only its own node; other threads read su only
+    if (lane >= 3 && lane < 3 + 2 * CX && ly >= 3 && ly < 3 + 2 * CY && i < n0 && j < n1)
+      u_out[(int64_t)j * n0 + i] = su[ly][lane];
   }
   __syncthreads();
-  // full weighting onto the owned coarse nodes
-  for (int q = threadIdx.x; q < CX * CY; q += NT) {
-    const int cx = q % CX, cy = q / CX;
-    const int I = I0 + cx, J = J0 + cy;
-    if (I >= c.n0 || J >= c.n1) continue;
-    cplx<R> acc = zero_c<R>();
-    if (I >= 1 && I <= c.n0 - 2 && J >= 1 && J <= c.n1 - 2) {
-      const int lc = (3 + 2 * cy) * WX + (3 + 2 * cx);
-      acc = R(0.25) * sb[lc] +
-            R(0.125) * (sb[lc - 1] + sb[lc + 1] + sb[lc - WX] + sb[lc + WX]) +
-            R(0.0625) * (sb[lc - WX - 1] + sb[lc - WX + 1] + sb[lc + WX - 1] + sb[lc + WX + 1]);
+  // full weighting onto the owned coarse nodes: lane = coarse column
+  if (lane < CX) {
+    const int I = I0 + lane;
+    for (int cy = wv; cy < CY; cy += 4) {
+      const int J = J0 + cy;
+      if (I >= c.n0 || J >= c.n1) continue;
+      cplx<R> acc = zero_c<R>();
+      if (I >= 1 && I <= c.n0 - 2 && J >= 1 && J <= c.n1 - 2) {
+        const int x = 3 + 2 * lane, y = 3 + 2 * cy;
+        acc = R(0.25) * sr[y][x] + R(0.125) * (sr[y][x - 1] + sr[y][x + 1] + sr[y - 1][x] + sr[y + 1][x]) +
+              R(0.0625) * (sr[y - 1][x - 1] + sr[y - 1][x + 1] + sr[y + 1][x - 1] + sr[y + 1][x + 1]);
+      }
+      rc[(int64_t)J * c.n0 + I] = acc;
     }
-    rc[(int64_t)J * c.n0 + I] = acc;
   }
 }
 
 // ------------------------------------------------------------------- up
-// Block tile: TX x TY fine nodes at (x0, y0) with x0, y0 even.  Staged: the
-// corrected iterate v = u + P ec on [x0 - 2, x0 + TX + 1] (halo 2: red nodes
-// one outside the tile are relaxed, and read black neighbours two outside),
-// b and D on the same region, the coarse correction under it.
-template <typename R, int TX, int TY>
+// Same layout: lane = tile column.  Block tile: 60 x TY fine nodes at
+// (x0, y0), both even; staged fine region: columns x0 - 2 + [0, 64), rows
+// y0 - 2 + [0, TY + 4) (halo 2: red nodes one outside the tile are relaxed
+// and read black neighbours two outside), and the coarse correction under it.
+template <typename R, int TY>
 __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
                                               const cplx<R> *__restrict__ u_in, const cplx<R> *__restrict__ ec,
                                               cplx<R> *__restrict__ u_out, R omega) {
-  constexpr int WX = TX + 4, WY = TY + 4;
-  constexpr int NR = WX * WY;
+  constexpr int TX = 60;
+  constexpr int WY = TY + 4;
+  constexpr int RPW = (WY + 3) / 4;
   constexpr int CWX = TX / 2 + 3, CWY = TY / 2 + 3;
-  __shared__ cplx<R> sv[NR];
-  __shared__ cplx<R> sb[NR];
-  __shared__ cplx<R> sd[NR];
-  __shared__ cplx<R> se[CWX * CWY];
+  __shared__ cplx<R> sv[WY][64];
+  __shared__ cplx<R> se[CWY][CWX];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
   const int gx0 = x0 - 2, gy0 = y0 - 2;
   const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1;  // coarse staging origin
   const int n0 = f.n0, n1 = f.n1;
+  const R om1 = R(1) - omega;
+  const int i = gx0 + lane;
+  const bool xin = i >= 1 && i <= n0 - 2;
+  const cplx<R> cxm = xin ? f.cm0[i] : zero_c<R>();
+  const cplx<R> cxp = xin ? f.cp0[i] : zero_c<R>();
 
-  for (int q = threadIdx.x; q < CWX * CWY; q += NT) {
-    const int I = cx0 + q % CWX, J = cy0 + q / CWX;
-    se[q] = (I >= 0 && I < c.n0 && J >= 0 && J < c.n1) ? ec[(int64_t)J * c.n0 + I] : zero_c<R>();
+  cplx<R> vv[RPW], bv[RPW], iv[RPW], cym[RPW], cyp[RPW];
+  R kv[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; r++) {
+    const int ly = wv + 4 * r;
+    const int j = gy0 + ly;
+    const bool yin = ly < WY && j >= 1 && j <= n1 - 2;
+    vv[r] = zero_c<R>();
+    bv[r] = zero_c<R>();
+    kv[r] = R(0);
+    cym[r] = yin ? f.cm1[j] : zero_c<R>();
+    cyp[r] = yin ? f.cp1[j] : zero_c<R>();
+    if (xin && yin) {
+      const int64_t p = (int64_t)j * n0 + i;
+      vv[r] = u_in[p];
+      bv[r] = b[p];
+      kv[r] = f.k2[p];
+    }
+  }
+  if (lane < CWX) {
+    const int I = cx0 + lane;
+    for (int cy = wv; cy < CWY; cy += 4) {
+      const int J = cy0 + cy;
+      se[cy][lane] = (I >= 0 && I < c.n0 && J >= 0 && J < c.n1) ? ec[(int64_t)J * c.n0 + I] : zero_c<R>();
+    }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < NR; q += NT) {
-    const int lx = q % WX, ly = q / WX;
-    const int i = gx0 + lx, j = gy0 + ly;
-    cplx<R> v = zero_c<R>(), bv = zero_c<R>(), dv = mk<R>(1, 0);
-    if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
-      const int64_t p = (int64_t)j * n0 + i;
-      // bilinear interpolation in index space from the staged coarse tile
-      const int I = i >> 1, J = j >> 1;
-      const int ci = I - cx0, cj = J - cy0;
-      const cplx<R> *e = se + cj * CWX + ci;
+  // v = u + P ec (bilinear in index space) and the inverse diagonal
+  const int ci = (i >> 1) - cx0;
+#pragma unroll
+  for (int r = 0; r < RPW; r++) {
+    const int ly = wv + 4 * r;
+    if (ly >= WY) break;
+    const int j = gy0 + ly;
+    const bool in = xin && j >= 1 && j <= n1 - 2;
+    iv[r] = zero_c<R>();
+    if (in) {
+      const int cj = (j >> 1) - cy0;
       cplx<R> pe;
-      if ((i & 1) == 0 && (j & 1) == 0) pe = e[0];
-      else if ((j & 1) == 0) pe = R(0.5) * (e[0] + e[1]);
-      else if ((i & 1) == 0) pe = R(0.5) * (e[0] + e[CWX]);
-      else pe = R(0.25) * (e[0] + e[1] + e[CWX] + e[CWX + 1]);
-      v = u_in[p] + pe;
-      bv = b[p];
-      dv = f.cm0[i] + f.cp0[i] + f.cm1[j] + f.cp1[j] + (f.k2[p] * f.beta + f.c);
+      if ((i & 1) == 0 && (j & 1) == 0) pe = se[cj][ci];
+      else if ((j & 1) == 0) pe = R(0.5) * (se[cj][ci] + se[cj][ci + 1]);
+      else if ((i & 1) == 0) pe = R(0.5) * (se[cj][ci] + se[cj + 1][ci]);
+      else pe = R(0.25) * (se[cj][ci] + se[cj][ci + 1] + se[cj + 1][ci] + se[cj + 1][ci + 1]);
+      vv[r] = vv[r] + pe;
+      iv[r] = inv_c(cxm + cxp + cym[r] + cyp[r] + (kv[r] * f.beta + f.c));
     }
-    sv[q] = v;
-    sb[q] = bv;
-    sd[q] = dv;
+    sv[ly][lane] = vv[r];
   }
   __syncthreads();
   // red relaxation on the tile plus a one-node ring
-  for (int q = threadIdx.x; q < NR; q += NT) {
-    const int lx = q % WX, ly = q / WX;
-    const int i = gx0 + lx, j = gy0 + ly;
-    if (lx < 1 || lx > WX - 2 || ly < 1 || ly > WY - 2) continue;
-    if (i < 1 || i > n0 - 2 || j < 1 || j > n1 - 2 || ((i + j) & 1) != 0) continue;
-    const cplx<R> u0 = sv[q];
-    cplx<R> o = f.cm0[i] * sv[q - 1] + f.cp0[i] * sv[q + 1] + f.cm1[j] * sv[q - WX] + f.cp1[j] * sv[q + WX];
-    cplx<R> res = sb[q] - (sd[q] * u0 - o);
-    sv[q] = u0 + omega * cdiv(res, sd[q]);
+  const bool xmid = lane >= 1 && lane <= 62;
+#pragma unroll
+  for (int r = 0; r < RPW; r++) {
+    const int ly = wv + 4 * r;
+    if (ly >= WY) break;
+    const int j = gy0 + ly;
+    if (!xmid || ly < 1 || ly > WY - 2 || !xin || j < 1 || j > n1 - 2 || ((i + j) & 1) != 0) continue;
+    const cplx<R> o = cxm * sv[ly][lane - 1] + cxp * sv[ly][lane + 1] + cym[r] * sv[ly - 1][lane] +
+                      cyp[r] * sv[ly + 1][lane];
+    vv[r] = om1 * vv[r] + omega * ((bv[r] + o) * iv[r]);
+    sv[ly][lane] = vv[r];
   }
   __syncthreads();
-  // black relaxation on the owned tile, then write every owned node
-  for (int q = threadIdx.x; q < TX * TY; q += NT) {
-    const int lx = 2 + q % TX, ly = 2 + q / TX;
-    const int i = gx0 + lx, j = gy0 + ly;
-    if (i >= n0 || j >= n1) continue;
-    const int s = ly * WX + lx;
-    cplx<R> out = sv[s];
-    if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 1) {
-      cplx<R> o = f.cm0[i] * sv[s - 1] + f.cp0[i] * sv[s + 1] + f.cm1[j] * sv[s - WX] + f.cp1[j] * sv[s + WX];
-      cplx<R> res = sb[s] - (sd[s] * out - o);
-      out = out + omega * cdiv(res, sd[s]);
+  // black relaxation on the owned tile; write every owned node
+  const bool xown = lane >= 2 && lane < TX + 2 && i < n0;
+#pragma unroll
+  for (int r = 0; r < RPW; r++) {
+    const int ly = wv + 4 * r;
+    if (ly >= WY) break;
+    const int j = gy0 + ly;
+    if (!xown || ly < 2 || ly >= TY + 2 || j >= n1) continue;
+    cplx<R> out = vv[r];
+    if (xin && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 1) {
+      const cplx<R> o = cxm * sv[ly][lane - 1] + cxp * sv[ly][lane + 1] + cym[r] * sv[ly - 1][lane] +
+                        cyp[r] * sv[ly + 1][lane];
+      out = om1 * out + omega * ((bv[r] + o) * iv[r]);
     }
     u_out[(int64_t)j * n0 + i] = out;
   }
 }
 
-// tile shapes: LDS per block stays near 32 KB (FP64) so several blocks share a CU
+// tile heights (coarse rows for down, fine rows for up)
 template <typename R>
 struct Tiles;
 template <>
 struct Tiles<double> {
-  static constexpr int DCX = 16, DCY = 8;   // down: 32 x 16 fine nodes per block
-  static constexpr int UTX = 32, UTY = 16;  // up
+  static constexpr int DCY = 8, UTY = 16;
 };
 template <>
 struct Tiles<float> {
-  static constexpr int DCX = 32, DCY = 8;   // down: 64 x 16 fine nodes per block
-  static constexpr int UTX = 64, UTY = 16;
+  static constexpr int DCY = 16, UTY = 32;
 };
 
 }  // namespace
@@ -203,17 +277,17 @@ struct Tiles<float> {
 template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *u, cplx<R> *rc, R omega,
                     hipStream_t s) {
-  constexpr int CX = Tiles<R>::DCX, CY = Tiles<R>::DCY;
+  constexpr int CX = 29, CY = Tiles<R>::DCY;
   dim3 grid((coarse.n0 + CX - 1) / CX, (coarse.n1 + CY - 1) / CY);
-  hipLaunchKernelGGL((k_down_rb<R, CX, CY>), grid, dim3(NT), 0, s, fine, coarse, b, u, rc, omega);
+  hipLaunchKernelGGL((k_down_rb<R, CY>), grid, dim3(NT), 0, s, fine, coarse, b, u, rc, omega);
 }
 
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
                   const cplx<R> *ec, cplx<R> *u_out, R omega, hipStream_t s) {
-  constexpr int TX = Tiles<R>::UTX, TY = Tiles<R>::UTY;
+  constexpr int TX = 60, TY = Tiles<R>::UTY;
   dim3 grid((fine.n0 + TX - 1) / TX, (fine.n1 + TY - 1) / TY);
-  hipLaunchKernelGGL((k_up_rb<R, TX, TY>), grid, dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out, omega);
+  hipLaunchKernelGGL((k_up_rb<R, TY>), grid, dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out, omega);
 }
 
 template void launch_down_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *, cplx<double> *,
