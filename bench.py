@@ -1,19 +1,28 @@
 """Benchmark: time to a 1e-8 true relative residual and V-cycle HBM bandwidth on
-the 2049^2 ECS grid (soft-Coulomb wavenumber, E = 2, h = 0.25 so k h ~ 0.5,
-ECS beyond 80% of the half width at theta = pi/6; QD preconditioner inverted by
-one V(1,1) red-black Gauss-Seidel cycle over 9 levels; flexible GMRES(40) in
-FP64), mixed precision versus FP64.
+the 2049^2 ECS grid, mixed precision versus FP64.
 
-One step = one complete solve from x = 0 to ||b - A x|| <= 1e-8 ||b|| with the
-mixed-precision form (complex-FP32 cycle inside FP64 flexible GMRES).  The
-FP64 form is timed the same way for the comparison.  Inputs are resident in
-HBM before the timed region.  Prints one JSON line.
+Workload: soft-Coulomb wavenumber k^2 = 2(E + 1/sqrt(r^2+1)), E = 2, h = 0.25
+(k h ~ 0.5) on [-256, 256]^2, ECS beyond |x|, |y| = 204.8 at theta = pi/6,
+right-hand side phi0 * V; QD preconditioner (|Re lambda0| = max k^2) inverted
+by one V(1,1) red-black Gauss-Seidel cycle over 9 levels (coarsest 9^2);
+flexible GMRES(40) in FP64.
+
+One step = one complete solve from x = 0 to ||b - A x|| <= 1e-8 ||b||, timed
+with inputs already resident in HBM.  `value` is the mixed-precision solve:
+FP64 FGMRES(40) whose preconditioner is a few iterations of complex-FP32
+Bi-CGSTAB around the complex-FP32 V-cycle (Arnoldi, Hessenberg least squares
+and the true residual stay FP64 on the GPU).  Reported beside it: the plain
+FP64 solve (FGMRES(40), FP64 cycle) timed the same way, the FP32-cycle-only
+FGMRES(40), FP64 Bi-CGSTAB, V-cycle bandwidth, per-kernel timings of the
+dominant kernel measured with HIP events inside the timed region, and the
+CPU oracle on a bounded sample.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +34,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1012_4307_amd", "csrc", f)
+                  for f in ("kernels_vcycle.hip", "kernels_blas.hip", "kernels_mg.hip")]
 
 
 def parse():
@@ -33,8 +45,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2049)
-    ap.add_argument("--inner", type=int, default=-1, help="FP32 inner Bi-CGSTAB iterations (mixed form); -1: default")
+    ap.add_argument("--restart", type=int, default=40)
+    ap.add_argument("--inner", type=int, default=8, help="FP32 inner Bi-CGSTAB iterations per FGMRES step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-context", action="store_true", help="skip the context solves (FP32-cycle FGMRES, "
+                                                               "FP64 Bi-CGSTAB)")
     ap.add_argument("--vcycles", type=int, default=20, help="cycles timed for the V-cycle bandwidth")
     return ap.parse_args()
 
@@ -53,15 +68,22 @@ def vcycle_algorithmic_bytes(n, nlev, real_bytes):
     and the coarse residual (2/4); up pass reads u (2), the coarse correction
     (2/4), b (2), k^2 (1) and writes u (2): 13 reals per node."""
     nodes = level_nodes(n, nlev)
-    per_node = (5.5 + 7.5) * real_bytes
-    return sum(nodes[:-1]) * per_node
+    return sum(nodes[:-1]) * 13 * real_bytes
+
+
+def sources_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is single-GPU in this build",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the solver has no multi-GPU path in this "
+              f"build; the slab decomposition it would use is described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1012_4307_amd as E
@@ -75,17 +97,18 @@ def main():
     w = W.large_coulomb(n=args.n)
     k2 = torch.from_numpy(w.k2).to(dev)
     b = torch.from_numpy(w.rhs[0]).to(dev)
-    inner = 0 if args.inner < 0 else args.inner
 
-    def make(dt, inner_it):
+    def make(dt, method, inner):
         pc = E.Precond(kind="qd", re_lambda0=0.0, smoother="rbgs", omega=1.0, nu1=1, nu2=1, gamma_f=1, gamma_c=1,
                        coarsest_nodes=9, vcycle_dtype=dt)
-        kr = E.Krylov(method="fgmres", restart=40, rtol=1e-8, maxit=20000, inner=inner_it)
+        kr = E.Krylov(method=method, restart=args.restart, rtol=1e-8, maxit=20000, inner=inner)
         return E.Solver(2, w.n, w.lo, w.hi, w.ecs, k2, pc, kr)
 
-    S64 = make("f64", 0)
-    S32 = make("f32", inner)
+    Smix = make("f32", "fgmres", args.inner)
+    S64 = make("f64", "fgmres", 0)
     nlev = S64.nlev
+
+    timed_classes = ("down", "up", "mdot", "mupdate", "apply_A")
 
     def timed_solves(S, k, timers=()):
         for cls in timers:
@@ -107,12 +130,22 @@ def main():
         return times, stats, x, out
 
     for _ in range(args.warmup):
-        S32.solve(b)
+        Smix.solve(b)
         S64.solve(b)
-    classes = ("smooth", "mdot", "apply_A", "coarse", "mupdate", "restrict", "prolong", "down", "up")
-    t32, st32, x32, ktim = timed_solves(S32, args.steps, classes)
-    t64, st64, x64, ktim64 = timed_solves(S64, args.steps, classes)
-    rel_diff = float((x32 - x64).abs().max() / x64.abs().max())
+    tmix, stmix, xmix, ktim = timed_solves(Smix, args.steps, timed_classes)
+    t64, st64, x64, _ = timed_solves(S64, args.steps)
+    rel_diff = float((xmix - x64).abs().max() / x64.abs().max())
+
+    context = {}
+    if not args.no_context:
+        for name, (dt, method, inner) in {"fgmres_fp32_cycle": ("f32", "fgmres", 0),
+                                          "bicgstab_fp64": ("f64", "bicgstab", 0)}.items():
+            S = make(dt, method, inner)
+            S.solve(b)
+            tt, st, _, _ = timed_solves(S, 1)
+            context[name] = dict(seconds=round(tt[0], 4), iterations=st["iterations"], vcycles=st["vcycles"],
+                                 rel_residual=st["rel_residual"])
+            del S
 
     # V-cycle bandwidth (algorithmic bytes of a V(1,1) RB cycle / cycle time)
     def vcycle_rate(S, real_bytes):
@@ -131,25 +164,49 @@ def main():
         return ms, by / (ms * 1e-3) / 1e9
 
     vc64_ms, vc64_gbs = vcycle_rate(S64, 8)
-    vc32_ms, vc32_gbs = vcycle_rate(S32, 4)
+    vc32_ms, vc32_gbs = vcycle_rate(Smix, 4)
+
+    # copy probe (plain device copy of 512 MiB): the practical HBM rate, and
+    # the reference dispatch that scales the FETCH_SIZE / WRITE_SIZE counters
+    src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        E.copy_probe(src, dst)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(5):
+        E.copy_probe(src, dst)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() / (ev0.elapsed_time(ev1) / 5 * 1e-3) / 1e9
+    del src, dst
 
     kernels = {}
     for cls, (nl, ms, by) in ktim.items():
         if nl:
             kernels[cls] = dict(launches=nl, total_ms=round(ms, 3), avg_us=round(1e3 * ms / nl, 2),
-                                gbs=round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None)
-    dom = max((c for c in kernels if c != "coarse"), key=lambda c: kernels[c]["total_ms"])
+                                algo_gbs=round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None)
+    dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
     nl, ms, by = ktim[dom]
     achieved = by / (ms * 1e-3) / 1e9
-    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    bytes_per_launch=round(by / nl), avg_launch_us=round(1e3 * ms / nl, 2))
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("sources_digest") == sources_digest() and dom in tr.get("kernels", {}):
+            traffic = tr["kernels"][dom]["hbm_bytes_per_launch"]
+    except (OSError, ValueError):
+        traffic = None
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom,
+                    algo_bytes_per_launch=round(by / nl), avg_launch_us=round(1e3 * ms / nl, 2), launches=nl)
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w, st64["iterations"])
+        cpu = cpu_baseline(w, st64["iterations"], args.restart)
 
-    value = float(np.median(t32))
+    value = float(np.median(tmix))
     line = {
         "metric": "time-to-1e-8 residual + V-cycle HBM GB/s, 2049^2 ECS grid, mixed vs FP64",
         "value": round(value, 4),
@@ -157,48 +214,52 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * float(np.mean(t32)), 2),
+        "ms_per_step": round(1e3 * float(np.mean(tmix)), 2),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"soft-Coulomb ECS Helmholtz {args.n}^2, h=0.25, E=2, QD, V(1,1) RB-GS, "
-                               f"{nlev} levels, FGMRES(40) to 1e-8",
-                   "grid": args.n, "h": 0.25, "E": 2.0, "theta": "pi/6", "levels": nlev, "restart": 40,
-                   "inner_fp32_iterations": inner},
-        "mixed": dict(seconds=round(value, 4), iterations=st32["iterations"], vcycles=st32["vcycles"],
-                      rel_residual=st32["rel_residual"], rel_diff_vs_fp64_solution=rel_diff),
+        "config": {"workload": f"soft-Coulomb ECS Helmholtz {args.n}^2 nodes, h=0.25, E=2, theta=pi/6, QD + "
+                               f"V(1,1) RB-GS over {nlev} levels, FP64 FGMRES({args.restart}) to 1e-8 with "
+                               f"{args.inner} FP32 Bi-CGSTAB inner iterations per step",
+                   "grid": args.n, "h": 0.25, "E": 2.0, "levels": nlev, "restart": args.restart,
+                   "inner_fp32_iterations": args.inner},
+        "mixed": dict(seconds=round(value, 4), iterations=stmix["iterations"],
+                      inner_iterations=stmix["inner_iterations"], vcycles=stmix["vcycles"],
+                      rel_residual=stmix["rel_residual"], rel_diff_vs_fp64_solution=rel_diff),
         "fp64": dict(seconds=round(float(np.median(t64)), 4), iterations=st64["iterations"],
                      vcycles=st64["vcycles"], rel_residual=st64["rel_residual"]),
         "speedup_mixed_vs_fp64": round(float(np.median(t64)) / value, 3),
-        "vcycle": {"fp64_ms": round(vc64_ms, 4), "fp64_gbs": round(vc64_gbs, 1),
-                   "fp32_ms": round(vc32_ms, 4), "fp32_gbs": round(vc32_gbs, 1),
-                   "model": "algorithmic bytes of a V(1,1) RB cycle, 13 reals/node/level"},
-        "kernels_mixed": kernels,
+        "context_solves": context,
+        "vcycle": {"fp64_ms": round(vc64_ms, 4), "fp64_algo_gbs": round(vc64_gbs, 1),
+                   "fp32_ms": round(vc32_ms, 4), "fp32_algo_gbs": round(vc32_gbs, 1),
+                   "bytes_model": "13 reals/node/level above the coarsest"},
+        "copy_probe_gbs": round(copy_gbs, 1),
+        "kernels_in_timed_region": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(w, gpu_iterations):
-    """The CPU oracle (plain FP64 C, OpenMP) on a bounded sample: one restart
-    cycle (40 FGMRES iterations, 40 V-cycles) of the same solve on the same
-    inputs, timed, then scaled by the GPU FP64 iteration count to an estimated
-    time-to-1e-8."""
+def cpu_baseline(w, gpu_iterations, restart):
+    """The CPU oracle (plain FP64 C with OpenMP) on a bounded sample: the first
+    restart cycle (`restart` FGMRES iterations with one FP64 V-cycle each) of
+    the plain FP64 solve on the same inputs, timed, then scaled by the number
+    of iterations the FP64 GPU solve needs to reach 1e-8."""
     import oracle
     P = oracle.Problem(w.dim, w.n, w.lo, w.hi, w.ecs, w.k2, w.nlev)
     P.set_operator("qd")
     P.set_cycle("rbgs", 1.0)
-    sample = 40
     t0 = time.perf_counter()
-    _, st = P.solve(w.rhs[0], "fgmres", 40, 1e-8, sample)
+    _, st = P.solve(w.rhs[0], "fgmres", restart, 1e-8, restart)
     dt = time.perf_counter() - t0
     per_it = dt / max(1, st["iterations"])
     return dict(value=round(per_it * gpu_iterations, 2), unit="s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{st['iterations']} FGMRES(40) iterations of the same {w.n[0]}^2 solve in {dt:.1f} s "
-                       f"({per_it:.3f} s/iteration), scaled by the {gpu_iterations} iterations the FP64 solve needs")
+                sample=f"{st['iterations']} FGMRES({restart}) iterations of the FP64 solve on the same "
+                       f"{w.n[0]}^2 inputs took {dt:.1f} s ({per_it:.3f} s/iteration); scaled by the "
+                       f"{gpu_iterations} iterations the FP64 solve needs to reach 1e-8")
 
 
 if __name__ == "__main__":

@@ -87,6 +87,24 @@ void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
                   const cplx<R> *ec, cplx<R> *u_out, R omega, hipStream_t s);
+// the coarsest levels of a 2D V(1,1) red-black cycle in one workgroup:
+// levels with at most kTailNodes nodes per axis (and 2048 nodes in all)
+constexpr int kTailMaxLevels = 8;
+constexpr int kTailNodes = 33;
+template <typename R>
+struct TailArgs {
+  int nl;  // levels in the tail, the last one the coarsest
+  Grid<R> g[kTailMaxLevels];
+  cplx<R> *b[kTailMaxLevels];        // b[0] input (read only); b[k > 0] written
+  cplx<R> *t[kTailMaxLevels];        // pre-smoothed iterates
+  cplx<R> *u[kTailMaxLevels];        // results; u[0] is the tail's output
+  const cplx<R> *minvT;
+  const int *unk;
+  int nunk;
+  R omega;
+};
+template <typename R>
+void launch_tail(const TailArgs<R> &a, hipStream_t s);
 template <typename R>
 void launch_inject_k2(int n0, int n1, int n2, const double *k2_fine, int f0, int f1, R *k2_coarse, hipStream_t s);
 

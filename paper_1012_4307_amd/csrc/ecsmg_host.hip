@@ -650,7 +650,12 @@ template <typename R>
 void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
   const int lc = C->nlev - 1;
   const R om = (R)C->prec.omega;
-  for (int l = 0; l < lc; l++) {
+  // first level handled by the tail: the coarsest k levels that are small
+  int lt = lc;
+  while (lt > 0 && C->hl[lt - 1].n[0] <= kTailNodes && C->hl[lt - 1].n[1] <= kTailNodes &&
+         lc - (lt - 1) + 1 <= kTailMaxLevels)
+    lt--;
+  for (int l = 0; l < lt; l++) {
     DevLevel<R> &D = dev_level<R>(C, l);
     DevLevel<R> &Dc = dev_level<R>(C, l + 1);
     const cplx<R> *b = l == 0 ? b0 : D.b;
@@ -659,11 +664,24 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
     launch_down_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.b, om, C->stream);
   }
   {
-    DevLevel<R> &Dc = dev_level<R>(C, lc);
+    TailArgs<R> a{};
+    a.nl = lc - lt + 1;
+    for (int k = 0; k < a.nl; k++) {
+      const int l = lt + k;
+      DevLevel<R> &D = dev_level<R>(C, l);
+      a.g[k] = grid_M<R>(C, l);
+      a.b[k] = (l == 0) ? const_cast<cplx<R> *>(b0) : D.b;  // the tail never writes b[0]
+      a.t[k] = D.t;
+      a.u[k] = (l == 0) ? u0 : D.u;
+    }
+    a.minvT = minv_of<R>(C);
+    a.unk = C->unk;
+    a.nunk = C->nunk;
+    a.omega = om;
     TimedScope ts(C, kTCoarse, 0.0);
-    coarse_solve<R>(C, Dc.b, Dc.u);
+    launch_tail<R>(a, C->stream);
   }
-  for (int l = lc - 1; l >= 0; l--) {
+  for (int l = lt - 1; l >= 0; l--) {
     DevLevel<R> &D = dev_level<R>(C, l);
     DevLevel<R> &Dc = dev_level<R>(C, l + 1);
     const cplx<R> *b = l == 0 ? b0 : D.b;

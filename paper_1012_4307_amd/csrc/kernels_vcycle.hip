@@ -260,7 +260,243 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
   }
 }
 
-// tile heights (coarse rows for down, fine rows for up)
+// ----------------------------------------------------------------- tail
+// The coarsest levels of the cycle in one workgroup: for grids of a few
+// thousand nodes a kernel launch per phase costs more than the work, so the
+// down passes, the dense coarsest solve and the up passes of every level from
+// the tail's first level to the coarsest run in one launch, phases separated
+// by workgroup barriers.  Level vectors live in global memory (L2-resident);
+// the 1D weights of all tail levels are staged in LDS; every phase first
+// gathers the operands of all of a thread's nodes (TS slots, unrolled) and
+// only then computes, so one memory round trip is paid per phase.
+// Level k of the tail: b[k] right-hand side, t[k] pre-smoothed iterate, u[k]
+// result.
+constexpr int TT = 1024;  // tail threads
+constexpr int TS = 2;     // node slots per thread: tail levels have <= 2048 nodes
+constexpr int TW = 128;   // LDS weights per axis and kind (sum of the tail level sizes)
+
+template <typename R>
+struct TailW {
+  cplx<R> xm[TW], xp[TW], ym[TW], yp[TW];
+};
+
+template <typename R>
+__global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
+  __shared__ TailW<R> W;
+  __shared__ int off[kTailMaxLevels];
+  const int tid = threadIdx.x;
+  const R om = a.omega, om1 = R(1) - a.omega;
+  const int last = a.nl - 1;
+  if (tid == 0) {
+    int o = 0;
+    for (int k = 0; k < a.nl; k++) {
+      off[k] = o;
+      o += a.g[k].n0 > a.g[k].n1 ? a.g[k].n0 : a.g[k].n1;
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < a.nl; k++) {
+    const Grid<R> &g = a.g[k];
+    for (int q = tid; q < g.n0; q += TT) {
+      W.xm[off[k] + q] = g.cm0[q];
+      W.xp[off[k] + q] = g.cp0[q];
+    }
+    for (int q = tid; q < g.n1; q += TT) {
+      W.ym[off[k] + q] = g.cm1[q];
+      W.yp[off[k] + q] = g.cp1[q];
+    }
+  }
+  __syncthreads();
+
+  // down: zero-guess red-black sweep, then the restricted residual
+  for (int k = 0; k < last; k++) {
+    const Grid<R> &g = a.g[k];
+    const cplx<R> *xm = W.xm + off[k], *xp = W.xp + off[k], *ym = W.ym + off[k], *yp = W.yp + off[k];
+    const cplx<R> *b = a.b[k];
+    cplx<R> *t = a.t[k];
+    const int n0 = g.n0, n1 = g.n1, nn = n0 * n1;
+    cplx<R> bs[TS], is[TS];
+#pragma unroll
+    for (int s = 0; s < TS; s++) {
+      const int p = tid + s * TT;
+      bs[s] = zero_c<R>();
+      is[s] = zero_c<R>();
+      if (p < nn) {
+        const int i = p % n0, j = p / n0;
+        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
+          bs[s] = b[p];
+          is[s] = inv_c(xm[i] + xp[i] + ym[j] + yp[j] + (g.k2[p] * g.beta + g.c));
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < TS; s++) {
+      const int p = tid + s * TT;
+      if (p < nn) {
+        const int i = p % n0, j = p / n0;
+        t[p] = ((i + j) & 1) == 0 ? om * (bs[s] * is[s]) : zero_c<R>();
+      }
+    }
+    __syncthreads();
+    cplx<R> nb[TS][4];
+#pragma unroll
+    for (int s = 0; s < TS; s++) {
+      const int p = tid + s * TT;
+      if (p < nn) {
+        const int i = p % n0, j = p / n0;
+        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 1) {
+          nb[s][0] = t[p - 1]; nb[s][1] = t[p + 1]; nb[s][2] = t[p - n0]; nb[s][3] = t[p + n0];
+        }
+      }
+    }
+    cplx<R> rs[TS];
+#pragma unroll
+    for (int s = 0; s < TS; s++) {
+      const int p = tid + s * TT;
+      rs[s] = zero_c<R>();
+      if (p < nn) {
+        const int i = p % n0, j = p / n0;
+        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 1) {
+          const cplx<R> tb = bs[s] + (xm[i] * nb[s][0] + xp[i] * nb[s][1] + ym[j] * nb[s][2] + yp[j] * nb[s][3]);
+          t[p] = om * (tb * is[s]);
+          rs[s] = om1 * tb;  // black residual
+        }
+      }
+    }
+    __syncthreads();
+    // red residuals from the relaxed black neighbours; residual vector kept in
+    // the tail's scratch u[k] (free until the up pass overwrites it)
+    cplx<R> *r = a.u[k];
+#pragma unroll
+    for (int s = 0; s < TS; s++) {
+      const int p = tid + s * TT;
+      if (p < nn) {
+        const int i = p % n0, j = p / n0;
+        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 0) {
+          nb[s][0] = t[p - 1]; nb[s][1] = t[p + 1]; nb[s][2] = t[p - n0]; nb[s][3] = t[p + n0];
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < TS; s++) {
+      const int p = tid + s * TT;
+      if (p < nn) {
+        const int i = p % n0, j = p / n0;
+        const bool in = i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2;
+        if (in && ((i + j) & 1) == 0)
+          rs[s] = om1 * bs[s] + (xm[i] * nb[s][0] + xp[i] * nb[s][1] + ym[j] * nb[s][2] + yp[j] * nb[s][3]);
+        r[p] = in ? rs[s] : zero_c<R>();
+      }
+    }
+    __syncthreads();
+    const Grid<R> &gc = a.g[k + 1];
+    cplx<R> *bc = a.b[k + 1];
+    const int nc = gc.n0 * gc.n1;
+    for (int q = tid; q < nc; q += TT) {
+      const int I = q % gc.n0, J = q / gc.n0;
+      cplx<R> acc = zero_c<R>();
+      if (I >= 1 && I <= gc.n0 - 2 && J >= 1 && J <= gc.n1 - 2) {
+        const cplx<R> *c0 = r + (int64_t)(2 * J) * n0 + 2 * I;
+        acc = R(0.25) * c0[0] + R(0.125) * (c0[-1] + c0[1] + c0[-n0] + c0[n0]) +
+              R(0.0625) * (c0[-n0 - 1] + c0[-n0 + 1] + c0[n0 - 1] + c0[n0 + 1]);
+      }
+      bc[q] = acc;
+    }
+    __syncthreads();
+  }
+  // dense solve on the coarsest level (inverse stored transposed)
+  {
+    const Grid<R> &g = a.g[last];
+    const int nn = g.n0 * g.n1;
+    cplx<R> *x = a.u[last];
+    const cplx<R> *bb = a.b[last];
+    for (int p = tid; p < nn; p += TT) {
+      const int i = p % g.n0, j = p / g.n0;
+      if (i < 1 || i > g.n0 - 2 || j < 1 || j > g.n1 - 2) x[p] = zero_c<R>();
+    }
+    for (int rr = tid; rr < a.nunk; rr += TT) {
+      cplx<R> acc = zero_c<R>();
+#pragma unroll 8
+      for (int c = 0; c < a.nunk; c++) acc = acc + a.minvT[(int64_t)c * a.nunk + rr] * bb[a.unk[c]];
+      x[a.unk[rr]] = acc;
+    }
+    __syncthreads();
+  }
+  // up: prolongation + correction, then the red-black post-sweep in place
+  for (int k = last - 1; k >= 0; k--) {
+    const Grid<R> &g = a.g[k];
+    const Grid<R> &gc = a.g[k + 1];
+    const cplx<R> *xm = W.xm + off[k], *xp = W.xp + off[k], *ym = W.ym + off[k], *yp = W.yp + off[k];
+    const cplx<R> *b = a.b[k];
+    const cplx<R> *t = a.t[k];
+    const cplx<R> *ec = a.u[k + 1];
+    cplx<R> *u = a.u[k];
+    const int n0 = g.n0, n1 = g.n1, nn = n0 * n1;
+    cplx<R> vs[TS], bs[TS], is[TS], e4[TS][4];
+#pragma unroll
+    for (int s = 0; s < TS; s++) {
+      const int p = tid + s * TT;
+      vs[s] = zero_c<R>();
+      bs[s] = zero_c<R>();
+      is[s] = zero_c<R>();
+      if (p < nn) {
+        const int i = p % n0, j = p / n0;
+        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
+          const cplx<R> *e = ec + (int64_t)(j >> 1) * gc.n0 + (i >> 1);
+          e4[s][0] = e[0];
+          e4[s][1] = (i & 1) ? e[1] : zero_c<R>();
+          e4[s][2] = (j & 1) ? e[gc.n0] : zero_c<R>();
+          e4[s][3] = ((i & 1) && (j & 1)) ? e[gc.n0 + 1] : zero_c<R>();
+          vs[s] = t[p];
+          bs[s] = b[p];
+          is[s] = inv_c(xm[i] + xp[i] + ym[j] + yp[j] + (g.k2[p] * g.beta + g.c));
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < TS; s++) {
+      const int p = tid + s * TT;
+      if (p < nn) {
+        const int i = p % n0, j = p / n0;
+        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
+          const R wx = (i & 1) ? R(0.5) : R(1), wy = (j & 1) ? R(0.5) : R(1);
+          vs[s] = vs[s] + (wx * wy) * (e4[s][0] + e4[s][1] + e4[s][2] + e4[s][3]);
+        }
+        u[p] = vs[s];
+      }
+    }
+    __syncthreads();
+    for (int colour = 0; colour < 2; colour++) {
+      cplx<R> nb[TS][4];
+#pragma unroll
+      for (int s = 0; s < TS; s++) {
+        const int p = tid + s * TT;
+        if (p < nn) {
+          const int i = p % n0, j = p / n0;
+          if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == colour) {
+            nb[s][0] = u[p - 1]; nb[s][1] = u[p + 1]; nb[s][2] = u[p - n0]; nb[s][3] = u[p + n0];
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < TS; s++) {
+        const int p = tid + s * TT;
+        if (p < nn) {
+          const int i = p % n0, j = p / n0;
+          if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == colour) {
+            const cplx<R> o = xm[i] * nb[s][0] + xp[i] * nb[s][1] + ym[j] * nb[s][2] + yp[j] * nb[s][3];
+            vs[s] = om1 * vs[s] + om * ((bs[s] + o) * is[s]);
+            u[p] = vs[s];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// tile heights (coarse rows for down, fine rows for up); small grids use
+// short tiles so that a block's serial row loop stays short
 template <typename R>
 struct Tiles;
 template <>
@@ -271,23 +507,44 @@ template <>
 struct Tiles<float> {
   static constexpr int DCY = 16, UTY = 32;
 };
+constexpr int kSmallDCY = 2, kSmallUTY = 4;
+constexpr int kSmallGrid = 513;  // fine grids up to this size use the short tiles
 
 }  // namespace
 
 template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *u, cplx<R> *rc, R omega,
                     hipStream_t s) {
-  constexpr int CX = 29, CY = Tiles<R>::DCY;
-  dim3 grid((coarse.n0 + CX - 1) / CX, (coarse.n1 + CY - 1) / CY);
-  hipLaunchKernelGGL((k_down_rb<R, CY>), grid, dim3(NT), 0, s, fine, coarse, b, u, rc, omega);
+  constexpr int CX = 29;
+  if (fine.n0 <= kSmallGrid && fine.n1 <= kSmallGrid) {
+    constexpr int CY = kSmallDCY;
+    dim3 grid((coarse.n0 + CX - 1) / CX, (coarse.n1 + CY - 1) / CY);
+    hipLaunchKernelGGL((k_down_rb<R, CY>), grid, dim3(NT), 0, s, fine, coarse, b, u, rc, omega);
+  } else {
+    constexpr int CY = Tiles<R>::DCY;
+    dim3 grid((coarse.n0 + CX - 1) / CX, (coarse.n1 + CY - 1) / CY);
+    hipLaunchKernelGGL((k_down_rb<R, CY>), grid, dim3(NT), 0, s, fine, coarse, b, u, rc, omega);
+  }
 }
 
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
                   const cplx<R> *ec, cplx<R> *u_out, R omega, hipStream_t s) {
-  constexpr int TX = 60, TY = Tiles<R>::UTY;
-  dim3 grid((fine.n0 + TX - 1) / TX, (fine.n1 + TY - 1) / TY);
-  hipLaunchKernelGGL((k_up_rb<R, TY>), grid, dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out, omega);
+  constexpr int TX = 60;
+  if (fine.n0 <= kSmallGrid && fine.n1 <= kSmallGrid) {
+    constexpr int TY = kSmallUTY;
+    dim3 grid((fine.n0 + TX - 1) / TX, (fine.n1 + TY - 1) / TY);
+    hipLaunchKernelGGL((k_up_rb<R, TY>), grid, dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out, omega);
+  } else {
+    constexpr int TY = Tiles<R>::UTY;
+    dim3 grid((fine.n0 + TX - 1) / TX, (fine.n1 + TY - 1) / TY);
+    hipLaunchKernelGGL((k_up_rb<R, TY>), grid, dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out, omega);
+  }
+}
+
+template <typename R>
+void launch_tail(const TailArgs<R> &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_tail<R>), dim3(1), dim3(TT), 0, s, a);
 }
 
 template void launch_down_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *, cplx<double> *,
@@ -296,6 +553,8 @@ template void launch_down_rb<float>(const Grid<float> &, const Grid<float> &, co
                                     cplx<float> *, float, hipStream_t);
 template void launch_up_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *,
                                    const cplx<double> *, const cplx<double> *, cplx<double> *, double, hipStream_t);
+template void launch_tail<double>(const TailArgs<double> &, hipStream_t);
+template void launch_tail<float>(const TailArgs<float> &, hipStream_t);
 template void launch_up_rb<float>(const Grid<float> &, const Grid<float> &, const cplx<float> *, const cplx<float> *,
                                   const cplx<float> *, cplx<float> *, float, hipStream_t);
 
