@@ -57,6 +57,20 @@ struct Grid {
   cplx<R> beta, c;
 };
 
+// XCD-aware tile order.  Workgroups are handed to the 8 XCDs of the chip in
+// round-robin order of their linear index, and each XCD has its own L2.  A 1D
+// launch of `padded` (a multiple of 8) blocks is mapped so that XCD x owns the
+// contiguous tile range [x * padded/8, (x+1) * padded/8): neighbouring tiles,
+// which share halo rows, are cached by the same L2.  Returns -1 for padding.
+constexpr int kXcds = 8;
+__host__ __device__ __forceinline__ int xcd_padded(int tiles) { return (tiles + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ int xcd_tile(int tiles) {
+  const int padded = gridDim.x;
+  const int b = blockIdx.x;
+  const int t = (b % kXcds) * (padded / kXcds) + b / kXcds;
+  return t < tiles ? t : -1;
+}
+
 // ---------------------------------------------------------------- launchers
 // Multigrid components (kernels_mg.hip); R = double or float.
 template <typename R, typename RI, typename RO>

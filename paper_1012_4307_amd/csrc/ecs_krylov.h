@@ -33,7 +33,7 @@ struct BicgScalars {
   int bad;
 };
 
-enum { kBicgRho = 0, kBicgAlpha = 1, kBicgOmega = 2, kBicgNorm = 3, kBicgInit = 4 };
+enum { kBicgAlpha = 1, kBicgOmega = 2, kBicgInit = 4, kBicgNormRho = 5 };
 
 int reduction_blocks(int64_t n);
 
@@ -64,9 +64,19 @@ template <typename R>
 void launch_bicg_p(cplx<R> *p, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s);
 template <typename R>
 void launch_bicg_s(cplx<R> *sv, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s);
+// x += alpha ph + omega sh; r = s - omega t; then ||r||^2 and (r^, r) reduce
+// (fixed-order second stage) into est and the next step's beta
 template <typename R, typename RZ>
 void launch_bicg_xr(cplx<R> *x, const cplx<RZ> *ph, const cplx<RZ> *sh, cplx<R> *r, const cplx<R> *sv,
-                    const cplx<R> *t, int64_t n, cplx<double> *partials, BicgScalars *S, hipStream_t s);
+                    const cplx<R> *t, const cplx<R> *rh, int64_t n, cplx<double> *partials, BicgScalars *S,
+                    hipStream_t s);
+// y = A x with a fused dot product: kBicgAlpha -> (d0, y) gives alpha;
+// kBicgOmega -> (y, d0) and (y, y) give omega (multigrid side, kernels_mg.hip)
+void launch_bicg_final(const cplx<double> *partials, int nblocks, int npairs, BicgScalars *S, int mode,
+                       hipStream_t s);
+template <typename R, typename RI>
+void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cplx<R> *d0, int mode,
+                      cplx<double> *partials, BicgScalars *S, hipStream_t s);
 
 template <typename RI, typename RO>
 void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s);

@@ -570,6 +570,10 @@ ecs_status setup(ecs_ctx *C) {
     if (f32 && (st = upload_cx<float>(C, C->minv32, MT, 1.0)) != ECS_OK) return st;
   }
   HIP_OK(hipMemcpy(C->unk, unk.data(), nu * sizeof(int), hipMemcpyHostToDevice));
+  // Krylov scalars start cleared
+  HIP_OK(hipMemsetAsync(C->gs, 0, sizeof(GmresScalars), s));
+  HIP_OK(hipMemsetAsync(C->bs, 0, sizeof(BicgScalars), s));
+  HIP_OK(hipMemsetAsync(C->bs_in, 0, sizeof(BicgScalars), s));
   HIP_OK(hipStreamSynchronize(s));
   HIP_OK(hipGetLastError());
   return ECS_OK;
@@ -787,16 +791,13 @@ void inner_bicgstab(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *v, cplx
   launch_pairdot<float>(K.fr, K.fr, nullptr, nullptr, 1, n, C->partials, S, kBicgInit, s);
   const Grid<float> gA = grid_A32(C);
   for (int it = 0; it < iters; it++) {
-    launch_pairdot<float>(K.frh, K.fr, nullptr, nullptr, 1, n, C->partials, S, kBicgRho, s);
     launch_bicg_p<float>(K.fp, K.fr, K.fv, n, S, s);
     vcycle<float>(C, K.fp, K.fph);
-    launch_apply<float, float, float>(gA, K.fph, K.fv, s);
-    launch_pairdot<float>(K.frh, K.fv, nullptr, nullptr, 1, n, C->partials, S, kBicgAlpha, s);
+    launch_apply_dot<float, float>(gA, K.fph, K.fv, K.frh, kBicgAlpha, C->partials, S, s);
     launch_bicg_s<float>(K.fs, K.fr, K.fv, n, S, s);
     vcycle<float>(C, K.fs, K.fsh);
-    launch_apply<float, float, float>(gA, K.fsh, K.ft, s);
-    launch_pairdot<float>(K.ft, K.fs, K.ft, K.ft, 2, n, C->partials, S, kBicgOmega, s);
-    launch_bicg_xr<float, float>(x, K.fph, K.fsh, K.fr, K.fs, K.ft, n, C->partials, S, s);
+    launch_apply_dot<float, float>(gA, K.fsh, K.ft, K.fs, kBicgOmega, C->partials, S, s);
+    launch_bicg_xr<float, float>(x, K.fph, K.fsh, K.fr, K.fs, K.ft, K.frh, n, C->partials, S, s);
   }
 }
 
@@ -951,22 +952,19 @@ ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, co
     launch_zero<double>(K.p, n, s);
     launch_zero<double>(K.v, n, s);
     while (it < d->maxit) {
-      launch_pairdot<double>(K.rh, K.r, nullptr, nullptr, 1, n, C->partials, S, kBicgRho, s);
       launch_bicg_p<double>(K.p, K.r, K.v, n, S, s);
       precond<RZ>(C, K.p, ph);
       {
-        TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 24));
-        launch_apply<double, RZ, double>(grid_A(C), ph, K.v, s);
+        TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 40));
+        launch_apply_dot<double, RZ>(grid_A(C), ph, K.v, K.rh, kBicgAlpha, C->partials, S, s);
       }
-      launch_pairdot<double>(K.rh, K.v, nullptr, nullptr, 1, n, C->partials, S, kBicgAlpha, s);
       launch_bicg_s<double>(K.s, K.r, K.v, n, S, s);
       precond<RZ>(C, K.s, sh);
       {
-        TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 24));
-        launch_apply<double, RZ, double>(grid_A(C), sh, K.tt, s);
+        TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 40));
+        launch_apply_dot<double, RZ>(grid_A(C), sh, K.tt, K.s, kBicgOmega, C->partials, S, s);
       }
-      launch_pairdot<double>(K.tt, K.s, K.tt, K.tt, 2, n, C->partials, S, kBicgOmega, s);
-      launch_bicg_xr<double, RZ>(x, ph, sh, K.r, K.s, K.tt, n, C->partials, S, s);
+      launch_bicg_xr<double, RZ>(x, ph, sh, K.r, K.s, K.tt, K.rh, n, C->partials, S, s);
       st->vcycles += 2;
       it++;
       // est and bad are contiguous: one readback per iteration

@@ -6,33 +6,13 @@
 // Givens least-squares update and the Bi-CGSTAB scalar recurrences run in
 // single-thread kernels right behind their reductions.  The host only reads a
 // residual estimate per iteration.
-#include "ecs_krylov.h"
+#include "ecs_reduce.h"
 
 namespace ecs {
 
 namespace {
 
-constexpr int BS = 256;  // 4 waves of 64
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// block-wide sum of a complex value; result valid in thread 0
-__device__ __forceinline__ cplx<double> block_sum(cplx<double> v, cplx<double> *lds /* >= 4 */) {
-  v.re = wave_sum(v.re);
-  v.im = wave_sum(v.im);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) lds[wid] = v;
-  __syncthreads();
-  cplx<double> s = mk<double>(0, 0);
-  if (threadIdx.x == 0)
-    for (int q = 0; q < BS / 64; q++) s = s + lds[q];
-  return s;
-}
+constexpr int BS = kRedThreads;
 
 inline int red_blocks(int64_t n) {
   int64_t b = (n + BS * 4 - 1) / (BS * 4);
@@ -285,51 +265,14 @@ __global__ __launch_bounds__(BS) void k_pairdot(const cplx<R> *__restrict__ x0, 
 __global__ __launch_bounds__(BS) void k_bicg_final(const cplx<double> *__restrict__ partials, int nblocks,
                                                    int npairs, BicgScalars *S, int mode) {
   __shared__ cplx<double> lds[BS / 64];
-  cplx<double> d[2];
+  cplx<double> d[2] = {mk<double>(0, 0), mk<double>(0, 0)};
   for (int q = 0; q < npairs; q++) {
     cplx<double> s = mk<double>(0, 0);
     for (int b = threadIdx.x; b < nblocks; b += BS) s = s + partials[(int64_t)q * nblocks + b];
     d[q] = block_sum(s, lds);
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
-  const cplx<double> zero = mk<double>(0, 0);
-  switch (mode) {
-    case kBicgRho: {  // rho1 = (r^, r); beta = (rho1/rho)(alpha/omega)
-      cplx<double> rho1 = d[0];
-      if (abs2(rho1) == 0 || abs2(S->rho) == 0 || abs2(S->omega) == 0 || S->bad) {
-        S->bad = 1; S->beta = zero; S->alpha = zero; S->omega = zero;
-        break;
-      }
-      S->beta = cdiv(rho1, S->rho) * cdiv(S->alpha, S->omega);
-      S->rho = rho1;
-      break;
-    }
-    case kBicgAlpha: {  // alpha = rho / (r^, v)
-      if (abs2(d[0]) == 0 || S->bad) { S->bad = 1; S->alpha = zero; break; }
-      S->alpha = cdiv(S->rho, d[0]);
-      break;
-    }
-    case kBicgOmega: {  // omega = (t, s) / (t, t)
-      if (d[1].re == 0 || S->bad) { S->bad = 1; S->omega = zero; break; }
-      S->omega = (1.0 / d[1].re) * d[0];
-      break;
-    }
-    case kBicgNorm: {  // ||r||^2
-      S->rnorm2 = d[0].re;
-      S->est = sqrt(d[0].re) / S->bnorm;
-      if (!(S->est == S->est) || isinf(S->est)) S->bad = 1;
-      break;
-    }
-    case kBicgInit: {  // restart: rho = alpha = omega = 1
-      S->rnorm2 = d[0].re;
-      S->est = sqrt(d[0].re) / S->bnorm;
-      S->rho = mk<double>(1, 0); S->alpha = mk<double>(1, 0); S->omega = mk<double>(1, 0);
-      S->beta = zero;
-      S->bad = !(S->est == S->est) || isinf(S->est);
-      break;
-    }
-  }
+  if (threadIdx.x == 0) bicg_update(S, mode, d[0], d[1]);
 }
 
 // p = r + beta (p - omega v)
@@ -350,23 +293,31 @@ __global__ __launch_bounds__(BS) void k_bicg_s(cplx<R> *__restrict__ s, const cp
     s[q] = r[q] - alpha * v[q];
 }
 
-// x += alpha ph + omega sh ; r = s - omega t ; partials of ||r||^2
+// x += alpha ph + omega sh ; r = s - omega t ; ||r||^2 and (r^, r) reduced by
+// the last block into est and the next step's beta
 template <typename R, typename RZ>
 __global__ __launch_bounds__(BS) void k_bicg_xr(cplx<R> *__restrict__ x, const cplx<RZ> *__restrict__ ph,
                                                 const cplx<RZ> *__restrict__ sh, cplx<R> *__restrict__ r,
                                                 const cplx<R> *__restrict__ s, const cplx<R> *__restrict__ t,
-                                                int64_t n, const BicgScalars *S, cplx<double> *partials) {
+                                                const cplx<R> *__restrict__ rh, int64_t n, BicgScalars *S,
+                                                cplx<double> *partials) {
   __shared__ cplx<double> lds[BS / 64];
   const cplx<R> alpha = cvt<R>(S->alpha), omega = cvt<R>(S->omega);
   double nrm = 0;
+  cplx<double> rr = mk<double>(0, 0);
   for (int64_t q = (int64_t)blockIdx.x * BS + threadIdx.x; q < n; q += (int64_t)gridDim.x * BS) {
     x[q] = x[q] + alpha * cvt<R>(ph[q]) + omega * cvt<R>(sh[q]);
-    cplx<R> rq = s[q] - omega * t[q];
+    const cplx<R> rq = s[q] - omega * t[q];
     r[q] = rq;
-    nrm += abs2(cvt<double>(rq));
+    const cplx<double> rd = cvt<double>(rq);
+    nrm += abs2(rd);
+    rr = rr + conjg(cvt<double>(rh[q])) * rd;
   }
-  cplx<double> sum = block_sum(mk<double>(nrm, 0), lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = sum;
+  cplx<double> a0 = block_sum(mk<double>(nrm, 0), lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = a0;
+  __syncthreads();
+  cplx<double> a1 = block_sum(rr, lds);
+  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = a1;
 }
 
 // ----------------------------------------------------------- utilities
@@ -524,10 +475,16 @@ void launch_bicg_s(cplx<R> *sv, const cplx<R> *r, const cplx<R> *v, int64_t n, c
 }
 template <typename R, typename RZ>
 void launch_bicg_xr(cplx<R> *x, const cplx<RZ> *ph, const cplx<RZ> *sh, cplx<R> *r, const cplx<R> *sv,
-                    const cplx<R> *t, int64_t n, cplx<double> *partials, BicgScalars *S, hipStream_t s) {
-  int nb = red_blocks(n);
-  hipLaunchKernelGGL((k_bicg_xr<R, RZ>), dim3(nb), dim3(BS), 0, s, x, ph, sh, r, sv, t, n, S, partials);
-  hipLaunchKernelGGL(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, 1, S, (int)kBicgNorm);
+                    const cplx<R> *t, const cplx<R> *rh, int64_t n, cplx<double> *partials, BicgScalars *S,
+                    hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_bicg_xr<R, RZ>), dim3(nb), dim3(BS), 0, s, x, ph, sh, r, sv, t, rh, n, S, partials);
+  hipLaunchKernelGGL(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, 2, S, (int)kBicgNormRho);
+}
+
+void launch_bicg_final(const cplx<double> *partials, int nblocks, int npairs, BicgScalars *S, int mode,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nblocks, npairs, S, mode);
 }
 
 template <typename RI, typename RO>
@@ -593,14 +550,14 @@ template void launch_bicg_s<double>(cplx<double> *, const cplx<double> *, const 
 template void launch_bicg_s<float>(cplx<float> *, const cplx<float> *, const cplx<float> *, int64_t,
                                    const BicgScalars *, hipStream_t);
 template void launch_bicg_xr<double, double>(cplx<double> *, const cplx<double> *, const cplx<double> *, cplx<double> *,
-                                             const cplx<double> *, const cplx<double> *, int64_t, cplx<double> *,
-                                             BicgScalars *, hipStream_t);
+                                             const cplx<double> *, const cplx<double> *, const cplx<double> *, int64_t,
+                                             cplx<double> *, BicgScalars *, hipStream_t);
 template void launch_bicg_xr<double, float>(cplx<double> *, const cplx<float> *, const cplx<float> *, cplx<double> *,
-                                            const cplx<double> *, const cplx<double> *, int64_t, cplx<double> *,
-                                            BicgScalars *, hipStream_t);
+                                            const cplx<double> *, const cplx<double> *, const cplx<double> *, int64_t,
+                                            cplx<double> *, BicgScalars *, hipStream_t);
 template void launch_bicg_xr<float, float>(cplx<float> *, const cplx<float> *, const cplx<float> *, cplx<float> *,
-                                           const cplx<float> *, const cplx<float> *, int64_t, cplx<double> *,
-                                           BicgScalars *, hipStream_t);
+                                           const cplx<float> *, const cplx<float> *, const cplx<float> *, int64_t,
+                                           cplx<double> *, BicgScalars *, hipStream_t);
 template void launch_cast<double, float>(const cplx<double> *, cplx<float> *, int64_t, hipStream_t);
 template void launch_cast<float, double>(const cplx<float> *, cplx<double> *, int64_t, hipStream_t);
 template void launch_zero<double>(cplx<double> *, int64_t, hipStream_t);

@@ -8,7 +8,7 @@
 // thread to one node of a (64 x 4) tile of an x-y plane; the z plane (3D) is
 // blockIdx.z.  Loads along x are unit stride, so a wave reads 64 consecutive
 // nodes (1 KB in FP64) per access.  Boundary nodes carry zeros.
-#include "ecs_internal.h"
+#include "ecs_reduce.h"
 
 namespace ecs {
 
@@ -25,13 +25,18 @@ struct Node {
   bool interior;  // not a Dirichlet node
 };
 
+// blocks are launched 1D over the (x tiles) x (y tiles) x (z planes) tiles
+// of the grid in XCD-aware order; padding blocks get in = false
 template <typename R>
 __device__ __forceinline__ Node<R> node_of(const Grid<R> &g) {
   Node<R> q;
-  q.i = blockIdx.x * TX + threadIdx.x;
-  q.j = blockIdx.y * TY + threadIdx.y;
-  q.k = blockIdx.z;
-  q.in = q.i < g.n0 && q.j < g.n1;
+  const int tx = (g.n0 + TX - 1) / TX, ty = (g.n1 + TY - 1) / TY;
+  const int tile = xcd_tile(tx * ty * g.n2);
+  const int tt = tile < 0 ? 0 : tile;
+  q.i = (tt % tx) * TX + threadIdx.x;
+  q.j = ((tt / tx) % ty) * TY + threadIdx.y;
+  q.k = tt / (tx * ty);
+  q.in = tile >= 0 && q.i < g.n0 && q.j < g.n1;
   q.p = ((int64_t)q.k * g.n1 + q.j) * g.n0 + q.i;
   bool zin = g.n2 == 1 || (q.k >= 1 && q.k <= g.n2 - 2);
   q.interior = q.in && q.i >= 1 && q.i <= g.n0 - 2 && q.j >= 1 && q.j <= g.n1 - 2 && zin;
@@ -62,7 +67,7 @@ __device__ __forceinline__ cplx<R> offd_at(const Grid<R> &g, const cplx<RI> *__r
 
 template <typename R>
 dim3 grid_of(const Grid<R> &g) {
-  return dim3((g.n0 + TX - 1) / TX, (g.n1 + TY - 1) / TY, g.n2);
+  return dim3(xcd_padded(((g.n0 + TX - 1) / TX) * ((g.n1 + TY - 1) / TY) * g.n2));
 }
 
 // y = M x; the input may be stored in a lower precision than the arithmetic
@@ -250,6 +255,48 @@ __global__ __launch_bounds__(1024) void k_coarse_solve(int nunk, const cplx<R> *
   }
 }
 
+// y = M x with a fused dot product for Bi-CGSTAB (grid-stride over 64 x 4
+// tiles; one thread per node):
+//   kBicgAlpha: sum conj(d0) y  -> alpha = rho / (r^, v)
+//   kBicgOmega: sum conj(y) d0, sum |y|^2 -> omega = (t, s) / (t, t)
+// Per-block partials; a second fixed-order stage (launch_bicg_final) reduces
+// them and updates the scalars.
+template <typename R, typename RI>
+__global__ __launch_bounds__(256) void k_apply_dot(Grid<R> g, const cplx<RI> *__restrict__ x,
+                                                   cplx<R> *__restrict__ y, const cplx<R> *__restrict__ d0,
+                                                   int mode, cplx<double> *partials, BicgScalars *S) {
+  __shared__ cplx<double> lds[4];
+  const int tx = (g.n0 + TX - 1) / TX, ty = (g.n1 + TY - 1) / TY;
+  const int ntiles = tx * ty * g.n2;
+  const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+  cplx<double> a0 = mk<double>(0, 0);
+  double a1 = 0;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int i = (t % tx) * TX + lx, j = ((t / tx) % ty) * TY + ly, k = t / (tx * ty);
+    if (i >= g.n0 || j >= g.n1) continue;
+    const int64_t p = ((int64_t)k * g.n1 + j) * g.n0 + i;
+    const bool zin = g.n2 == 1 || (k >= 1 && k <= g.n2 - 2);
+    cplx<R> v = mk<R>(0, 0);
+    if (i >= 1 && i <= g.n0 - 2 && j >= 1 && j <= g.n1 - 2 && zin)
+      v = diag_at(g, i, j, k, p) * cvt<R>(x[p]) - offd_at<R, RI>(g, x, i, j, k, p);
+    y[p] = v;
+    const cplx<double> vd = cvt<double>(v), dd = cvt<double>(d0[p]);
+    if (mode == kBicgAlpha) {
+      a0 = a0 + conjg(dd) * vd;
+    } else {
+      a0 = a0 + conjg(vd) * dd;
+      a1 += abs2(vd);
+    }
+  }
+  cplx<double> s0 = block_sum(a0, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s0;
+  if (mode != kBicgAlpha) {
+    __syncthreads();
+    cplx<double> s1 = block_sum(mk<double>(a1, 0), lds);
+    if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = s1;
+  }
+}
+
 template <typename R>
 __global__ void k_inject_k2(int n0, int n1, int n2, const double *__restrict__ kf, int f0, int f1, int stride,
                             R *__restrict__ kc) {
@@ -299,6 +346,18 @@ void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, 
                          cplx<R> *x, hipStream_t s) {
   hipLaunchKernelGGL((k_coarse_solve<R>), dim3(1), dim3(1024), 0, s, nunk, minv, unk, n0, n1, n2, b, x);
 }
+template <typename R, typename RI>
+void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cplx<R> *d0, int mode,
+                      cplx<double> *partials, BicgScalars *S, hipStream_t s) {
+  // one block per 64 x 4 tile while the partials (two per block) fit the
+  // reduction buffer (kRedBlocks x (kMaxRestart + 2) entries)
+  const int ntiles = ((g.n0 + TX - 1) / TX) * ((g.n1 + TY - 1) / TY) * g.n2;
+  const int cap = kRedBlocks * (kMaxRestart + 2) / 2;
+  const int nb = ntiles < cap ? ntiles : cap;
+  hipLaunchKernelGGL((k_apply_dot<R, RI>), dim3(nb), dim3(256), 0, s, g, x, y, d0, mode, partials, S);
+  launch_bicg_final(partials, nb, mode == kBicgAlpha ? 1 : 2, S, mode, s);
+}
+
 template <typename R>
 void launch_inject_k2(int n0, int n1, int n2, const double *k2_fine, int f0, int f1, R *k2_coarse, hipStream_t s) {
   int stride = (f0 - 1) / (n0 - 1);
@@ -323,6 +382,12 @@ void launch_inject_k2(int n0, int n1, int n2, const double *k2_fine, int f0, int
 ECS_INST_MG(double)
 ECS_INST_MG(float)
 
+template void launch_apply_dot<double, double>(const Grid<double> &, const cplx<double> *, cplx<double> *,
+                                               const cplx<double> *, int, cplx<double> *, BicgScalars *, hipStream_t);
+template void launch_apply_dot<double, float>(const Grid<double> &, const cplx<float> *, cplx<double> *,
+                                              const cplx<double> *, int, cplx<double> *, BicgScalars *, hipStream_t);
+template void launch_apply_dot<float, float>(const Grid<float> &, const cplx<float> *, cplx<float> *,
+                                             const cplx<float> *, int, cplx<double> *, BicgScalars *, hipStream_t);
 template void launch_apply<double, double, double>(const Grid<double> &, const cplx<double> *, cplx<double> *,
                                                    hipStream_t);
 template void launch_apply<double, float, double>(const Grid<double> &, const cplx<float> *, cplx<double> *,

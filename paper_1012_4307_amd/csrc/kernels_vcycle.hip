@@ -59,7 +59,8 @@ __device__ __forceinline__ cplx<R> inv_c(cplx<R> d) {
 // reads red values one further still.
 template <typename R, int CY>
 __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
-                                                cplx<R> *__restrict__ u_out, cplx<R> *__restrict__ rc, R omega) {
+                                                cplx<R> *__restrict__ u_out, cplx<R> *__restrict__ rc, R omega,
+                                                int tiles_x, int tiles) {
   constexpr int CX = 29;
   constexpr int WX = 2 * CX + 5;          // 63 used columns
   constexpr int WY = 2 * CY + 5;
@@ -67,7 +68,9 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
   __shared__ cplx<R> su[WY][64];          // relaxed iterate
   __shared__ cplx<R> sr[WY][64];          // residual
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int I0 = blockIdx.x * CX, J0 = blockIdx.y * CY;
+  const int tile = xcd_tile(tiles);
+  if (tile < 0) return;
+  const int I0 = (tile % tiles_x) * CX, J0 = (tile / tiles_x) * CY;
   const int gx0 = 2 * I0 - 3, gy0 = 2 * J0 - 3;
   const int n0 = f.n0, n1 = f.n1;
   const R om1 = R(1) - omega;
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
 template <typename R, int TY>
 __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
                                               const cplx<R> *__restrict__ u_in, const cplx<R> *__restrict__ ec,
-                                              cplx<R> *__restrict__ u_out, R omega) {
+                                              cplx<R> *__restrict__ u_out, R omega, int tiles_x, int tiles) {
   constexpr int TX = 60;
   constexpr int WY = TY + 4;
   constexpr int RPW = (WY + 3) / 4;
@@ -169,7 +172,9 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
   __shared__ cplx<R> sv[WY][64];
   __shared__ cplx<R> se[CWY][CWX];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int tile = xcd_tile(tiles);
+  if (tile < 0) return;
+  const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
   const int gx0 = x0 - 2, gy0 = y0 - 2;
   const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1;  // coarse staging origin
   const int n0 = f.n0, n1 = f.n1;
@@ -516,14 +521,17 @@ template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *u, cplx<R> *rc, R omega,
                     hipStream_t s) {
   constexpr int CX = 29;
+  const int tx = (coarse.n0 + CX - 1) / CX;
   if (fine.n0 <= kSmallGrid && fine.n1 <= kSmallGrid) {
     constexpr int CY = kSmallDCY;
-    dim3 grid((coarse.n0 + CX - 1) / CX, (coarse.n1 + CY - 1) / CY);
-    hipLaunchKernelGGL((k_down_rb<R, CY>), grid, dim3(NT), 0, s, fine, coarse, b, u, rc, omega);
+    const int tiles = tx * ((coarse.n1 + CY - 1) / CY);
+    hipLaunchKernelGGL((k_down_rb<R, CY>), dim3(xcd_padded(tiles)), dim3(NT), 0, s, fine, coarse, b, u, rc, omega,
+                       tx, tiles);
   } else {
     constexpr int CY = Tiles<R>::DCY;
-    dim3 grid((coarse.n0 + CX - 1) / CX, (coarse.n1 + CY - 1) / CY);
-    hipLaunchKernelGGL((k_down_rb<R, CY>), grid, dim3(NT), 0, s, fine, coarse, b, u, rc, omega);
+    const int tiles = tx * ((coarse.n1 + CY - 1) / CY);
+    hipLaunchKernelGGL((k_down_rb<R, CY>), dim3(xcd_padded(tiles)), dim3(NT), 0, s, fine, coarse, b, u, rc, omega,
+                       tx, tiles);
   }
 }
 
@@ -531,14 +539,17 @@ template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
                   const cplx<R> *ec, cplx<R> *u_out, R omega, hipStream_t s) {
   constexpr int TX = 60;
+  const int tx = (fine.n0 + TX - 1) / TX;
   if (fine.n0 <= kSmallGrid && fine.n1 <= kSmallGrid) {
     constexpr int TY = kSmallUTY;
-    dim3 grid((fine.n0 + TX - 1) / TX, (fine.n1 + TY - 1) / TY);
-    hipLaunchKernelGGL((k_up_rb<R, TY>), grid, dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out, omega);
+    const int tiles = tx * ((fine.n1 + TY - 1) / TY);
+    hipLaunchKernelGGL((k_up_rb<R, TY>), dim3(xcd_padded(tiles)), dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out,
+                       omega, tx, tiles);
   } else {
     constexpr int TY = Tiles<R>::UTY;
-    dim3 grid((fine.n0 + TX - 1) / TX, (fine.n1 + TY - 1) / TY);
-    hipLaunchKernelGGL((k_up_rb<R, TY>), grid, dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out, omega);
+    const int tiles = tx * ((fine.n1 + TY - 1) / TY);
+    hipLaunchKernelGGL((k_up_rb<R, TY>), dim3(xcd_padded(tiles)), dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out,
+                       omega, tx, tiles);
   }
 }
 
