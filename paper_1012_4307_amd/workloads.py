@@ -197,9 +197,12 @@ def adjoint_case(n: int = 1025, E: float = 2.0, seed: int = SEED_ADJOINT):
     cx, cy = rng.uniform(-4.0, 4.0, size=2)
     bump = np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * 1.0 ** 2))
     k2_true = w.k2 * (1.0 + 0.05 * bump)
-    s = (n - 1) // 128
+    # 64 x 64 sampling nodes covering the same physical patch at every size
+    # (fewer on grids too coarse to hold 64 distinct nodes there)
+    count = min(64, (n - 1) // 2)
+    s = max(1, (n - 1) // 128)
     i0 = (n - 1) // 4
-    idx = i0 + s * np.arange(64)
+    idx = i0 + s * np.arange(count)
     fd_rng = np.random.default_rng(seed)
     w.name = f"adjoint_n{n}"
     return w, k2_true, idx, fd_rng

@@ -1,0 +1,109 @@
+"""The differentiable solve (torch.autograd.Function over the C ABI's adjoint
+solve) against central finite differences and against the oracle's gradient
+computed with its explicitly transposed operator.
+
+Loss: L(k^2) = 1/2 ||M(u) - d||^2, u = A(k^2)^{-1} f, M = sampling on a 64 x 64
+sub-grid, d = M(u) for a k^2 carrying a +5% Gaussian bump (seeded)."""
+import numpy as np
+import pytest
+
+from helpers import gpu_for, oracle_for, relerr, to_gpu, to_np
+import paper_1012_4307_amd as E
+from paper_1012_4307_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = E.Krylov(method="bicgstab", restart=40, rtol=1e-13, maxit=20000)
+
+
+def setup(n):
+    import torch
+    from paper_1012_4307_amd.autograd import helmholtz_solve
+    w, k2_true, idx, rng = W.adjoint_case(n=n)
+    S = gpu_for(w, "f64", krylov=TIGHT)
+    f = to_gpu(w.rhs[0])
+    S_true = gpu_for(W.Workload(w.name, 2, w.n, w.lo, w.hi, w.ecs, k2_true, w.rhs, w.precond, w.cycle, w.krylov,
+                                w.nlev), "f64", krylov=TIGHT)
+    u_true, _ = S_true.solve(f)
+    ii = torch.as_tensor(idx, device="cuda")
+    d = u_true[ii][:, ii]
+
+    def loss_of(k2):
+        u = helmholtz_solve(S, k2, f, krylov=TIGHT)
+        r = u[ii][:, ii] - d
+        return 0.5 * (r.real ** 2 + r.imag ** 2).sum(), u
+
+    return w, S, f, idx, d, loss_of, rng
+
+
+def test_autograd_gradient_vs_central_differences():
+    import torch
+    w, S, f, idx, d, loss_of, rng = setup(129)
+    k2 = to_gpu(w.k2).requires_grad_(True)
+    L, _ = loss_of(k2)
+    (g,) = torch.autograd.grad(L, k2)
+    g = to_np(g)
+    n = w.n[0]
+    x = W.real_nodes(n, -10.0, 10.0)
+    interior = [(j, i) for j in range(1, n - 1) for i in range(1, n - 1) if abs(x[i]) <= 8 and abs(x[j]) <= 8]
+    picks = [interior[q] for q in rng.choice(len(interior), size=12, replace=False)]
+    # eps = 1e-6 (the specified step): the FD quotient carries ~1e-15/eps of
+    # solve noise, so it is compared relative to the gradient's scale; eps =
+    # 1e-4 (truncation error O(eps^2) and 100x less noise): per-cell relative
+    gscale = np.abs(g).max()
+    with torch.no_grad():
+        for (j, i) in picks:
+            fds = {}
+            for eps in (1e-6, 1e-4):
+                kp = to_gpu(w.k2.copy()); kp[j, i] += eps
+                km = to_gpu(w.k2.copy()); km[j, i] -= eps
+                fds[eps] = (float(loss_of(kp)[0]) - float(loss_of(km)[0])) / (2 * eps)
+            assert abs(fds[1e-6] - g[j, i]) <= 1e-5 * gscale, (j, i, fds[1e-6], g[j, i], gscale)
+            assert abs(fds[1e-4] - g[j, i]) <= 1e-5 * abs(g[j, i]) + 1e-9 * gscale, (j, i, fds[1e-4], g[j, i])
+
+
+def test_autograd_gradient_vs_oracle():
+    """The oracle builds A^T explicitly (no W similarity) and solves
+    A^T lam = conj(M^T (M u - d)); grad = Re(lam u).  129^2 instance."""
+    import torch
+    w, S, f, idx, d, loss_of, _ = setup(129)
+    k2 = to_gpu(w.k2).requires_grad_(True)
+    L, u = loss_of(k2)
+    (g,) = torch.autograd.grad(L, k2)
+    P = oracle_for(w)
+    uo, st = P.solve(w.rhs[0], "gmres", 40, 1e-13, 20000)
+    assert st["status"] == 0
+    dn = to_np(d)
+    gg = np.zeros(w.shape, complex)
+    gg[np.ix_(idx, idx)] = uo[np.ix_(idx, idx)] - dn
+    lam, st = P.solve(np.conj(gg), "gmres", 40, 1e-13, 20000, transpose=True)
+    assert st["status"] == 0
+    go = (lam * uo).real
+    assert relerr(to_np(g), go) < 1e-7
+    assert relerr(to_np(u.detach()), uo) < 1e-9
+
+
+def test_autograd_gradient_wrt_rhs():
+    """dL/df = conj(lam): checked by central differences along random complex
+    directions of f."""
+    import torch
+    from paper_1012_4307_amd.autograd import helmholtz_solve
+    w, S, f, idx, d, loss_of, rng = setup(65)
+    k2 = to_gpu(w.k2)
+    ii = torch.as_tensor(idx, device="cuda")
+    fr = f.clone().requires_grad_(True)
+    u = helmholtz_solve(S, k2, fr, krylov=TIGHT)
+    r = u[ii][:, ii] - d
+    L = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
+    (gf,) = torch.autograd.grad(L, fr)
+    with torch.no_grad():
+        for _ in range(3):
+            dirn = to_gpu(W.random_complex(w.shape, rng))
+            eps = 1e-6
+            def Lf(ff):
+                uu = helmholtz_solve(S, k2, ff, krylov=TIGHT)
+                rr = uu[ii][:, ii] - d
+                return float(0.5 * (rr.real ** 2 + rr.imag ** 2).sum())
+            fd = (Lf(f + eps * dirn) - Lf(f - eps * dirn)) / (2 * eps)
+            an = float((torch.conj(gf) * dirn).real.sum())
+            assert abs(fd - an) <= 1e-5 * abs(fd) + 1e-14, (fd, an)
