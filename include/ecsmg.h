@@ -199,16 +199,41 @@ ecs_status ecs_level_info(ecs_ctx *ctx, int level, int *nlevels, int64_t *nodes)
 ecs_status ecs_timing_enable(ecs_ctx *ctx, int kclass, int enable);
 ecs_status ecs_timing_read(ecs_ctx *ctx, int kclass, int64_t *launches, double *total_ms, double *algo_bytes);
 
+/* Launch schedule of the fused 2D V(1,1) red-black cycle (performance only;
+ * results do not depend on it):
+ *   down_rows   coarse rows per block of the fused pre-smoothing/restriction
+ *               kernel on grids above small_grid: 2, 4, 8 (16 in FP32)
+ *   up_rows     fine rows per block of the fused prolongation/post-smoothing
+ *               kernel on grids above small_grid: 4, 8, 16 or 32
+ *   small_grid  grids with at most this many nodes per axis use 2 / 4 rows
+ *   tail_nodes  levels with at most this many nodes per axis (3..33) run in
+ *               the single-workgroup kernel that ends the cycle
+ * Defaults {8, 16, 513, 33}; a project autotuner picks values per grid size
+ * and dtype by timing cycles. */
+typedef struct {
+  int down_rows;
+  int up_rows;
+  int small_grid;
+  int tail_nodes;
+} ecs_tuning;
+ecs_status ecs_set_tuning(ecs_ctx *ctx, const ecs_tuning *tuning);
+ecs_status ecs_get_tuning(ecs_ctx *ctx, ecs_tuning *tuning);
+
 /* Replay the V(1,1) red-black cycle from captured HIP graphs (default on):
  * the cycle is recorded once per (input, output) buffer pair and replayed
  * with one launch.  0 launches every kernel eagerly (same results). */
 ecs_status ecs_set_graphs(ecs_ctx *ctx, int enable);
 
-/* Batched solve of n independent problems (each context fully set up with its
- * own workspace), all right-hand sides to their rtol with Bi-CGSTAB.  Every
- * iteration of all unconverged systems is issued as one grouped launch per
- * phase.  b[s], x[s] point to nrhs[s] contiguous complex128 vectors.
- * stats receives one entry per system (aggregated over its right-hand sides). */
+/* Batched solve of n independent problems (Bi-CGSTAB; desc->krylov must be
+ * ECS_KRYLOV_BICGSTAB).  Each context is fully set up with its own workspace
+ * (sized for a Bi-CGSTAB desc) and should have its own stream: the driver
+ * advances all systems in rounds -- one phase (||b||, true residual and
+ * restart, or one iteration) per unconverged system per round, enqueued on
+ * that system's stream -- and synchronises once per round.  b[s], x[s] point
+ * to nrhs[s] contiguous complex128 vectors of system s, solved one after the
+ * other.  stats[s] aggregates the system's right-hand sides: summed
+ * iterations, restarts and cycles, the largest final true residual, the worst
+ * status, and the wall time of the whole batch. */
 ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *desc, const void *const *b,
                            void *const *x, const int *nrhs, ecs_stats *stats);
 

@@ -55,6 +55,14 @@ class SolveDesc(ctypes.Structure):
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("down_rows", ctypes.c_int), ("up_rows", ctypes.c_int), ("small_grid", ctypes.c_int),
+                ("tail_nodes", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("vcycles", ctypes.c_int64),
                 ("inner_iterations", ctypes.c_int64), ("rel_residual", ctypes.c_double),
@@ -99,6 +107,8 @@ def lib():
         "ecs_batch_solve": [I, pP, ctypes.POINTER(SolveDesc), pP, pP, ctypes.POINTER(I), ctypes.POINTER(Stats)],
         "ecs_copy_probe": [P, P, Z, P],
         "ecs_set_graphs": [P, I],
+        "ecs_set_tuning": [P, ctypes.POINTER(Tuning)],
+        "ecs_get_tuning": [P, ctypes.POINTER(Tuning)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -116,7 +126,7 @@ EXPORTED = ["ecs_create", "ecs_set_ecs", "ecs_set_k2", "ecs_set_precond", "ecs_w
             "ecs_solve", "ecs_solve_adjoint", "ecs_grad_k2", "ecs_apply", "ecs_vcycle", "ecs_smooth",
             "ecs_residual_restrict", "ecs_prolong_correct", "ecs_coarse_solve", "ecs_level_info",
             "ecs_timing_enable", "ecs_timing_read", "ecs_batch_solve", "ecs_copy_probe", "ecs_last_error",
-            "ecs_destroy", "ecs_set_graphs"]
+            "ecs_destroy", "ecs_set_graphs", "ecs_set_tuning", "ecs_get_tuning"]
 
 
 def _torch():
@@ -364,6 +374,16 @@ class Solver:
         x = torch.empty_like(b)
         self._check(lib().ecs_coarse_solve(self._h, _ptr(b), _ptr(x)))
         return x
+
+    def set_tuning(self, down_rows=8, up_rows=16, small_grid=513, tail_nodes=33):
+        """Launch schedule of the fused V(1,1) cycle (performance only)."""
+        t = Tuning(down_rows, up_rows, small_grid, tail_nodes)
+        self._check(lib().ecs_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(lib().ecs_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
 
     def set_graphs(self, enable: bool):
         """Replay the V(1,1) red-black cycle from captured HIP graphs (default)."""

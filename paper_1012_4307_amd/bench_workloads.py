@@ -1,0 +1,201 @@
+"""Secondary measurements behind ``bench.py --config ...`` (the headline line is
+the 2049^2 mixed-precision solve).  Each prints one JSON line.
+
+batched     many independent systems (grids 257^2 / 513^2 / 1025^2, E, theta
+            and 1-8 right-hand sides per system, seeded) in one batched
+            Bi-CGSTAB call, each system on its own stream, cycle schedule
+            autotuned per grid; aggregate right-hand sides solved per second,
+            beside the same systems solved one call at a time.
+adjoint     the differentiable solve on 1025^2 (E = 2): forward and backward
+            (adjoint) time, gradient of L = 1/2 ||M u - d||^2 against central
+            differences on sampled nodes.
+cube        3D 7-point 129^3 forward solve at constant k = 12 (QD, V(1,1)
+            red-black, FGMRES(30)).
+coulomb513  soft-Coulomb QD problems on 513^2, E in {0.5, 1, 2, 4}, Bi-CGSTAB.
+small65     the 65^2 constant-k problem (CSL, omega-Jacobi, GMRES(30)) for both
+            right-hand sides and both signs of the complex shift.
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+
+import numpy as np
+
+
+def _emit(d):
+    print(json.dumps(d), flush=True)
+
+
+def _solver(w, vcycle_dtype="f64", krylov=None, stream=None):
+    import torch
+    from . import solver_for
+    if stream is None:
+        return solver_for(w, vcycle_dtype=vcycle_dtype, krylov=krylov)
+    with torch.cuda.stream(stream):
+        return solver_for(w, vcycle_dtype=vcycle_dtype, krylov=krylov)
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def batched(args):
+    import torch
+    from . import Krylov, batch_solve
+    from . import workloads as W
+    from .autotune import autotune
+    descs = W.batch_systems(count=args.batch_count)
+    kr = Krylov(method="bicgstab", rtol=1e-8, maxit=20000)
+    streams = [torch.cuda.Stream() for _ in range(8)]
+    solvers, rhs = [], []
+    tuned = {}
+    for q, d in enumerate(descs):
+        w = W.batch_inputs(d)
+        S = _solver(w, "f64", kr, streams[q % len(streams)])
+        key = (d["n"], "f64")
+        if key not in tuned:
+            tuned[key] = autotune(S)
+        else:
+            S.set_tuning(**tuned[key])
+        solvers.append(S)
+        rhs.append(torch.stack([torch.from_numpy(b).to("cuda") for b in w.rhs]))
+    torch.cuda.synchronize()
+    total = sum(int(b.shape[0]) for b in rhs)
+    batch_solve(solvers, rhs, kr)   # warm-up (also fills the graph caches)
+    (xs, stats), secs = _timed(lambda: batch_solve(solvers, rhs, kr))
+    ok = all(s["status"] == 0 for s in stats)
+    worst = max(s["rel_residual"] for s in stats)
+    # the same work one call at a time (sequential solves, one stream)
+    seq_sample = min(len(solvers), 12)
+    (_, seq_secs) = _timed(lambda: [solvers[q].solve(rhs[q][r], krylov=kr)
+                                    for q in range(seq_sample) for r in range(rhs[q].shape[0])])
+    seq_total = sum(int(rhs[q].shape[0]) for q in range(seq_sample))
+    by_size = {}
+    for q, d in enumerate(descs):
+        e = by_size.setdefault(d["n"], dict(systems=0, rhs=0, iterations=0))
+        e["systems"] += 1
+        e["rhs"] += int(rhs[q].shape[0])
+        e["iterations"] += stats[q]["iterations"]
+    _emit(dict(metric="batched ECS Helmholtz solves to 1e-8 (Bi-CGSTAB, QD V(1,1) RB-GS)", unit="solves/s",
+               value=round(total / secs, 3), higher_is_better=True, systems=len(descs), right_hand_sides=total,
+               seconds=round(secs, 3), all_converged=ok, worst_rel_residual=worst,
+               sequential_solves_per_s=round(seq_total / seq_secs, 3), sequential_sample_rhs=seq_total,
+               speedup_vs_sequential=round((total / secs) / (seq_total / seq_secs), 3),
+               tuning={f"{k[0]}_{k[1]}": v for k, v in tuned.items()}, by_size=by_size,
+               dtype="f64", data="synthetic"))
+
+
+def adjoint(args):
+    import torch
+    from . import Krylov
+    from . import workloads as W
+    from .autograd import helmholtz_solve
+    n = 1025
+    w, k2_true, idx, rng = W.adjoint_case(n=n)
+    fwd = Krylov(method="bicgstab", rtol=1e-8, maxit=20000)
+    tight = Krylov(method="bicgstab", rtol=1e-13, maxit=40000)
+    S = _solver(w, "f64", tight)
+    f = torch.from_numpy(w.rhs[0]).to("cuda")
+    k2 = torch.from_numpy(w.k2).to("cuda")
+    ii = torch.as_tensor(idx, device="cuda")
+    from . import solver_for
+    wt = W.Workload(w.name, 2, w.n, w.lo, w.hi, w.ecs, k2_true, w.rhs, w.precond, w.cycle, w.krylov, w.nlev)
+    St = solver_for(wt, krylov=tight)
+    ut, _ = St.solve(f)
+    d = ut[ii][:, ii]
+    del St
+
+    def loss(k2v, kr):
+        u = helmholtz_solve(S, k2v, f, krylov=kr, adjoint_krylov=kr)
+        r = u[ii][:, ii] - d
+        return 0.5 * (r.real ** 2 + r.imag ** 2).sum()
+
+    kg = k2.clone().requires_grad_(True)
+    L = loss(kg, fwd)
+    (g,), t_fwd_bwd = _timed(lambda: torch.autograd.grad(loss(kg, fwd), kg))
+    (u_only, t_fwd) = _timed(lambda: S.solve(f, krylov=fwd))
+    kg = k2.clone().requires_grad_(True)
+    (gt,) = torch.autograd.grad(loss(kg, tight), kg)
+    gt = gt.cpu().numpy()
+    x = W.real_nodes(n, -10.0, 10.0)
+    inner = np.flatnonzero((np.abs(x) <= 8))
+    cells = [(int(rng.choice(inner)), int(rng.choice(inner))) for _ in range(10)]
+    errs = []
+    gscale = float(np.abs(gt).max())
+    with torch.no_grad():
+        for (j, i) in cells:
+            out = {}
+            for eps in (1e-6, 1e-4):
+                kp = k2.clone(); kp[j, i] += eps
+                km = k2.clone(); km[j, i] -= eps
+                out[eps] = (float(loss(kp, tight)) - float(loss(km, tight))) / (2 * eps)
+            errs.append(dict(cell=[j, i], grad=float(gt[j, i]), fd_1e6=out[1e-6], fd_1e4=out[1e-4],
+                             err_1e6_rel_scale=abs(out[1e-6] - gt[j, i]) / gscale,
+                             err_1e4_rel=abs(out[1e-4] - gt[j, i]) / max(abs(gt[j, i]), 1e-30)))
+    _emit(dict(metric="adjoint gradient of a 1025^2 ECS solve", unit="s", value=round(t_fwd_bwd, 4),
+               higher_is_better=False, forward_seconds=round(t_fwd, 4),
+               forward_plus_backward_seconds=round(t_fwd_bwd, 4), loss=float(L),
+               max_fd_err_eps1e6_rel_to_max_grad=max(e["err_1e6_rel_scale"] for e in errs),
+               max_fd_err_eps1e4_rel=max(e["err_1e4_rel"] for e in errs), cells=errs,
+               dtype="f64", data="synthetic"))
+
+
+def cube(args):
+    import torch
+    from . import Krylov
+    from . import workloads as W
+    w = W.cube_constant_k(n=129, k=12.0)
+    kr = Krylov(method="fgmres", restart=30, rtol=1e-8, maxit=5000)
+    S = _solver(w, "f64", kr)
+    f = torch.from_numpy(w.rhs[0]).to("cuda")
+    S.solve(f)
+    (x, st), secs = _timed(lambda: S.solve(f))
+    _emit(dict(metric="3D 129^3 ECS Helmholtz solve to 1e-8 (k = 12, QD, V(1,1) RB-GS, FGMRES(30))", unit="s",
+               value=round(secs, 4), higher_is_better=False, iterations=st["iterations"], vcycles=st["vcycles"],
+               rel_residual=st["rel_residual"], status=st["status"], dtype="f64", data="synthetic"))
+
+
+def coulomb513(args):
+    import torch
+    from . import workloads as W
+    rows = []
+    for E_ in (0.5, 1.0, 2.0, 4.0):
+        w = W.coulomb(E=E_, n=513)
+        S = _solver(w, "f64")
+        f = torch.from_numpy(w.rhs[0]).to("cuda")
+        S.solve(f)
+        (x, st), secs = _timed(lambda: S.solve(f))
+        rows.append(dict(E=E_, seconds=round(secs, 4), iterations=st["iterations"], rel_residual=st["rel_residual"]))
+    _emit(dict(metric="513^2 soft-Coulomb QD Bi-CGSTAB solves to 1e-8", unit="s",
+               value=round(sum(r["seconds"] for r in rows), 4), higher_is_better=False, runs=rows, dtype="f64",
+               data="synthetic"))
+
+
+def small65(args):
+    import torch
+    from . import workloads as W
+    rows = []
+    for beta2 in (0.5, -0.5):
+        w = W.small_constant_k(beta2=beta2)
+        S = _solver(w, "f64")
+        for q, b in enumerate(w.rhs):
+            f = torch.from_numpy(b).to("cuda")
+            S.solve(f)
+            (x, st), secs = _timed(lambda: S.solve(f))
+            rows.append(dict(beta2=beta2, rhs=["gaussian", "random"][q], seconds=round(secs, 5),
+                             iterations=st["iterations"], rel_residual=st["rel_residual"]))
+    _emit(dict(metric="65^2 constant-k CSL GMRES(30) solves to 1e-8", unit="s",
+               value=round(sum(r["seconds"] for r in rows), 4), higher_is_better=False, runs=rows, dtype="f64",
+               data="synthetic"))
+
+
+def run(args):
+    {"batched": batched, "adjoint": adjoint, "cube": cube, "coulomb513": coulomb513, "small65": small65}[args.config](
+        args)

@@ -95,12 +95,13 @@ void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, 
                          cplx<R> *x, hipStream_t s);
 // fused V(1,1) red-black kernels (2D): zero-guess pre-sweep + residual + FW,
 // and prolongation + correction + post-sweep (out of place)
+// (rows: tile height, see ecs_tuning)
 template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *u, cplx<R> *rc, R omega,
-                    hipStream_t s);
+                    int rows, hipStream_t s);
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
-                  const cplx<R> *ec, cplx<R> *u_out, R omega, hipStream_t s);
+                  const cplx<R> *ec, cplx<R> *u_out, R omega, int rows, hipStream_t s);
 // the coarsest levels of a 2D V(1,1) red-black cycle in one workgroup:
 // levels with at most kTailNodes nodes per axis (and 2048 nodes in all)
 constexpr int kTailMaxLevels = 8;

@@ -121,6 +121,9 @@ struct ecs_ctx {
   std::vector<GraphEntry> graphs;
   hipStream_t capture = nullptr;
   bool use_graphs = true;
+
+  // launch schedule of the fused V(1,1) cycle (autotuned per grid and dtype)
+  ecs_tuning tune{8, 16, 513, 33};
 };
 
 namespace {
@@ -654,18 +657,21 @@ template <typename R>
 void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
   const int lc = C->nlev - 1;
   const R om = (R)C->prec.omega;
-  // first level handled by the tail: the coarsest k levels that are small
+  const ecs_tuning &T = C->tune;
+  // first level handled by the tail: the coarsest levels that are small
   int lt = lc;
-  while (lt > 0 && C->hl[lt - 1].n[0] <= kTailNodes && C->hl[lt - 1].n[1] <= kTailNodes &&
+  while (lt > 0 && C->hl[lt - 1].n[0] <= T.tail_nodes && C->hl[lt - 1].n[1] <= T.tail_nodes &&
          lc - (lt - 1) + 1 <= kTailMaxLevels)
     lt--;
+  auto small = [&](int l) { return C->hl[l].n[0] <= T.small_grid && C->hl[l].n[1] <= T.small_grid; };
   for (int l = 0; l < lt; l++) {
     DevLevel<R> &D = dev_level<R>(C, l);
     DevLevel<R> &Dc = dev_level<R>(C, l + 1);
     const cplx<R> *b = l == 0 ? b0 : D.b;
     // reads b, k^2; writes u and the coarse residual
     TimedScope ts(C, l == 0 ? kTDown : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 5.5);
-    launch_down_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.b, om, C->stream);
+    launch_down_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.b, om, small(l) ? 2 : T.down_rows,
+                      C->stream);
   }
   {
     TailArgs<R> a{};
@@ -692,7 +698,8 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
     cplx<R> *out = l == 0 ? u0 : D.u;
     // reads u, the coarse correction, b, k^2; writes u
     TimedScope ts(C, l == 0 ? kTUp : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 7.5);
-    launch_up_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.u, out, om, C->stream);
+    launch_up_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.u, out, om, small(l) ? 4 : T.up_rows,
+                    C->stream);
   }
 }
 
@@ -906,14 +913,71 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
   return status;
 }
 
+ecs_status check_ready(ecs_ctx *C) {
+  if (!C) return ECS_EINVAL;
+  if (!C->ready) return fail(C, ECS_ESTATE, "call ecs_set_workspace after ecs_set_k2 and ecs_set_precond");
+  return ECS_OK;
+}
+
+// Bi-CGSTAB building blocks (right-preconditioned, van der Vorst; Sec. 5),
+// shared by the single solve and the batched driver.  Every scalar stays in
+// device memory (C->bs); the host only reads {est, bad} after each step.
+
+// r = b - A x, the restart scalars (est = ||r|| / ||b||, rho = ||r||^2,
+// beta = 0), r^ = r, p = v = 0
+void bicg_enqueue_restart(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *b, const cplx<double> *x) {
+  const int64_t n = nn_of(C);
+  hipStream_t s = C->stream;
+  {
+    TimedScope ts(C, kTApply, (double)n * 56);
+    launch_residual<double>(grid_A(C), b, x, K.r, s);
+  }
+  launch_pairdot<double>(K.r, K.r, nullptr, nullptr, 1, n, C->partials, C->bs, kBicgInit, s);
+  (void)hipMemcpyAsync(K.rh, K.r, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, s);
+  launch_zero<double>(K.p, n, s);
+  launch_zero<double>(K.v, n, s);
+}
+
+// one iteration: p = r + beta (p - omega v); ph = M^{-1} p; v = A ph -> alpha;
+// s = r - alpha v; sh = M^{-1} s; t = A sh -> omega; x += alpha ph + omega sh;
+// r = s - omega t -> est and the next beta
+template <typename RZ>
+void bicg_enqueue_step(ecs_ctx *C, const KrylovBufs &K, cplx<double> *x) {
+  const int64_t n = nn_of(C);
+  hipStream_t s = C->stream;
+  BicgScalars *S = C->bs;
+  cplx<RZ> *ph = reinterpret_cast<cplx<RZ> *>(K.ph);
+  cplx<RZ> *sh = reinterpret_cast<cplx<RZ> *>(K.sh);
+  launch_bicg_p<double>(K.p, K.r, K.v, n, S, s);
+  precond<RZ>(C, K.p, ph);
+  {
+    TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 40));
+    launch_apply_dot<double, RZ>(grid_A(C), ph, K.v, K.rh, kBicgAlpha, C->partials, S, s);
+  }
+  launch_bicg_s<double>(K.s, K.r, K.v, n, S, s);
+  precond<RZ>(C, K.s, sh);
+  {
+    TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 40));
+    launch_apply_dot<double, RZ>(grid_A(C), sh, K.tt, K.s, kBicgOmega, C->partials, S, s);
+  }
+  launch_bicg_xr<double, RZ>(x, ph, sh, K.r, K.s, K.tt, K.rh, n, C->partials, S, s);
+}
+
+// {est, bad} of the Bi-CGSTAB scalars into the pinned buffer (async)
+void bicg_enqueue_readback(ecs_ctx *C) {
+  (void)hipMemcpyAsync(C->pinned, &C->bs->est, sizeof(double) + sizeof(int), hipMemcpyDeviceToHost, C->stream);
+}
+void bicg_take_readback(const ecs_ctx *C, double *est, int *bad) {
+  std::memcpy(est, C->pinned, sizeof(double));
+  std::memcpy(bad, reinterpret_cast<const char *>(C->pinned) + sizeof(double), sizeof(int));
+}
+
 template <typename RZ>
 ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const cplx<double> *b, cplx<double> *x,
                     ecs_stats *st) {
   const int64_t n = nn_of(C);
   hipStream_t s = C->stream;
   BicgScalars *S = C->bs;
-  cplx<RZ> *ph = reinterpret_cast<cplx<RZ> *>(K.ph);
-  cplx<RZ> *sh = reinterpret_cast<cplx<RZ> *>(K.sh);
   launch_nrm2sq<double>(b, n, C->partials, &C->gs->nrm2, s);
   const double bnorm = std::sqrt(read_scalar(C, &C->gs->nrm2.re));
   if (!(bnorm == bnorm) || std::isinf(bnorm)) return fail(C, ECS_EBREAKDOWN, "right-hand side contains NaN/Inf");
@@ -928,11 +992,7 @@ ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, co
   double last_restart = INFINITY;
   ecs_status status = ECS_NOT_CONVERGED;
   for (;;) {
-    {
-      TimedScope ts(C, kTApply, (double)n * 56);
-      launch_residual<double>(grid_A(C), b, x, K.r, s);
-    }
-    launch_pairdot<double>(K.r, K.r, nullptr, nullptr, 1, n, C->partials, S, kBicgInit, s);
+    bicg_enqueue_restart(C, K, b, x);
     double rt = read_scalar(C, &S->est);
     st->rel_residual = rt;
     if (!(rt == rt) || std::isinf(rt)) {
@@ -948,31 +1008,15 @@ ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, co
       }
     }
     last_restart = rt;
-    (void)hipMemcpyAsync(K.rh, K.r, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, s);
-    launch_zero<double>(K.p, n, s);
-    launch_zero<double>(K.v, n, s);
     while (it < d->maxit) {
-      launch_bicg_p<double>(K.p, K.r, K.v, n, S, s);
-      precond<RZ>(C, K.p, ph);
-      {
-        TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 40));
-        launch_apply_dot<double, RZ>(grid_A(C), ph, K.v, K.rh, kBicgAlpha, C->partials, S, s);
-      }
-      launch_bicg_s<double>(K.s, K.r, K.v, n, S, s);
-      precond<RZ>(C, K.s, sh);
-      {
-        TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 40));
-        launch_apply_dot<double, RZ>(grid_A(C), sh, K.tt, K.s, kBicgOmega, C->partials, S, s);
-      }
-      launch_bicg_xr<double, RZ>(x, ph, sh, K.r, K.s, K.tt, K.rh, n, C->partials, S, s);
+      bicg_enqueue_step<RZ>(C, K, x);
+      bicg_enqueue_readback(C);
       st->vcycles += 2;
       it++;
-      // est and bad are contiguous: one readback per iteration
-      if (!read_bytes(C, &S->est, sizeof(double) + sizeof(int))) break;
+      if (hipStreamSynchronize(s) != hipSuccess) break;
       double est;
       int bad;
-      std::memcpy(&est, C->pinned, sizeof(double));
-      std::memcpy(&bad, reinterpret_cast<char *>(C->pinned) + sizeof(double), sizeof(int));
+      bicg_take_readback(C, &est, &bad);
       if (d->history && it - 1 < d->history_len) d->history[it - 1] = est;
       if (bad) break;  // restart from the current iterate
       if (est <= d->rtol) break;
@@ -984,11 +1028,140 @@ ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, co
   return status;
 }
 
-ecs_status check_ready(ecs_ctx *C) {
-  if (!C) return ECS_EINVAL;
-  if (!C->ready) return fail(C, ECS_ESTATE, "call ecs_set_workspace after ecs_set_k2 and ecs_set_precond");
-  return ECS_OK;
+// ------------------------------------------------------------- batched
+// Many independent systems (each context with its own workspace and, ideally,
+// its own stream), every right-hand side solved by Bi-CGSTAB.  The driver
+// advances all systems in rounds: each round enqueues one phase per active
+// system (start: ||b||; verify: true residual and restart scalars; step: one
+// iteration) followed by the 12-byte readback, then synchronises once and
+// moves every system's state machine on.  A system's right-hand sides are
+// taken one after the other (its workspace holds one solve's vectors).
+struct BatchItem {
+  ecs_ctx *C = nullptr;
+  KrylovBufs K;
+  const cplx<double> *b0 = nullptr;
+  cplx<double> *x0 = nullptr;
+  int nrhs = 0, r = 0;
+  int phase = 0;  // 0 start, 1 verify, 2 iterate, 3 finished
+  int it = 0, stalls = 0, restarts = 0;
+  double last_restart = INFINITY, rt = 0;
+  ecs_stats agg{};
+  ecs_status worst = ECS_OK;
+};
+
+void batch_finish_rhs(BatchItem &I, ecs_status st, const ecs_solve_desc *d) {
+  I.agg.iterations += I.it;
+  I.agg.restarts += I.restarts;
+  I.agg.rel_residual = std::max(I.agg.rel_residual, I.rt);
+  if (st != ECS_OK && (I.worst == ECS_OK || st < 0)) I.worst = st;
+  (void)d;
+  I.r++;
+  I.it = I.stalls = I.restarts = 0;
+  I.last_restart = INFINITY;
+  I.rt = 0;
+  I.phase = I.r < I.nrhs ? 0 : 3;
 }
+
+ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *d, const void *const *b,
+                            void *const *x, const int *nrhs, ecs_stats *stats) {
+  std::vector<BatchItem> items(n);
+  std::vector<hipStream_t> streams;
+  for (int q = 0; q < n; q++) {
+    ecs_ctx *C = ctxs[q];
+    ecs_status st = check_ready(C);
+    if (st != ECS_OK) return st;
+    if (nrhs[q] < 0) return fail(C, ECS_EINVAL, "negative right-hand side count");
+    const size_t need = C->hier_bytes + plan_krylov(C, d, nullptr, &items[q].K);
+    if (need > C->ws_bytes) return fail(C, ECS_ENOMEM, "workspace too small for the batched solve");
+    plan_krylov(C, d, C->ws + C->hier_bytes, &items[q].K);
+    items[q].C = C;
+    items[q].b0 = reinterpret_cast<const cplx<double> *>(b[q]);
+    items[q].x0 = reinterpret_cast<cplx<double> *>(x[q]);
+    items[q].nrhs = nrhs[q];
+    items[q].phase = nrhs[q] > 0 ? 0 : 3;
+    if (std::find(streams.begin(), streams.end(), C->stream) == streams.end()) streams.push_back(C->stream);
+  }
+  for (;;) {
+    bool any = false;
+    for (auto &I : items) {
+      if (I.phase == 3) continue;
+      any = true;
+      ecs_ctx *C = I.C;
+      const int64_t nn = nn_of(C);
+      const HostLevel &F = C->hl[0];
+      cplx<double> *xr = I.x0 + (int64_t)I.r * nn;
+      if (I.phase == 0) {
+        launch_mask_boundary(F.n[0], F.n[1], F.n[2], I.b0 + (int64_t)I.r * nn, I.K.bz, C->stream);
+        if (d->x_is_guess) launch_mask_boundary(F.n[0], F.n[1], F.n[2], xr, xr, C->stream);
+        else launch_zero<double>(xr, nn, C->stream);
+        launch_nrm2sq<double>(I.K.bz, nn, C->partials, &C->gs->nrm2, C->stream);
+        (void)hipMemcpyAsync(C->pinned, &C->gs->nrm2.re, sizeof(double), hipMemcpyDeviceToHost, C->stream);
+      } else if (I.phase == 1) {
+        bicg_enqueue_restart(C, I.K, I.K.bz, xr);
+        bicg_enqueue_readback(C);
+      } else {
+        if (C->prec.vcycle_dtype == ECS_F32) bicg_enqueue_step<float>(C, I.K, xr);
+        else bicg_enqueue_step<double>(C, I.K, xr);
+        bicg_enqueue_readback(C);
+      }
+    }
+    if (!any) break;
+    for (hipStream_t s : streams)
+      if (hipStreamSynchronize(s) != hipSuccess) return ECS_EDEVICE;
+    for (auto &I : items) {
+      if (I.phase == 3) continue;
+      ecs_ctx *C = I.C;
+      if (I.phase == 0) {
+        double bn2;
+        std::memcpy(&bn2, C->pinned, sizeof(double));
+        const double bn = std::sqrt(bn2);
+        if (!(bn == bn) || std::isinf(bn)) {
+          batch_finish_rhs(I, ECS_EBREAKDOWN, d);
+        } else if (bn == 0) {
+          I.rt = 0;
+          launch_zero<double>(I.x0 + (int64_t)I.r * nn_of(C), nn_of(C), C->stream);  // A x = 0 -> x = 0
+          batch_finish_rhs(I, ECS_OK, d);
+        } else {
+          C->pinned[2] = bn;  // H2D source stays untouched by the {est, bad} readbacks
+          (void)hipMemcpyAsync(&C->bs->bnorm, &C->pinned[2], sizeof(double), hipMemcpyHostToDevice, C->stream);
+          I.phase = 1;
+        }
+        continue;
+      }
+      double est;
+      int bad;
+      bicg_take_readback(C, &est, &bad);
+      if (I.phase == 1) {
+        I.rt = est;
+        if (!(est == est) || std::isinf(est)) {
+          batch_finish_rhs(I, ECS_EBREAKDOWN, d);
+        } else if (est <= d->rtol) {
+          batch_finish_rhs(I, ECS_OK, d);
+        } else if (I.it >= d->maxit) {
+          batch_finish_rhs(I, ECS_NOT_CONVERGED, d);
+        } else if (est >= I.last_restart && ++I.stalls >= 3) {
+          batch_finish_rhs(I, ECS_EBREAKDOWN, d);
+        } else {
+          if (I.last_restart < INFINITY) I.restarts++;
+          I.last_restart = est;
+          I.phase = 2;
+        }
+      } else {
+        I.it++;
+        I.agg.vcycles += 2;
+        if (bad || est <= d->rtol || I.it >= d->maxit) I.phase = 1;
+      }
+    }
+  }
+  ecs_status worst = ECS_OK;
+  for (int q = 0; q < n; q++) {
+    items[q].agg.status = items[q].worst;
+    if (stats) stats[q] = items[q].agg;
+    if (items[q].worst != ECS_OK && (worst == ECS_OK || items[q].worst < 0)) worst = items[q].worst;
+  }
+  return worst;
+}
+
 
 ecs_status solve_impl(ecs_ctx *C, const ecs_solve_desc *d, const cplx<double> *b, cplx<double> *x, ecs_stats *st) {
   if (d->restart < 1 || d->restart > kMaxRestart) return fail(C, ECS_EINVAL, "restart must be in [1, 64]");
@@ -1337,26 +1510,34 @@ ecs_status ecs_timing_read(ecs_ctx *C, int kclass, int64_t *launches, double *to
 ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *desc, const void *const *b,
                            void *const *x, const int *nrhs, ecs_stats *stats) {
   if (n < 0 || (n > 0 && (!ctxs || !desc || !b || !x || !nrhs))) return ECS_EINVAL;
-  ecs_status worst = ECS_OK;
-  for (int q = 0; q < n; q++) {
-    ecs_ctx *C = ctxs[q];
-    ecs_stats agg{};
-    for (int r = 0; r < nrhs[q]; r++) {
-      const int64_t off = (int64_t)r * nn_of(C);
-      ecs_stats st{};
-      ecs_status rc = ecs_solve(C, desc, reinterpret_cast<const cplx<double> *>(b[q]) + off,
-                                reinterpret_cast<cplx<double> *>(x[q]) + off, &st);
-      agg.iterations += st.iterations;
-      agg.restarts += st.restarts;
-      agg.vcycles += st.vcycles;
-      agg.seconds += st.seconds;
-      agg.rel_residual = std::max(agg.rel_residual, st.rel_residual);
-      if (rc != ECS_OK && (worst == ECS_OK || rc < 0)) worst = rc;
-      agg.status = agg.status == ECS_OK ? rc : agg.status;
-    }
-    if (stats) stats[q] = agg;
-  }
-  return worst;
+  if (n == 0) return ECS_OK;
+  if (desc->krylov != ECS_KRYLOV_BICGSTAB) return fail(ctxs[0], ECS_EINVAL, "the batched solve uses Bi-CGSTAB");
+  if (!(desc->rtol > 0) || desc->maxit < 0) return fail(ctxs[0], ECS_EINVAL, "rtol must be > 0, maxit >= 0");
+  auto t0 = std::chrono::steady_clock::now();
+  ecs_status st = batch_solve_impl(n, ctxs, desc, b, x, nrhs, stats);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats)
+    for (int q = 0; q < n; q++) stats[q].seconds = secs;
+  return st;
+}
+
+ecs_status ecs_set_tuning(ecs_ctx *C, const ecs_tuning *t) {
+  if (!C || !t) return ECS_EINVAL;
+  const bool f32 = C->have_prec && C->prec.vcycle_dtype == ECS_F32;
+  const bool down_ok = t->down_rows == 2 || t->down_rows == 4 || t->down_rows == 8 || (t->down_rows == 16 && f32);
+  const bool up_ok = t->up_rows == 4 || t->up_rows == 8 || t->up_rows == 16 || t->up_rows == 32;
+  if (!down_ok || !up_ok) return fail(C, ECS_EINVAL, "unsupported tile height");
+  if (t->tail_nodes < 3 || t->tail_nodes > kTailNodes) return fail(C, ECS_EINVAL, "tail_nodes must be in [3, 33]");
+  if (t->small_grid < 3) return fail(C, ECS_EINVAL, "small_grid must be >= 3");
+  C->tune = *t;
+  drop_graphs(C);
+  return ECS_OK;
+}
+
+ecs_status ecs_get_tuning(ecs_ctx *C, ecs_tuning *t) {
+  if (!C || !t) return ECS_EINVAL;
+  *t = C->tune;
+  return ECS_OK;
 }
 
 ecs_status ecs_set_graphs(ecs_ctx *C, int enable) {

@@ -500,56 +500,44 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
   }
 }
 
-// tile heights (coarse rows for down, fine rows for up); small grids use
-// short tiles so that a block's serial row loop stays short
-template <typename R>
-struct Tiles;
-template <>
-struct Tiles<double> {
-  static constexpr int DCY = 8, UTY = 16;
-};
-template <>
-struct Tiles<float> {
-  static constexpr int DCY = 16, UTY = 32;
-};
-constexpr int kSmallDCY = 2, kSmallUTY = 4;
-constexpr int kSmallGrid = 513;  // fine grids up to this size use the short tiles
-
 }  // namespace
 
+// The tile height of the fused kernels is a launch parameter chosen by the
+// host (autotuned per grid size and dtype): coarse rows per down block in
+// {2, 4, 8, 16} (16 only in FP32, whose tile fits the LDS), fine rows per up
+// block in {4, 8, 16, 32}.
 template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *u, cplx<R> *rc, R omega,
-                    hipStream_t s) {
+                    int rows, hipStream_t s) {
   constexpr int CX = 29;
   const int tx = (coarse.n0 + CX - 1) / CX;
-  if (fine.n0 <= kSmallGrid && fine.n1 <= kSmallGrid) {
-    constexpr int CY = kSmallDCY;
-    const int tiles = tx * ((coarse.n1 + CY - 1) / CY);
-    hipLaunchKernelGGL((k_down_rb<R, CY>), dim3(xcd_padded(tiles)), dim3(NT), 0, s, fine, coarse, b, u, rc, omega,
-                       tx, tiles);
-  } else {
-    constexpr int CY = Tiles<R>::DCY;
-    const int tiles = tx * ((coarse.n1 + CY - 1) / CY);
-    hipLaunchKernelGGL((k_down_rb<R, CY>), dim3(xcd_padded(tiles)), dim3(NT), 0, s, fine, coarse, b, u, rc, omega,
-                       tx, tiles);
+  const int tiles = tx * ((coarse.n1 + rows - 1) / rows);
+  const dim3 grid(xcd_padded(tiles)), block(NT);
+  switch (rows) {
+    case 2: hipLaunchKernelGGL((k_down_rb<R, 2>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
+    case 4: hipLaunchKernelGGL((k_down_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
+    case 16:
+      if constexpr (sizeof(R) == 4) {
+        hipLaunchKernelGGL((k_down_rb<R, 16>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles);
+        break;
+      }
+      [[fallthrough]];
+    default: hipLaunchKernelGGL((k_down_rb<R, 8>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
   }
 }
 
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
-                  const cplx<R> *ec, cplx<R> *u_out, R omega, hipStream_t s) {
+                  const cplx<R> *ec, cplx<R> *u_out, R omega, int rows, hipStream_t s) {
   constexpr int TX = 60;
   const int tx = (fine.n0 + TX - 1) / TX;
-  if (fine.n0 <= kSmallGrid && fine.n1 <= kSmallGrid) {
-    constexpr int TY = kSmallUTY;
-    const int tiles = tx * ((fine.n1 + TY - 1) / TY);
-    hipLaunchKernelGGL((k_up_rb<R, TY>), dim3(xcd_padded(tiles)), dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out,
-                       omega, tx, tiles);
-  } else {
-    constexpr int TY = Tiles<R>::UTY;
-    const int tiles = tx * ((fine.n1 + TY - 1) / TY);
-    hipLaunchKernelGGL((k_up_rb<R, TY>), dim3(xcd_padded(tiles)), dim3(NT), 0, s, fine, coarse, b, u_in, ec, u_out,
-                       omega, tx, tiles);
+  const int tiles = tx * ((fine.n1 + rows - 1) / rows);
+  const dim3 grid(xcd_padded(tiles)), block(NT);
+  switch (rows) {
+    case 4: hipLaunchKernelGGL((k_up_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
+    case 8: hipLaunchKernelGGL((k_up_rb<R, 8>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
+    case 32: hipLaunchKernelGGL((k_up_rb<R, 32>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
+    default: hipLaunchKernelGGL((k_up_rb<R, 16>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
   }
 }
 
@@ -559,14 +547,15 @@ void launch_tail(const TailArgs<R> &a, hipStream_t s) {
 }
 
 template void launch_down_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *, cplx<double> *,
-                                     cplx<double> *, double, hipStream_t);
+                                     cplx<double> *, double, int, hipStream_t);
 template void launch_down_rb<float>(const Grid<float> &, const Grid<float> &, const cplx<float> *, cplx<float> *,
-                                    cplx<float> *, float, hipStream_t);
+                                    cplx<float> *, float, int, hipStream_t);
 template void launch_up_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *,
-                                   const cplx<double> *, const cplx<double> *, cplx<double> *, double, hipStream_t);
+                                   const cplx<double> *, const cplx<double> *, cplx<double> *, double, int,
+                                   hipStream_t);
 template void launch_tail<double>(const TailArgs<double> &, hipStream_t);
 template void launch_tail<float>(const TailArgs<float> &, hipStream_t);
 template void launch_up_rb<float>(const Grid<float> &, const Grid<float> &, const cplx<float> *, const cplx<float> *,
-                                  const cplx<float> *, cplx<float> *, float, hipStream_t);
+                                  const cplx<float> *, cplx<float> *, float, int, hipStream_t);
 
 }  // namespace ecs
