@@ -100,7 +100,9 @@ def adjoint(args):
     n = 1025
     w, k2_true, idx, rng = W.adjoint_case(n=n)
     fwd = Krylov(method="bicgstab", rtol=1e-8, maxit=20000)
-    tight = Krylov(method="bicgstab", rtol=1e-13, maxit=40000)
+    # the finite-difference check needs solves far below the FD step: 1e-12
+    # by FGMRES (Bi-CGSTAB's true residual stalls just above 1e-13 here)
+    tight = Krylov(method="fgmres", restart=40, rtol=1e-12, maxit=40000)
     S = _solver(w, "f64", tight)
     f = torch.from_numpy(w.rhs[0]).to("cuda")
     k2 = torch.from_numpy(w.k2).to("cuda")
@@ -126,7 +128,11 @@ def adjoint(args):
     gt = gt.cpu().numpy()
     x = W.real_nodes(n, -10.0, 10.0)
     inner = np.flatnonzero((np.abs(x) <= 8))
-    cells = [(int(rng.choice(inner)), int(rng.choice(inner))) for _ in range(10)]
+    # random interior nodes, and random nodes among those whose gradient is
+    # within 1e-2 of the largest (where central differences resolve it)
+    cells = [(int(rng.choice(inner)), int(rng.choice(inner))) for _ in range(5)]
+    big = np.flatnonzero(np.abs(gt).ravel() >= 1e-2 * np.abs(gt).max())
+    cells += [(int(t // n), int(t % n)) for t in rng.choice(big, size=5, replace=False)]
     errs = []
     gscale = float(np.abs(gt).max())
     with torch.no_grad():
@@ -143,7 +149,8 @@ def adjoint(args):
                higher_is_better=False, forward_seconds=round(t_fwd, 4),
                forward_plus_backward_seconds=round(t_fwd_bwd, 4), loss=float(L),
                max_fd_err_eps1e6_rel_to_max_grad=max(e["err_1e6_rel_scale"] for e in errs),
-               max_fd_err_eps1e4_rel=max(e["err_1e4_rel"] for e in errs), cells=errs,
+               max_fd_err_eps1e4_rel=max(e["err_1e4_rel"] for e in errs),
+               max_fd_err_eps1e4_rel_large_grad=max(e["err_1e4_rel"] for e in errs[5:]), cells=errs,
                dtype="f64", data="synthetic"))
 
 

@@ -1002,8 +1002,8 @@ ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, co
     if (rt <= d->rtol) { status = ECS_OK; break; }
     if (it >= d->maxit) { status = ECS_NOT_CONVERGED; break; }
     if (rt >= last_restart) {
-      if (++stalls >= 3) {
-        status = fail(C, ECS_EBREAKDOWN, "Bi-CGSTAB: no progress over three restarts");
+      if (++stalls >= 3) {  // the true residual stalled (rounding floor): best iterate, not converged
+        status = fail(C, ECS_NOT_CONVERGED, "Bi-CGSTAB: true residual stalled over three restarts");
         break;
       }
     }
@@ -1140,7 +1140,7 @@ ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *d
         } else if (I.it >= d->maxit) {
           batch_finish_rhs(I, ECS_NOT_CONVERGED, d);
         } else if (est >= I.last_restart && ++I.stalls >= 3) {
-          batch_finish_rhs(I, ECS_EBREAKDOWN, d);
+          batch_finish_rhs(I, ECS_NOT_CONVERGED, d);
         } else {
           if (I.last_restart < INFINITY) I.restarts++;
           I.last_restart = est;
