@@ -102,20 +102,25 @@ void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
                   const cplx<R> *ec, cplx<R> *u_out, R omega, int rows, hipStream_t s);
-// the coarsest levels of a 2D V(1,1) red-black cycle in one workgroup:
-// levels with at most kTailNodes nodes per axis (and 2048 nodes in all)
+// the coarsest levels of a 2D V(1,1) red-black cycle in one workgroup, every
+// level vector resident in LDS: levels with at most kTailNodes nodes per axis,
+// at least two of them (the last is the coarsest, solved densely), kTailCap
+// nodes in all
 constexpr int kTailMaxLevels = 8;
 constexpr int kTailNodes = 33;
+constexpr int kTailCap = 1536;
 template <typename R>
 struct TailArgs {
-  int nl;  // levels in the tail, the last one the coarsest
+  int nl;                            // levels in the tail, the last one the coarsest
+  int noff[kTailMaxLevels + 1];      // node offsets of the levels in the LDS vectors
+  int woff[kTailMaxLevels + 1];      // offsets of the levels' 1D weights
   Grid<R> g[kTailMaxLevels];
-  cplx<R> *b[kTailMaxLevels];        // b[0] input (read only); b[k > 0] written
-  cplx<R> *t[kTailMaxLevels];        // pre-smoothed iterates
-  cplx<R> *u[kTailMaxLevels];        // results; u[0] is the tail's output
-  const cplx<R> *minvT;
+  const cplx<R> *b0;                 // right-hand side of the tail's first level
+  cplx<R> *u0;                       // its result
+  const cplx<R> *minvT;              // coarsest inverse, transposed
   const int *unk;
   int nunk;
+  int tpr;                           // threads per row of the dense solve (power of 2, <= 64)
   R omega;
 };
 template <typename R>

@@ -660,9 +660,12 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
   const ecs_tuning &T = C->tune;
   // first level handled by the tail: the coarsest levels that are small
   int lt = lc;
+  int64_t tail_nn = C->hl[lc].nn;
   while (lt > 0 && C->hl[lt - 1].n[0] <= T.tail_nodes && C->hl[lt - 1].n[1] <= T.tail_nodes &&
-         lc - (lt - 1) + 1 <= kTailMaxLevels)
+         lc - (lt - 1) + 1 <= kTailMaxLevels && tail_nn + C->hl[lt - 1].nn <= kTailCap) {
     lt--;
+    tail_nn += C->hl[lt].nn;
+  }
   auto small = [&](int l) { return C->hl[l].n[0] <= T.small_grid && C->hl[l].n[1] <= T.small_grid; };
   for (int l = 0; l < lt; l++) {
     DevLevel<R> &D = dev_level<R>(C, l);
@@ -673,20 +676,29 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
     launch_down_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.b, om, small(l) ? 2 : T.down_rows,
                       C->stream);
   }
-  {
+  if (lt == lc) {
+    // no small levels above the coarsest: dense solve only
+    const cplx<R> *b = lc == 0 ? b0 : dev_level<R>(C, lc).b;
+    cplx<R> *u = lc == 0 ? u0 : dev_level<R>(C, lc).u;
+    TimedScope ts(C, kTCoarse, 0.0);
+    coarse_solve<R>(C, b, u);
+  } else {
     TailArgs<R> a{};
     a.nl = lc - lt + 1;
+    a.noff[0] = a.woff[0] = 0;
     for (int k = 0; k < a.nl; k++) {
       const int l = lt + k;
-      DevLevel<R> &D = dev_level<R>(C, l);
       a.g[k] = grid_M<R>(C, l);
-      a.b[k] = (l == 0) ? const_cast<cplx<R> *>(b0) : D.b;  // the tail never writes b[0]
-      a.t[k] = D.t;
-      a.u[k] = (l == 0) ? u0 : D.u;
+      a.noff[k + 1] = a.noff[k] + (int)C->hl[l].nn;
+      a.woff[k + 1] = a.woff[k] + (int)std::max(C->hl[l].n[0], C->hl[l].n[1]);
     }
+    a.b0 = lt == 0 ? b0 : dev_level<R>(C, lt).b;
+    a.u0 = lt == 0 ? u0 : dev_level<R>(C, lt).u;
     a.minvT = minv_of<R>(C);
     a.unk = C->unk;
     a.nunk = C->nunk;
+    a.tpr = 64;
+    while (a.tpr > 1 && a.tpr * C->nunk > 1024) a.tpr >>= 1;
     a.omega = om;
     TimedScope ts(C, kTCoarse, 0.0);
     launch_tail<R>(a, C->stream);

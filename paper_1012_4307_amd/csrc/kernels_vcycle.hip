@@ -267,233 +267,183 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
 
 // ----------------------------------------------------------------- tail
 // The coarsest levels of the cycle in one workgroup: for grids of a few
-// thousand nodes a kernel launch per phase costs more than the work, so the
-// down passes, the dense coarsest solve and the up passes of every level from
-// the tail's first level to the coarsest run in one launch, phases separated
-// by workgroup barriers.  Level vectors live in global memory (L2-resident);
-// the 1D weights of all tail levels are staged in LDS; every phase first
-// gathers the operands of all of a thread's nodes (TS slots, unrolled) and
-// only then computes, so one memory round trip is paid per phase.
-// Level k of the tail: b[k] right-hand side, t[k] pre-smoothed iterate, u[k]
-// result.
+// thousand nodes a launch per level costs more than the work, so the down
+// passes, the dense coarsest solve and the up passes of every level from the
+// tail's first level to the coarsest run in one launch, phases separated by
+// workgroup barriers.  Every level vector of the tail lives in LDS (at most
+// kTailCap nodes over all tail levels): global memory is touched once at the
+// start (the first level's right-hand side, the 1D weights and k^2 of all
+// levels) and once at the end (the first level's result).
+// Per level k (nodes [noff[k], noff[k+1]) of the LDS vectors):
+//   b  right-hand side (the restricted residual of the level above)
+//   t  pre-smoothed iterate
+//   w  residual on the way down, corrected and post-smoothed iterate on the way up
+//   d  inverse diagonal
 constexpr int TT = 1024;  // tail threads
-constexpr int TS = 2;     // node slots per thread: tail levels have <= 2048 nodes
-constexpr int TW = 128;   // LDS weights per axis and kind (sum of the tail level sizes)
+constexpr int TW = 128;   // LDS weights per axis and kind (>= sum of the tail level sizes)
 
 template <typename R>
-struct TailW {
+struct TailLds {
   cplx<R> xm[TW], xp[TW], ym[TW], yp[TW];
+  cplx<R> b[kTailCap], t[kTailCap], w[kTailCap], d[kTailCap];
 };
+
+// level of flattened node P (divergent; unrolled select chain on kernel args)
+template <typename R>
+__device__ __forceinline__ int tail_level(const TailArgs<R> &a, int P) {
+  int k = 0;
+#pragma unroll
+  for (int q = 1; q < kTailMaxLevels; q++) k = (q < a.nl && P >= a.noff[q]) ? q : k;
+  return k;
+}
 
 template <typename R>
 __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
-  __shared__ TailW<R> W;
-  __shared__ int off[kTailMaxLevels];
+  __shared__ TailLds<R> S;
   const int tid = threadIdx.x;
   const R om = a.omega, om1 = R(1) - a.omega;
   const int last = a.nl - 1;
-  if (tid == 0) {
-    int o = 0;
-    for (int k = 0; k < a.nl; k++) {
-      off[k] = o;
-      o += a.g[k].n0 > a.g[k].n1 ? a.g[k].n0 : a.g[k].n1;
+
+  // setup: 1D weights of every level into LDS; inverse diagonals of every
+  // node of every level; the first level's right-hand side and its
+  // zero-guess red relaxation.  All loads are issued before any is used.
+#pragma unroll
+  for (int k = 0; k < kTailMaxLevels; k++) {
+    if (k < a.nl) {
+      const Grid<R> &g = a.g[k];
+      if (tid < g.n0) {
+        S.xm[a.woff[k] + tid] = g.cm0[tid];
+        S.xp[a.woff[k] + tid] = g.cp0[tid];
+      }
+      if (tid < g.n1) {
+        S.ym[a.woff[k] + tid] = g.cm1[tid];
+        S.yp[a.woff[k] + tid] = g.cp1[tid];
+      }
     }
   }
-  __syncthreads();
-  for (int k = 0; k < a.nl; k++) {
-    const Grid<R> &g = a.g[k];
-    for (int q = tid; q < g.n0; q += TT) {
-      W.xm[off[k] + q] = g.cm0[q];
-      W.xp[off[k] + q] = g.cp0[q];
+  const int total = a.noff[a.nl];
+#pragma unroll
+  for (int sl = 0; sl < (kTailCap + TT - 1) / TT; sl++) {
+    const int P = tid + sl * TT;
+    if (P >= total) break;
+    const int k = tail_level(a, P);
+    Grid<R> g = a.g[0];
+#pragma unroll
+    for (int q = 1; q < kTailMaxLevels; q++)
+      if (q == k) g = a.g[q];
+    const int p = P - a.noff[k];
+    const int i = p % g.n0, j = p / g.n0;
+    const bool in = i >= 1 && i <= g.n0 - 2 && j >= 1 && j <= g.n1 - 2;
+    cplx<R> dv = zero_c<R>(), bv = zero_c<R>();
+    if (in) {
+      dv = inv_c(g.cm0[i] + g.cp0[i] + g.cm1[j] + g.cp1[j] + (g.k2[p] * g.beta + g.c));
+      if (k == 0) bv = a.b0[p];
     }
-    for (int q = tid; q < g.n1; q += TT) {
-      W.ym[off[k] + q] = g.cm1[q];
-      W.yp[off[k] + q] = g.cp1[q];
+    S.d[P] = dv;
+    if (k == 0) {
+      S.b[P] = bv;
+      S.t[P] = (in && ((i + j) & 1) == 0) ? om * (bv * dv) : zero_c<R>();
     }
   }
   __syncthreads();
 
-  // down: zero-guess red-black sweep, then the restricted residual
+  // down: black relaxation, red residual, restriction (which also performs
+  // the next level's zero-guess red relaxation on the nodes it produces)
   for (int k = 0; k < last; k++) {
     const Grid<R> &g = a.g[k];
-    const cplx<R> *xm = W.xm + off[k], *xp = W.xp + off[k], *ym = W.ym + off[k], *yp = W.yp + off[k];
-    const cplx<R> *b = a.b[k];
-    cplx<R> *t = a.t[k];
-    const int n0 = g.n0, n1 = g.n1, nn = n0 * n1;
-    cplx<R> bs[TS], is[TS];
-#pragma unroll
-    for (int s = 0; s < TS; s++) {
-      const int p = tid + s * TT;
-      bs[s] = zero_c<R>();
-      is[s] = zero_c<R>();
-      if (p < nn) {
-        const int i = p % n0, j = p / n0;
-        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
-          bs[s] = b[p];
-          is[s] = inv_c(xm[i] + xp[i] + ym[j] + yp[j] + (g.k2[p] * g.beta + g.c));
-        }
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < TS; s++) {
-      const int p = tid + s * TT;
-      if (p < nn) {
-        const int i = p % n0, j = p / n0;
-        t[p] = ((i + j) & 1) == 0 ? om * (bs[s] * is[s]) : zero_c<R>();
+    const int n0 = g.n0, n1 = g.n1, nn = n0 * n1, no = a.noff[k], wo = a.woff[k];
+    const cplx<R> *xm = S.xm + wo, *xp = S.xp + wo, *ym = S.ym + wo, *yp = S.yp + wo;
+    cplx<R> *b = S.b + no, *t = S.t + no, *w = S.w + no, *d = S.d + no;
+    for (int p = tid; p < nn; p += TT) {
+      const int i = p % n0, j = p / n0;
+      if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 1) {
+        const cplx<R> tb = b[p] + (xm[i] * t[p - 1] + xp[i] * t[p + 1] + ym[j] * t[p - n0] + yp[j] * t[p + n0]);
+        t[p] = om * (tb * d[p]);
+        w[p] = om1 * tb;  // black residual (1 - w)(b + o)
       }
     }
     __syncthreads();
-    cplx<R> nb[TS][4];
-#pragma unroll
-    for (int s = 0; s < TS; s++) {
-      const int p = tid + s * TT;
-      if (p < nn) {
-        const int i = p % n0, j = p / n0;
-        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 1) {
-          nb[s][0] = t[p - 1]; nb[s][1] = t[p + 1]; nb[s][2] = t[p - n0]; nb[s][3] = t[p + n0];
-        }
-      }
-    }
-    cplx<R> rs[TS];
-#pragma unroll
-    for (int s = 0; s < TS; s++) {
-      const int p = tid + s * TT;
-      rs[s] = zero_c<R>();
-      if (p < nn) {
-        const int i = p % n0, j = p / n0;
-        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 1) {
-          const cplx<R> tb = bs[s] + (xm[i] * nb[s][0] + xp[i] * nb[s][1] + ym[j] * nb[s][2] + yp[j] * nb[s][3]);
-          t[p] = om * (tb * is[s]);
-          rs[s] = om1 * tb;  // black residual
-        }
-      }
-    }
-    __syncthreads();
-    // red residuals from the relaxed black neighbours; residual vector kept in
-    // the tail's scratch u[k] (free until the up pass overwrites it)
-    cplx<R> *r = a.u[k];
-#pragma unroll
-    for (int s = 0; s < TS; s++) {
-      const int p = tid + s * TT;
-      if (p < nn) {
-        const int i = p % n0, j = p / n0;
-        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 0) {
-          nb[s][0] = t[p - 1]; nb[s][1] = t[p + 1]; nb[s][2] = t[p - n0]; nb[s][3] = t[p + n0];
-        }
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < TS; s++) {
-      const int p = tid + s * TT;
-      if (p < nn) {
-        const int i = p % n0, j = p / n0;
-        const bool in = i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2;
-        if (in && ((i + j) & 1) == 0)
-          rs[s] = om1 * bs[s] + (xm[i] * nb[s][0] + xp[i] * nb[s][1] + ym[j] * nb[s][2] + yp[j] * nb[s][3]);
-        r[p] = in ? rs[s] : zero_c<R>();
-      }
+    for (int p = tid; p < nn; p += TT) {
+      const int i = p % n0, j = p / n0;
+      const bool in = i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2;
+      if (!in) w[p] = zero_c<R>();
+      else if (((i + j) & 1) == 0)  // red residual (1 - w) b + o
+        w[p] = om1 * b[p] + (xm[i] * t[p - 1] + xp[i] * t[p + 1] + ym[j] * t[p - n0] + yp[j] * t[p + n0]);
     }
     __syncthreads();
     const Grid<R> &gc = a.g[k + 1];
-    cplx<R> *bc = a.b[k + 1];
-    const int nc = gc.n0 * gc.n1;
+    const int c0 = gc.n0, nc = c0 * gc.n1, nco = a.noff[k + 1];
     for (int q = tid; q < nc; q += TT) {
-      const int I = q % gc.n0, J = q / gc.n0;
-      cplx<R> acc = zero_c<R>();
-      if (I >= 1 && I <= gc.n0 - 2 && J >= 1 && J <= gc.n1 - 2) {
-        const cplx<R> *c0 = r + (int64_t)(2 * J) * n0 + 2 * I;
-        acc = R(0.25) * c0[0] + R(0.125) * (c0[-1] + c0[1] + c0[-n0] + c0[n0]) +
-              R(0.0625) * (c0[-n0 - 1] + c0[-n0 + 1] + c0[n0 - 1] + c0[n0 + 1]);
+      const int I = q % c0, J = q / c0;
+      cplx<R> acc = zero_c<R>(), tv = zero_c<R>();
+      if (I >= 1 && I <= c0 - 2 && J >= 1 && J <= gc.n1 - 2) {
+        const cplx<R> *r0 = w + (2 * J) * n0 + 2 * I;
+        acc = R(0.25) * r0[0] + R(0.125) * (r0[-1] + r0[1] + r0[-n0] + r0[n0]) +
+              R(0.0625) * (r0[-n0 - 1] + r0[-n0 + 1] + r0[n0 - 1] + r0[n0 + 1]);
+        if (((I + J) & 1) == 0) tv = om * (acc * S.d[nco + q]);
       }
-      bc[q] = acc;
+      S.b[nco + q] = acc;
+      S.t[nco + q] = tv;
     }
     __syncthreads();
   }
-  // dense solve on the coarsest level (inverse stored transposed)
+
+  // dense solve on the coarsest level: tpr threads per row of the transposed
+  // inverse, partial sums combined across the row's lanes
   {
     const Grid<R> &g = a.g[last];
-    const int nn = g.n0 * g.n1;
-    cplx<R> *x = a.u[last];
-    const cplx<R> *bb = a.b[last];
-    for (int p = tid; p < nn; p += TT) {
-      const int i = p % g.n0, j = p / g.n0;
-      if (i < 1 || i > g.n0 - 2 || j < 1 || j > g.n1 - 2) x[p] = zero_c<R>();
-    }
-    for (int rr = tid; rr < a.nunk; rr += TT) {
+    const int nn = g.n0 * g.n1, no = a.noff[last];
+    for (int p = tid; p < nn; p += TT) S.w[no + p] = zero_c<R>();
+    __syncthreads();
+    const int tpr = a.tpr, nu = a.nunk, rows_per_pass = TT / tpr;
+    for (int r0 = 0; r0 < nu; r0 += rows_per_pass) {
+      const int rr = r0 + tid / tpr;
       cplx<R> acc = zero_c<R>();
-#pragma unroll 8
-      for (int c = 0; c < a.nunk; c++) acc = acc + a.minvT[(int64_t)c * a.nunk + rr] * bb[a.unk[c]];
-      x[a.unk[rr]] = acc;
+      if (rr < nu)
+        for (int c = tid % tpr; c < nu; c += tpr) acc = acc + a.minvT[(int64_t)c * nu + rr] * S.b[no + a.unk[c]];
+      for (int m = tpr >> 1; m >= 1; m >>= 1) {
+        acc.re += __shfl_xor(acc.re, m, 64);
+        acc.im += __shfl_xor(acc.im, m, 64);
+      }
+      if (rr < nu && tid % tpr == 0) S.w[no + a.unk[rr]] = acc;
     }
     __syncthreads();
   }
-  // up: prolongation + correction, then the red-black post-sweep in place
+
+  // up: prolongation + correction, then the red-black post-sweep in place;
+  // the first level's black sweep writes the result to global memory
   for (int k = last - 1; k >= 0; k--) {
     const Grid<R> &g = a.g[k];
-    const Grid<R> &gc = a.g[k + 1];
-    const cplx<R> *xm = W.xm + off[k], *xp = W.xp + off[k], *ym = W.ym + off[k], *yp = W.yp + off[k];
-    const cplx<R> *b = a.b[k];
-    const cplx<R> *t = a.t[k];
-    const cplx<R> *ec = a.u[k + 1];
-    cplx<R> *u = a.u[k];
-    const int n0 = g.n0, n1 = g.n1, nn = n0 * n1;
-    cplx<R> vs[TS], bs[TS], is[TS], e4[TS][4];
-#pragma unroll
-    for (int s = 0; s < TS; s++) {
-      const int p = tid + s * TT;
-      vs[s] = zero_c<R>();
-      bs[s] = zero_c<R>();
-      is[s] = zero_c<R>();
-      if (p < nn) {
-        const int i = p % n0, j = p / n0;
-        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
-          const cplx<R> *e = ec + (int64_t)(j >> 1) * gc.n0 + (i >> 1);
-          e4[s][0] = e[0];
-          e4[s][1] = (i & 1) ? e[1] : zero_c<R>();
-          e4[s][2] = (j & 1) ? e[gc.n0] : zero_c<R>();
-          e4[s][3] = ((i & 1) && (j & 1)) ? e[gc.n0 + 1] : zero_c<R>();
-          vs[s] = t[p];
-          bs[s] = b[p];
-          is[s] = inv_c(xm[i] + xp[i] + ym[j] + yp[j] + (g.k2[p] * g.beta + g.c));
-        }
+    const int n0 = g.n0, n1 = g.n1, nn = n0 * n1, no = a.noff[k], wo = a.woff[k];
+    const int c0 = a.g[k + 1].n0;
+    const cplx<R> *xm = S.xm + wo, *xp = S.xp + wo, *ym = S.ym + wo, *yp = S.yp + wo;
+    const cplx<R> *b = S.b + no, *t = S.t + no, *d = S.d + no, *e = S.w + a.noff[k + 1];
+    cplx<R> *w = S.w + no;
+    for (int p = tid; p < nn; p += TT) {
+      const int i = p % n0, j = p / n0;
+      cplx<R> v = zero_c<R>();
+      if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
+        const cplx<R> *e0 = e + (j >> 1) * c0 + (i >> 1);
+        const cplx<R> e1 = (i & 1) ? e0[1] : zero_c<R>();
+        const cplx<R> e2 = (j & 1) ? e0[c0] : zero_c<R>();
+        const cplx<R> e3 = ((i & 1) && (j & 1)) ? e0[c0 + 1] : zero_c<R>();
+        const R wx = (i & 1) ? R(0.5) : R(1), wy = (j & 1) ? R(0.5) : R(1);
+        v = t[p] + (wx * wy) * (e0[0] + e1 + e2 + e3);
       }
-    }
-#pragma unroll
-    for (int s = 0; s < TS; s++) {
-      const int p = tid + s * TT;
-      if (p < nn) {
-        const int i = p % n0, j = p / n0;
-        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
-          const R wx = (i & 1) ? R(0.5) : R(1), wy = (j & 1) ? R(0.5) : R(1);
-          vs[s] = vs[s] + (wx * wy) * (e4[s][0] + e4[s][1] + e4[s][2] + e4[s][3]);
-        }
-        u[p] = vs[s];
-      }
+      w[p] = v;
     }
     __syncthreads();
     for (int colour = 0; colour < 2; colour++) {
-      cplx<R> nb[TS][4];
-#pragma unroll
-      for (int s = 0; s < TS; s++) {
-        const int p = tid + s * TT;
-        if (p < nn) {
-          const int i = p % n0, j = p / n0;
-          if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == colour) {
-            nb[s][0] = u[p - 1]; nb[s][1] = u[p + 1]; nb[s][2] = u[p - n0]; nb[s][3] = u[p + n0];
-          }
+      for (int p = tid; p < nn; p += TT) {
+        const int i = p % n0, j = p / n0;
+        const bool upd = i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == colour;
+        cplx<R> v = w[p];
+        if (upd) {
+          const cplx<R> o = xm[i] * w[p - 1] + xp[i] * w[p + 1] + ym[j] * w[p - n0] + yp[j] * w[p + n0];
+          v = om1 * v + om * ((b[p] + o) * d[p]);
+          w[p] = v;
         }
-      }
-#pragma unroll
-      for (int s = 0; s < TS; s++) {
-        const int p = tid + s * TT;
-        if (p < nn) {
-          const int i = p % n0, j = p / n0;
-          if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == colour) {
-            const cplx<R> o = xm[i] * nb[s][0] + xp[i] * nb[s][1] + ym[j] * nb[s][2] + yp[j] * nb[s][3];
-            vs[s] = om1 * vs[s] + om * ((bs[s] + o) * is[s]);
-            u[p] = vs[s];
-          }
-        }
+        if (k == 0 && colour == 1) a.u0[p] = v;
       }
       __syncthreads();
     }

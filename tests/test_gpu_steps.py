@@ -109,6 +109,27 @@ def test_vcycle(case, dt):
         assert relerr(z, P.mg_apply(v)) < CYCLE_TOL[dt]
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_vcycle_tail_schedules(dt):
+    """The single-workgroup tail over every admissible range of coarse levels:
+    the whole cycle (33^2 grid), the dense solve alone, and coarsest grids of
+    9, 4, 225 and 49 unknowns (64, 64, 4 and 16 threads per row of the dense
+    solve), against the oracle's cycle."""
+    rng = np.random.default_rng(12)
+    runs = [(W.coulomb(E=1.0, n=33), (33, 17, 9, 5, 3)),
+            (ragged_workload(), (3, 4, 7, 13, 25)),
+            (ragged_workload(n=129, coarsest=17), (17, 33)),
+            (W.coulomb(E=2.0, n=129, coarsest=9), (9, 17, 33))]
+    for w, tails in runs:
+        P = oracle_for(w)
+        S = gpu_for(w, dt)
+        for v in (w.rhs[0], W.random_complex(w.shape, rng)):
+            ref = P.mg_apply(v)
+            for tn in tails:
+                S.set_tuning(tail_nodes=tn)
+                assert relerr(to_np(S.vcycle(to_gpu(v))), ref) < CYCLE_TOL[dt], (w.name, w.n, tn)
+
+
 @pytest.mark.parametrize("gf,gc,smoother,omega,nu", [(2, 2, "rbgs", 1.05, 1), (1, 2, "jacobi", 0.8, 1),
                                                       (1, 4, "jacobi", 0.5, 2), (1, 1, "rbgs", 1.0, 2)])
 def test_general_cycles(gf, gc, smoother, omega, nu):
