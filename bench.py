@@ -22,7 +22,6 @@ CPU oracle on a bounded sample.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -35,9 +34,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1012_4307_amd", "csrc", f)
-                  for f in ("kernels_vcycle.hip", "kernels_blas.hip", "kernels_mg.hip")]
-
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -75,14 +71,6 @@ def vcycle_algorithmic_bytes(n, nlev, real_bytes):
     return sum(nodes[:-1]) * 13 * real_bytes
 
 
-def sources_digest():
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def main():
     args = parse()
     if args.gpus != 1:
@@ -91,6 +79,7 @@ def main():
         sys.exit(2)
     import torch
     import paper_1012_4307_amd as E
+    from paper_1012_4307_amd import profile_summary as PS
     from paper_1012_4307_amd import workloads as W
 
     if not os.path.exists(E.LIB_PATH):
@@ -202,7 +191,7 @@ def main():
     try:
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("sources_digest") == sources_digest() and dom in tr.get("kernels", {}):
+        if tr.get("sources_digest") == PS.sources_digest() and dom in tr.get("kernels", {}):
             traffic = tr["kernels"][dom]["hbm_bytes_per_launch"]
     except (OSError, ValueError):
         traffic = None

@@ -109,17 +109,18 @@ void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, 
 constexpr int kTailMaxLevels = 8;
 constexpr int kTailNodes = 33;
 constexpr int kTailCap = 1536;
+constexpr int kTailMinv = 2401;  // coarsest inverse entries staged in LDS (49 unknowns)
 template <typename R>
 struct TailArgs {
   int nl;                            // levels in the tail, the last one the coarsest
   int noff[kTailMaxLevels + 1];      // node offsets of the levels in the LDS vectors
+  int poff[kTailMaxLevels + 1];      // the same, each level padded to a multiple of 64 nodes
   int woff[kTailMaxLevels + 1];      // offsets of the levels' 1D weights
   Grid<R> g[kTailMaxLevels];
   const cplx<R> *b0;                 // right-hand side of the tail's first level
   cplx<R> *u0;                       // its result
   const cplx<R> *minvT;              // coarsest inverse, transposed
-  const int *unk;
-  int nunk;
+  int nunk;                          // interior nodes of the coarsest level, row-major
   int tpr;                           // threads per row of the dense solve (power of 2, <= 64)
   R omega;
 };

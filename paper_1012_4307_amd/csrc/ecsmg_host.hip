@@ -685,17 +685,17 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
   } else {
     TailArgs<R> a{};
     a.nl = lc - lt + 1;
-    a.noff[0] = a.woff[0] = 0;
+    a.noff[0] = a.woff[0] = a.poff[0] = 0;
     for (int k = 0; k < a.nl; k++) {
       const int l = lt + k;
       a.g[k] = grid_M<R>(C, l);
       a.noff[k + 1] = a.noff[k] + (int)C->hl[l].nn;
+      a.poff[k + 1] = a.poff[k] + ((int)C->hl[l].nn + 63) / 64 * 64;
       a.woff[k + 1] = a.woff[k] + (int)std::max(C->hl[l].n[0], C->hl[l].n[1]);
     }
     a.b0 = lt == 0 ? b0 : dev_level<R>(C, lt).b;
     a.u0 = lt == 0 ? u0 : dev_level<R>(C, lt).u;
     a.minvT = minv_of<R>(C);
-    a.unk = C->unk;
     a.nunk = C->nunk;
     a.tpr = 64;
     while (a.tpr > 1 && a.tpr * C->nunk > 1024) a.tpr >>= 1;

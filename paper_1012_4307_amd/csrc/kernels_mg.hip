@@ -297,6 +297,100 @@ __global__ __launch_bounds__(256) void k_apply_dot(Grid<R> g, const cplx<RI> *__
   }
 }
 
+// 2D y = M x by column strips (the form every 2D matvec of the solve takes):
+// a wave owns SX = 62 columns (lanes 1..62; lanes 0 and 63 load the halo
+// columns) and SY consecutive rows, with all SY + 2 rows of x it needs in
+// registers, the x-neighbours taken from the adjacent lanes.  x is read once
+// (plus 2 halo rows per SY), so the pass streams at close to copy speed.  The
+// operator's arithmetic is that of k_apply term for term.  MODE fuses the
+// Bi-CGSTAB dot products of k_apply_dot (kBicgAlpha / kBicgOmega), 0 = none.
+constexpr int SX = 62;
+
+template <typename R, typename RI, typename RO, int MODE, int SY>
+__global__ __launch_bounds__(256) void k_apply2d(Grid<R> g, const cplx<RI> *__restrict__ x, cplx<RO> *__restrict__ y,
+                                                 const cplx<R> *__restrict__ d0, cplx<double> *partials, int tiles_x,
+                                                 int tiles) {
+  __shared__ cplx<double> lds[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n0 = g.n0, n1 = g.n1;
+  const int padded = gridDim.x, b = blockIdx.x;
+  const int local = (b % kXcds) * (padded / kXcds) + b / kXcds;  // XCD-aware order within a pass
+  cplx<double> a0 = mk<double>(0, 0);
+  double a1 = 0;
+  for (int t0 = 0; t0 < tiles; t0 += padded) {
+    const int tile = t0 + local;
+    if (tile >= tiles) continue;
+    const int i = (tile % tiles_x) * SX + lane;
+    const int j0 = ((tile / tiles_x) * 4 + wv) * SY;
+    const bool xin = i < n0;
+    const bool xint = i >= 1 && i <= n0 - 2;
+    const bool own = xin && ((lane >= 1 && lane <= SX) || i == 0);
+    const cplx<R> cxm = xint ? g.cm0[i] : mk<R>(0, 0);
+    const cplx<R> cxp = xint ? g.cp0[i] : mk<R>(0, 0);
+    cplx<R> xv[SY + 2];
+#pragma unroll
+    for (int r = 0; r < SY + 2; r++) {
+      const int jj = j0 - 1 + r;
+      xv[r] = (xin && jj >= 0 && jj < n1) ? cvt<R>(x[(int64_t)jj * n0 + i]) : mk<R>(0, 0);
+    }
+    R kv[SY];
+    cplx<R> dv[SY];
+#pragma unroll
+    for (int r = 0; r < SY; r++) {
+      const int jj = j0 + r;
+      kv[r] = R(0);
+      dv[r] = mk<R>(0, 0);
+      if (xin && jj < n1) {
+        kv[r] = g.k2[(int64_t)jj * n0 + i];
+        if (MODE != 0) dv[r] = d0[(int64_t)jj * n0 + i];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < SY; r++) {
+      const int jj = j0 + r;
+      cplx<R> xl, xr;
+      xl.re = __shfl_up(xv[r + 1].re, 1, 64);
+      xl.im = __shfl_up(xv[r + 1].im, 1, 64);
+      xr.re = __shfl_down(xv[r + 1].re, 1, 64);
+      xr.im = __shfl_down(xv[r + 1].im, 1, 64);
+      if (!own || jj >= n1) continue;
+      cplx<R> v = mk<R>(0, 0);
+      if (xint && jj >= 1 && jj <= n1 - 2) {
+        const cplx<R> cym = g.cm1[jj], cyp = g.cp1[jj];
+        const cplx<R> d = cxm + cxp + cym + cyp + (kv[r] * g.beta + g.c);
+        cplx<R> o = cxm * xl + cxp * xr;
+        o = o + cym * xv[r] + cyp * xv[r + 2];
+        v = d * xv[r + 1] - o;
+      }
+      y[(int64_t)jj * n0 + i] = cvt<RO>(v);
+      if (MODE != 0) {
+        const cplx<double> vd = cvt<double>(v), dd = cvt<double>(dv[r]);
+        if (MODE == kBicgAlpha) {
+          a0 = a0 + conjg(dd) * vd;
+        } else {
+          a0 = a0 + conjg(vd) * dd;
+          a1 += abs2(vd);
+        }
+      }
+    }
+  }
+  if (MODE != 0) {
+    cplx<double> s0 = block_sum(a0, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s0;
+    if (MODE != kBicgAlpha) {
+      __syncthreads();
+      cplx<double> s1 = block_sum(mk<double>(a1, 0), lds);
+      if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = s1;
+    }
+  }
+}
+
+// strip rows per wave: the x window lives in registers
+template <typename R>
+constexpr int strip_rows() {
+  return sizeof(R) == 4 ? 16 : 8;
+}
+
 template <typename R>
 __global__ void k_inject_k2(int n0, int n1, int n2, const double *__restrict__ kf, int f0, int f1, int stride,
                             R *__restrict__ kc) {
@@ -310,8 +404,26 @@ __global__ void k_inject_k2(int n0, int n1, int n2, const double *__restrict__ k
 
 }  // namespace
 
+// 2D launches of the strip kernel: one block (4 waves, 62 x 4 SY nodes) per
+// tile while the tile count fits the reduction buffer, grid-stride beyond
+template <typename R>
+void strip_grid(const Grid<R> &g, int sy, int *tiles_x, int *tiles, int *blocks) {
+  *tiles_x = (g.n0 - 1 + SX - 1) / SX;
+  *tiles = *tiles_x * ((g.n1 + 4 * sy - 1) / (4 * sy));
+  const int cap = kRedBlocks * (kMaxRestart + 2) / 2;
+  *blocks = xcd_padded(*tiles < cap ? *tiles : cap);
+}
+
 template <typename R, typename RI, typename RO>
 void launch_apply(const Grid<R> &g, const cplx<RI> *x, cplx<RO> *y, hipStream_t s) {
+  if (g.n2 == 1) {
+    constexpr int sy = strip_rows<R>();
+    int tx, tiles, nb;
+    strip_grid(g, sy, &tx, &tiles, &nb);
+    hipLaunchKernelGGL((k_apply2d<R, RI, RO, 0, sy>), dim3(nb), dim3(256), 0, s, g, x, y,
+                       (const cplx<R> *)nullptr, (cplx<double> *)nullptr, tx, tiles);
+    return;
+  }
   hipLaunchKernelGGL((k_apply<R, RI, RO>), grid_of(g), dim3(TX, TY), 0, s, g, x, y);
 }
 template <typename R>
@@ -351,9 +463,21 @@ void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cpl
                       cplx<double> *partials, BicgScalars *S, hipStream_t s) {
   // one block per 64 x 4 tile while the partials (two per block) fit the
   // reduction buffer (kRedBlocks x (kMaxRestart + 2) entries)
+  if (g.n2 == 1) {
+    constexpr int sy = strip_rows<R>();
+    int tx, tiles, nb;
+    strip_grid(g, sy, &tx, &tiles, &nb);
+    if (mode == kBicgAlpha)
+      hipLaunchKernelGGL((k_apply2d<R, RI, R, kBicgAlpha, sy>), dim3(nb), dim3(256), 0, s, g, x, y, d0, partials, tx,
+                         tiles);
+    else
+      hipLaunchKernelGGL((k_apply2d<R, RI, R, kBicgOmega, sy>), dim3(nb), dim3(256), 0, s, g, x, y, d0, partials, tx,
+                         tiles);
+    launch_bicg_final(partials, nb, mode == kBicgAlpha ? 1 : 2, S, mode, s);
+    return;
+  }
   const int ntiles = ((g.n0 + TX - 1) / TX) * ((g.n1 + TY - 1) / TY) * g.n2;
-  const int cap = kRedBlocks * (kMaxRestart + 2) / 2;
-  const int nb = ntiles < cap ? ntiles : cap;
+  const int nb = ntiles < kRedBlocks ? ntiles : kRedBlocks;
   hipLaunchKernelGGL((k_apply_dot<R, RI>), dim3(nb), dim3(256), 0, s, g, x, y, d0, mode, partials, S);
   launch_bicg_final(partials, nb, mode == kBicgAlpha ? 1 : 2, S, mode, s);
 }

@@ -284,17 +284,31 @@ constexpr int TW = 128;   // LDS weights per axis and kind (>= sum of the tail l
 
 template <typename R>
 struct TailLds {
-  cplx<R> xm[TW], xp[TW], ym[TW], yp[TW];
+  cplx<R> xm[TW + 1], xp[TW + 1], ym[TW + 1], yp[TW + 1];  // + a spare slot
   cplx<R> b[kTailCap], t[kTailCap], w[kTailCap], d[kTailCap];
+  cplx<R> mi[kTailMinv + 1];  // the coarsest inverse (transposed) when it fits, and a spare slot
 };
 
-// level of flattened node P (divergent; unrolled select chain on kernel args)
-template <typename R>
-__device__ __forceinline__ int tail_level(const TailArgs<R> &a, int P) {
-  int k = 0;
-#pragma unroll
-  for (int q = 1; q < kTailMaxLevels; q++) k = (q < a.nl && P >= a.noff[q]) ? q : k;
-  return k;
+// rows of the dense coarsest solve: tpr lanes per row, partial sums combined
+// across the row's lanes; the interior unknowns are the interior nodes in
+// row-major order
+template <typename R, typename M>
+__device__ __forceinline__ void tail_dense(int nu, int tpr, const M *mi, const cplx<R> *b, cplx<R> *x, int n0) {
+  const int tid = threadIdx.x, ni = n0 - 2, rows_per_pass = TT / tpr;
+  for (int r0 = 0; r0 < nu; r0 += rows_per_pass) {
+    const int rr = r0 + tid / tpr;
+    cplx<R> acc = zero_c<R>();
+    if (rr < nu) {
+#pragma unroll 4
+      for (int c = tid % tpr; c < nu; c += tpr)
+        acc = acc + mi[(int64_t)c * nu + rr] * b[(c / ni + 1) * n0 + c % ni + 1];
+    }
+    for (int m = tpr >> 1; m >= 1; m >>= 1) {
+      acc.re += __shfl_xor(acc.re, m, 64);
+      acc.im += __shfl_xor(acc.im, m, 64);
+    }
+    if (rr < nu && tid % tpr == 0) x[(rr / ni + 1) * n0 + rr % ni + 1] = acc;
+  }
 }
 
 template <typename R>
@@ -303,46 +317,81 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
   const int tid = threadIdx.x;
   const R om = a.omega, om1 = R(1) - a.omega;
   const int last = a.nl - 1;
+  const bool minv_lds = a.nunk * a.nunk <= kTailMinv;
 
-  // setup: 1D weights of every level into LDS; inverse diagonals of every
-  // node of every level; the first level's right-hand side and its
-  // zero-guess red relaxation.  All loads are issued before any is used.
+  // setup, one memory round trip: the 1D weights of every level into LDS, the
+  // inverse diagonal of every node of every level, the first level's
+  // right-hand side and its zero-guess red relaxation, the coarsest inverse.
+  // Waves never straddle levels (per-level ranges padded to 64 lanes), so a
+  // wave's level is uniform and the kernel arguments are indexed uniformly.
+  // Loads use clamped (always valid) indexes and are issued before any use.
+  {
+    constexpr int kSlots = (kTailCap + kTailMaxLevels * 63 + TT - 1) / TT;
+    // weights: wave k (k < nl) loads level k's, lane = node index
+    const int kw = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool wl = kw < a.nl;
+    const Grid<R> &gw = a.g[wl ? kw : 0];
+    const int ln = tid & 63;
+    const int q0 = ln < gw.n0 ? ln : gw.n0 - 1, q1 = ln < gw.n1 ? ln : gw.n1 - 1;
+    const cplx<R> wxm = gw.cm0[q0], wxp = gw.cp0[q0], wym = gw.cm1[q1], wyp = gw.cp1[q1];
+    // nodes: slot sl of thread tid is padded index P = tid + sl TT
+    cplx<R> cxm[kSlots], cxp[kSlots], cym[kSlots], cyp[kSlots], bv[kSlots];
+    R kv[kSlots];
+    int lv[kSlots], pv[kSlots];
 #pragma unroll
-  for (int k = 0; k < kTailMaxLevels; k++) {
-    if (k < a.nl) {
+    for (int sl = 0; sl < kSlots; sl++) {
+      const int P = tid + sl * TT;
+      int k = 0;
+      for (int q = 1; q < a.nl; q++) k = P >= a.poff[q] ? q : k;
+      k = __builtin_amdgcn_readfirstlane(k);
       const Grid<R> &g = a.g[k];
-      if (tid < g.n0) {
-        S.xm[a.woff[k] + tid] = g.cm0[tid];
-        S.xp[a.woff[k] + tid] = g.cp0[tid];
-      }
-      if (tid < g.n1) {
-        S.ym[a.woff[k] + tid] = g.cm1[tid];
-        S.yp[a.woff[k] + tid] = g.cp1[tid];
-      }
+      const int nn = g.n0 * g.n1;
+      const int p0 = P - a.poff[k], p = p0 < nn ? p0 : nn - 1;
+      const int i = p % g.n0, j = p / g.n0;
+      lv[sl] = P < a.poff[a.nl] && p0 < nn ? k : -1;
+      pv[sl] = p;
+      cxm[sl] = g.cm0[i];
+      cxp[sl] = g.cp0[i];
+      cym[sl] = g.cm1[j];
+      cyp[sl] = g.cp1[j];
+      kv[sl] = g.k2[p];
+      bv[sl] = a.b0[k == 0 ? p : 0];
     }
-  }
-  const int total = a.noff[a.nl];
+    constexpr int kMiSlots = (kTailMinv + TT - 1) / TT;
+    const int nmi = a.nunk * a.nunk;
+    cplx<R> mv[kMiSlots];
 #pragma unroll
-  for (int sl = 0; sl < (kTailCap + TT - 1) / TT; sl++) {
-    const int P = tid + sl * TT;
-    if (P >= total) break;
-    const int k = tail_level(a, P);
-    Grid<R> g = a.g[0];
-#pragma unroll
-    for (int q = 1; q < kTailMaxLevels; q++)
-      if (q == k) g = a.g[q];
-    const int p = P - a.noff[k];
-    const int i = p % g.n0, j = p / g.n0;
-    const bool in = i >= 1 && i <= g.n0 - 2 && j >= 1 && j <= g.n1 - 2;
-    cplx<R> dv = zero_c<R>(), bv = zero_c<R>();
-    if (in) {
-      dv = inv_c(g.cm0[i] + g.cp0[i] + g.cm1[j] + g.cp1[j] + (g.k2[p] * g.beta + g.c));
-      if (k == 0) bv = a.b0[p];
+    for (int m = 0; m < kMiSlots; m++) {
+      const int q2 = tid + m * TT;
+      mv[m] = a.minvT[minv_lds && q2 < nmi ? q2 : 0];
     }
-    S.d[P] = dv;
-    if (k == 0) {
-      S.b[P] = bv;
-      S.t[P] = (in && ((i + j) & 1) == 0) ? om * (bv * dv) : zero_c<R>();
+    // unconditional stores (unused entries to a spare slot) keep the loads
+    // above ahead of every wait
+#pragma unroll
+    for (int m = 0; m < kMiSlots; m++) {
+      const int q2 = tid + m * TT;
+      S.mi[minv_lds && q2 < nmi ? q2 : kTailMinv] = mv[m];
+    }
+    const int wx = wl && ln < gw.n0 ? a.woff[kw] + ln : TW, wy = wl && ln < gw.n1 ? a.woff[kw] + ln : TW;
+    S.xm[wx] = wxm;
+    S.xp[wx] = wxp;
+    S.ym[wy] = wym;
+    S.yp[wy] = wyp;
+#pragma unroll
+    for (int sl = 0; sl < kSlots; sl++) {
+      const int k = lv[sl];
+      if (k < 0) continue;
+      const int kk = __builtin_amdgcn_readfirstlane(k < 0 ? 0 : k);
+      const Grid<R> &g = a.g[kk];
+      const int p = pv[sl], i = p % g.n0, j = p / g.n0, P = a.noff[kk] + p;
+      const bool in = i >= 1 && i <= g.n0 - 2 && j >= 1 && j <= g.n1 - 2;
+      const cplx<R> dv = in ? inv_c(cxm[sl] + cxp[sl] + cym[sl] + cyp[sl] + (kv[sl] * g.beta + g.c)) : zero_c<R>();
+      S.d[P] = dv;
+      if (kk == 0) {
+        const cplx<R> b = in ? bv[sl] : zero_c<R>();
+        S.b[P] = b;
+        S.t[P] = (in && ((i + j) & 1) == 0) ? om * (b * dv) : zero_c<R>();
+      }
     }
   }
   __syncthreads();
@@ -388,25 +437,14 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
     __syncthreads();
   }
 
-  // dense solve on the coarsest level: tpr threads per row of the transposed
-  // inverse, partial sums combined across the row's lanes
+  // dense solve on the coarsest level
   {
     const Grid<R> &g = a.g[last];
     const int nn = g.n0 * g.n1, no = a.noff[last];
     for (int p = tid; p < nn; p += TT) S.w[no + p] = zero_c<R>();
     __syncthreads();
-    const int tpr = a.tpr, nu = a.nunk, rows_per_pass = TT / tpr;
-    for (int r0 = 0; r0 < nu; r0 += rows_per_pass) {
-      const int rr = r0 + tid / tpr;
-      cplx<R> acc = zero_c<R>();
-      if (rr < nu)
-        for (int c = tid % tpr; c < nu; c += tpr) acc = acc + a.minvT[(int64_t)c * nu + rr] * S.b[no + a.unk[c]];
-      for (int m = tpr >> 1; m >= 1; m >>= 1) {
-        acc.re += __shfl_xor(acc.re, m, 64);
-        acc.im += __shfl_xor(acc.im, m, 64);
-      }
-      if (rr < nu && tid % tpr == 0) S.w[no + a.unk[rr]] = acc;
-    }
+    if (minv_lds) tail_dense(a.nunk, a.tpr, S.mi, S.b + no, S.w + no, g.n0);
+    else tail_dense(a.nunk, a.tpr, a.minvT, S.b + no, S.w + no, g.n0);
     __syncthreads();
   }
 
