@@ -208,7 +208,7 @@ ecs_status ecs_timing_read(ecs_ctx *ctx, int kclass, int64_t *launches, double *
  *   small_grid  grids with at most this many nodes per axis use 2 / 4 rows
  *   tail_nodes  levels with at most this many nodes per axis (3..33) run in
  *               the single-workgroup kernel that ends the cycle
- * Defaults {8, 16, 513, 33}; a project autotuner picks values per grid size
+ * Defaults {4, 8, 513, 33}; a project autotuner picks values per grid size
  * and dtype by timing cycles. */
 typedef struct {
   int down_rows;

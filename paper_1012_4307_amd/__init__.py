@@ -237,8 +237,9 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().ecs_destroy(h)
+        L = _lib  # None once the interpreter is tearing the module down
+        if h is not None and h.value and L is not None:
+            L.ecs_destroy(h)
             self._h = None
 
     def _ensure_workspace(self, kr: Krylov):
@@ -375,7 +376,7 @@ class Solver:
         self._check(lib().ecs_coarse_solve(self._h, _ptr(b), _ptr(x)))
         return x
 
-    def set_tuning(self, down_rows=8, up_rows=16, small_grid=513, tail_nodes=33):
+    def set_tuning(self, down_rows=4, up_rows=8, small_grid=513, tail_nodes=33):
         """Launch schedule of the fused V(1,1) cycle (performance only)."""
         t = Tuning(down_rows, up_rows, small_grid, tail_nodes)
         self._check(lib().ecs_set_tuning(self._h, ctypes.byref(t)))

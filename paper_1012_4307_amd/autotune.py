@@ -16,7 +16,7 @@ import json
 import os
 from typing import Dict
 
-DEFAULT = dict(down_rows=8, up_rows=16, small_grid=513, tail_nodes=33)
+DEFAULT = dict(down_rows=4, up_rows=8, small_grid=513, tail_nodes=33)
 
 
 def cache_path() -> str:

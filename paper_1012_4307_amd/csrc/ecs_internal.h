@@ -2,6 +2,7 @@
 // HIP translation units of the library (not part of the public ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -69,6 +70,27 @@ __device__ __forceinline__ int xcd_tile(int tiles) {
   const int b = blockIdx.x;
   const int t = (b % kXcds) * (padded / kXcds) + b / kXcds;
   return t < tiles ? t : -1;
+}
+
+// Kernel timing.  When a timed scope has armed these events, the next launch
+// made through launch_k() records the kernel's own begin and end timestamps
+// into them (hipExtLaunchKernelGGL) and disarms them, so a timed duration is
+// the kernel's execution alone, without the dispatch latency that events
+// recorded on the stream around the launch would add.
+struct KernelEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local KernelEvents g_kernel_events;
+
+template <typename... Args, typename F = void (*)(Args...)>
+inline void launch_k(F kernel, const dim3 &grid, const dim3 &block, uint32_t shmem, hipStream_t s, Args... args) {
+  KernelEvents &e = g_kernel_events;
+  if (e.start) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, e.start, e.stop, 0, args...);
+    e.start = e.stop = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+  }
 }
 
 // ---------------------------------------------------------------- launchers

@@ -21,6 +21,8 @@
 using namespace ecs;
 using cd = std::complex<double>;
 
+thread_local KernelEvents ecs::g_kernel_events;
+
 namespace {
 
 constexpr int kMaxLev = 16;
@@ -123,7 +125,7 @@ struct ecs_ctx {
   bool use_graphs = true;
 
   // launch schedule of the fused V(1,1) cycle (autotuned per grid and dtype)
-  ecs_tuning tune{8, 16, 513, 33};
+  ecs_tuning tune{4, 8, 513, 33};
 };
 
 namespace {
@@ -327,9 +329,9 @@ struct TimedScope {
   ecs_ctx *C;
   Timer *T;
   size_t slot = SIZE_MAX;
-  TimedScope(ecs_ctx *c, int cls, double bytes) : C(c), T(&c->timers[cls]) {
+  double bytes = 0;
+  TimedScope(ecs_ctx *c, int cls, double b) : C(c), T(&c->timers[cls]) {
     if (!T->on) return;
-    T->bytes += bytes;
     if (T->used + 2 > T->ev.size()) {
       if (T->ev.size() >= 2 * 65536) return;
       size_t old = T->ev.size();
@@ -338,11 +340,19 @@ struct TimedScope {
     }
     slot = T->used;
     T->used += 2;
-    (void)hipEventRecord(T->ev[slot], C->stream);
+    bytes = b;
+    T->bytes += b;
+    // the scope's first kernel launch records into this pair
+    g_kernel_events.start = T->ev[slot];
+    g_kernel_events.stop = T->ev[slot + 1];
   }
   ~TimedScope() {
     if (slot == SIZE_MAX) return;
-    (void)hipEventRecord(T->ev[slot + 1], C->stream);
+    if (g_kernel_events.start == T->ev[slot]) {  // nothing was launched: drop the sample
+      g_kernel_events.start = g_kernel_events.stop = nullptr;
+      T->used -= 2;
+      T->bytes -= bytes;
+    }
   }
 };
 

@@ -416,114 +416,114 @@ int reduction_blocks(int64_t n) { return red_blocks(n); }
 template <typename RA, typename RB>
 void launch_mdot_partial(const cplx<RA> *V, int64_t ldv, int ncols, const cplx<RB> *w, int64_t n,
                          cplx<double> *partials, hipStream_t s) {
-  hipLaunchKernelGGL((k_mdot<RA, RB>), dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, w, n, partials);
+  launch_k((k_mdot<RA, RB>), dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, w, n, partials);
 }
 
 void launch_reduce_cols(const cplx<double> *partials, int64_t n, int ncols, cplx<double> *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_cols, dim3(ncols), dim3(BS), 0, s, partials, red_blocks(n), out);
+  launch_k(k_reduce_cols, dim3(ncols), dim3(BS), 0, s, partials, red_blocks(n), out);
 }
 
 void launch_mupdate_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w,
                             int64_t n, cplx<double> *partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_mupdate, dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, h, w, n, partials);
+  launch_k(k_mupdate, dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, h, w, n, partials);
 }
 
 template <typename R>
 void launch_nrm2sq(const cplx<R> *x, int64_t n, cplx<double> *partials, cplx<double> *out, hipStream_t s) {
   int nb = red_blocks(n);
-  hipLaunchKernelGGL((k_nrm2sq<R>), dim3(nb), dim3(BS), 0, s, x, n, partials);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(BS), 0, s, partials, nb, out);
+  launch_k((k_nrm2sq<R>), dim3(nb), dim3(BS), 0, s, x, n, partials);
+  launch_k(k_reduce_cols, dim3(1), dim3(BS), 0, s, partials, nb, out);
 }
 
 template <typename RZ>
 void launch_lincomb(const cplx<RZ> *Z, int64_t ldz, int ncols, const cplx<double> *y, cplx<double> *x, int64_t n,
                     hipStream_t s) {
-  hipLaunchKernelGGL((k_lincomb<RZ>), dim3(grid_for(n)), dim3(BS), 0, s, Z, ldz, ncols, y, x, n);
+  launch_k((k_lincomb<RZ>), dim3(grid_for(n)), dim3(BS), 0, s, Z, ldz, ncols, y, x, n);
 }
 
 void launch_scale_dev(cplx<double> *x, int64_t n, const double *scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n)), dim3(BS), 0, s, x, n, scal);
+  launch_k(k_scale_dev, dim3(grid_for(n)), dim3(BS), 0, s, x, n, scal);
 }
 void launch_gmres_start(GmresScalars *S, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(1), 0, s, S, m);
+  launch_k(k_gmres_start, dim3(1), dim3(1), 0, s, S, m);
 }
 void launch_gmres_givens(GmresScalars *S, int j, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(1), 0, s, S, j, m);
+  launch_k(k_gmres_givens, dim3(1), dim3(1), 0, s, S, j, m);
 }
 void launch_gmres_backsolve(GmresScalars *S, int k, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_backsolve, dim3(1), dim3(1), 0, s, S, k, m);
+  launch_k(k_gmres_backsolve, dim3(1), dim3(1), 0, s, S, k, m);
 }
 
 void launch_add_h2(GmresScalars *S, int j, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_add_h2, dim3(1), dim3(kMaxRestart + 2), 0, s, S, j, m);
+  launch_k(k_add_h2, dim3(1), dim3(kMaxRestart + 2), 0, s, S, j, m);
 }
 
 template <typename R>
 void launch_pairdot(const cplx<R> *x0, const cplx<R> *y0, const cplx<R> *x1, const cplx<R> *y1, int npairs, int64_t n,
                     cplx<double> *partials, BicgScalars *S, int mode, hipStream_t s) {
   int nb = red_blocks(n);
-  hipLaunchKernelGGL((k_pairdot<R>), dim3(nb), dim3(BS), 0, s, x0, y0, x1, y1, npairs, n, partials);
-  hipLaunchKernelGGL(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, npairs, S, mode);
+  launch_k((k_pairdot<R>), dim3(nb), dim3(BS), 0, s, x0, y0, x1, y1, npairs, n, partials);
+  launch_k(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, npairs, S, mode);
 }
 template <typename R>
 void launch_bicg_p(cplx<R> *p, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s) {
-  hipLaunchKernelGGL((k_bicg_p<R>), dim3(grid_for(n)), dim3(BS), 0, s, p, r, v, n, S);
+  launch_k((k_bicg_p<R>), dim3(grid_for(n)), dim3(BS), 0, s, p, r, v, n, S);
 }
 template <typename R>
 void launch_bicg_s(cplx<R> *sv, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s) {
-  hipLaunchKernelGGL((k_bicg_s<R>), dim3(grid_for(n)), dim3(BS), 0, s, sv, r, v, n, S);
+  launch_k((k_bicg_s<R>), dim3(grid_for(n)), dim3(BS), 0, s, sv, r, v, n, S);
 }
 template <typename R, typename RZ>
 void launch_bicg_xr(cplx<R> *x, const cplx<RZ> *ph, const cplx<RZ> *sh, cplx<R> *r, const cplx<R> *sv,
                     const cplx<R> *t, const cplx<R> *rh, int64_t n, cplx<double> *partials, BicgScalars *S,
                     hipStream_t s) {
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL((k_bicg_xr<R, RZ>), dim3(nb), dim3(BS), 0, s, x, ph, sh, r, sv, t, rh, n, S, partials);
-  hipLaunchKernelGGL(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, 2, S, (int)kBicgNormRho);
+  launch_k((k_bicg_xr<R, RZ>), dim3(nb), dim3(BS), 0, s, x, ph, sh, r, sv, t, rh, n, S, partials);
+  launch_k(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, 2, S, (int)kBicgNormRho);
 }
 
 void launch_bicg_final(const cplx<double> *partials, int nblocks, int npairs, BicgScalars *S, int mode,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nblocks, npairs, S, mode);
+  launch_k(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nblocks, npairs, S, mode);
 }
 
 template <typename RI, typename RO>
 void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL((k_cast<RI, RO>), dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
+  launch_k((k_cast<RI, RO>), dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
 }
 void launch_cast_real(const double *x, float *y, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_cast_real, dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
+  launch_k(k_cast_real, dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
 }
 template <typename R>
 void launch_zero(cplx<R> *x, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL((k_zero<R>), dim3(grid_for(n)), dim3(BS), 0, s, x, n);
+  launch_k((k_zero<R>), dim3(grid_for(n)), dim3(BS), 0, s, x, n);
 }
 void launch_scale_w(int n0, int n1, int n2, const cplx<double> *w0, const cplx<double> *w1, const cplx<double> *w2,
                     const cplx<double> *x, cplx<double> *y, bool inverse, hipStream_t s) {
   int64_t n = (int64_t)n0 * n1 * n2;
-  hipLaunchKernelGGL(k_scale_w, dim3(grid_for(n)), dim3(BS), 0, s, n0, n1, n2, w0, w1, w2, x, y, inverse ? 1 : 0);
+  launch_k(k_scale_w, dim3(grid_for(n)), dim3(BS), 0, s, n0, n1, n2, w0, w1, w2, x, y, inverse ? 1 : 0);
 }
 void launch_mask_boundary(int n0, int n1, int n2, const cplx<double> *x, cplx<double> *y, hipStream_t s) {
   int64_t n = (int64_t)n0 * n1 * n2;
-  hipLaunchKernelGGL(k_mask_boundary, dim3(grid_for(n)), dim3(BS), 0, s, n0, n1, n2, x, y);
+  launch_k(k_mask_boundary, dim3(grid_for(n)), dim3(BS), 0, s, n0, n1, n2, x, y);
 }
 void launch_grad_k2(const cplx<double> *lam, const cplx<double> *u, double *g, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_k2, dim3(grid_for(n)), dim3(BS), 0, s, lam, u, g, n);
+  launch_k(k_grad_k2, dim3(grid_for(n)), dim3(BS), 0, s, lam, u, g, n);
 }
 void launch_max_real(const double *x, int64_t n, double *partials, double *out, hipStream_t s) {
   int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_max_partial, dim3(nb), dim3(BS), 0, s, x, n, partials);
-  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(1), 0, s, partials, nb, out);
+  launch_k(k_max_partial, dim3(nb), dim3(BS), 0, s, x, n, partials);
+  launch_k(k_max_final, dim3(1), dim3(1), 0, s, partials, nb, out);
 }
 void launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t s) {
   if (((uintptr_t)src % 16) == 0 && ((uintptr_t)dst % 16) == 0 && bytes % 16 == 0) {
     int64_t n = (int64_t)(bytes / 16);
     int64_t b = (n + BS - 1) / BS;
     if (b > 65536) b = 65536;
-    hipLaunchKernelGGL(k_copy16, dim3((unsigned)b), dim3(BS), 0, s, (const uint4 *)src, (uint4 *)dst, n);
+    launch_k(k_copy16, dim3((unsigned)b), dim3(BS), 0, s, (const uint4 *)src, (uint4 *)dst, n);
   } else {
     int64_t n = (int64_t)bytes;
-    hipLaunchKernelGGL(k_copy1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const unsigned char *)src,
+    launch_k(k_copy1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const unsigned char *)src,
                        (unsigned char *)dst, n);
   }
 }

@@ -420,43 +420,43 @@ void launch_apply(const Grid<R> &g, const cplx<RI> *x, cplx<RO> *y, hipStream_t 
     constexpr int sy = strip_rows<R>();
     int tx, tiles, nb;
     strip_grid(g, sy, &tx, &tiles, &nb);
-    hipLaunchKernelGGL((k_apply2d<R, RI, RO, 0, sy>), dim3(nb), dim3(256), 0, s, g, x, y,
+    launch_k((k_apply2d<R, RI, RO, 0, sy>), dim3(nb), dim3(256), 0, s, g, x, y,
                        (const cplx<R> *)nullptr, (cplx<double> *)nullptr, tx, tiles);
     return;
   }
-  hipLaunchKernelGGL((k_apply<R, RI, RO>), grid_of(g), dim3(TX, TY), 0, s, g, x, y);
+  launch_k((k_apply<R, RI, RO>), grid_of(g), dim3(TX, TY), 0, s, g, x, y);
 }
 template <typename R>
 void launch_residual(const Grid<R> &g, const cplx<R> *b, const cplx<R> *u, cplx<R> *r, hipStream_t s) {
-  hipLaunchKernelGGL((k_residual<R>), grid_of(g), dim3(TX, TY), 0, s, g, b, u, r);
+  launch_k((k_residual<R>), grid_of(g), dim3(TX, TY), 0, s, g, b, u, r);
 }
 template <typename R>
 void launch_jacobi(const Grid<R> &g, const cplx<R> *b, const cplx<R> *u, cplx<R> *out, R omega, bool zero_guess,
                    hipStream_t s) {
-  hipLaunchKernelGGL((k_jacobi<R>), grid_of(g), dim3(TX, TY), 0, s, g, b, u, out, omega, zero_guess ? 1 : 0);
+  launch_k((k_jacobi<R>), grid_of(g), dim3(TX, TY), 0, s, g, b, u, out, omega, zero_guess ? 1 : 0);
 }
 template <typename R>
 void launch_rb_colour(const Grid<R> &g, const cplx<R> *b, cplx<R> *u, R omega, int colour, bool zero_guess,
                       hipStream_t s) {
-  hipLaunchKernelGGL((k_rb_colour<R>), grid_of(g), dim3(TX, TY), 0, s, g, b, u, omega, colour, zero_guess ? 1 : 0);
+  launch_k((k_rb_colour<R>), grid_of(g), dim3(TX, TY), 0, s, g, b, u, omega, colour, zero_guess ? 1 : 0);
 }
 template <typename R>
 void launch_restrict(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *rf, cplx<R> *rc, hipStream_t s) {
-  hipLaunchKernelGGL((k_restrict<R>), grid_of(coarse), dim3(TX, TY), 0, s, fine, coarse, rf, rc);
+  launch_k((k_restrict<R>), grid_of(coarse), dim3(TX, TY), 0, s, fine, coarse, rf, rc);
 }
 template <typename R>
 void launch_residual_restrict(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u,
                               cplx<R> *rc, hipStream_t s) {
-  hipLaunchKernelGGL((k_residual_restrict<R>), grid_of(coarse), dim3(TX, TY), 0, s, fine, coarse, b, u, rc);
+  launch_k((k_residual_restrict<R>), grid_of(coarse), dim3(TX, TY), 0, s, fine, coarse, b, u, rc);
 }
 template <typename R>
 void launch_prolong_add(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *ec, cplx<R> *u, hipStream_t s) {
-  hipLaunchKernelGGL((k_prolong_add<R>), grid_of(fine), dim3(TX, TY), 0, s, fine, coarse, ec, u);
+  launch_k((k_prolong_add<R>), grid_of(fine), dim3(TX, TY), 0, s, fine, coarse, ec, u);
 }
 template <typename R>
 void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, int n1, int n2, const cplx<R> *b,
                          cplx<R> *x, hipStream_t s) {
-  hipLaunchKernelGGL((k_coarse_solve<R>), dim3(1), dim3(1024), 0, s, nunk, minv, unk, n0, n1, n2, b, x);
+  launch_k((k_coarse_solve<R>), dim3(1), dim3(1024), 0, s, nunk, minv, unk, n0, n1, n2, b, x);
 }
 template <typename R, typename RI>
 void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cplx<R> *d0, int mode,
@@ -468,24 +468,24 @@ void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cpl
     int tx, tiles, nb;
     strip_grid(g, sy, &tx, &tiles, &nb);
     if (mode == kBicgAlpha)
-      hipLaunchKernelGGL((k_apply2d<R, RI, R, kBicgAlpha, sy>), dim3(nb), dim3(256), 0, s, g, x, y, d0, partials, tx,
+      launch_k((k_apply2d<R, RI, R, kBicgAlpha, sy>), dim3(nb), dim3(256), 0, s, g, x, y, d0, partials, tx,
                          tiles);
     else
-      hipLaunchKernelGGL((k_apply2d<R, RI, R, kBicgOmega, sy>), dim3(nb), dim3(256), 0, s, g, x, y, d0, partials, tx,
+      launch_k((k_apply2d<R, RI, R, kBicgOmega, sy>), dim3(nb), dim3(256), 0, s, g, x, y, d0, partials, tx,
                          tiles);
     launch_bicg_final(partials, nb, mode == kBicgAlpha ? 1 : 2, S, mode, s);
     return;
   }
   const int ntiles = ((g.n0 + TX - 1) / TX) * ((g.n1 + TY - 1) / TY) * g.n2;
   const int nb = ntiles < kRedBlocks ? ntiles : kRedBlocks;
-  hipLaunchKernelGGL((k_apply_dot<R, RI>), dim3(nb), dim3(256), 0, s, g, x, y, d0, mode, partials, S);
+  launch_k((k_apply_dot<R, RI>), dim3(nb), dim3(256), 0, s, g, x, y, d0, mode, partials, S);
   launch_bicg_final(partials, nb, mode == kBicgAlpha ? 1 : 2, S, mode, s);
 }
 
 template <typename R>
 void launch_inject_k2(int n0, int n1, int n2, const double *k2_fine, int f0, int f1, R *k2_coarse, hipStream_t s) {
   int stride = (f0 - 1) / (n0 - 1);
-  hipLaunchKernelGGL((k_inject_k2<R>), dim3((n0 + 255) / 256, n1, n2), dim3(256), 0, s, n0, n1, n2, k2_fine, f0, f1,
+  launch_k((k_inject_k2<R>), dim3((n0 + 255) / 256, n1, n2), dim3(256), 0, s, n0, n1, n2, k2_fine, f0, f1,
                      stride, k2_coarse);
 }
 

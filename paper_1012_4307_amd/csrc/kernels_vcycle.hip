@@ -30,10 +30,21 @@ __device__ __forceinline__ cplx<R> zero_c() {
 }
 
 // Both kernels first issue every global load of the block (register arrays
-// of PER entries per thread, unrolled, so all are in flight together) and
-// stage the tile's 1D weights in LDS.  A thread keeps the values of its own
-// nodes (b, the inverse diagonal, its iterate) in registers across the phases;
-// only the iterate and the residual, which neighbours read, go through LDS.
+// of RPW rows per thread, unrolled, so all are in flight together).  A thread
+// keeps the values of its own nodes (b, the inverse diagonal, its iterate) in
+// registers across the phases; only the iterate and the residual, which
+// neighbours read, go through LDS.
+//
+// Pair layout: lane l owns the two adjacent columns 2l, 2l + 1 of the staged
+// region.  In every row one of them is red and the other black, so each lane
+// has exactly one node of each colour per row, and a colour phase keeps every
+// lane busy (with one lane per column, half the lanes of every instruction of
+// a colour phase would idle).  The 4 waves of a block take every fourth row,
+// so all rows of a wave have one parity and the colour of column 2l is the
+// same for the whole wave.  LDS holds the red and the black values of each
+// row apart, [row][pair]: a node's four neighbours are the other colour of
+// its own pair, of the pair to one side, and of its own pair one row up and
+// down.
 //
 // With M u = D u - o(u), o the off-diagonal part, a red-black sweep relaxes
 // u_p <- (1 - w) u_p + w (b_p + o_p) / D_p.  From a zero guess the residual
@@ -47,109 +58,158 @@ __device__ __forceinline__ cplx<R> inv_c(cplx<R> d) {
   return mk<R>(d.re * s, -d.im * s);
 }
 
+// inverse diagonal inside the fused cycle: in FP32 the hardware reciprocal
+// (1 ulp) replaces the correctly rounded division
+template <typename R>
+__device__ __forceinline__ cplx<R> inv_cycle(cplx<R> d) {
+  R s;
+  if constexpr (sizeof(R) == 4) s = __builtin_amdgcn_rcpf(abs2(d));
+  else s = R(1) / abs2(d);
+  return mk<R>(d.re * s, -d.im * s);
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> sel(bool c, cplx<R> a, cplx<R> b) {
+  return c ? a : b;
+}
+
 // ----------------------------------------------------------------- down
-// One lane per tile column (64 lanes = the tile width, so the x index, the x
-// weights and the x bounds test are per-thread constants), the 4 waves of the
-// block take every fourth tile row.  Block tile: CX = 29 coarse columns x CY
-// coarse rows from (I0, J0); owned fine nodes [2 I0, 2 I0 + 58) x
-// [2 J0, 2 J0 + 2 CY).  Staged fine region: columns 2 I0 - 3 + [0, 63) (lane
-// 63 idles), rows 2 J0 - 3 + [0, 2 CY + 5): halo 3 below, 2 above, because
-// the FW stencil of the tile's coarse nodes reads residuals one node out, a
-// residual reads the relaxed iterate one further out, and a relaxed black node
-// reads red values one further still.
+// Block tile: CX = 61 coarse columns x CY coarse rows from (I0, J0); owned
+// fine nodes [2 I0, 2 I0 + 122) x [2 J0, 2 J0 + 2 CY).  Staged fine region:
+// columns 2 I0 - 3 + [0, 127) (the second column of pair 63 idles), rows
+// 2 J0 - 3 + [0, 2 CY + 5): halo 3 below, 2 above, because the FW stencil of
+// the tile's coarse nodes reads residuals one node out, a residual reads the
+// relaxed iterate one further out, and a relaxed black node reads red values
+// one further still.
 template <typename R, int CY>
 __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
                                                 cplx<R> *__restrict__ u_out, cplx<R> *__restrict__ rc, R omega,
                                                 int tiles_x, int tiles) {
-  constexpr int CX = 29;
-  constexpr int WX = 2 * CX + 5;          // 63 used columns
+  constexpr int CX = 61;
+  constexpr int WX = 2 * CX + 5;          // 127 staged columns
   constexpr int WY = 2 * CY + 5;
   constexpr int RPW = (WY + 3) / 4;       // rows per wave
-  __shared__ cplx<R> su[WY][64];          // relaxed iterate
-  __shared__ cplx<R> sr[WY][64];          // residual
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ cplx<R> sR[WY][64], sB[WY][64];  // relaxed iterate, by colour
+  __shared__ cplx<R> rR[WY][64], rB[WY][64];  // residual, by colour
+  // the wave index is uniform: row indices and row weights live in scalars
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
   const int I0 = (tile % tiles_x) * CX, J0 = (tile / tiles_x) * CY;
   const int gx0 = 2 * I0 - 3, gy0 = 2 * J0 - 3;
   const int n0 = f.n0, n1 = f.n1;
   const R om1 = R(1) - omega;
-  const int i = gx0 + lane;
-  const bool xin = lane < WX && i >= 1 && i <= n0 - 2;
-  const cplx<R> cxm = xin ? f.cm0[i] : zero_c<R>();
-  const cplx<R> cxp = xin ? f.cp0[i] : zero_c<R>();
+  // the lane's columns a = 2 lane, b = 2 lane + 1 (relative)
+  const int ia = gx0 + 2 * lane, ib = ia + 1;
+  const bool ina = 2 * lane < WX && ia >= 1 && ia <= n0 - 2;
+  const bool inb = 2 * lane + 1 < WX && ib >= 1 && ib <= n0 - 2;
+  // column a is red in this wave's rows iff ia + j is even (one parity for all)
+  const bool ared = ((ia + gy0 + wv) & 1) == 0;
+  const bool inR = ared ? ina : inb, inBk = ared ? inb : ina;
+  const int iR = ared ? ia : ib, iBk = ared ? ib : ia;
+  const cplx<R> xmR = inR ? f.cm0[iR] : zero_c<R>(), xpR = inR ? f.cp0[iR] : zero_c<R>();
+  const cplx<R> xmB = inBk ? f.cm0[iBk] : zero_c<R>(), xpB = inBk ? f.cp0[iBk] : zero_c<R>();
 
-  cplx<R> bv[RPW], iv[RPW], cym[RPW], cyp[RPW];
-  R kv[RPW];
+  cplx<R> bR[RPW], bB[RPW], dR[RPW], dB[RPW], cym[RPW], cyp[RPW];
+  R kR[RPW], kB[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     const int j = gy0 + ly;
     const bool yin = ly < WY && j >= 1 && j <= n1 - 2;
-    bv[r] = zero_c<R>();
-    kv[r] = R(0);
     cym[r] = yin ? f.cm1[j] : zero_c<R>();
     cyp[r] = yin ? f.cp1[j] : zero_c<R>();
-    if (xin && yin) {
-      const int64_t p = (int64_t)j * n0 + i;
-      bv[r] = b[p];
-      kv[r] = f.k2[p];
+    bR[r] = bB[r] = zero_c<R>();
+    kR[r] = kB[r] = R(0);
+    const int64_t row = (int64_t)j * n0;
+    if (yin && inR) {
+      bR[r] = b[row + iR];
+      kR[r] = f.k2[row + iR];
+    }
+    if (yin && inBk) {
+      bB[r] = b[row + iBk];
+      kB[r] = f.k2[row + iBk];
     }
   }
-  // inverse diagonal; red iterate omega b / D (zero guess), black 0
+  // inverse diagonals; red relaxation from zero: omega b / D
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     if (ly >= WY) break;
     const int j = gy0 + ly;
-    const bool in = xin && j >= 1 && j <= n1 - 2;
-    iv[r] = in ? inv_c(cxm + cxp + cym[r] + cyp[r] + (kv[r] * f.beta + f.c)) : zero_c<R>();
-    su[ly][lane] = (in && ((i + j) & 1) == 0) ? omega * (bv[r] * iv[r]) : zero_c<R>();
+    const bool yin = j >= 1 && j <= n1 - 2;
+    dR[r] = (yin && inR) ? inv_cycle(xmR + xpR + cym[r] + cyp[r] + (kR[r] * f.beta + f.c)) : zero_c<R>();
+    dB[r] = (yin && inBk) ? inv_cycle(xmB + xpB + cym[r] + cyp[r] + (kB[r] * f.beta + f.c)) : zero_c<R>();
+    sR[ly][lane] = omega * (bR[r] * dR[r]);
+    sB[ly][lane] = zero_c<R>();
   }
   __syncthreads();
-  // black relaxation; black residual (1 - w)(b + o)
-  const bool xmid = lane >= 1 && lane <= WX - 2;
+  // black relaxation and the black residual (1 - w)(b + o).  The black node's
+  // red neighbours: its own pair's red and the red of pair lane + 1 (black in
+  // column a... mirrored: lane - 1) in its row, its own pair's red one row up
+  // and down.
+  const int side = ared ? 1 : -1;  // pair holding the black node's other row neighbour
+  const bool pin = lane + side >= 0 && lane + side < 64;
+  const int ps = pin ? lane + side : lane;
+  // black in column b: left = own red, right = red of lane + 1; in column a:
+  // left = red of lane - 1, right = own red.  Weights of the own-pair and the
+  // other-pair neighbour:
+  const cplx<R> wBo = ared ? xmB : xpB, wBn = ared ? xpB : xmB;
+  cplx<R> resB[RPW], tB[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
+    resB[r] = tB[r] = zero_c<R>();
     if (ly >= WY) break;
-    const int j = gy0 + ly;
-    if (!xmid || ly < 1 || ly > WY - 2 || !xin || j < 1 || j > n1 - 2 || ((i + j) & 1) == 0) continue;
-    const cplx<R> tb = bv[r] + (cxm * su[ly][lane - 1] + cxp * su[ly][lane + 1] + cym[r] * su[ly - 1][lane] +
-                                cyp[r] * su[ly + 1][lane]);
-    su[ly][lane] = omega * (tb * iv[r]);
-    sr[ly][lane] = om1 * tb;
+    if (ly < 1 || ly > WY - 2 || !pin) continue;
+    const cplx<R> tb =
+        bB[r] + (wBo * sR[ly][lane] + wBn * sR[ly][ps] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane]);
+    tB[r] = omega * (tb * dB[r]);
+    resB[r] = om1 * tb;
+    sB[ly][lane] = tB[r];
   }
   __syncthreads();
-  // red residual (1 - w) b + o, zero off the interior; write the owned iterate
+  // red residual (1 - w) b + o from the relaxed black neighbours: own black
+  // and the black of pair lane - side (red in column a: left = black of
+  // lane - 1, right = own black); zero off the interior.  Residuals to LDS;
+  // owned iterates to global memory.
+  const int qs = lane - side;
+  const bool qin = qs >= 0 && qs < 64;
+  const int pq = qin ? qs : lane;
+  const cplx<R> wRo = ared ? xpR : xmR, wRn = ared ? xmR : xpR;
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     if (ly >= WY) break;
     const int j = gy0 + ly;
-    if (!xmid || ly < 1 || ly > WY - 2) continue;
-    const bool in = xin && j >= 1 && j <= n1 - 2;
-    if (!in) {
-      sr[ly][lane] = zero_c<R>();
-    } else if (((i + j) & 1) == 0) {
-      sr[ly][lane] = om1 * bv[r] + (cxm * su[ly][lane - 1] + cxp * su[ly][lane + 1] + cym[r] * su[ly - 1][lane] +
-                                    cyp[r] * su[ly + 1][lane]);
+    const bool yin = j >= 1 && j <= n1 - 2;
+    cplx<R> resR = zero_c<R>();
+    if (yin && inR && qin && ly >= 1 && ly <= WY - 2)
+      resR = om1 * bR[r] +
+             (wRo * sB[ly][lane] + wRn * sB[ly][pq] + cym[r] * sB[ly - 1][lane] + cyp[r] * sB[ly + 1][lane]);
+    rR[ly][lane] = resR;
+    rB[ly][lane] = (yin && inBk) ? resB[r] : zero_c<R>();
+    if (ly >= 3 && ly < 3 + 2 * CY && j < n1) {
+      const int64_t row = (int64_t)j * n0;
+      const int xr = iR - gx0, xb = iBk - gx0;  // relative columns of the two nodes
+      if (xr >= 3 && xr < 3 + 2 * CX && iR < n0) u_out[row + iR] = sR[ly][lane];
+      if (xb >= 3 && xb < 3 + 2 * CX && iBk < n0) u_out[row + iBk] = tB[r];
     }
-    if (lane >= 3 && lane < 3 + 2 * CX && ly >= 3 && ly < 3 + 2 * CY && i < n0 && j < n1)
-      u_out[(int64_t)j * n0 + i] = su[ly][lane];
   }
   __syncthreads();
-  // full weighting onto the owned coarse nodes: lane = coarse column
+  // full weighting onto the owned coarse nodes: lane = coarse column.  The
+  // coarse node (I, J) sits on the red fine node in column b of pair P =
+  // I - I0 + 1, row y = 2 (J - J0) + 3 (rows y +- 1 have the other colouring).
   if (lane < CX) {
-    const int I = I0 + lane;
+    const int I = I0 + lane, P = lane + 1;
     for (int cy = wv; cy < CY; cy += 4) {
       const int J = J0 + cy;
       if (I >= c.n0 || J >= c.n1) continue;
       cplx<R> acc = zero_c<R>();
       if (I >= 1 && I <= c.n0 - 2 && J >= 1 && J <= c.n1 - 2) {
-        const int x = 3 + 2 * lane, y = 3 + 2 * cy;
-        acc = R(0.25) * sr[y][x] + R(0.125) * (sr[y][x - 1] + sr[y][x + 1] + sr[y - 1][x] + sr[y + 1][x]) +
-              R(0.0625) * (sr[y - 1][x - 1] + sr[y - 1][x + 1] + sr[y + 1][x - 1] + sr[y + 1][x + 1]);
+        const int y = 3 + 2 * cy;
+        acc = R(0.25) * rR[y][P] + R(0.125) * (rB[y][P] + rB[y][P + 1] + rB[y - 1][P] + rB[y + 1][P]) +
+              R(0.0625) * (rR[y - 1][P] + rR[y - 1][P + 1] + rR[y + 1][P] + rR[y + 1][P + 1]);
       }
       rc[(int64_t)J * c.n0 + I] = acc;
     }
@@ -157,21 +217,23 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
 }
 
 // ------------------------------------------------------------------- up
-// Same layout: lane = tile column.  Block tile: 60 x TY fine nodes at
-// (x0, y0), both even; staged fine region: columns x0 - 2 + [0, 64), rows
-// y0 - 2 + [0, TY + 4) (halo 2: red nodes one outside the tile are relaxed
-// and read black neighbours two outside), and the coarse correction under it.
+// Block tile: TX = 124 x TY fine nodes at (x0, y0), both even; staged fine
+// region: columns x0 - 2 + [0, 128) (pairs 1..62 owned, pairs 0 and 63 halo),
+// rows y0 - 2 + [0, TY + 4) (halo 2: red nodes one outside the tile are
+// relaxed and read black neighbours two outside), and the coarse correction
+// under it.  Column a = x0 - 2 + 2 lane is even, so both columns of pair l
+// interpolate from coarse column x0/2 - 1 + l (= staged coarse column l).
 template <typename R, int TY>
 __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
                                               const cplx<R> *__restrict__ u_in, const cplx<R> *__restrict__ ec,
                                               cplx<R> *__restrict__ u_out, R omega, int tiles_x, int tiles) {
-  constexpr int TX = 60;
+  constexpr int TX = 124;
   constexpr int WY = TY + 4;
   constexpr int RPW = (WY + 3) / 4;
   constexpr int CWX = TX / 2 + 3, CWY = TY / 2 + 3;
-  __shared__ cplx<R> sv[WY][64];
+  __shared__ cplx<R> sR[WY][64], sB[WY][64];
   __shared__ cplx<R> se[CWY][CWX];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
   const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
@@ -179,89 +241,116 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
   const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1;  // coarse staging origin
   const int n0 = f.n0, n1 = f.n1;
   const R om1 = R(1) - omega;
-  const int i = gx0 + lane;
-  const bool xin = i >= 1 && i <= n0 - 2;
-  const cplx<R> cxm = xin ? f.cm0[i] : zero_c<R>();
-  const cplx<R> cxp = xin ? f.cp0[i] : zero_c<R>();
+  const int ia = gx0 + 2 * lane, ib = ia + 1;     // ia even
+  const bool ina = ia >= 1 && ia <= n0 - 2;
+  const bool inb = ib >= 1 && ib <= n0 - 2;
+  // column a (even) is red in this wave's rows iff j is even
+  const bool ared = ((gy0 + wv) & 1) == 0;
+  const bool inR = ared ? ina : inb, inBk = ared ? inb : ina;
+  const int iR = ared ? ia : ib, iBk = ared ? ib : ia;
+  const cplx<R> xmR = inR ? f.cm0[iR] : zero_c<R>(), xpR = inR ? f.cp0[iR] : zero_c<R>();
+  const cplx<R> xmB = inBk ? f.cm0[iBk] : zero_c<R>(), xpB = inBk ? f.cp0[iBk] : zero_c<R>();
 
-  cplx<R> vv[RPW], bv[RPW], iv[RPW], cym[RPW], cyp[RPW];
-  R kv[RPW];
+  cplx<R> vR[RPW], vB[RPW], bR[RPW], bB[RPW], dR[RPW], dB[RPW], cym[RPW], cyp[RPW];
+  R kR[RPW], kB[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     const int j = gy0 + ly;
     const bool yin = ly < WY && j >= 1 && j <= n1 - 2;
-    vv[r] = zero_c<R>();
-    bv[r] = zero_c<R>();
-    kv[r] = R(0);
     cym[r] = yin ? f.cm1[j] : zero_c<R>();
     cyp[r] = yin ? f.cp1[j] : zero_c<R>();
-    if (xin && yin) {
-      const int64_t p = (int64_t)j * n0 + i;
-      vv[r] = u_in[p];
-      bv[r] = b[p];
-      kv[r] = f.k2[p];
+    vR[r] = vB[r] = bR[r] = bB[r] = zero_c<R>();
+    kR[r] = kB[r] = R(0);
+    const int64_t row = (int64_t)j * n0;
+    if (yin && inR) {
+      vR[r] = u_in[row + iR];
+      bR[r] = b[row + iR];
+      kR[r] = f.k2[row + iR];
+    }
+    if (yin && inBk) {
+      vB[r] = u_in[row + iBk];
+      bB[r] = b[row + iBk];
+      kB[r] = f.k2[row + iBk];
     }
   }
-  if (lane < CWX) {
-    const int I = cx0 + lane;
-    for (int cy = wv; cy < CWY; cy += 4) {
-      const int J = cy0 + cy;
-      se[cy][lane] = (I >= 0 && I < c.n0 && J >= 0 && J < c.n1) ? ec[(int64_t)J * c.n0 + I] : zero_c<R>();
-    }
+  for (int q = threadIdx.x; q < CWY * CWX; q += NT) {
+    const int cy = q / CWX, cx = q % CWX;
+    const int I = cx0 + cx, J = cy0 + cy;
+    se[cy][cx] = (I >= 0 && I < c.n0 && J >= 0 && J < c.n1) ? ec[(int64_t)J * c.n0 + I] : zero_c<R>();
   }
   __syncthreads();
-  // v = u + P ec (bilinear in index space) and the inverse diagonal
-  const int ci = (i >> 1) - cx0;
+  // v = u + P ec (bilinear in index space) and the inverse diagonals.  Column
+  // a is even: its correction is se[cj][lane] (j even) or the mean over
+  // rows cj, cj + 1 (j odd); column b (odd) adds the neighbour column.
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     if (ly >= WY) break;
     const int j = gy0 + ly;
-    const bool in = xin && j >= 1 && j <= n1 - 2;
-    iv[r] = zero_c<R>();
-    if (in) {
+    const bool yin = j >= 1 && j <= n1 - 2;
+    dR[r] = dB[r] = zero_c<R>();
+    if (yin) {
       const int cj = (j >> 1) - cy0;
-      cplx<R> pe;
-      if ((i & 1) == 0 && (j & 1) == 0) pe = se[cj][ci];
-      else if ((j & 1) == 0) pe = R(0.5) * (se[cj][ci] + se[cj][ci + 1]);
-      else if ((i & 1) == 0) pe = R(0.5) * (se[cj][ci] + se[cj + 1][ci]);
-      else pe = R(0.25) * (se[cj][ci] + se[cj][ci + 1] + se[cj + 1][ci] + se[cj + 1][ci + 1]);
-      vv[r] = vv[r] + pe;
-      iv[r] = inv_c(cxm + cxp + cym[r] + cyp[r] + (kv[r] * f.beta + f.c));
+      cplx<R> pa, pb;
+      if ((j & 1) == 0) {
+        pa = se[cj][lane];
+        pb = R(0.5) * (se[cj][lane] + se[cj][lane + 1]);
+      } else {
+        pa = R(0.5) * (se[cj][lane] + se[cj + 1][lane]);
+        pb = R(0.25) * (se[cj][lane] + se[cj][lane + 1] + se[cj + 1][lane] + se[cj + 1][lane + 1]);
+      }
+      if (inR) {
+        vR[r] = vR[r] + (ared ? pa : pb);
+        dR[r] = inv_cycle(xmR + xpR + cym[r] + cyp[r] + (kR[r] * f.beta + f.c));
+      }
+      if (inBk) {
+        vB[r] = vB[r] + (ared ? pb : pa);
+        dB[r] = inv_cycle(xmB + xpB + cym[r] + cyp[r] + (kB[r] * f.beta + f.c));
+      }
     }
-    sv[ly][lane] = vv[r];
+    sR[ly][lane] = vR[r];
+    sB[ly][lane] = vB[r];
   }
   __syncthreads();
-  // red relaxation on the tile plus a one-node ring
-  const bool xmid = lane >= 1 && lane <= 62;
+  // red relaxation on the tile plus a one-node ring.  The red node's black
+  // neighbours: own black and the black of pair lane - side in its row (red
+  // in column a: left = black of lane - 1), own black one row up and down.
+  const int side = ared ? 1 : -1;
+  const int qs = lane - side;
+  const bool qin = qs >= 0 && qs < 64;
+  const int pq = qin ? qs : lane;
+  const cplx<R> wRo = ared ? xpR : xmR, wRn = ared ? xmR : xpR;  // own-pair / other-pair neighbour weights
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     if (ly >= WY) break;
     const int j = gy0 + ly;
-    if (!xmid || ly < 1 || ly > WY - 2 || !xin || j < 1 || j > n1 - 2 || ((i + j) & 1) != 0) continue;
-    const cplx<R> o = cxm * sv[ly][lane - 1] + cxp * sv[ly][lane + 1] + cym[r] * sv[ly - 1][lane] +
-                      cyp[r] * sv[ly + 1][lane];
-    vv[r] = om1 * vv[r] + omega * ((bv[r] + o) * iv[r]);
-    sv[ly][lane] = vv[r];
+    if (ly < 1 || ly > WY - 2 || !qin || !inR || j < 1 || j > n1 - 2) continue;
+    const cplx<R> o = wRo * sB[ly][lane] + wRn * sB[ly][pq] + cym[r] * sB[ly - 1][lane] + cyp[r] * sB[ly + 1][lane];
+    vR[r] = om1 * vR[r] + omega * ((bR[r] + o) * dR[r]);
+    sR[ly][lane] = vR[r];
   }
   __syncthreads();
-  // black relaxation on the owned tile; write every owned node
-  const bool xown = lane >= 2 && lane < TX + 2 && i < n0;
+  // black relaxation on the owned tile (pairs 1..62, rows 2..TY+1); write
+  // both nodes of every owned pair
+  const int ps = lane + side;
+  const bool own_x = lane >= 1 && lane <= 62;
+  const cplx<R> wBo = ared ? xmB : xpB, wBn = ared ? xpB : xmB;
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     if (ly >= WY) break;
     const int j = gy0 + ly;
-    if (!xown || ly < 2 || ly >= TY + 2 || j >= n1) continue;
-    cplx<R> out = vv[r];
-    if (xin && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 1) {
-      const cplx<R> o = cxm * sv[ly][lane - 1] + cxp * sv[ly][lane + 1] + cym[r] * sv[ly - 1][lane] +
-                        cyp[r] * sv[ly + 1][lane];
-      out = om1 * out + omega * ((bv[r] + o) * iv[r]);
+    if (!own_x || ly < 2 || ly >= TY + 2 || j >= n1) continue;
+    cplx<R> outB = vB[r];
+    if (inBk && j >= 1 && j <= n1 - 2) {
+      const cplx<R> o = wBo * sR[ly][lane] + wBn * sR[ly][ps] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane];
+      outB = om1 * outB + omega * ((bB[r] + o) * dB[r]);
     }
-    u_out[(int64_t)j * n0 + i] = out;
+    const int64_t row = (int64_t)j * n0;
+    if (iR < n0) u_out[row + iR] = vR[r];
+    if (iBk < n0) u_out[row + iBk] = outB;
   }
 }
 
@@ -396,34 +485,43 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
   }
   __syncthreads();
 
+  // Colour phases enumerate node pairs (columns 2h, 2h + 1 of a row: one red,
+  // one black), so every thread has one node of the colour at hand; row
+  // indices come from a float reciprocal (exact for these sizes: the error is
+  // far below the half-node margin), not an integer division.
   // down: black relaxation, red residual, restriction (which also performs
   // the next level's zero-guess red relaxation on the nodes it produces)
   for (int k = 0; k < last; k++) {
     const Grid<R> &g = a.g[k];
-    const int n0 = g.n0, n1 = g.n1, nn = n0 * n1, no = a.noff[k], wo = a.woff[k];
+    const int n0 = g.n0, n1 = g.n1, no = a.noff[k], wo = a.woff[k];
+    const int H = (n0 + 1) >> 1, np = n1 * H;
+    const float invH = 1.0f / (float)H;
     const cplx<R> *xm = S.xm + wo, *xp = S.xp + wo, *ym = S.ym + wo, *yp = S.yp + wo;
     cplx<R> *b = S.b + no, *t = S.t + no, *w = S.w + no, *d = S.d + no;
-    for (int p = tid; p < nn; p += TT) {
-      const int i = p % n0, j = p / n0;
-      if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == 1) {
+    for (int q = tid; q < np; q += TT) {
+      const int j = (int)(((float)q + 0.5f) * invH), i = 2 * (q - j * H) + ((j + 1) & 1);  // black
+      if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
+        const int p = j * n0 + i;
         const cplx<R> tb = b[p] + (xm[i] * t[p - 1] + xp[i] * t[p + 1] + ym[j] * t[p - n0] + yp[j] * t[p + n0]);
         t[p] = om * (tb * d[p]);
         w[p] = om1 * tb;  // black residual (1 - w)(b + o)
       }
     }
     __syncthreads();
-    for (int p = tid; p < nn; p += TT) {
-      const int i = p % n0, j = p / n0;
-      const bool in = i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2;
-      if (!in) w[p] = zero_c<R>();
-      else if (((i + j) & 1) == 0)  // red residual (1 - w) b + o
+    // red residual (1 - w) b + o; only interior residuals are read below
+    for (int q = tid; q < np; q += TT) {
+      const int j = (int)(((float)q + 0.5f) * invH), i = 2 * (q - j * H) + (j & 1);  // red
+      if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
+        const int p = j * n0 + i;
         w[p] = om1 * b[p] + (xm[i] * t[p - 1] + xp[i] * t[p + 1] + ym[j] * t[p - n0] + yp[j] * t[p + n0]);
+      }
     }
     __syncthreads();
     const Grid<R> &gc = a.g[k + 1];
     const int c0 = gc.n0, nc = c0 * gc.n1, nco = a.noff[k + 1];
+    const float inv0 = 1.0f / (float)c0;
     for (int q = tid; q < nc; q += TT) {
-      const int I = q % c0, J = q / c0;
+      const int J = (int)(((float)q + 0.5f) * inv0), I = q - J * c0;
       cplx<R> acc = zero_c<R>(), tv = zero_c<R>();
       if (I >= 1 && I <= c0 - 2 && J >= 1 && J <= gc.n1 - 2) {
         const cplx<R> *r0 = w + (2 * J) * n0 + 2 * I;
@@ -449,39 +547,51 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
   }
 
   // up: prolongation + correction, then the red-black post-sweep in place;
-  // the first level's black sweep writes the result to global memory
+  // the first level's black sweep writes the result (both nodes of every
+  // pair) to global memory
   for (int k = last - 1; k >= 0; k--) {
     const Grid<R> &g = a.g[k];
-    const int n0 = g.n0, n1 = g.n1, nn = n0 * n1, no = a.noff[k], wo = a.woff[k];
+    const int n0 = g.n0, n1 = g.n1, no = a.noff[k], wo = a.woff[k];
+    const int H = (n0 + 1) >> 1, np = n1 * H;
+    const float invH = 1.0f / (float)H;
     const int c0 = a.g[k + 1].n0;
     const cplx<R> *xm = S.xm + wo, *xp = S.xp + wo, *ym = S.ym + wo, *yp = S.yp + wo;
     const cplx<R> *b = S.b + no, *t = S.t + no, *d = S.d + no, *e = S.w + a.noff[k + 1];
     cplx<R> *w = S.w + no;
-    for (int p = tid; p < nn; p += TT) {
-      const int i = p % n0, j = p / n0;
-      cplx<R> v = zero_c<R>();
-      if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
-        const cplx<R> *e0 = e + (j >> 1) * c0 + (i >> 1);
-        const cplx<R> e1 = (i & 1) ? e0[1] : zero_c<R>();
-        const cplx<R> e2 = (j & 1) ? e0[c0] : zero_c<R>();
-        const cplx<R> e3 = ((i & 1) && (j & 1)) ? e0[c0 + 1] : zero_c<R>();
-        const R wx = (i & 1) ? R(0.5) : R(1), wy = (j & 1) ? R(0.5) : R(1);
-        v = t[p] + (wx * wy) * (e0[0] + e1 + e2 + e3);
+    for (int q = tid; q < np; q += TT) {
+      const int j = (int)(((float)q + 0.5f) * invH), i0 = 2 * (q - j * H);
+      const bool yin = j >= 1 && j <= n1 - 2;
+      const cplx<R> *e0 = e + (j >> 1) * c0 + (i0 >> 1);  // i0 even: coarse column i0 / 2
+      // column i0 (even): coarse node or the mean over two coarse rows
+      cplx<R> pa = zero_c<R>(), pb = zero_c<R>();
+      if (yin) {
+        if ((j & 1) == 0) {
+          pa = e0[0];
+          pb = R(0.5) * (e0[0] + e0[1]);
+        } else {
+          pa = R(0.5) * (e0[0] + e0[c0]);
+          pb = R(0.25) * (e0[0] + e0[1] + e0[c0] + e0[c0 + 1]);
+        }
       }
-      w[p] = v;
+      const int p = j * n0 + i0;
+      w[p] = (yin && i0 >= 1 && i0 <= n0 - 2) ? t[p] + pa : zero_c<R>();
+      if (i0 + 1 < n0) w[p + 1] = (yin && i0 + 1 <= n0 - 2) ? t[p + 1] + pb : zero_c<R>();
     }
     __syncthreads();
     for (int colour = 0; colour < 2; colour++) {
-      for (int p = tid; p < nn; p += TT) {
-        const int i = p % n0, j = p / n0;
-        const bool upd = i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2 && ((i + j) & 1) == colour;
-        cplx<R> v = w[p];
-        if (upd) {
+      for (int q = tid; q < np; q += TT) {
+        const int j = (int)(((float)q + 0.5f) * invH), h2 = 2 * (q - j * H);
+        const int i = h2 + ((j + colour) & 1);  // the pair's node of this colour
+        const int p = j * n0 + i;
+        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
           const cplx<R> o = xm[i] * w[p - 1] + xp[i] * w[p + 1] + ym[j] * w[p - n0] + yp[j] * w[p + n0];
-          v = om1 * v + om * ((b[p] + o) * d[p]);
-          w[p] = v;
+          w[p] = om1 * w[p] + om * ((b[p] + o) * d[p]);
         }
-        if (k == 0 && colour == 1) a.u0[p] = v;
+        if (k == 0 && colour == 1) {
+          const int pp = j * n0 + h2;  // both nodes of the pair (the red one is final)
+          a.u0[pp] = w[pp];
+          if (h2 + 1 < n0) a.u0[pp + 1] = w[pp + 1];
+        }
       }
       __syncthreads();
     }
@@ -497,41 +607,41 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
 template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *u, cplx<R> *rc, R omega,
                     int rows, hipStream_t s) {
-  constexpr int CX = 29;
+  constexpr int CX = 61;
   const int tx = (coarse.n0 + CX - 1) / CX;
   const int tiles = tx * ((coarse.n1 + rows - 1) / rows);
   const dim3 grid(xcd_padded(tiles)), block(NT);
   switch (rows) {
-    case 2: hipLaunchKernelGGL((k_down_rb<R, 2>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
-    case 4: hipLaunchKernelGGL((k_down_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
+    case 2: launch_k((k_down_rb<R, 2>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
+    case 4: launch_k((k_down_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
     case 16:
       if constexpr (sizeof(R) == 4) {
-        hipLaunchKernelGGL((k_down_rb<R, 16>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles);
+        launch_k((k_down_rb<R, 16>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles);
         break;
       }
       [[fallthrough]];
-    default: hipLaunchKernelGGL((k_down_rb<R, 8>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
+    default: launch_k((k_down_rb<R, 8>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
   }
 }
 
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
                   const cplx<R> *ec, cplx<R> *u_out, R omega, int rows, hipStream_t s) {
-  constexpr int TX = 60;
+  constexpr int TX = 124;
   const int tx = (fine.n0 + TX - 1) / TX;
   const int tiles = tx * ((fine.n1 + rows - 1) / rows);
   const dim3 grid(xcd_padded(tiles)), block(NT);
   switch (rows) {
-    case 4: hipLaunchKernelGGL((k_up_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
-    case 8: hipLaunchKernelGGL((k_up_rb<R, 8>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
-    case 32: hipLaunchKernelGGL((k_up_rb<R, 32>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
-    default: hipLaunchKernelGGL((k_up_rb<R, 16>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
+    case 4: launch_k((k_up_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
+    case 8: launch_k((k_up_rb<R, 8>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
+    case 32: launch_k((k_up_rb<R, 32>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
+    default: launch_k((k_up_rb<R, 16>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
   }
 }
 
 template <typename R>
 void launch_tail(const TailArgs<R> &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_tail<R>), dim3(1), dim3(TT), 0, s, a);
+  launch_k((k_tail<R>), dim3(1), dim3(TT), 0, s, a);
 }
 
 template void launch_down_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *, cplx<double> *,
