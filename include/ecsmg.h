@@ -208,13 +208,16 @@ ecs_status ecs_timing_read(ecs_ctx *ctx, int kclass, int64_t *launches, double *
  *   small_grid  grids with at most this many nodes per axis use 2 / 4 rows
  *   tail_nodes  levels with at most this many nodes per axis (3..33) run in
  *               the single-workgroup kernel that ends the cycle
- * Defaults {4, 8, 513, 33}; a project autotuner picks values per grid size
- * and dtype by timing cycles. */
+ *   pair_grid   levels above the tail with at most this many nodes per axis
+ *               run two per kernel (pairs counted from the tail up); 0: none
+ * Defaults {4, 8, 513, 33, 129}; a project autotuner picks values per grid
+ * size and dtype by timing cycles. */
 typedef struct {
   int down_rows;
   int up_rows;
   int small_grid;
   int tail_nodes;
+  int pair_grid;
 } ecs_tuning;
 ecs_status ecs_set_tuning(ecs_ctx *ctx, const ecs_tuning *tuning);
 ecs_status ecs_get_tuning(ecs_ctx *ctx, ecs_tuning *tuning);

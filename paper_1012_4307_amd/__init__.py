@@ -57,7 +57,7 @@ class SolveDesc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("down_rows", ctypes.c_int), ("up_rows", ctypes.c_int), ("small_grid", ctypes.c_int),
-                ("tail_nodes", ctypes.c_int)]
+                ("tail_nodes", ctypes.c_int), ("pair_grid", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -376,9 +376,9 @@ class Solver:
         self._check(lib().ecs_coarse_solve(self._h, _ptr(b), _ptr(x)))
         return x
 
-    def set_tuning(self, down_rows=4, up_rows=8, small_grid=513, tail_nodes=33):
+    def set_tuning(self, down_rows=4, up_rows=8, small_grid=513, tail_nodes=33, pair_grid=129):
         """Launch schedule of the fused V(1,1) cycle (performance only)."""
-        t = Tuning(down_rows, up_rows, small_grid, tail_nodes)
+        t = Tuning(down_rows, up_rows, small_grid, tail_nodes, pair_grid)
         self._check(lib().ecs_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self):

@@ -2,8 +2,9 @@
 
 For one solver (grid size, dimension, cycle dtype) it times the cycle under
 every candidate schedule -- tile heights of the fused down / up kernels, the
-grid size below which short tiles are used, and the size below which levels
-run in the single-workgroup tail kernel -- and keeps the fastest.  Results
+grid size below which short tiles are used, the size below which levels run
+in the single-workgroup tail kernel, and the size below which levels run two
+per kernel -- and keeps the fastest.  Results
 are cached in a JSON file keyed by GPU architecture, grid and dtype
 (``$ECSMG_TUNING_CACHE``, default ``~/.cache/ecsmg/tuning.json``), so a
 batch of systems of the same size pays the search once.  The schedule only
@@ -16,7 +17,7 @@ import json
 import os
 from typing import Dict
 
-DEFAULT = dict(down_rows=4, up_rows=8, small_grid=513, tail_nodes=33)
+DEFAULT = dict(down_rows=4, up_rows=8, small_grid=513, tail_nodes=33, pair_grid=129)
 
 
 def cache_path() -> str:
@@ -32,8 +33,8 @@ def _key(solver) -> str:
 
 def candidates(dtype: str):
     downs = (2, 4, 8, 16) if dtype == "f32" else (2, 4, 8)
-    for d, u, sg, tn in itertools.product(downs, (8, 16, 32), (257, 513), (17, 33)):
-        yield dict(down_rows=d, up_rows=u, small_grid=sg, tail_nodes=tn)
+    for d, u, sg, tn, pg in itertools.product(downs, (4, 8, 16), (257, 513), (17, 33), (0, 129, 513)):
+        yield dict(down_rows=d, up_rows=u, small_grid=sg, tail_nodes=tn, pair_grid=pg)
 
 
 def time_cycles(solver, v, reps: int = 10) -> float:

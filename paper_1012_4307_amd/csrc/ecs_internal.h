@@ -124,6 +124,16 @@ void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
                   const cplx<R> *ec, cplx<R> *u_out, R omega, int rows, hipStream_t s);
+// two levels of the fused cycle in one kernel (small levels): down over
+// levels l, l+1 (writes u_l, u_{l+1}, b_{l+1} and b_{l+2}); up over levels
+// l+1, l (reads the correction u_{l+2}, writes u_l)
+template <typename R>
+void launch_down2_rb(const Grid<R> &f, const Grid<R> &m, const Grid<R> &c, const cplx<R> *b, cplx<R> *t_f,
+                     cplx<R> *b_m, cplx<R> *t_m, cplx<R> *rc, R omega, hipStream_t s);
+template <typename R>
+void launch_up2_rb(const Grid<R> &f, const Grid<R> &m, const Grid<R> &c, const cplx<R> *b_f, const cplx<R> *t_f,
+                   const cplx<R> *b_m, const cplx<R> *t_m, const cplx<R> *ec, cplx<R> *u_out, R omega,
+                   hipStream_t s);
 // the coarsest levels of a 2D V(1,1) red-black cycle in one workgroup, every
 // level vector resident in LDS: levels with at most kTailNodes nodes per axis,
 // at least two of them (the last is the coarsest, solved densely), kTailCap

@@ -125,7 +125,7 @@ struct ecs_ctx {
   bool use_graphs = true;
 
   // launch schedule of the fused V(1,1) cycle (autotuned per grid and dtype)
-  ecs_tuning tune{4, 8, 513, 33};
+  ecs_tuning tune{4, 8, 513, 33, 129};
 };
 
 namespace {
@@ -677,14 +677,32 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
     tail_nn += C->hl[lt].nn;
   }
   auto small = [&](int l) { return C->hl[l].n[0] <= T.small_grid && C->hl[l].n[1] <= T.small_grid; };
-  for (int l = 0; l < lt; l++) {
+  // the levels above the tail with at most pair_grid nodes per axis run two
+  // per kernel, pairs counted from the tail up; pair_start[l]: levels l, l+1
+  bool pair_start[kMaxLev + 1] = {};
+  {
+    int ls = lt;
+    while (ls > 0 && C->hl[ls - 1].n[0] <= T.pair_grid && C->hl[ls - 1].n[1] <= T.pair_grid) ls--;
+    for (int l = lt - 2; l >= ls; l -= 2) pair_start[l] = true;
+  }
+  for (int l = 0; l < lt;) {
     DevLevel<R> &D = dev_level<R>(C, l);
     DevLevel<R> &Dc = dev_level<R>(C, l + 1);
     const cplx<R> *b = l == 0 ? b0 : D.b;
+    if (pair_start[l]) {
+      // reads b, k^2 of both levels; writes u of both, b of level l+1, the
+      // residual restricted to level l+2
+      TimedScope ts(C, kTCoarse, (double)(C->hl[l].nn + C->hl[l + 1].nn) * sizeof(R) * 5.5);
+      launch_down2_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), grid_M<R>(C, l + 2), b, D.t, Dc.b, Dc.t,
+                         dev_level<R>(C, l + 2).b, om, C->stream);
+      l += 2;
+      continue;
+    }
     // reads b, k^2; writes u and the coarse residual
     TimedScope ts(C, l == 0 ? kTDown : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 5.5);
     launch_down_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.b, om, small(l) ? 2 : T.down_rows,
                       C->stream);
+    l++;
   }
   if (lt == lc) {
     // no small levels above the coarsest: dense solve only
@@ -713,7 +731,21 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
     TimedScope ts(C, kTCoarse, 0.0);
     launch_tail<R>(a, C->stream);
   }
-  for (int l = lt - 1; l >= 0; l--) {
+  for (int l = lt - 1; l >= 0;) {
+    if (l >= 1 && pair_start[l - 1]) {
+      // levels l - 1 and l: reads u, b, k^2 of both and the correction from
+      // level l + 1; writes u of level l - 1
+      const int lf = l - 1;
+      DevLevel<R> &D = dev_level<R>(C, lf);
+      DevLevel<R> &Dm = dev_level<R>(C, lf + 1);
+      const cplx<R> *b = lf == 0 ? b0 : D.b;
+      cplx<R> *out = lf == 0 ? u0 : D.u;
+      TimedScope ts(C, kTCoarse, (double)(C->hl[lf].nn + C->hl[lf + 1].nn) * sizeof(R) * 7.5);
+      launch_up2_rb<R>(grid_M<R>(C, lf), grid_M<R>(C, lf + 1), grid_M<R>(C, lf + 2), b, D.t, Dm.b, Dm.t,
+                       dev_level<R>(C, lf + 2).u, out, om, C->stream);
+      l -= 2;
+      continue;
+    }
     DevLevel<R> &D = dev_level<R>(C, l);
     DevLevel<R> &Dc = dev_level<R>(C, l + 1);
     const cplx<R> *b = l == 0 ? b0 : D.b;
@@ -722,6 +754,7 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
     TimedScope ts(C, l == 0 ? kTUp : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 7.5);
     launch_up_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.u, out, om, small(l) ? 4 : T.up_rows,
                     C->stream);
+    l--;
   }
 }
 
@@ -1551,6 +1584,7 @@ ecs_status ecs_set_tuning(ecs_ctx *C, const ecs_tuning *t) {
   if (!down_ok || !up_ok) return fail(C, ECS_EINVAL, "unsupported tile height");
   if (t->tail_nodes < 3 || t->tail_nodes > kTailNodes) return fail(C, ECS_EINVAL, "tail_nodes must be in [3, 33]");
   if (t->small_grid < 3) return fail(C, ECS_EINVAL, "small_grid must be >= 3");
+  if (t->pair_grid < 0) return fail(C, ECS_EINVAL, "pair_grid must be >= 0");
   C->tune = *t;
   drop_graphs(C);
   return ECS_OK;

@@ -130,6 +130,27 @@ def test_vcycle_tail_schedules(dt):
                 assert relerr(to_np(S.vcycle(to_gpu(v))), ref) < CYCLE_TOL[dt], (w.name, w.n, tn)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_vcycle_two_level_kernels(dt):
+    """Levels run two per kernel (down: levels l, l+1 in one block with the
+    intermediate right-hand side in LDS; up: levels l+1, l): every pairing
+    the schedule allows -- none, only the smallest levels, all levels above
+    the tail, an odd count with a single level on top -- against the oracle."""
+    rng = np.random.default_rng(13)
+    runs = [(W.coulomb(E=2.0, n=257), (0, 33, 65, 129, 257)),
+            (ragged_workload(n=193, coarsest=7), (0, 25, 49, 97, 193)),
+            (W.coulomb(E=1.0, n=65), (0, 65))]
+    for w, pgs in runs:
+        P = oracle_for(w)
+        S = gpu_for(w, dt)
+        v = W.random_complex(w.shape, rng)
+        ref = P.mg_apply(v)
+        for pg in pgs:
+            for tn in (9, 33):
+                S.set_tuning(tail_nodes=tn, pair_grid=pg)
+                assert relerr(to_np(S.vcycle(to_gpu(v))), ref) < CYCLE_TOL[dt], (w.name, w.n, pg, tn)
+
+
 @pytest.mark.parametrize("gf,gc,smoother,omega,nu", [(2, 2, "rbgs", 1.05, 1), (1, 2, "jacobi", 0.8, 1),
                                                       (1, 4, "jacobi", 0.5, 2), (1, 1, "rbgs", 1.0, 2)])
 def test_general_cycles(gf, gc, smoother, omega, nu):
