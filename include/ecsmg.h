@@ -192,12 +192,21 @@ ecs_status ecs_level_info(ecs_ctx *ctx, int level, int *nlevels, int64_t *nodes)
  *   2 FP64 operator A (matvec)          7 finest-level fused down kernel
  *   3 coarse-level cycle kernels        8 finest-level fused up kernel
  *   4 Arnoldi orthogonal update
+ *                                       9 empty kernel (ecs_timing_calibrate)
+ * A timed duration runs from the dispatch of the kernel to its completion.
  * ecs_timing_read synchronises the stream and returns the number of timed
  * launches, their summed duration in ms and their summed algorithmic bytes
  * (the minimum HBM traffic of each launch: every input read once, every
  * output written once), then resets the class. */
 ecs_status ecs_timing_enable(ecs_ctx *ctx, int kclass, int enable);
 ecs_status ecs_timing_read(ecs_ctx *ctx, int kclass, int64_t *launches, double *total_ms, double *algo_bytes);
+
+/* Time `launches` (1..65536) launches of an empty kernel on the context's
+ * stream as class 9: their average is the fixed part of a timed duration
+ * (dispatch to the first wave, completion) that carries no work, which a
+ * measurement may subtract from the average of another class.  Enables
+ * class 9 for the call only. */
+ecs_status ecs_timing_calibrate(ecs_ctx *ctx, int launches);
 
 /* Launch schedule of the fused 2D V(1,1) red-black cycle (performance only;
  * results do not depend on it):

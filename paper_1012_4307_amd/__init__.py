@@ -33,7 +33,7 @@ KRYLOV = {"gmres": 0, "fgmres": 1, "bicgstab": 2}
 OP = {"A": 0, "AT": 1, "M": 2}
 STATUS = {0: "ok", 1: "not_converged", -1: "einval", -2: "enomem", -3: "edevice", -4: "ebreakdown", -5: "estate"}
 TIMER = {"smooth": 0, "mdot": 1, "apply_A": 2, "coarse": 3, "mupdate": 4, "restrict": 5, "prolong": 6, "down": 7,
-         "up": 8}
+         "up": 8, "empty": 9}
 
 
 class EcsError(RuntimeError):
@@ -106,6 +106,7 @@ def lib():
         "ecs_timing_read": [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D)],
         "ecs_batch_solve": [I, pP, ctypes.POINTER(SolveDesc), pP, pP, ctypes.POINTER(I), ctypes.POINTER(Stats)],
         "ecs_copy_probe": [P, P, Z, P],
+        "ecs_timing_calibrate": [P, I],
         "ecs_set_graphs": [P, I],
         "ecs_set_tuning": [P, ctypes.POINTER(Tuning)],
         "ecs_get_tuning": [P, ctypes.POINTER(Tuning)],
@@ -126,7 +127,7 @@ EXPORTED = ["ecs_create", "ecs_set_ecs", "ecs_set_k2", "ecs_set_precond", "ecs_w
             "ecs_solve", "ecs_solve_adjoint", "ecs_grad_k2", "ecs_apply", "ecs_vcycle", "ecs_smooth",
             "ecs_residual_restrict", "ecs_prolong_correct", "ecs_coarse_solve", "ecs_level_info",
             "ecs_timing_enable", "ecs_timing_read", "ecs_batch_solve", "ecs_copy_probe", "ecs_last_error",
-            "ecs_destroy", "ecs_set_graphs", "ecs_set_tuning", "ecs_get_tuning"]
+            "ecs_destroy", "ecs_set_graphs", "ecs_set_tuning", "ecs_get_tuning", "ecs_timing_calibrate"]
 
 
 def _torch():
@@ -393,6 +394,13 @@ class Solver:
     # ----------------------------------------------------------- timing
     def timing(self, kclass: str, enable: bool = True):
         self._check(lib().ecs_timing_enable(self._h, TIMER[kclass], 1 if enable else 0))
+
+    def timing_calibrate(self, launches: int = 200) -> float:
+        """Mean timed duration (us) of an empty kernel: the fixed part of every
+        timed duration."""
+        self._check(lib().ecs_timing_calibrate(self._h, launches))
+        n, ms, _ = self.timing_read("empty")
+        return 1e3 * ms / max(n, 1)
 
     def timing_read(self, kclass: str):
         """(launches, total ms, algorithmic bytes) of one kernel class since the last read."""

@@ -89,5 +89,7 @@ void launch_mask_boundary(int n0, int n1, int n2, const cplx<double> *x, cplx<do
 void launch_grad_k2(const cplx<double> *lam, const cplx<double> *u, double *g, int64_t n, hipStream_t s);
 void launch_max_real(const double *x, int64_t n, double *partials, double *out, hipStream_t s);
 void launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t s);
+// a kernel that does nothing (timing calibration)
+void launch_empty(hipStream_t s);
 
 }  // namespace ecs

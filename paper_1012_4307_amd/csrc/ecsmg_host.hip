@@ -56,7 +56,7 @@ struct Timer {
 
 // timing classes (see ecs_timing_enable in ecsmg.h)
 enum { kTSmooth = 0, kTMdot = 1, kTApply = 2, kTCoarse = 3, kTMupdate = 4, kTRestrict = 5, kTProlong = 6,
-       kTDown = 7, kTUp = 8, kTClasses = 9 };
+       kTDown = 7, kTUp = 8, kTEmpty = 9, kTClasses = 10 };
 
 // bump allocator over the caller's workspace (256 B alignment); with a null
 // base it only measures
@@ -1542,6 +1542,19 @@ ecs_status ecs_timing_enable(ecs_ctx *C, int kclass, int enable) {
   if (!C || kclass < 0 || kclass >= kTClasses) return ECS_EINVAL;
   C->timers[kclass].on = enable != 0;
   return ECS_OK;
+}
+
+ecs_status ecs_timing_calibrate(ecs_ctx *C, int launches) {
+  if (!C || launches < 1 || launches > 65536) return ECS_EINVAL;
+  Timer &T = C->timers[kTEmpty];
+  const bool was = T.on;
+  T.on = true;
+  for (int q = 0; q < launches; q++) {
+    TimedScope ts(C, kTEmpty, 0.0);
+    launch_empty(C->stream);
+  }
+  T.on = was;
+  return hipGetLastError() == hipSuccess ? ECS_OK : fail(C, ECS_EDEVICE, "empty kernel launch failed");
 }
 
 ecs_status ecs_timing_read(ecs_ctx *C, int kclass, int64_t *launches, double *total_ms, double *algo_bytes) {

@@ -18,6 +18,7 @@ from __future__ import annotations
 import argparse
 import collections
 import csv
+import glob
 import hashlib
 import json
 import os
@@ -25,8 +26,7 @@ import re
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1012_4307_amd", "csrc", f)
-                  for f in ("kernels_vcycle.hip", "kernels_blas.hip", "kernels_mg.hip")]
+KERNEL_SOURCES = sorted(glob.glob(os.path.join(ROOT, "paper_1012_4307_amd", "csrc", "kernels_*.hip")))
 COPY_BYTES = 512 << 20   # the copy probe moves 512 MiB each way
 
 
