@@ -385,10 +385,11 @@ __global__ __launch_bounds__(256) void k_apply2d(Grid<R> g, const cplx<RI> *__re
   }
 }
 
-// strip rows per wave: the x window lives in registers
-template <typename R>
+// strip rows per wave: the x window lives in registers; the dot-product
+// variants hold a second operand per row, so they take shorter strips
+template <typename R, int MODE>
 constexpr int strip_rows() {
-  return sizeof(R) == 4 ? 16 : 8;
+  return MODE != 0 ? 8 : (sizeof(R) == 4 ? 16 : 8);
 }
 
 template <typename R>
@@ -417,7 +418,7 @@ void strip_grid(const Grid<R> &g, int sy, int *tiles_x, int *tiles, int *blocks)
 template <typename R, typename RI, typename RO>
 void launch_apply(const Grid<R> &g, const cplx<RI> *x, cplx<RO> *y, hipStream_t s) {
   if (g.n2 == 1) {
-    constexpr int sy = strip_rows<R>();
+    constexpr int sy = strip_rows<R, 0>();
     int tx, tiles, nb;
     strip_grid(g, sy, &tx, &tiles, &nb);
     launch_k((k_apply2d<R, RI, RO, 0, sy>), dim3(nb), dim3(256), 0, s, g, x, y,
@@ -464,7 +465,7 @@ void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cpl
   // one block per 64 x 4 tile while the partials (two per block) fit the
   // reduction buffer (kRedBlocks x (kMaxRestart + 2) entries)
   if (g.n2 == 1) {
-    constexpr int sy = strip_rows<R>();
+    constexpr int sy = strip_rows<R, 1>();
     int tx, tiles, nb;
     strip_grid(g, sy, &tx, &tiles, &nb);
     if (mode == kBicgAlpha)
