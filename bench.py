@@ -38,7 +38,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2049)
     ap.add_argument("--restart", type=int, default=40)
@@ -145,23 +145,38 @@ def main():
             del S
 
     # V-cycle bandwidth (algorithmic bytes of a V(1,1) RB cycle / cycle time)
+    # V-cycle rate (algorithmic bytes of a V(1,1) RB cycle / cycle time), on
+    # vectors in the cycle's dtype: warm (back to back) and cold (a 512 MiB
+    # write between cycles evicts the 256 MB last-level cache)
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+
     def vcycle_rate(S, real_bytes):
-        v = b.clone()
+        v = b.to(S.cycle_dtype)
         for _ in range(3):
-            S.vcycle(v)
+            S.vcycle_native(v)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record()
         for _ in range(args.vcycles):
-            S.vcycle(v)
+            S.vcycle_native(v)
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / args.vcycles
+        cold = []
+        for _ in range(5):
+            E.copy_probe(flush, flush)
+            ev0.record()
+            S.vcycle_native(v)
+            ev1.record()
+            torch.cuda.synchronize()
+            cold.append(ev0.elapsed_time(ev1))
         by = vcycle_algorithmic_bytes(args.n, nlev, real_bytes)
-        return ms, by / (ms * 1e-3) / 1e9
+        cms = float(np.median(cold))
+        return ms, by / (ms * 1e-3) / 1e9, cms, by / (cms * 1e-3) / 1e9
 
-    vc64_ms, vc64_gbs = vcycle_rate(S64, 8)
-    vc32_ms, vc32_gbs = vcycle_rate(Smix, 4)
+    vc64_ms, vc64_gbs, vc64_cold, vc64_cold_gbs = vcycle_rate(S64, 8)
+    vc32_ms, vc32_gbs, vc32_cold, vc32_cold_gbs = vcycle_rate(Smix, 4)
+    del flush
 
     # copy probe (plain device copy of 512 MiB): the practical HBM rate, and
     # the reference dispatch that scales the FETCH_SIZE / WRITE_SIZE counters
@@ -237,7 +252,10 @@ def main():
         "context_solves": context,
         "vcycle": {"fp64_ms": round(vc64_ms, 4), "fp64_algo_gbs": round(vc64_gbs, 1),
                    "fp32_ms": round(vc32_ms, 4), "fp32_algo_gbs": round(vc32_gbs, 1),
-                   "bytes_model": "13 reals/node/level above the coarsest"},
+                   "fp64_cold_ms": round(vc64_cold, 4), "fp64_cold_algo_gbs": round(vc64_cold_gbs, 1),
+                   "fp32_cold_ms": round(vc32_cold, 4), "fp32_cold_algo_gbs": round(vc32_cold_gbs, 1),
+                   "bytes_model": "13 reals/node/level above the coarsest",
+                   "vectors": "in the cycle's dtype (no conversion passes)"},
         "copy_probe_gbs": round(copy_gbs, 1),
         "kernels_in_timed_region": kernels,
         "roofline": roofline,

@@ -170,6 +170,10 @@ ecs_status ecs_apply(ecs_ctx *ctx, int op, const void *x_dev, void *y_dev);
  * preconditioner's vcycle_dtype. */
 ecs_status ecs_vcycle(ecs_ctx *ctx, const void *v_dev, void *z_dev);
 
+/* The same cycle on vectors already in the cycle's dtype (complex64 when
+ * vcycle_dtype is ECS_F32, complex128 otherwise): no conversion passes. */
+ecs_status ecs_vcycle_native(ecs_ctx *ctx, const void *v_dev, void *z_dev);
+
 /* Per-step entry points on level `level` (0 = finest) of the hierarchy,
  * operating on arrays of that level's size in the cycle's dtype (complex128
  * for ECS_F64, complex64 for ECS_F32):

@@ -107,6 +107,7 @@ def lib():
         "ecs_batch_solve": [I, pP, ctypes.POINTER(SolveDesc), pP, pP, ctypes.POINTER(I), ctypes.POINTER(Stats)],
         "ecs_copy_probe": [P, P, Z, P],
         "ecs_timing_calibrate": [P, I],
+        "ecs_vcycle_native": [P, P, P],
         "ecs_set_graphs": [P, I],
         "ecs_set_tuning": [P, ctypes.POINTER(Tuning)],
         "ecs_get_tuning": [P, ctypes.POINTER(Tuning)],
@@ -127,7 +128,8 @@ EXPORTED = ["ecs_create", "ecs_set_ecs", "ecs_set_k2", "ecs_set_precond", "ecs_w
             "ecs_solve", "ecs_solve_adjoint", "ecs_grad_k2", "ecs_apply", "ecs_vcycle", "ecs_smooth",
             "ecs_residual_restrict", "ecs_prolong_correct", "ecs_coarse_solve", "ecs_level_info",
             "ecs_timing_enable", "ecs_timing_read", "ecs_batch_solve", "ecs_copy_probe", "ecs_last_error",
-            "ecs_destroy", "ecs_set_graphs", "ecs_set_tuning", "ecs_get_tuning", "ecs_timing_calibrate"]
+            "ecs_destroy", "ecs_set_graphs", "ecs_set_tuning", "ecs_get_tuning", "ecs_timing_calibrate",
+            "ecs_vcycle_native"]
 
 
 def _torch():
@@ -341,10 +343,20 @@ class Solver:
         return y
 
     def vcycle(self, v):
+        """z = MG(v): complex128 in and out (converted around an FP32 cycle)."""
         torch = _torch()
         v = self._vec(v)
         z = torch.empty_like(v)
         self._check(lib().ecs_vcycle(self._h, _ptr(v), _ptr(z)))
+        return z
+
+    def vcycle_native(self, v):
+        """z = MG(v) on vectors in the cycle's own dtype (complex64 for an FP32
+        cycle), without conversion passes."""
+        torch = _torch()
+        v = self._vec(v, self.cycle_dtype)
+        z = torch.empty_like(v)
+        self._check(lib().ecs_vcycle_native(self._h, _ptr(v), _ptr(z)))
         return z
 
     def smooth(self, b, u, level=0, nsweeps=1):

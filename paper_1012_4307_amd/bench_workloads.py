@@ -8,7 +8,8 @@ batched     many independent systems (grids 257^2 / 513^2 / 1025^2, E, theta
             beside the same systems solved one call at a time.
 adjoint     the differentiable solve on 1025^2 (E = 2): forward and backward
             (adjoint) time, gradient of L = 1/2 ||M u - d||^2 against central
-            differences on sampled nodes.
+            differences (eps = 1e-6) on 50 random interior nodes and on 5 nodes
+            with large gradients.
 cube        3D 7-point 129^3 forward solve at constant k = 12 (QD, V(1,1)
             red-black, FGMRES(30)).
 coulomb513  soft-Coulomb QD problems on 513^2, E in {0.5, 1, 2, 4}, Bi-CGSTAB.
@@ -121,37 +122,48 @@ def adjoint(args):
 
     kg = k2.clone().requires_grad_(True)
     L = loss(kg, fwd)
-    (g,), t_fwd_bwd = _timed(lambda: torch.autograd.grad(loss(kg, fwd), kg))
-    (u_only, t_fwd) = _timed(lambda: S.solve(f, krylov=fwd))
+    torch.autograd.grad(loss(kg, fwd), kg)   # warm-up of both directions
+    reps = [_timed(lambda: torch.autograd.grad(loss(kg, fwd), kg))[1] for _ in range(3)]
+    t_fwd_bwd = float(np.median(reps))
+    S.solve(f, krylov=fwd)
+    t_fwd = float(np.median([_timed(lambda: S.solve(f, krylov=fwd))[1] for _ in range(3)]))
     kg = k2.clone().requires_grad_(True)
     (gt,) = torch.autograd.grad(loss(kg, tight), kg)
     gt = gt.cpu().numpy()
     x = W.real_nodes(n, -10.0, 10.0)
     inner = np.flatnonzero((np.abs(x) <= 8))
-    # random interior nodes, and random nodes among those whose gradient is
-    # within 1e-2 of the largest (where central differences resolve it)
-    cells = [(int(rng.choice(inner)), int(rng.choice(inner))) for _ in range(5)]
+    # 50 random interior nodes (|x|, |y| <= 8) at eps = 1e-6; and 5 nodes
+    # among those whose gradient is within 1e-2 of the largest at eps = 1e-6
+    # and 1e-3.  With gradients ~1e-7 and the loss known to ~1e-15 from
+    # 1e-12 solves, eps = 1e-6 leaves ~1e-3 relative noise in the quotient;
+    # eps = 1e-3 brings it below 1e-5 while the truncation error stays
+    # O((eps / k^2)^2) ~ 1e-8
+    rand_cells = [(int(rng.choice(inner)), int(rng.choice(inner))) for _ in range(50)]
     big = np.flatnonzero(np.abs(gt).ravel() >= 1e-2 * np.abs(gt).max())
-    cells += [(int(t // n), int(t % n)) for t in rng.choice(big, size=5, replace=False)]
-    errs = []
+    big_cells = [(int(t // n), int(t % n)) for t in rng.choice(big, size=5, replace=False)]
     gscale = float(np.abs(gt).max())
+
+    def fd(j, i, eps):
+        kp = k2.clone(); kp[j, i] += eps
+        km = k2.clone(); km[j, i] -= eps
+        return (float(loss(kp, tight)) - float(loss(km, tight))) / (2 * eps)
+
     with torch.no_grad():
-        for (j, i) in cells:
-            out = {}
-            for eps in (1e-6, 1e-4):
-                kp = k2.clone(); kp[j, i] += eps
-                km = k2.clone(); km[j, i] -= eps
-                out[eps] = (float(loss(kp, tight)) - float(loss(km, tight))) / (2 * eps)
-            errs.append(dict(cell=[j, i], grad=float(gt[j, i]), fd_1e6=out[1e-6], fd_1e4=out[1e-4],
-                             err_1e6_rel_scale=abs(out[1e-6] - gt[j, i]) / gscale,
-                             err_1e4_rel=abs(out[1e-4] - gt[j, i]) / max(abs(gt[j, i]), 1e-30)))
+        rand_err = [abs(fd(j, i, 1e-6) - gt[j, i]) / gscale for (j, i) in rand_cells]
+        big = []
+        for (j, i) in big_cells:
+            f6, f3 = fd(j, i, 1e-6), fd(j, i, 1e-3)
+            big.append(dict(cell=[j, i], grad=float(gt[j, i]), fd_1e6=f6, fd_1e3=f3,
+                            err_1e6_rel=abs(f6 - gt[j, i]) / abs(gt[j, i]),
+                            err_1e3_rel=abs(f3 - gt[j, i]) / abs(gt[j, i])))
     _emit(dict(metric="adjoint gradient of a 1025^2 ECS solve", unit="s", value=round(t_fwd_bwd, 4),
                higher_is_better=False, forward_seconds=round(t_fwd, 4),
                forward_plus_backward_seconds=round(t_fwd_bwd, 4), loss=float(L),
-               max_fd_err_eps1e6_rel_to_max_grad=max(e["err_1e6_rel_scale"] for e in errs),
-               max_fd_err_eps1e4_rel=max(e["err_1e4_rel"] for e in errs),
-               max_fd_err_eps1e4_rel_large_grad=max(e["err_1e4_rel"] for e in errs[5:]), cells=errs,
-               dtype="f64", data="synthetic"))
+               fd_random_cells=len(rand_cells),
+               fd_random_max_err_rel_to_max_grad=float(max(rand_err)),
+               fd_random_median_err_rel_to_max_grad=float(np.median(rand_err)),
+               fd_large_grad_max_err_eps1e3_rel=max(e["err_1e3_rel"] for e in big),
+               fd_large_grad_cells=big, dtype="f64", data="synthetic"))
 
 
 def cube(args):

@@ -1460,6 +1460,19 @@ ecs_status ecs_vcycle(ecs_ctx *C, const void *v, void *z) {
   return ECS_OK;
 }
 
+ecs_status ecs_vcycle_native(ecs_ctx *C, const void *v, void *z) {
+  ecs_status st = check_ready(C);
+  if (st != ECS_OK) return st;
+  if (!v || !z) return fail(C, ECS_EINVAL, "null argument");
+  if (C->prec.kind == ECS_PREC_NONE) return fail(C, ECS_EINVAL, "no preconditioner configured");
+  if (C->prec.vcycle_dtype == ECS_F64)
+    vcycle<double>(C, reinterpret_cast<const cplx<double> *>(v), reinterpret_cast<cplx<double> *>(z));
+  else
+    vcycle<float>(C, reinterpret_cast<const cplx<float> *>(v), reinterpret_cast<cplx<float> *>(z));
+  HIP_OK(hipGetLastError());
+  return ECS_OK;
+}
+
 #define LEVEL_CHECK(l)                                                                                    \
   do {                                                                                                    \
     ecs_status st_ = check_ready(C);                                                                      \

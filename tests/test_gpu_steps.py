@@ -110,6 +110,22 @@ def test_vcycle(case, dt):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_vcycle_native_dtype(dt):
+    """The cycle on vectors in its own dtype (no conversion passes) equals the
+    oracle's cycle of the same right-hand side."""
+    import torch
+    w = W.coulomb(E=2.0, n=257)
+    P = oracle_for(w)
+    S = gpu_for(w, dt)
+    v = W.random_complex(w.shape, np.random.default_rng(14))
+    vd = to_gpu(v).to(torch.complex64 if dt == "f32" else torch.complex128)
+    z = S.vcycle_native(vd)
+    assert z.dtype == vd.dtype
+    ref = P.mg_apply(to_np(vd).astype(np.complex128))
+    assert relerr(to_np(z).astype(np.complex128), ref) < CYCLE_TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_vcycle_tail_schedules(dt):
     """The single-workgroup tail over every admissible range of coarse levels:
     the whole cycle (33^2 grid), the dense solve alone, and coarsest grids of
