@@ -32,7 +32,7 @@ def _key(solver) -> str:
 
 
 def candidates(dtype: str):
-    downs = (2, 4, 8, 16) if dtype == "f32" else (2, 4, 8)
+    downs = (2, 4, 6, 8, 16) if dtype == "f32" else (2, 4, 6, 8)
     for d, u, sg, tn, pg in itertools.product(downs, (4, 8, 16), (257, 513), (17, 33), (0, 129, 513)):
         yield dict(down_rows=d, up_rows=u, small_grid=sg, tail_nodes=tn, pair_grid=pg)
 

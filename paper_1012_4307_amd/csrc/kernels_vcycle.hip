@@ -614,6 +614,7 @@ void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b
   switch (rows) {
     case 2: launch_k((k_down_rb<R, 2>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
     case 4: launch_k((k_down_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
+    case 6: launch_k((k_down_rb<R, 6>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
     case 16:
       if constexpr (sizeof(R) == 4) {
         launch_k((k_down_rb<R, 16>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles);
@@ -634,6 +635,7 @@ void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, 
   switch (rows) {
     case 4: launch_k((k_up_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
     case 8: launch_k((k_up_rb<R, 8>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
+    case 12: launch_k((k_up_rb<R, 12>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
     case 32: launch_k((k_up_rb<R, 32>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
     default: launch_k((k_up_rb<R, 16>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
   }
