@@ -65,8 +65,9 @@ enum { ECS_OP_A = 0, ECS_OP_AT = 1, ECS_OP_M = 2 };
  *   LAPLACE  M = -Lap
  *   CSL      M = -Lap + (beta1 + i beta2) k^2
  *   CSG      M = Z on the grid rotated by e^{i theta_alpha}
- *   QD       M = (1 - i) I + Z / |Re lambda0|; re_lambda0 <= 0 selects
- *            |Re lambda0| = max k^2 (the rough rule of Sec. 5)
+ *   QD       M = (1 - i) I + Z / |Re lambda0| with |Re lambda0| =
+ *            |re_lambda0| (Sec. 5 quotes Re lambda0 as negative numbers);
+ *            re_lambda0 = 0 selects max k^2 (the rough rule of Sec. 5)
  *   NONE     no preconditioner (Krylov on A alone)
  * smoother: omega-Jacobi or red-black SOR ("omega-red-black Jacobi"),
  * red = nodes with i+j(+k) even first.  gamma_f = gamma_c = 1 is the V cycle.

@@ -472,8 +472,8 @@ ohier *ora_create(int dim, const int n[3], const double *z0, const double *z1, c
  *   kind 1: Laplace  M = -Lap                        (1, 0, 0)
  *   kind 2: CSL      M = -Lap + (p1 + i p2) k^2      (1, p1 + i p2, 0)
  *   kind 3: CSG      M = Z on the grid rotated by e^{i p1}
- *   kind 4: QD       M = (1 - i) I + Z / |Re lambda0|, |Re lambda0| = p1,
- *                    or max k^2 over the fine grid when p1 <= 0 (Sec. 5: the
+ *   kind 4: QD       M = (1 - i) I + Z / |Re lambda0|, |Re lambda0| = |p1|,
+ *                    or max k^2 over the fine grid when p1 = 0 (Sec. 5: the
  *                    largest wavenumber as a rough approximation of lambda0)
  * Returns the |Re lambda0| actually used for QD (0 otherwise).
  */
@@ -486,8 +486,8 @@ double ora_set_operator(ohier *H, int kind, double p1, double p2) {
     case 2: H->alpha = 1; H->beta = p1 + I * p2; H->c = 0; break;
     case 3: H->alpha = 1; H->beta = -1; H->c = 0; break;
     case 4: {
-      lam = p1;
-      if (lam <= 0) {
+      lam = fabs(p1); /* Sec. 5 quotes Re(lambda0) as a negative number */
+      if (lam == 0) {
         olevel *F = &H->lev[0];
         lam = 0;
         for (int64_t p = 0; p < F->nn; p++) if (F->k2[p] > lam) lam = F->k2[p];

@@ -153,7 +153,7 @@ class Precond:
     beta1: float = -1.0
     beta2: float = -0.5
     theta_alpha: float = math.pi / 13
-    re_lambda0: float = 0.0            # QD: <= 0 -> max k^2
+    re_lambda0: float = 0.0            # QD: Re(lambda0) (its magnitude is used); 0 -> max k^2
     smoother: str = "rbgs"
     omega: float = 1.0
     nu1: int = 1

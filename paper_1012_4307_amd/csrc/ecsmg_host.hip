@@ -489,8 +489,8 @@ ecs_status setup(ecs_ctx *C) {
   const ecs_prec_desc &P = C->prec;
   double lam0 = 0;
   if (P.kind == ECS_PREC_QD) {
-    lam0 = P.re_lambda0;
-    if (lam0 <= 0) {
+    lam0 = std::fabs(P.re_lambda0);
+    if (lam0 == 0) {
       launch_max_real(C->k2, nn0, C->dscal, C->dscal + kRedBlocks, s);
       HIP_OK(hipMemcpyAsync(C->pinned, C->dscal + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_OK(hipStreamSynchronize(s));
