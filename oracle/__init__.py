@@ -139,7 +139,7 @@ class Problem:
     # -- configuration --------------------------------------------------
     def set_operator(self, kind: str, p1: float = 0.0, p2: float = 0.0) -> float:
         """Preconditioner operator (Sec. 5): 'A', 'laplace', 'csl' (p1=b1, p2=b2),
-        'csg' (p1=theta_alpha), 'qd' (p1=|Re lambda0|, <=0 means max k^2)."""
+        'csg' (p1=theta_alpha), 'qd' (p1=Re lambda0, its magnitude is used; 0 means max k^2)."""
         self.lam0 = float(_load().ora_set_operator(self._h, KIND[kind], float(p1), float(p2)))
         return self.lam0
 

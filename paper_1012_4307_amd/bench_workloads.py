@@ -15,6 +15,13 @@ cube        3D 7-point 129^3 forward solve at constant k = 12 (QD, V(1,1)
 coulomb513  soft-Coulomb QD problems on 513^2, E in {0.5, 1, 2, 4}, Bi-CGSTAB.
 small65     the 65^2 constant-k problem (CSL, omega-Jacobi, GMRES(30)) for both
             right-hand sides and both signs of the complex shift.
+paper_mp    the model problems of Sec. 5 (Tables 1-4: MP1 k = 160 on 385^2,
+            MP2 on 641^2, MP3 k = 2 on 641^2 and k = 4 on 897^2), each with the
+            CSL, CSG and QD set-ups of its table: stand-alone multigrid on
+            M x = f (cycles to a 1e-6 residual reduction; mg-conv = geometric
+            mean of the residual ratios over all cycles, with the mean of the
+            last 5 beside it) and right preconditioned Bi-CGSTAB on A u = f to
+            1e-6, FP64 throughout.
 """
 from __future__ import annotations
 
@@ -215,6 +222,89 @@ def small65(args):
                data="synthetic"))
 
 
+def _standalone_mg(S, f, rtol=1e-6, maxcycles=200):
+    """x_{m+1} = x_m + MG(f - M x_m) from x_0 = 0, i.e. the cycle of Algorithm 1
+    run with the previous iterate as its initial guess (the smoothers and the
+    coarse solve are linear, so the zero-guess cycle applied to the residual is
+    the same map).  Returns (cycles, average reduction per cycle over all
+    cycles, geometric mean of the last 5 ratios, seconds, final reduction)."""
+    import torch
+
+    def rnorm(r):
+        return float(torch.linalg.vector_norm(r[..., 1:-1, 1:-1]))
+
+    def go():
+        x = torch.zeros_like(f)
+        r = f.clone()
+        hist = [rnorm(r)]
+        while len(hist) <= maxcycles and hist[-1] > rtol * hist[0]:
+            x += S.vcycle(r)
+            r = f - S.apply(x, "M")
+            hist.append(rnorm(r))
+        return hist
+
+    go()
+    hist, secs = _timed(go)
+    ratios = [hist[i + 1] / hist[i] for i in range(len(hist) - 1)]
+    last = ratios[-5:]
+    last5 = math.exp(sum(math.log(q) for q in last) / len(last)) if last else 0.0
+    cycles = len(hist) - 1
+    conv = (hist[-1] / hist[0]) ** (1.0 / cycles) if cycles else 0.0
+    return cycles, conv, last5, secs, hist[-1] / hist[0]
+
+
+# Printed results of Tables 1-4 (Sec. 5), per set-up: mg-conv, # stand-alone
+# cycles, Bi-CGSTAB iterations, Bi-CGSTAB cputime in seconds (the authors'
+# machine; context only).
+PAPER_TABLES = {
+    ("T1 MP1 k=160", "csl"): (0.43, 17, 60, 131), ("T1 MP1 k=160", "csg"): (0.39, 15, 62, 122),
+    ("T1 MP1 k=160", "qd"): (0.09, 6, 170, 339),
+    ("T2 MP2 nu=7 k=4", "csl"): (0.53, 22, 137, 454), ("T2 MP2 nu=7 k=4", "csg"): (0.53, 22, 143, 456),
+    ("T2 MP2 nu=7 k=4", "qd"): (0.15, 8, 357, 1180),
+    ("T3 MP3 k=2", "csl"): (0.32, 13, 60, 189), ("T3 MP3 k=2", "csg"): (0.32, 13, 61, 190),
+    ("T3 MP3 k=2", "qd"): (0.17, 8, 164, 540),
+    ("T4 MP3 k=4", "csl"): (0.32, 13, 210, 1100), ("T4 MP3 k=4", "csg"): (0.31, 12, 160, 854),
+    ("T4 MP3 k=4", "qd"): (0.13, 7, 545, 2800),
+}
+
+
+def paper_mp(args):
+    import torch
+    from . import Krylov, Precond, Solver
+    from . import workloads as W
+    tables = (("T1 MP1 k=160", W.paper_mp1), ("T2 MP2 nu=7 k=4", W.paper_mp2),
+              ("T3 MP3 k=2", lambda: W.paper_mp3(2.0)), ("T4 MP3 k=4", lambda: W.paper_mp3(4.0, 75.0, 768)))
+    rows = []
+    total = 0.0
+    for label, make in tables:
+        w, setups = make()
+        k2 = torch.from_numpy(w.k2).to("cuda")
+        f = torch.from_numpy(w.rhs[0]).to("cuda")
+        kr = Krylov(method="bicgstab", rtol=1e-6, maxit=5000)
+        for name, p, cyc in setups:
+            pc = Precond(kind=p["kind"], beta1=p.get("beta1", -1.0), beta2=p.get("beta2", -0.5),
+                         theta_alpha=p.get("theta_alpha", math.pi / 13), re_lambda0=p.get("lam0", 0.0),
+                         smoother=cyc["smoother"], omega=cyc["omega"], nu1=cyc["nu1"], nu2=cyc["nu2"],
+                         gamma_f=cyc["gamma_f"], gamma_c=cyc["gamma_c"], coarsest_nodes=cyc["coarsest"],
+                         vcycle_dtype="f64")
+            S = Solver(w.dim, w.n, w.lo, w.hi, w.ecs, k2, pc, kr)
+            cycles, conv, last5, mg_secs, red = _standalone_mg(S, f)
+            S.solve(f)
+            (x, st), secs = _timed(lambda: S.solve(f))
+            total += secs
+            rows.append(dict(table=label, grid=w.n[0], precond=name, cycle=f"F{cyc['gamma_f']}^{cyc['gamma_c']}"
+                             if cyc["gamma_c"] > 1 else "V", smoother=cyc["smoother"], omega=cyc["omega"],
+                             mg_conv=round(conv, 3), mg_conv_last5=round(last5, 3), mg_cycles=cycles, mg_seconds=round(mg_secs, 4),
+                             mg_reduction=red, bicgstab_iterations=st["iterations"], vcycles=st["vcycles"],
+                             seconds=round(secs, 4), rel_residual=st["rel_residual"], status=st["status_name"],
+                             paper=dict(zip(("mg_conv", "mg_cycles", "bicgstab_iterations", "seconds"),
+                                            PAPER_TABLES[(label, name)]))))
+            print(json.dumps(rows[-1]), flush=True)
+            del S
+    _emit(dict(metric="Sec. 5 model problems: Bi-CGSTAB solves to 1e-6, all 12 set-ups", unit="s",
+               value=round(total, 4), higher_is_better=False, runs=rows, dtype="f64", data="synthetic"))
+
+
 def run(args):
-    {"batched": batched, "adjoint": adjoint, "cube": cube, "coulomb513": coulomb513, "small65": small65}[args.config](
-        args)
+    {"batched": batched, "adjoint": adjoint, "cube": cube, "coulomb513": coulomb513, "small65": small65,
+     "paper_mp": paper_mp}[args.config](args)

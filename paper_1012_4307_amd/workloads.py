@@ -27,6 +27,14 @@ Workloads (sizes are nodes per axis including both Dirichlet end nodes):
   sampling sub-grid and data from a +5% Gaussian bump of k^2.
 * ``cube_constant_k(n)`` -- 3D [-1,1]^3, ECS from 0.75 at pi/6, k = 12,
   Gaussian source.
+* ``paper_mp1`` / ``paper_mp2`` / ``paper_mp3`` -- the model problems of
+  Sec. 5 with the grids of Tables 1-4: MP1 (-Lap - k^2, k = 160, unit
+  source at the centre node, interior [0,1]^2 with 64-cell layers on all
+  four sides); MP2 (k^2 = 16 + 7 (exp(-x^2) + exp(-y^2)), [0,50]^2 with
+  128-cell layers on the east and north sides, Dirichlet at x = 0 and y = 0);
+  MP3 (k^2 = k0^2 + 1/x + 1/y on [0,50]^2 or [0,75]^2, same layers).  The
+  sources of MP2/MP3 are exp(-(x^2 + y^2)).  Each comes with the three
+  preconditioner set-ups of its table (CSL, CSG, QD).
 """
 from __future__ import annotations
 
@@ -221,3 +229,82 @@ def cube_constant_k(n: int = 129, k: float = 12.0, coarsest: int = 5) -> Workloa
                     dict(kind="qd", lam0=0.0),
                     dict(smoother="rbgs", omega=1.0, nu1=1, nu2=1, gamma_f=1, gamma_c=1, coarsest=coarsest),
                     dict(method="fgmres", m=30, rtol=1e-8, maxit=3000), levels_to(n, coarsest))
+
+
+# ------------------------------------------------------------------ Sec. 5
+def _paper_grid(n_int: int, n_layer: int, L: float, sides: str):
+    """Nodes of an interior [0, L] split into n_int cells plus n_layer cells of
+    the same width in each ECS layer (sides 'both': layers below 0 and above L;
+    'hi': above L only)."""
+    h = L / n_int
+    lo = -n_layer * h if sides == "both" else 0.0
+    n = n_int + (2 if sides == "both" else 1) * n_layer + 1
+    return n, lo, lo + (n - 1) * h
+
+
+def _coarsest(n: int) -> int:
+    """Coarsest grid reached by halving n - 1 down to its odd part (>= 3 nodes)."""
+    m = n - 1
+    while m % 2 == 0 and m > 2:
+        m //= 2
+    return m + 1
+
+
+def _paper_setups(csl, csg, qd, cyc_csl, cyc_csg, om_jac, om_rb, coarsest):
+    """The three preconditioners of one table: (name, precond, cycle)."""
+    def jac(gc):
+        return dict(smoother="jacobi", omega=om_jac, nu1=1, nu2=1, gamma_f=1, gamma_c=gc, coarsest=coarsest)
+    return [("csl", dict(kind="csl", beta1=csl[0], beta2=csl[1]), jac(cyc_csl)),
+            ("csg", dict(kind="csg", theta_alpha=csg), jac(cyc_csg)),
+            ("qd", dict(kind="qd", lam0=qd),
+             dict(smoother="rbgs", omega=om_rb, nu1=1, nu2=1, gamma_f=1, gamma_c=1, coarsest=coarsest))]
+
+
+def _paper_workload(name, n, lo, hi, side, k2, f, coarsest):
+    return Workload(name, 2, (n, n), (lo, lo), (hi, hi), (side, side), k2, [f],
+                    dict(kind="qd", lam0=0.0),
+                    dict(smoother="rbgs", omega=1.0, nu1=1, nu2=1, gamma_f=1, gamma_c=1, coarsest=coarsest),
+                    dict(method="bicgstab", rtol=1e-6, maxit=5000), levels_to(n, coarsest))
+
+
+def paper_mp1(k: float = 160.0, n_int: int = 256, n_layer: int = 64):
+    """MP1 of Table 1: -Lap - k^2 on the interior [0,1]^2 with ECS layers on
+    all four sides and a unit value at the centre node as the source."""
+    n, lo, hi = _paper_grid(n_int, n_layer, 1.0, "both")
+    th = math.pi / 6
+    k2 = np.full((n, n), k * k)
+    f = np.zeros((n, n), np.complex128)
+    f[n // 2, n // 2] = 1.0
+    c = _coarsest(n)
+    w = _paper_workload("paper_mp1", n, lo, hi, ((0.0, th), (1.0, th)), k2, f, c)
+    return w, _paper_setups((-1.0, -0.3), math.pi / 14, -2.6e4, 4, 3, 0.8, 1.0, c)
+
+
+def _paper_mp23(k2_of, L, n_int, n_layer, name):
+    n, lo, hi = _paper_grid(n_int, n_layer, L, "hi")
+    X, Y = _grid2(n, lo, hi)
+    k2 = k2_of(X, Y)
+    f = _zero_boundary(np.exp(-(X * X + Y * Y)).astype(np.complex128))
+    return _paper_workload(name, n, lo, hi, (None, (L, math.pi / 6)), k2, f, _coarsest(n))
+
+
+def paper_mp2(nu: float = 7.0, k: float = 4.0, L: float = 50.0, n_int: int = 512, n_layer: int = 128):
+    """MP2 of Table 2: k^2(x, y) = k^2 + nu (exp(-x^2) + exp(-y^2)) on the
+    interior [0, L]^2, ECS layers on the east and north sides."""
+    w = _paper_mp23(lambda X, Y: k * k + nu * (np.exp(-X * X) + np.exp(-Y * Y)), L, n_int, n_layer, "paper_mp2")
+    return w, _paper_setups((-1.0, -0.4), math.pi / 17, -16.88, 3, 3, 0.5, 1.0, w.cycle["coarsest"])
+
+
+def paper_mp3(k: float = 2.0, L: float = 50.0, n_int: int = 512, n_layer: int = 128):
+    """MP3 of Tables 3 (k = 2, [0,50]^2) and 4 (k = 4, [0,75]^2):
+    k^2(x, y) = k^2 + 1/x + 1/y (the Dirichlet nodes x = 0, y = 0 carry 0)."""
+    def k2_of(X, Y):
+        with np.errstate(divide="ignore"):
+            v = k * k + 1.0 / X + 1.0 / Y
+        v[~np.isfinite(v)] = 0.0
+        return v
+    w = _paper_mp23(k2_of, L, n_int, n_layer, f"paper_mp3_k{k:g}")
+    c = w.cycle["coarsest"]
+    if k == 2.0:
+        return w, _paper_setups((-1.0, -0.6), math.pi / 13, -4.19, 2, 2, 0.8, 1.05, c)
+    return w, _paper_setups((-1.0, -0.6), math.pi / 13, -16.18, 4, 3, 0.8, 1.05, c)
