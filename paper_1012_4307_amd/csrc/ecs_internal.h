@@ -112,6 +112,14 @@ void launch_residual_restrict(const Grid<R> &fine, const Grid<R> &coarse, const 
                               cplx<R> *rc, hipStream_t s);
 template <typename R>
 void launch_prolong_add(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *ec, cplx<R> *u, hipStream_t s);
+// u_out = u_in + P ec on the fine interior, 0 on its boundary (out of place)
+template <typename R>
+void launch_prolong_to(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *ec, const cplx<R> *u_in,
+                       cplx<R> *u_out, hipStream_t s);
+// 2D: out = one omega-Jacobi sweep of (u + P ec), out of place
+template <typename R>
+void launch_prolong_jacobi(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *ec, const cplx<R> *b,
+                           const cplx<R> *u, cplx<R> *out, R omega, hipStream_t s);
 template <typename R>
 void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, int n1, int n2, const cplx<R> *b,
                          cplx<R> *x, hipStream_t s);
@@ -158,6 +166,42 @@ struct TailArgs {
 };
 template <typename R>
 void launch_tail(const TailArgs<R> &a, hipStream_t s);
+
+// The coarse end of a general cycle (any gamma_f, gamma_c, nu1, nu2,
+// omega-Jacobi or red-black) in one workgroup, driven by a schedule that the
+// host unrolls from Algorithm 1.  One 32-bit word per operation:
+//   bits 0-3 code, 4-7 level k (0 = the tail's first level), 8 zero guess,
+//   9 f0, 10 f1 (buffer / colour selectors, per code):
+//   kSchedJacobi  u[f1] <- one omega-Jacobi sweep of u[f0] (zero guess: of 0)
+//   kSchedRB      one colour f1 of a red-black sweep, in place on u[f0]
+//   kSchedResid   b_{k+1} <- FW (b_k - M_k u[f0]_k)   (uses u[!f0]_k as scratch)
+//   kSchedCoarse  u[f0]_k <- M_k^{-1} b_k              (k: the coarsest level)
+//   kSchedProlong u[f0]_k += P u[f1]_{k+1}
+//   kSchedZero    u[f0]_k <- 0
+//   kSchedEnd     the tail's result is u[f0]_0
+enum : uint32_t { kSchedEnd = 0, kSchedJacobi = 1, kSchedRB = 2, kSchedResid = 3, kSchedCoarse = 4,
+                  kSchedProlong = 5, kSchedZero = 6 };
+constexpr int kSchedPack = kTailCap + 512;  // packed weights + inverse diagonals of the tail levels
+constexpr int kSchedProgCap = 4096;         // operations per schedule
+template <typename R>
+struct SchedArgs {
+  int nl;                             // levels in the tail, the last one the coarsest
+  int noff[kTailMaxLevels + 1];       // node offsets of the levels in the LDS vectors
+  int pko[kTailMaxLevels + 1];        // offsets of the levels in the pack
+  int n0[kTailMaxLevels], n1[kTailMaxLevels];
+  const cplx<R> *pack;                // per level: alpha a-, alpha a+ (x), the same (y), 1 / diag(M)
+  int pack_len;
+  const cplx<R> *minvT;               // coarsest inverse, transposed
+  int nunk, tpr;                      // coarsest interior nodes; threads per row of the dense solve
+  const cplx<R> *b_in;                // right-hand side of the first level
+  const cplx<R> *u_in;                // its initial iterate, or null for a zero guess
+  cplx<R> *u_out;                     // its result (may alias u_in)
+  const uint32_t *prog;
+  int prog_len;
+  R omega;
+};
+template <typename R>
+void launch_sched_tail(const SchedArgs<R> &a, hipStream_t s);
 template <typename R>
 void launch_inject_k2(int n0, int n1, int n2, const double *k2_fine, int f0, int f1, R *k2_coarse, hipStream_t s);
 

@@ -126,6 +126,20 @@ struct ecs_ctx {
 
   // launch schedule of the fused V(1,1) cycle (autotuned per grid and dtype)
   ecs_tuning tune{4, 8, 513, 33, 129};
+
+  // coarse end of the general cycle in one workgroup (2D): packed weights and
+  // inverse diagonals of the levels that may form it (levels sfirst .. coarsest,
+  // level l at spko[l] - spko[sfirst]), and the schedules unrolled from
+  // Algorithm 1 for the loaded key (tail level, gamma_f, gamma_c, nu1, nu2,
+  // smoother); variants: (gf, gc) or (gc, gf), each from zero or from a guess
+  cplx<double> *spack64 = nullptr;
+  cplx<float> *spack32 = nullptr;
+  int sfirst = -1;
+  int spko[kMaxLev + 1] = {};
+  uint32_t *sprog = nullptr;
+  int sprog_len[4] = {};
+  int skey[6] = {-2, 0, 0, 0, 0, 0};
+  int gt_l = -1;  // first level of the tail in use, -1: none
 };
 
 namespace {
@@ -247,6 +261,9 @@ size_t plan_layout(ecs_ctx *C, Carver &cv) {
   C->minv64 = cv.take<cplx<double>>((size_t)nunk * nunk);
   if (f32) C->minv32 = cv.take<cplx<float>>((size_t)nunk * nunk);
   C->unk = cv.take<int>(nunk);
+  C->spack64 = cv.take<cplx<double>>(kSchedPack);
+  if (f32) C->spack32 = cv.take<cplx<float>>(kSchedPack);
+  C->sprog = cv.take<uint32_t>(4 * kSchedProgCap);
   C->partials = cv.take<cplx<double>>((size_t)kRedBlocks * (kMaxRestart + 2));
   C->dscal = cv.take<double>(kRedBlocks + 8);
   C->gs = cv.take<GmresScalars>(1);
@@ -583,6 +600,51 @@ ecs_status setup(ecs_ctx *C) {
     if (f32 && (st = upload_cx<float>(C, C->minv32, MT, 1.0)) != ECS_OK) return st;
   }
   HIP_OK(hipMemcpy(C->unk, unk.data(), nu * sizeof(int), hipMemcpyHostToDevice));
+  // pack of the levels that may form the one-workgroup tail of a general cycle
+  C->sfirst = -1;
+  C->gt_l = -1;
+  C->skey[0] = -2;
+  if (C->dim == 2 && C->nlev >= 2) {
+    auto plen = [&](int l) { return 2 * C->hl[l].n[0] + 2 * C->hl[l].n[1] + (int)C->hl[l].nn; };
+    int first = lc;
+    int64_t nodes = Lc.nn;
+    int len = plen(lc);
+    while (first > 0 && C->hl[first - 1].n[0] <= kTailNodes && C->hl[first - 1].n[1] <= kTailNodes &&
+           lc - (first - 1) + 1 <= kTailMaxLevels && nodes + C->hl[first - 1].nn <= kTailCap &&
+           len + plen(first - 1) <= kSchedPack) {
+      first--;
+      nodes += C->hl[first].nn;
+      len += plen(first);
+    }
+    if (first < lc) {
+      std::vector<cd> pack;
+      pack.reserve(len);
+      for (int l = first; l <= lc; l++) {
+        const HostLevel &L = C->hl[l];
+        C->spko[l] = (int)pack.size();
+        std::vector<double> k2l(L.nn);
+        const double *src = l == 0 ? C->k2 : C->L64[l].k2;
+        HIP_OK(hipMemcpyAsync(k2l.data(), src, L.nn * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        for (int a = 0; a < 2; a++) {
+          for (int i = 0; i < L.n[a]; i++) pack.push_back(C->alpha * L.am[a][i]);
+          for (int i = 0; i < L.n[a]; i++) pack.push_back(C->alpha * L.ap[a][i]);
+        }
+        for (int j = 0; j < L.n[1]; j++)
+          for (int i = 0; i < L.n[0]; i++) {
+            const bool in = i >= 1 && i <= L.n[0] - 2 && j >= 1 && j <= L.n[1] - 2;
+            const cd dg = C->alpha * (L.am[0][i] + L.ap[0][i] + L.am[1][j] + L.ap[1][j]) +
+                          C->beta * k2l[(size_t)j * L.n[0] + i] + C->c;
+            pack.push_back(in ? 1.0 / dg : cd(0.0));
+          }
+      }
+      C->spko[lc + 1] = (int)pack.size();
+      ecs_status st;
+      if ((st = upload_cx<double>(C, C->spack64, pack, 1.0)) != ECS_OK) return st;
+      if (f32 && (st = upload_cx<float>(C, C->spack32, pack, 1.0)) != ECS_OK) return st;
+      C->sfirst = first;
+    }
+  }
   // Krylov scalars start cleared
   HIP_OK(hipMemsetAsync(C->gs, 0, sizeof(GmresScalars), s));
   HIP_OK(hipMemsetAsync(C->bs, 0, sizeof(BicgScalars), s));
@@ -620,8 +682,70 @@ void coarse_solve(ecs_ctx *C, const cplx<R> *b, cplx<R> *x) {
   launch_coarse_solve<R>(C->nunk, minv_of<R>(C), C->unk, L.n[0], L.n[1], L.n[2], b, x, C->stream);
 }
 
+// omega-Jacobi sweeps of Algorithm 1 on level l, alternating out of place
+// between the iterate's buffer `cur` and `oth` (no copies); returns the
+// buffer that holds the result
+template <typename R>
+cplx<R> *jacobi_sweeps(ecs_ctx *C, int l, const cplx<R> *b, cplx<R> *cur, cplx<R> *oth, int nsweeps,
+                       bool zero_guess) {
+  Grid<R> g = grid_M<R>(C, l);
+  const int64_t nn = C->hl[l].nn;
+  for (int q = 0; q < nsweeps; q++) {
+    const bool zg = zero_guess && q == 0;
+    TimedScope ts(C, l == 0 ? kTSmooth : kTCoarse, (double)nn * sizeof(R) * (zg ? 5 : 7));
+    launch_jacobi<R>(g, b, cur, oth, (R)C->prec.omega, zg, C->stream);
+    std::swap(cur, oth);
+  }
+  if (nsweeps == 0 && zero_guess) launch_zero<R>(cur, nn, C->stream);
+  return cur;
+}
+
+template <typename R>
+const cplx<R> *spack_of(const ecs_ctx *C);
+template <>
+const cplx<double> *spack_of<double>(const ecs_ctx *C) { return C->spack64; }
+template <>
+const cplx<float> *spack_of<float>(const ecs_ctx *C) { return C->spack32; }
+
+// Algorithm 1 from tail level l to the coarsest in one launch, following the
+// schedule unrolled for (gf, gc) and the guess
+template <typename R>
+void sched_tail(ecs_ctx *C, int l, const cplx<R> *b, cplx<R> *u, int gf, int gc, bool zero_guess) {
+  const ecs_prec_desc &P = C->prec;
+  const int lc = C->nlev - 1;
+  SchedArgs<R> a{};
+  a.nl = lc - l + 1;
+  const int base = C->spko[l];
+  for (int k = 0; k < a.nl; k++) {
+    const HostLevel &L = C->hl[l + k];
+    a.n0[k] = L.n[0];
+    a.n1[k] = L.n[1];
+    a.noff[k + 1] = a.noff[k] + (int)L.nn;
+    a.pko[k] = C->spko[l + k] - base;
+  }
+  a.pko[a.nl] = C->spko[lc + 1] - base;
+  a.pack = spack_of<R>(C) + base;
+  a.pack_len = a.pko[a.nl];
+  a.minvT = minv_of<R>(C);
+  a.nunk = C->nunk;
+  a.tpr = 64;
+  while (a.tpr > 1 && a.tpr * C->nunk > 1024) a.tpr >>= 1;
+  a.b_in = b;
+  a.u_in = zero_guess ? nullptr : u;
+  a.u_out = u;
+  const int v = ((gf == P.gamma_f && gc == P.gamma_c) ? 0 : 2) + (zero_guess ? 0 : 1);
+  a.prog = C->sprog + (size_t)v * kSchedProgCap;
+  a.prog_len = C->sprog_len[v];
+  a.omega = (R)P.omega;
+  TimedScope ts(C, kTCoarse, 0.0);
+  launch_sched_tail<R>(a, C->stream);
+}
+
 // Algorithm 1: u <- MG(l, M_l, b, u, nu1, nu2, C, gf, gc).  zero_guess: u == 0
-// on entry (u's contents are not read and need not be cleared).
+// on entry (u's contents are not read and need not be cleared).  From the
+// tail level on (2D, small levels) the rest of the recursion runs in one
+// launch; above it each step is a launch, omega-Jacobi alternating between u
+// and the level scratch t.
 template <typename R>
 void mg(ecs_ctx *C, int l, const cplx<R> *b, cplx<R> *u, int gf, int gc, bool zero_guess) {
   const int lc = C->nlev - 1;
@@ -629,14 +753,21 @@ void mg(ecs_ctx *C, int l, const cplx<R> *b, cplx<R> *u, int gf, int gc, bool ze
     coarse_solve<R>(C, b, u);
     return;
   }
+  if (l == C->gt_l) {
+    sched_tail<R>(C, l, b, u, gf, gc, zero_guess);
+    return;
+  }
   DevLevel<R> &D = dev_level<R>(C, l);
   DevLevel<R> &Dc = dev_level<R>(C, l + 1);
-  smooth<R>(C, l, b, u, D.t, C->prec.nu1, zero_guess);
+  const bool jac = C->prec.smoother == ECS_SMOOTH_JACOBI;
+  cplx<R> *cur = u;
+  if (jac) cur = jacobi_sweeps<R>(C, l, b, u, D.t, C->prec.nu1, zero_guess);
+  else smooth<R>(C, l, b, u, D.t, C->prec.nu1, zero_guess);
   {
     // read b, u, k^2, write the coarse residual
     const double per = 5.0 + 2.0 / (C->dim == 3 ? 8 : 4);
     TimedScope ts(C, l == 0 ? kTRestrict : kTCoarse, (double)C->hl[l].nn * sizeof(R) * per);
-    launch_residual_restrict<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, u, Dc.b, C->stream);
+    launch_residual_restrict<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, cur, Dc.b, C->stream);
   }
   if (l + 1 == lc) {
     coarse_solve<R>(C, Dc.b, Dc.u);
@@ -646,13 +777,31 @@ void mg(ecs_ctx *C, int l, const cplx<R> *b, cplx<R> *u, int gf, int gc, bool ze
       else mg<R>(C, l + 1, Dc.b, Dc.u, gc, gf, false);
     }
   }
+  const int nu2 = C->prec.nu2;
+  if (jac && C->dim == 2 && nu2 >= 1 && (cur == u) == ((nu2 & 1) == 0)) {
+    // correction fused with the first post-sweep (cur -> its other buffer);
+    // the remaining out-of-place sweeps end in u
+    cplx<R> *oth = cur == u ? D.t : u;
+    {
+      // read u, b, k^2, the coarse correction; write the swept iterate
+      TimedScope ts(C, l == 0 ? kTProlong : kTCoarse, (double)C->hl[l].nn * sizeof(R) * (7.0 + 2.0 / 4));
+      launch_prolong_jacobi<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), Dc.u, b, cur, oth, (R)C->prec.omega,
+                               C->stream);
+    }
+    jacobi_sweeps<R>(C, l, b, oth, cur, nu2 - 1, false);
+    return;
+  }
+  // the corrected iterate goes where an odd / even number of out-of-place
+  // post-sweeps ends in u
+  cplx<R> *dst = (jac && (nu2 & 1)) ? D.t : u;
   {
     // read u and the coarse correction, write u
     const double per = 4.0 + 2.0 / (C->dim == 3 ? 8 : 4);
     TimedScope ts(C, l == 0 ? kTProlong : kTCoarse, (double)C->hl[l].nn * sizeof(R) * per);
-    launch_prolong_add<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), Dc.u, u, C->stream);
+    launch_prolong_to<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), Dc.u, cur, dst, C->stream);
   }
-  smooth<R>(C, l, b, u, D.t, C->prec.nu2, false);
+  if (jac) jacobi_sweeps<R>(C, l, b, dst, dst == u ? D.t : u, C->prec.nu2, false);
+  else smooth<R>(C, l, b, u, D.t, C->prec.nu2, false);
 }
 
 // V(1,1) red-black in 2D (the QD set-up of Sec. 4.2) runs on the fused
@@ -768,9 +917,24 @@ void drop_graphs(ecs_ctx *C) {
 // whole cycle is captured once per (input, output) pair and replayed as one
 // graph launch.  Per-kernel timing needs eager launches, so graphs are
 // bypassed while any cycle timer is on.
+// launches of one general cycle (capped): cycles with very many coarse
+// visits (large gamma over many levels) are not captured
+int64_t cycle_launches(const ecs_ctx *C, int l, int gf, int gc, int64_t cap) {
+  const int lc = C->nlev - 1;
+  if (l == lc || l == C->gt_l) return 1;
+  int64_t n = C->prec.nu1 + C->prec.nu2 + 2;
+  if (l + 1 == lc) return n + 1;
+  for (int i = 1; i <= gc && n < cap; i++)
+    n += i == 1 ? cycle_launches(C, l + 1, gf, gc, cap) : cycle_launches(C, l + 1, gc, gf, cap);
+  return n;
+}
+
 template <typename R>
 bool vcycle_graph(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
-  if (!C->use_graphs || C->timers[kTDown].on || C->timers[kTUp].on || C->timers[kTCoarse].on) return false;
+  for (int k : {kTSmooth, kTCoarse, kTRestrict, kTProlong, kTDown, kTUp})
+    if (C->timers[k].on) return false;
+  if (!C->use_graphs) return false;
+  if (!fused_vcycle(C) && cycle_launches(C, 0, C->prec.gamma_f, C->prec.gamma_c, 4096) >= 4096) return false;
   for (auto &g : C->graphs)
     if (g.b == b0 && g.u == u0 && g.real_bytes == (int)sizeof(R))
       return hipGraphLaunch(g.exec, C->stream) == hipSuccess;
@@ -782,7 +946,8 @@ bool vcycle_graph(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
   if (hipStreamBeginCapture(C->capture, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
   hipStream_t user = C->stream;
   C->stream = C->capture;
-  vcycle_fused<R>(C, b0, u0);
+  if (fused_vcycle(C)) vcycle_fused<R>(C, b0, u0);
+  else mg<R>(C, 0, b0, u0, C->prec.gamma_f, C->prec.gamma_c, true);
   C->stream = user;
   hipGraph_t graph = nullptr;
   if (hipStreamEndCapture(C->capture, &graph) != hipSuccess || !graph) return false;
@@ -794,6 +959,99 @@ bool vcycle_graph(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
   return hipGraphLaunch(exec, C->stream) == hipSuccess;
 }
 
+// Unrolls Algorithm 1 from tail level k (0 = the tail's first level) into the
+// operations of k_sched_tail, tracking which of the two LDS buffers of each
+// level holds its iterate (omega-Jacobi alternates; red-black stays in place).
+struct SchedGen {
+  const ecs_prec_desc *P;
+  int nl;
+  int cur[kTailMaxLevels] = {};
+  std::vector<uint32_t> ops;
+  bool overflow = false;
+
+  void emit(uint32_t code, int k, bool zg, int f0, int f1) {
+    if (ops.size() >= (size_t)kSchedProgCap) {
+      overflow = true;
+      return;
+    }
+    ops.push_back(code | (uint32_t)k << 4 | (uint32_t)zg << 8 | (uint32_t)f0 << 9 | (uint32_t)f1 << 10);
+  }
+  void smooth(int k, int nsweeps, bool zero_guess) {
+    for (int q = 0; q < nsweeps; q++) {
+      const bool zg = zero_guess && q == 0;
+      if (P->smoother == ECS_SMOOTH_JACOBI) {
+        emit(kSchedJacobi, k, zg, cur[k], cur[k] ^ 1);
+        cur[k] ^= 1;
+      } else {
+        emit(kSchedRB, k, zg, cur[k], 0);
+        emit(kSchedRB, k, false, cur[k], 1);
+      }
+    }
+    if (nsweeps == 0 && zero_guess) emit(kSchedZero, k, false, cur[k], 0);
+  }
+  void cycle(int k, int gf, int gc, bool zero_guess) {
+    const int last = nl - 1;
+    if (overflow) return;
+    if (k == last) {
+      emit(kSchedCoarse, k, false, cur[k], 0);
+      return;
+    }
+    smooth(k, P->nu1, zero_guess);
+    emit(kSchedResid, k, false, cur[k], 0);
+    if (k + 1 == last) {
+      emit(kSchedCoarse, k + 1, false, cur[k + 1], 0);
+    } else {
+      for (int i = 1; i <= gc && !overflow; i++) {
+        if (i == 1) cycle(k + 1, gf, gc, true);
+        else cycle(k + 1, gc, gf, false);
+      }
+    }
+    emit(kSchedProlong, k, false, cur[k], cur[k + 1]);
+    smooth(k, P->nu2, false);
+  }
+};
+
+// Loads the schedules of the general cycle's tail for the current set-up
+// (outside any capture: it may copy to the device and drops the graphs that
+// replay older schedules).
+void ensure_sched(ecs_ctx *C) {
+  const ecs_prec_desc &P = C->prec;
+  const int lc = C->nlev - 1;
+  int lt = -1;
+  if (C->sfirst >= 0) {
+    lt = lc;
+    while (lt - 1 >= C->sfirst && C->hl[lt - 1].n[0] <= C->tune.tail_nodes &&
+           C->hl[lt - 1].n[1] <= C->tune.tail_nodes)
+      lt--;
+    if (lt == lc) lt = -1;
+  }
+  const int key[6] = {lt, P.gamma_f, P.gamma_c, P.nu1, P.nu2, P.smoother};
+  if (std::memcmp(key, C->skey, sizeof key) == 0) return;
+  std::memcpy(C->skey, key, sizeof key);
+  C->gt_l = -1;
+  drop_graphs(C);
+  if (lt < 0) return;
+  std::vector<uint32_t> progs[4];
+  for (int v = 0; v < 4; v++) {
+    SchedGen G;
+    G.P = &P;
+    G.nl = lc - lt + 1;
+    const bool swap = v >= 2;
+    G.cycle(0, swap ? P.gamma_c : P.gamma_f, swap ? P.gamma_f : P.gamma_c, (v & 1) == 0);
+    G.emit(kSchedEnd, 0, false, G.cur[0], 0);
+    if (G.overflow) return;  // too long: the per-level launches stay in use
+    progs[v].swap(G.ops);
+  }
+  for (int v = 0; v < 4; v++) {
+    if (hipMemcpyAsync(C->sprog + (size_t)v * kSchedProgCap, progs[v].data(), progs[v].size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, C->stream) != hipSuccess)
+      return;
+    C->sprog_len[v] = (int)progs[v].size();
+  }
+  if (hipStreamSynchronize(C->stream) != hipSuccess) return;
+  C->gt_l = lt;
+}
+
 // z = M^{-1} v approximately: one cycle from zero on the finest level
 template <typename R>
 void vcycle(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
@@ -801,11 +1059,10 @@ void vcycle(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
     coarse_solve<R>(C, b0, u0);
     return;
   }
-  if (fused_vcycle(C)) {
-    if (!vcycle_graph<R>(C, b0, u0)) vcycle_fused<R>(C, b0, u0);
-    return;
-  }
-  mg<R>(C, 0, b0, u0, C->prec.gamma_f, C->prec.gamma_c, true);
+  if (!fused_vcycle(C)) ensure_sched(C);
+  if (vcycle_graph<R>(C, b0, u0)) return;
+  if (fused_vcycle(C)) vcycle_fused<R>(C, b0, u0);
+  else mg<R>(C, 0, b0, u0, C->prec.gamma_f, C->prec.gamma_c, true);
 }
 
 // preconditioner application from an FP64 vector into the cycle's dtype

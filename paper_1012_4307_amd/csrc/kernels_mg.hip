@@ -199,12 +199,17 @@ __global__ __launch_bounds__(256) void k_residual_restrict(Grid<R> f, Grid<R> c,
   rc[q.p] = acc;
 }
 
-// u += P ec on the fine interior (bilinear / trilinear in index space)
+// u_out = u_in + P ec on the fine interior (bilinear / trilinear in index
+// space); in place when u_out == u_in, else the boundary of u_out gets 0
 template <typename R>
 __global__ __launch_bounds__(256) void k_prolong_add(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ ec,
-                                                     cplx<R> *__restrict__ u) {
+                                                     const cplx<R> *u_in, cplx<R> *u_out) {
   Node<R> q = node_of(f);
-  if (!q.interior) return;
+  if (!q.in) return;
+  if (!q.interior) {
+    if (u_out != u_in) u_out[q.p] = mk<R>(0, 0);
+    return;
+  }
   int ci[3][2], nc[3];
   R cw[3][2];
   const int fi[3] = {q.i, q.j, q.k};
@@ -225,7 +230,43 @@ __global__ __launch_bounds__(256) void k_prolong_add(Grid<R> f, Grid<R> c, const
         int64_t pc = ((int64_t)ci[2][cz] * c.n1 + ci[1][cy]) * c.n0 + ci[0][cx];
         e = e + (cw[0][cx] * cw[1][cy] * cw[2][cz]) * ec[pc];
       }
-  u[q.p] = u[q.p] + e;
+  u_out[q.p] = u_in[q.p] + e;
+}
+
+// (P ec) at fine node (i, j) of a 2D level: bilinear in index space; zero on
+// the fine boundary because ec is zero on the coarse boundary
+template <typename R>
+__device__ __forceinline__ cplx<R> prolong_at(const cplx<R> *__restrict__ ec, int c0, int i, int j) {
+  const cplx<R> *e0 = ec + (int64_t)(j >> 1) * c0 + (i >> 1);
+  if ((i & 1) == 0 && (j & 1) == 0) return e0[0];
+  if ((j & 1) == 0) return R(0.5) * (e0[0] + e0[1]);
+  if ((i & 1) == 0) return R(0.5) * (e0[0] + e0[c0]);
+  return R(0.25) * (e0[0] + e0[1] + e0[c0] + e0[c0 + 1]);
+}
+
+// 2D coarse-grid correction fused with the first omega-Jacobi post-sweep, out
+// of place: out = J(u + P ec).  The corrected iterate at the node's four
+// neighbours is formed on the fly (u and ec are zero on their boundaries).
+template <typename R>
+__global__ __launch_bounds__(256) void k_prolong_jacobi(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ ec,
+                                                        const cplx<R> *__restrict__ b,
+                                                        const cplx<R> *__restrict__ u, cplx<R> *__restrict__ out,
+                                                        R omega) {
+  Node<R> q = node_of(f);
+  if (!q.in) return;
+  if (!q.interior) {
+    out[q.p] = mk<R>(0, 0);
+    return;
+  }
+  const int i = q.i, j = q.j, n0 = f.n0, c0 = c.n0;
+  const int64_t p = q.p;
+  const cplx<R> v = u[p] + prolong_at(ec, c0, i, j);
+  const cplx<R> vw = u[p - 1] + prolong_at(ec, c0, i - 1, j), ve = u[p + 1] + prolong_at(ec, c0, i + 1, j);
+  const cplx<R> vs = u[p - n0] + prolong_at(ec, c0, i, j - 1), vn = u[p + n0] + prolong_at(ec, c0, i, j + 1);
+  const cplx<R> o = f.cm0[i] * vw + f.cp0[i] * ve + f.cm1[j] * vs + f.cp1[j] * vn;
+  const cplx<R> d = diag_at(f, i, j, 0, p);
+  const cplx<R> res = b[p] - (d * v - o);
+  out[p] = v + omega * cdiv(res, d);
 }
 
 // x = M_C^{-1} b on the coarsest level from the precomputed dense inverse,
@@ -452,7 +493,17 @@ void launch_residual_restrict(const Grid<R> &fine, const Grid<R> &coarse, const 
 }
 template <typename R>
 void launch_prolong_add(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *ec, cplx<R> *u, hipStream_t s) {
-  launch_k((k_prolong_add<R>), grid_of(fine), dim3(TX, TY), 0, s, fine, coarse, ec, u);
+  launch_k((k_prolong_add<R>), grid_of(fine), dim3(TX, TY), 0, s, fine, coarse, ec, (const cplx<R> *)u, u);
+}
+template <typename R>
+void launch_prolong_to(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *ec, const cplx<R> *u_in,
+                       cplx<R> *u_out, hipStream_t s) {
+  launch_k((k_prolong_add<R>), grid_of(fine), dim3(TX, TY), 0, s, fine, coarse, ec, u_in, u_out);
+}
+template <typename R>
+void launch_prolong_jacobi(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *ec, const cplx<R> *b,
+                           const cplx<R> *u, cplx<R> *out, R omega, hipStream_t s) {
+  launch_k((k_prolong_jacobi<R>), grid_of(fine), dim3(TX, TY), 0, s, fine, coarse, ec, b, u, out, omega);
 }
 template <typename R>
 void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, int n1, int n2, const cplx<R> *b,
@@ -500,6 +551,10 @@ void launch_inject_k2(int n0, int n1, int n2, const double *k2_fine, int f0, int
                                             cplx<R> *, hipStream_t);                                            \
   template void launch_prolong_add<R>(const Grid<R> &, const Grid<R> &, const cplx<R> *, cplx<R> *,              \
                                       hipStream_t);                                                             \
+  template void launch_prolong_jacobi<R>(const Grid<R> &, const Grid<R> &, const cplx<R> *, const cplx<R> *,      \
+                                         const cplx<R> *, cplx<R> *, R, hipStream_t);                           \
+  template void launch_prolong_to<R>(const Grid<R> &, const Grid<R> &, const cplx<R> *, const cplx<R> *,         \
+                                     cplx<R> *, hipStream_t);                                                   \
   template void launch_coarse_solve<R>(int, const cplx<R> *, const int *, int, int, int, const cplx<R> *,      \
                                        cplx<R> *, hipStream_t);                                                 \
   template void launch_inject_k2<R>(int, int, int, const double *, int, int, R *, hipStream_t);

@@ -181,6 +181,40 @@ def test_general_cycles(gf, gc, smoother, omega, nu):
         assert relerr(z, P.mg_apply(w.rhs[0])) < 1e-12, (prec["kind"], gf, gc)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("gf,gc,smoother,omega,nu1,nu2", [(1, 4, "jacobi", 0.8, 1, 1), (1, 3, "jacobi", 0.5, 2, 1),
+                                                          (2, 2, "rbgs", 1.05, 0, 2), (1, 2, "rbgs", 1.0, 1, 0),
+                                                          (2, 3, "jacobi", 0.8, 1, 2)])
+def test_general_cycle_tail(dt, gf, gc, smoother, omega, nu1, nu2):
+    """General cycles whose coarse end runs as one single-workgroup schedule:
+    every tail start (none, the last levels, the whole hierarchy), unequal
+    and zero sweep counts, against the oracle; the captured cycle replays the
+    eager one bit for bit."""
+    import torch
+    rng = np.random.default_rng(15)
+    cyc = dict(smoother=smoother, omega=omega, nu1=nu1, nu2=nu2, gamma_f=gf, gamma_c=gc)
+    runs = [(ragged_workload(n=97, coarsest=4), 4, (3, 7, 13, 25, 33)),
+            (W.paper_mp2(L=6.25, n_int=64, n_layer=16)[0], 6, (3, 11, 21, 33)),
+            (W.coulomb(E=1.0, n=33), 5, (9, 33))]
+    for w, c, tails in runs:
+        cy = dict(cyc, coarsest=c)
+        prec = dict(kind="csl", beta1=-1.0, beta2=-0.5)
+        P = oracle_for(w, prec=prec, cycle=cy)
+        S = gpu_for(w, dt, prec=prec, cycle=cy)
+        v = W.random_complex(w.shape, rng)
+        ref = P.mg_apply(v)
+        for tn in tails:
+            S.set_tuning(tail_nodes=tn)
+            S.set_graphs(False)
+            ze = S.vcycle(to_gpu(v))
+            assert relerr(to_np(ze), ref) < (1e-12 if dt == "f64" else CYCLE_TOL[dt]), (w.name, tn)
+            S.set_graphs(True)
+            for _ in range(3):
+                zg = S.vcycle(to_gpu(v))
+                torch.cuda.synchronize()
+                assert torch.equal(zg, ze), (w.name, tn)
+
+
 def test_3d_steps_and_cycle():
     w = W.cube_constant_k(n=33, k=6.0)
     P = oracle_for(w)
