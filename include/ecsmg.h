@@ -175,6 +175,23 @@ ecs_status ecs_vcycle(ecs_ctx *ctx, const void *v_dev, void *z_dev);
  * vcycle_dtype is ECS_F32, complex128 otherwise): no conversion passes. */
 ecs_status ecs_vcycle_native(ecs_ctx *ctx, const void *v_dev, void *z_dev);
 
+/* Stand-alone multigrid on the preconditioner, M x = b (Sec. 5: the
+ * preconditioner solved on its own, the "mg-conv" and "# cycles" columns of
+ * Tables 1-4): x <- x + MG(b - M x), which is Algorithm 1 started from the
+ * previous iterate, until ||b - M x||_2 <= rtol ||b||_2 over interior nodes
+ * or after maxcycles cycles.  Also a warm start for ecs_solve (Sec. 5 feeds
+ * the preconditioner's solution at 1e-2 to the Krylov method as its guess).
+ * b, x: complex128 device arrays; x_is_guess = 0 starts from x = 0.  M's
+ * residual is formed in FP64; the cycle runs in the preconditioner's
+ * vcycle_dtype.  history (optional host array of history_len doubles)
+ * receives ||b - M x_m|| / ||b|| for m = 0, 1, ... (the entry before the
+ * first cycle included).  stats: iterations = vcycles = cycles done,
+ * rel_residual = the last ratio.  Returns ECS_OK, ECS_NOT_CONVERGED after
+ * maxcycles cycles, or ECS_EBREAKDOWN on NaN/Inf.  Uses the workspace's
+ * Krylov scratch (any workspace size is enough). */
+ecs_status ecs_mg_solve(ecs_ctx *ctx, const void *b_dev, void *x_dev, double rtol, int maxcycles, int x_is_guess,
+                        double *history, int history_len, ecs_stats *stats);
+
 /* Per-step entry points on level `level` (0 = finest) of the hierarchy,
  * operating on arrays of that level's size in the cycle's dtype (complex128
  * for ECS_F64, complex64 for ECS_F32):

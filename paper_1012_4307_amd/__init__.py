@@ -108,6 +108,7 @@ def lib():
         "ecs_copy_probe": [P, P, Z, P],
         "ecs_timing_calibrate": [P, I],
         "ecs_vcycle_native": [P, P, P],
+        "ecs_mg_solve": [P, P, P, D, I, I, ctypes.POINTER(D), I, ctypes.POINTER(Stats)],
         "ecs_set_graphs": [P, I],
         "ecs_set_tuning": [P, ctypes.POINTER(Tuning)],
         "ecs_get_tuning": [P, ctypes.POINTER(Tuning)],
@@ -129,7 +130,7 @@ EXPORTED = ["ecs_create", "ecs_set_ecs", "ecs_set_k2", "ecs_set_precond", "ecs_w
             "ecs_residual_restrict", "ecs_prolong_correct", "ecs_coarse_solve", "ecs_level_info",
             "ecs_timing_enable", "ecs_timing_read", "ecs_batch_solve", "ecs_copy_probe", "ecs_last_error",
             "ecs_destroy", "ecs_set_graphs", "ecs_set_tuning", "ecs_get_tuning", "ecs_timing_calibrate",
-            "ecs_vcycle_native"]
+            "ecs_vcycle_native", "ecs_mg_solve"]
 
 
 def _torch():
@@ -309,6 +310,25 @@ class Solver:
         out = st.as_dict()
         out["status_name"] = STATUS.get(rc, rc)
         return x, out
+
+    def mg_solve(self, b, x0=None, rtol=1e-6, maxcycles=100):
+        """Stand-alone multigrid on the preconditioner, M x = b: x <- x + MG(b - M x)
+        until ||b - M x|| <= rtol ||b|| (Sec. 5).  Returns (x, stats dict, history of
+        ||b - M x_m|| / ||b||, m = 0 .. cycles)."""
+        import numpy as np
+        torch = _torch()
+        self._ensure_workspace(self.krylov)
+        b = self._vec(b)
+        x = x0.clone() if x0 is not None else torch.empty_like(b)
+        hist = np.zeros(maxcycles + 1)
+        st = Stats()
+        rc = lib().ecs_mg_solve(self._h, _ptr(b), _ptr(x), float(rtol), int(maxcycles), 1 if x0 is not None else 0,
+                                hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist.size, ctypes.byref(st))
+        if rc < 0:
+            self._check(rc)
+        out = st.as_dict()
+        out["status_name"] = STATUS.get(rc, rc)
+        return x, out, hist[: out["iterations"] + 1]
 
     def solve_adjoint(self, g, krylov: Optional[Krylov] = None):
         """Solve A^T lam = g (no conjugation); returns (lam, stats dict)."""

@@ -164,11 +164,15 @@ def test_paper_setups_match_oracle(prob, which):
     S = gpu_for(w, "f64", prec=p, cycle=c, krylov=E.Krylov(method="bicgstab", rtol=1e-11, maxit=3000))
     f = w.rhs[0]
     ho, xo = _history(P.mg_apply, lambda x: P.apply(x, which="M"), f, 8)
-    hg, xg = _history(lambda r: to_np(S.vcycle(to_gpu(r))), lambda x: to_np(S.apply(to_gpu(x), "M")), f, 8)
+    xg, stg, hg = S.mg_solve(to_gpu(f), rtol=0.0, maxcycles=8)
+    assert stg["iterations"] == 8 and stg["status_name"] == "not_converged", stg
     print(prob, name, "oracle factors", ho[1:] / ho[:-1])
-    live = ho > 1e-11 * ho[0]          # below that the history is rounding noise
-    assert np.max(np.abs(hg - ho)[live] / ho[live]) < 1e-9
-    assert relerr(xg, xo) < 1e-10
+    # relative agreement, down to the rounding floor of a residual norm (~1e-16 ||f|| times the operator's size)
+    assert np.all(np.abs(hg * ho[0] - ho) <= 1e-9 * ho + 1e-14 * ho[0])
+    assert relerr(to_np(xg), xo) < 1e-10
+    # started from a guess (no cycle): the residual of the oracle's 8th iterate
+    xg3, _, hg3 = S.mg_solve(to_gpu(f), x0=to_gpu(xo), rtol=0.0, maxcycles=0)
+    assert abs(hg3[0] * ho[0] - ho[-1]) <= 1e-9 * ho[-1] + 1e-12 * ho[0]
     x, st = S.solve(to_gpu(f))
     assert st["status"] == 0, st
     xs, _ = P.solve(f, "fgmres", 30, 1e-13, 5000)
@@ -192,10 +196,35 @@ def test_tables_on_gpu():
         w, setups = built[row["problem"]]
         _, p, c = next(s for s in setups if s[0] == row["precond"])
         S = gpu_for(w, "f64", prec=p, cycle=c, krylov=E.Krylov(method="bicgstab", rtol=1e-6, maxit=2000))
-        f = w.rhs[0]
-        h = standalone_mg(lambda r: to_np(S.vcycle(to_gpu(r))), lambda x: to_np(S.apply(to_gpu(x), "M")), f)
-        x, st = S.solve(to_gpu(f))
-        print(row, "gpu cycles", len(h) - 1, "gpu iterations", st["iterations"], flush=True)
-        assert len(h) - 1 == row["cycles"], row
+        f = to_gpu(w.rhs[0])
+        _, stm, h = S.mg_solve(f, rtol=1e-6, maxcycles=60)
+        x, st = S.solve(f)
+        print(row, "gpu cycles", stm["iterations"], "gpu iterations", st["iterations"], flush=True)
+        assert stm["status"] == 0 and stm["iterations"] == row["cycles"] == len(h) - 1, (row, stm)
+        assert abs((h[-1] / h[0]) ** (1.0 / len(h[1:])) - row["mg_conv"]) <= 0.01, row
         assert st["status"] == 0 and abs(st["iterations"] - row["bicgstab"]) <= 0.15 * row["bicgstab"], (row, st)
         del S
+
+
+@pytest.mark.gpu
+def test_warm_start_from_preconditioner_solution():
+    """Sec. 5 (MP1) feeds the preconditioner's solution at 1e-2 to the Krylov
+    method as its initial guess: the stand-alone solve stops at the first
+    cycle below 1e-2, and Bi-CGSTAB from that guess meets the tolerance.  For
+    CSL (M close to A in scale) the guess does not cost iterations; the saving
+    of 50 iterations that Sec. 5 reports is not reproduced (counts stay within
+    a few iterations, see the bench), so only the mechanism is asserted."""
+    import paper_1012_4307_amd as E
+    w, setups = W.paper_mp1()
+    for which in (0, 2):
+        _, p, c = setups[which]
+        S = gpu_for(w, "f64", prec=p, cycle=c, krylov=E.Krylov(method="bicgstab", rtol=1e-6, maxit=2000))
+        f = to_gpu(w.rhs[0])
+        _, cold = S.solve(f)
+        x0, st0, h0 = S.mg_solve(f, rtol=1e-2, maxcycles=50)
+        assert st0["status"] == 0 and h0[-1] <= 1e-2 < h0[-2]
+        x, warm = S.solve(f, x0=x0)
+        print(p["kind"], "cold", cold["iterations"], "warm", warm["iterations"], "mg cycles", st0["iterations"])
+        assert warm["status"] == 0 and warm["rel_residual"] <= 1.05e-6
+        if p["kind"] == "csl":
+            assert warm["iterations"] <= cold["iterations"] + 3
