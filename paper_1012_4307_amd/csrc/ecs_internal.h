@@ -58,6 +58,51 @@ struct Grid {
   cplx<R> beta, c;
 };
 
+// Grid rows through buffer resources.  One wave-uniform resource covers the
+// rows [j_lo, j_hi) of an n0-wide array that a block may touch; a lane adds
+// the byte offset of its column (fixed for the kernel) to the uniform offset
+// of the row.  An offset at or beyond the resource's size reads 0 and drops a
+// store (range-checked buffer access, no fault): rows outside the window and
+// lanes outside the grid (column offset 2^31) need neither branches nor
+// per-row address arithmetic.  Windows stay below 2^31 bytes.
+constexpr uint32_t kOutside = 0x80000000u;   // column offset of a lane outside the grid
+constexpr int kRsrcWord3 = 0x00020000;       // buffer resource word 3 for gfx9-family raw access
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const T *base, int j_lo, int j_hi, int n0) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(base + (int64_t)j_lo * n0), 0,
+                                           j_hi > j_lo ? (j_hi - j_lo) * n0 * (int)sizeof(T) : 0, kRsrcWord3);
+}
+template <typename T>
+__device__ __forceinline__ uint32_t col_off(bool in, int i) {
+  return in ? (uint32_t)i * (uint32_t)sizeof(T) : kOutside;
+}
+// byte offset of row q of the window (q < 0 wraps far outside)
+template <typename T>
+__device__ __forceinline__ uint32_t row_off(int q, int n0) {
+  return (uint32_t)(q * n0 * (int)sizeof(T));
+}
+__device__ __forceinline__ cplx<float> ld_c(__amdgpu_buffer_rsrc_t r, uint32_t off, cplx<float>) {
+  return __builtin_bit_cast(cplx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ cplx<double> ld_c(__amdgpu_buffer_rsrc_t r, uint32_t off, cplx<double>) {
+  return __builtin_bit_cast(cplx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ float ld_r(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double ld_r(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void st_c(__amdgpu_buffer_rsrc_t r, uint32_t off, cplx<float> v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, off,
+                                        0, 0);
+}
+__device__ __forceinline__ void st_c(__amdgpu_buffer_rsrc_t r, uint32_t off, cplx<double> v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r, off,
+                                         0, 0);
+}
+
 // XCD-aware tile order.  Workgroups are handed to the 8 XCDs of the chip in
 // round-robin order of their linear index, and each XCD has its own L2.  A 1D
 // launch of `padded` (a multiple of 8) blocks is mapped so that XCD x owns the

@@ -352,7 +352,7 @@ __global__ __launch_bounds__(256) void k_apply2d(Grid<R> g, const cplx<RI> *__re
                                                  const cplx<R> *__restrict__ d0, cplx<double> *partials, int tiles_x,
                                                  int tiles) {
   __shared__ cplx<double> lds[4];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n0 = g.n0, n1 = g.n1;
   const int padded = gridDim.x, b = blockIdx.x;
   const int local = (b % kXcds) * (padded / kXcds) + b / kXcds;  // XCD-aware order within a pass
@@ -368,23 +368,24 @@ __global__ __launch_bounds__(256) void k_apply2d(Grid<R> g, const cplx<RI> *__re
     const bool own = xin && ((lane >= 1 && lane <= SX) || i == 0);
     const cplx<R> cxm = xint ? g.cm0[i] : mk<R>(0, 0);
     const cplx<R> cxp = xint ? g.cp0[i] : mk<R>(0, 0);
+    // the strip's rows through buffer resources (rows outside the grid and
+    // lanes beyond it read 0); the lane's column offsets are fixed
+    const int jx = max(j0 - 1, 0), je = min(j0 + SY, n1);
+    const __amdgpu_buffer_rsrc_t rx = rows_rsrc(x, jx, min(j0 + SY + 1, n1), n0);
+    const __amdgpu_buffer_rsrc_t rk = rows_rsrc(g.k2, j0, je, n0), rd = rows_rsrc(d0, j0, je, n0);
+    const __amdgpu_buffer_rsrc_t ry = rows_rsrc(y, j0, je, n0);
+    const uint32_t ox = col_off<cplx<RI>>(xin, i), ok = col_off<R>(xin, i), od = col_off<cplx<R>>(xin, i);
+    const uint32_t oy = col_off<cplx<RO>>(own, i);
     cplx<R> xv[SY + 2];
 #pragma unroll
-    for (int r = 0; r < SY + 2; r++) {
-      const int jj = j0 - 1 + r;
-      xv[r] = (xin && jj >= 0 && jj < n1) ? cvt<R>(x[(int64_t)jj * n0 + i]) : mk<R>(0, 0);
-    }
+    for (int r = 0; r < SY + 2; r++)
+      xv[r] = cvt<R>(ld_c(rx, ox + row_off<cplx<RI>>(j0 - 1 + r - jx, n0), cplx<RI>()));
     R kv[SY];
     cplx<R> dv[SY];
 #pragma unroll
     for (int r = 0; r < SY; r++) {
-      const int jj = j0 + r;
-      kv[r] = R(0);
-      dv[r] = mk<R>(0, 0);
-      if (xin && jj < n1) {
-        kv[r] = g.k2[(int64_t)jj * n0 + i];
-        if (MODE != 0) dv[r] = d0[(int64_t)jj * n0 + i];
-      }
+      kv[r] = ld_r(rk, ok + row_off<R>(r, n0), R());
+      dv[r] = MODE != 0 ? ld_c(rd, od + row_off<cplx<R>>(r, n0), cplx<R>()) : mk<R>(0, 0);
     }
 #pragma unroll
     for (int r = 0; r < SY; r++) {
@@ -394,17 +395,16 @@ __global__ __launch_bounds__(256) void k_apply2d(Grid<R> g, const cplx<RI> *__re
       xl.im = __shfl_up(xv[r + 1].im, 1, 64);
       xr.re = __shfl_down(xv[r + 1].re, 1, 64);
       xr.im = __shfl_down(xv[r + 1].im, 1, 64);
-      if (!own || jj >= n1) continue;
-      cplx<R> v = mk<R>(0, 0);
-      if (xint && jj >= 1 && jj <= n1 - 2) {
-        const cplx<R> cym = g.cm1[jj], cyp = g.cp1[jj];
-        const cplx<R> d = cxm + cxp + cym + cyp + (kv[r] * g.beta + g.c);
-        cplx<R> o = cxm * xl + cxp * xr;
-        o = o + cym * xv[r] + cyp * xv[r + 2];
-        v = d * xv[r + 1] - o;
-      }
-      y[(int64_t)jj * n0 + i] = cvt<RO>(v);
-      if (MODE != 0) {
+      if (jj >= n1) continue;
+      const bool yint = jj >= 1 && jj <= n1 - 2;
+      const int jc = yint ? jj : 1;
+      const cplx<R> cym = yint ? g.cm1[jc] : mk<R>(0, 0), cyp = yint ? g.cp1[jc] : mk<R>(0, 0);
+      const cplx<R> d = cxm + cxp + cym + cyp + (kv[r] * g.beta + g.c);
+      cplx<R> o = cxm * xl + cxp * xr;
+      o = o + cym * xv[r] + cyp * xv[r + 2];
+      const cplx<R> v = (xint && yint) ? d * xv[r + 1] - o : mk<R>(0, 0);
+      st_c(ry, oy + row_off<cplx<RO>>(r, n0), cvt<RO>(v));
+      if (MODE != 0 && own) {
         const cplx<double> vd = cvt<double>(v), dd = cvt<double>(dv[r]);
         if (MODE == kBicgAlpha) {
           a0 = a0 + conjg(dd) * vd;

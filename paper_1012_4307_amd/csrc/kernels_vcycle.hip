@@ -109,6 +109,12 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
   const int iR = ared ? ia : ib, iBk = ared ? ib : ia;
   const cplx<R> xmR = inR ? f.cm0[iR] : zero_c<R>(), xpR = inR ? f.cp0[iR] : zero_c<R>();
   const cplx<R> xmB = inBk ? f.cm0[iBk] : zero_c<R>(), xpB = inBk ? f.cp0[iBk] : zero_c<R>();
+  // interior rows of the staged window through buffer resources: halo and
+  // boundary nodes read as 0
+  const int jl = min(max(gy0, 1), n1 - 1), jh = min(max(gy0 + WY, 1), n1 - 1);
+  const __amdgpu_buffer_rsrc_t rb = rows_rsrc(b, jl, jh, n0), rk = rows_rsrc(f.k2, jl, jh, n0);
+  const uint32_t obR = col_off<cplx<R>>(inR, iR), obB = col_off<cplx<R>>(inBk, iBk);
+  const uint32_t okR = col_off<R>(inR, iR), okB = col_off<R>(inBk, iBk);
 
   cplx<R> bR[RPW], bB[RPW], dR[RPW], dB[RPW], cym[RPW], cyp[RPW];
   R kR[RPW], kB[RPW];
@@ -117,19 +123,14 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
     const int ly = wv + 4 * r;
     const int j = gy0 + ly;
     const bool yin = ly < WY && j >= 1 && j <= n1 - 2;
-    cym[r] = yin ? f.cm1[j] : zero_c<R>();
-    cyp[r] = yin ? f.cp1[j] : zero_c<R>();
-    bR[r] = bB[r] = zero_c<R>();
-    kR[r] = kB[r] = R(0);
-    const int64_t row = (int64_t)j * n0;
-    if (yin && inR) {
-      bR[r] = b[row + iR];
-      kR[r] = f.k2[row + iR];
-    }
-    if (yin && inBk) {
-      bB[r] = b[row + iBk];
-      kB[r] = f.k2[row + iBk];
-    }
+    const int jc = yin ? j : 1;
+    cym[r] = yin ? f.cm1[jc] : zero_c<R>();
+    cyp[r] = yin ? f.cp1[jc] : zero_c<R>();
+    const uint32_t qb = row_off<cplx<R>>(j - jl, n0), qk = row_off<R>(j - jl, n0);
+    bR[r] = ld_c(rb, obR + qb, cplx<R>());
+    bB[r] = ld_c(rb, obB + qb, cplx<R>());
+    kR[r] = ld_r(rk, okR + qk, R());
+    kB[r] = ld_r(rk, okB + qk, R());
   }
   // inverse diagonals; red relaxation from zero: omega b / D
 #pragma unroll
@@ -177,6 +178,12 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
   const bool qin = qs >= 0 && qs < 64;
   const int pq = qin ? qs : lane;
   const cplx<R> wRo = ared ? xpR : xmR, wRn = ared ? xmR : xpR;
+  // stores: owned rows and owned columns only
+  const int xr = iR - gx0, xb = iBk - gx0;
+  const uint32_t osR = col_off<cplx<R>>(xr >= 3 && xr < 3 + 2 * CX && iR < n0, iR);
+  const uint32_t osB = col_off<cplx<R>>(xb >= 3 && xb < 3 + 2 * CX && iBk < n0, iBk);
+  const int jo = gy0 + 3;
+  const __amdgpu_buffer_rsrc_t ru = rows_rsrc(u_out, jo, min(jo + 2 * CY, n1), n0);
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
@@ -189,12 +196,10 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
              (wRo * sB[ly][lane] + wRn * sB[ly][pq] + cym[r] * sB[ly - 1][lane] + cyp[r] * sB[ly + 1][lane]);
     rR[ly][lane] = resR;
     rB[ly][lane] = (yin && inBk) ? resB[r] : zero_c<R>();
-    if (ly >= 3 && ly < 3 + 2 * CY && j < n1) {
-      const int64_t row = (int64_t)j * n0;
-      const int xr = iR - gx0, xb = iBk - gx0;  // relative columns of the two nodes
-      if (xr >= 3 && xr < 3 + 2 * CX && iR < n0) u_out[row + iR] = sR[ly][lane];
-      if (xb >= 3 && xb < 3 + 2 * CX && iBk < n0) u_out[row + iBk] = tB[r];
-    }
+    // owned nodes to global memory (the others fall outside the window)
+    const uint32_t qo = row_off<cplx<R>>(j - jo, n0);
+    st_c(ru, osR + qo, sR[ly][lane]);
+    st_c(ru, osB + qo, tB[r]);
   }
   __syncthreads();
   // full weighting onto the owned coarse nodes: lane = coarse column.  The
@@ -251,6 +256,14 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
   const cplx<R> xmR = inR ? f.cm0[iR] : zero_c<R>(), xpR = inR ? f.cp0[iR] : zero_c<R>();
   const cplx<R> xmB = inBk ? f.cm0[iBk] : zero_c<R>(), xpB = inBk ? f.cp0[iBk] : zero_c<R>();
 
+  // interior rows of the staged window through buffer resources: halo and
+  // boundary nodes read as 0
+  const int jl = min(max(gy0, 1), n1 - 1), jh = min(max(gy0 + WY, 1), n1 - 1);
+  const __amdgpu_buffer_rsrc_t ru = rows_rsrc(u_in, jl, jh, n0), rb = rows_rsrc(b, jl, jh, n0),
+                               rk = rows_rsrc(f.k2, jl, jh, n0);
+  const uint32_t obR = col_off<cplx<R>>(inR, iR), obB = col_off<cplx<R>>(inBk, iBk);
+  const uint32_t okR = col_off<R>(inR, iR), okB = col_off<R>(inBk, iBk);
+
   cplx<R> vR[RPW], vB[RPW], bR[RPW], bB[RPW], dR[RPW], dB[RPW], cym[RPW], cyp[RPW];
   R kR[RPW], kB[RPW];
 #pragma unroll
@@ -258,21 +271,16 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
     const int ly = wv + 4 * r;
     const int j = gy0 + ly;
     const bool yin = ly < WY && j >= 1 && j <= n1 - 2;
-    cym[r] = yin ? f.cm1[j] : zero_c<R>();
-    cyp[r] = yin ? f.cp1[j] : zero_c<R>();
-    vR[r] = vB[r] = bR[r] = bB[r] = zero_c<R>();
-    kR[r] = kB[r] = R(0);
-    const int64_t row = (int64_t)j * n0;
-    if (yin && inR) {
-      vR[r] = u_in[row + iR];
-      bR[r] = b[row + iR];
-      kR[r] = f.k2[row + iR];
-    }
-    if (yin && inBk) {
-      vB[r] = u_in[row + iBk];
-      bB[r] = b[row + iBk];
-      kB[r] = f.k2[row + iBk];
-    }
+    const int jc = yin ? j : 1;
+    cym[r] = yin ? f.cm1[jc] : zero_c<R>();
+    cyp[r] = yin ? f.cp1[jc] : zero_c<R>();
+    const uint32_t qb = row_off<cplx<R>>(j - jl, n0), qk = row_off<R>(j - jl, n0);
+    vR[r] = ld_c(ru, obR + qb, cplx<R>());
+    vB[r] = ld_c(ru, obB + qb, cplx<R>());
+    bR[r] = ld_c(rb, obR + qb, cplx<R>());
+    bB[r] = ld_c(rb, obB + qb, cplx<R>());
+    kR[r] = ld_r(rk, okR + qk, R());
+    kB[r] = ld_r(rk, okB + qk, R());
   }
   for (int q = threadIdx.x; q < CWY * CWX; q += NT) {
     const int cy = q / CWX, cx = q % CWX;
@@ -337,20 +345,22 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
   const int ps = lane + side;
   const bool own_x = lane >= 1 && lane <= 62;
   const cplx<R> wBo = ared ? xmB : xpB, wBn = ared ? xpB : xmB;
+  const uint32_t osR = col_off<cplx<R>>(own_x && iR < n0, iR), osB = col_off<cplx<R>>(own_x && iBk < n0, iBk);
+  const __amdgpu_buffer_rsrc_t ro = rows_rsrc(u_out, y0, min(y0 + TY, n1), n0);
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     if (ly >= WY) break;
     const int j = gy0 + ly;
-    if (!own_x || ly < 2 || ly >= TY + 2 || j >= n1) continue;
+    if (ly < 2 || ly >= TY + 2 || j >= n1) continue;
     cplx<R> outB = vB[r];
-    if (inBk && j >= 1 && j <= n1 - 2) {
+    if (own_x && inBk && j >= 1 && j <= n1 - 2) {
       const cplx<R> o = wBo * sR[ly][lane] + wBn * sR[ly][ps] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane];
       outB = om1 * outB + omega * ((bB[r] + o) * dB[r]);
     }
-    const int64_t row = (int64_t)j * n0;
-    if (iR < n0) u_out[row + iR] = vR[r];
-    if (iBk < n0) u_out[row + iBk] = outB;
+    const uint32_t qo = row_off<cplx<R>>(j - y0, n0);
+    st_c(ro, osR + qo, vR[r]);
+    st_c(ro, osB + qo, outB);
   }
 }
 
