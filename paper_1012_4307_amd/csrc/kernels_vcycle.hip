@@ -89,8 +89,11 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
   constexpr int WX = 2 * CX + 5;          // 127 staged columns
   constexpr int WY = 2 * CY + 5;
   constexpr int RPW = (WY + 3) / 4;       // rows per wave
-  __shared__ cplx<R> sR[WY][64], sB[WY][64];  // relaxed iterate, by colour
-  __shared__ cplx<R> rR[WY][64], rB[WY][64];  // residual, by colour
+  // relaxed iterate by colour; the residual by colour, the red one in the
+  // red iterate's slots (in the residual phase a lane reads only its own red
+  // node there, before overwriting it): three arrays keep eight blocks per CU
+  __shared__ cplx<R> sR[WY][64], sB[WY][64], rB[WY][64];
+  cplx<R>(*const rR)[64] = sR;
   // the wave index is uniform: row indices and row weights live in scalars
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = xcd_tile(tiles);
@@ -194,12 +197,12 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
     if (yin && inR && qin && ly >= 1 && ly <= WY - 2)
       resR = om1 * bR[r] +
              (wRo * sB[ly][lane] + wRn * sB[ly][pq] + cym[r] * sB[ly - 1][lane] + cyp[r] * sB[ly + 1][lane]);
-    rR[ly][lane] = resR;
-    rB[ly][lane] = (yin && inBk) ? resB[r] : zero_c<R>();
     // owned nodes to global memory (the others fall outside the window)
     const uint32_t qo = row_off<cplx<R>>(j - jo, n0);
     st_c(ru, osR + qo, sR[ly][lane]);
     st_c(ru, osB + qo, tB[r]);
+    rR[ly][lane] = resR;
+    rB[ly][lane] = (yin && inBk) ? resB[r] : zero_c<R>();
   }
   __syncthreads();
   // full weighting onto the owned coarse nodes: lane = coarse column.  The
