@@ -48,7 +48,7 @@ def parse():
                                                                "FP64 Bi-CGSTAB)")
     ap.add_argument("--vcycles", type=int, default=20, help="cycles timed for the V-cycle bandwidth")
     ap.add_argument("--config", default="mixed2049",
-                    choices=["mixed2049", "batched", "adjoint", "cube", "coulomb513", "small65", "paper_mp"],
+                    choices=["mixed2049", "batched", "adjoint", "cube", "coulomb513", "small65", "paper_mp", "coupled"],
                     help="mixed2049 (default): the headline line; the others report the secondary workloads")
     ap.add_argument("--batch-count", type=int, default=96)
     return ap.parse_args()

@@ -175,6 +175,33 @@ ecs_status ecs_vcycle(ecs_ctx *ctx, const void *v_dev, void *z_dev);
  * vcycle_dtype is ECS_F32, complex128 otherwise): no conversion passes. */
 ecs_status ecs_vcycle_native(ecs_ctx *ctx, const void *v_dev, void *z_dev);
 
+/* Coupled block system (Sec. 2: the partial-wave expansion couples 2D
+ * Helmholtz problems only through potentials): sum_j A_ij x_j = b_i,
+ * i = 0 .. nb-1 (nb <= 8), with A_ii the ECS operator -Lap - k^2_ii of block i
+ * (context ctx[i]: its k^2, contour and preconditioner; every block on the same
+ * grid and device) and A_ij = -diag(k2c_ij) for i != j.  Solved by right-
+ * preconditioned FGMRES(outer->restart) over the stacked vector (FP64, true
+ * residual over interior nodes <= outer->rtol) with the block-diagonal
+ * preconditioner z_i ~ A_ii^{-1} r_i of Sec. 2, each block solved by its own
+ * context: all blocks together by the batched Bi-CGSTAB driver to
+ * inner->rtol (inner->maxit iterations at most), or, with inner = NULL, one
+ * multigrid cycle of each block's preconditioner.
+ *   k2c: device array of nb * nb * nodes doubles, the potential k2c_ij of the
+ *        pair (i, j) at offset (i nb + j) * nodes (entries i == j are not
+ *        read); NULL for uncoupled blocks.  Borrowed for the call.
+ *   b, x: stacked complex128 device arrays of nb * nodes entries, block i at
+ *        offset i * nodes; x is a guess when outer->x_is_guess.
+ *   workspace: device memory of ecs_coupled_workspace_size bytes, 256-byte
+ *        aligned, caller-owned; the contexts' own workspaces must be sized for
+ *        `inner` (ecs_workspace_size with inner).
+ *   stats: iterations = outer iterations, inner_iterations and vcycles summed
+ *        over all block solves.  Outer work runs on ctx[0]'s stream; the call
+ *        returns after every stream involved has finished. */
+ecs_status ecs_coupled_workspace_size(int nb, ecs_ctx *const *ctx, const ecs_solve_desc *outer, size_t *bytes);
+ecs_status ecs_coupled_solve(int nb, ecs_ctx *const *ctx, const double *k2c, const ecs_solve_desc *outer,
+                             const ecs_solve_desc *inner, void *workspace, size_t ws_bytes, const void *b_dev,
+                             void *x_dev, ecs_stats *stats);
+
 /* Stand-alone multigrid on the preconditioner, M x = b (Sec. 5: the
  * preconditioner solved on its own, the "mg-conv" and "# cycles" columns of
  * Tables 1-4): x <- x + MG(b - M x), which is Algorithm 1 started from the

@@ -5,7 +5,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 it shares no code with the GPU path: the C source ``ecs_oracle.c`` restates
 the method of bin Zubair, Reps and Vanroose (Sec. 3.1-3.2 discretisation,
 Sec. 4 preconditioners and Algorithm 1, Sec. 5 Krylov outer solvers) as plain
-loops.  This module only marshals numpy arrays through ctypes.
+loops.  This module marshals numpy arrays through ctypes, and assembles the
+coupled block system of Sec. 2 densely from the per-block operators for small
+grids (``coupled_dense``).
 
 Arrays are numpy ``complex128`` (vectors) or ``float64`` (k^2), C-contiguous,
 shaped ``(n1, n0)`` in 2D and ``(n2, n1, n0)`` in 3D (x fastest).
@@ -258,3 +260,35 @@ class Problem:
             y = self.apply(e.reshape(shape), level, which).ravel()
             A[:, c] = y[idx]
         return A, mask
+
+
+def coupled_dense(problems, k2c):
+    """Dense matrix of the coupled block system of Sec. 2 (the blocked
+    Helmholtz operator): diagonal blocks A_ii from each problem's operator on
+    the interior unknowns, off-diagonal blocks -diag(k2c[i, j]) at the same
+    unknowns.  Small grids only.  Returns (matrix, interior mask)."""
+    nb = len(problems)
+    blocks = [P.dense("A") for P in problems]
+    mask = blocks[0][1]
+    nu = blocks[0][0].shape[0]
+    A = np.zeros((nb * nu, nb * nu), dtype=np.complex128)
+    for i in range(nb):
+        A[i * nu:(i + 1) * nu, i * nu:(i + 1) * nu] = blocks[i][0]
+        for j in range(nb):
+            if j != i and k2c is not None:
+                A[i * nu:(i + 1) * nu, j * nu:(j + 1) * nu] = -np.diag(np.asarray(k2c[i, j])[mask])
+    return A, mask
+
+
+def coupled_solve_dense(problems, k2c, b):
+    """Solution of the coupled system by a dense direct solve (stacked
+    (nb, *shape) arrays, zero on the boundary)."""
+    A, mask = coupled_dense(problems, k2c)
+    nb = len(problems)
+    rhs = np.concatenate([np.asarray(b[i])[mask] for i in range(nb)])
+    sol = np.linalg.solve(A, rhs)
+    x = np.zeros((nb,) + mask.shape, dtype=np.complex128)
+    nu = int(mask.sum())
+    for i in range(nb):
+        x[i][mask] = sol[i * nu:(i + 1) * nu]
+    return x

@@ -109,6 +109,9 @@ def lib():
         "ecs_timing_calibrate": [P, I],
         "ecs_vcycle_native": [P, P, P],
         "ecs_mg_solve": [P, P, P, D, I, I, ctypes.POINTER(D), I, ctypes.POINTER(Stats)],
+        "ecs_coupled_workspace_size": [I, pP, ctypes.POINTER(SolveDesc), ctypes.POINTER(Z)],
+        "ecs_coupled_solve": [I, pP, P, ctypes.POINTER(SolveDesc), ctypes.POINTER(SolveDesc), P, Z, P, P,
+                              ctypes.POINTER(Stats)],
         "ecs_set_graphs": [P, I],
         "ecs_set_tuning": [P, ctypes.POINTER(Tuning)],
         "ecs_get_tuning": [P, ctypes.POINTER(Tuning)],
@@ -130,7 +133,7 @@ EXPORTED = ["ecs_create", "ecs_set_ecs", "ecs_set_k2", "ecs_set_precond", "ecs_w
             "ecs_residual_restrict", "ecs_prolong_correct", "ecs_coarse_solve", "ecs_level_info",
             "ecs_timing_enable", "ecs_timing_read", "ecs_batch_solve", "ecs_copy_probe", "ecs_last_error",
             "ecs_destroy", "ecs_set_graphs", "ecs_set_tuning", "ecs_get_tuning", "ecs_timing_calibrate",
-            "ecs_vcycle_native", "ecs_mg_solve"]
+            "ecs_vcycle_native", "ecs_mg_solve", "ecs_coupled_workspace_size", "ecs_coupled_solve"]
 
 
 def _torch():
@@ -462,6 +465,48 @@ def batch_solve(solvers, rhs, krylov: Krylov):
     if rc < 0:
         raise EcsError(rc, "batched solve failed")
     return xs, [s.as_dict() for s in st]
+
+
+def coupled_solve(solvers, k2c, b, x0=None, outer: Optional[Krylov] = None, inner: Optional[Krylov] = None,
+                  cycles_only: bool = False):
+    """Solve the coupled block system sum_j A_ij x_j = b_i (A_ii: solver i's
+    operator, A_ij = -k2c[i, j]) by FGMRES with the block-diagonal preconditioner
+    (Sec. 2): every block solved by its solver through the batched Bi-CGSTAB
+    driver to ``inner.rtol`` (or one multigrid cycle each with ``cycles_only``).
+    k2c: float64 CUDA tensor (nb, nb, *shape) or None; b: complex128 CUDA tensor
+    (nb, *shape).  Returns (x, stats dict)."""
+    torch = _torch()
+    nb = len(solvers)
+    outer = outer or Krylov(method="fgmres", restart=30, rtol=1e-8, maxit=500)
+    inner = inner or Krylov(method="bicgstab", rtol=1e-3, maxit=200)
+    shape = tuple(solvers[0].shape)
+    if not (b.is_cuda and b.dtype == torch.complex128 and b.is_contiguous() and tuple(b.shape) == (nb,) + shape):
+        raise ValueError(f"b must be a contiguous complex128 CUDA tensor of shape {(nb,) + shape}")
+    if k2c is not None and not (k2c.is_cuda and k2c.dtype == torch.float64 and k2c.is_contiguous()
+                                and tuple(k2c.shape) == (nb, nb) + shape):
+        raise ValueError(f"k2c must be a contiguous float64 CUDA tensor of shape {(nb, nb) + shape}")
+    for S in solvers:
+        S._ensure_workspace(inner)
+    hs = (ctypes.c_void_p * nb)(*[S._h.value for S in solvers])
+    do = outer.to_c(x0 is not None)
+    di = inner.to_c()
+    need = ctypes.c_size_t()
+    L = lib()
+    rc = L.ecs_coupled_workspace_size(nb, hs, ctypes.byref(do), ctypes.byref(need))
+    if rc != 0:
+        raise EcsError(rc, L.ecs_last_error(solvers[0]._h).decode())
+    ws = torch.empty(need.value + 256, dtype=torch.uint8, device=b.device)
+    off = (-ws.data_ptr()) % 256
+    x = x0.clone() if x0 is not None else torch.empty_like(b)
+    st = Stats()
+    rc = L.ecs_coupled_solve(nb, hs, _ptr(k2c) if k2c is not None else None, ctypes.byref(do),
+                             None if cycles_only else ctypes.byref(di), ctypes.c_void_p(ws.data_ptr() + off),
+                             need.value + 256 - off, _ptr(b), _ptr(x), ctypes.byref(st))
+    if rc < 0:
+        raise EcsError(rc, L.ecs_last_error(solvers[0]._h).decode())
+    out = st.as_dict()
+    out["status_name"] = STATUS.get(rc, rc)
+    return x, out
 
 
 def copy_probe(src, dst):

@@ -87,6 +87,11 @@ void launch_scale_w(int n0, int n1, int n2, const cplx<double> *w0, const cplx<d
                     const cplx<double> *x, cplx<double> *y, bool inverse, hipStream_t s);
 void launch_mask_boundary(int n0, int n1, int n2, const cplx<double> *x, cplx<double> *y, hipStream_t s);
 void launch_grad_k2(const cplx<double> *lam, const cplx<double> *u, double *g, int64_t n, hipStream_t s);
+// coupled block system (nb <= kMaxBlocks): y_i -= sum_{j != i} k2c[i nb + j] x_j,
+// then y_i = b_i - y_i when b is given
+constexpr int kMaxBlocks = 8;
+void launch_couple(int nb, int64_t nn, const double *k2c, const cplx<double> *x, cplx<double> *y,
+                   const cplx<double> *b, hipStream_t s);
 void launch_max_real(const double *x, int64_t n, double *partials, double *out, hipStream_t s);
 void launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t s);
 // a kernel that does nothing (timing calibration)

@@ -1475,6 +1475,165 @@ ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *d
 }
 
 
+// ------------------------------------------------------- coupled blocks
+// Storage of the outer FGMRES of a coupled block system (caller's workspace):
+// the stacked right-hand side with boundary entries zeroed, the Arnoldi basis,
+// the preconditioned directions, the outer scalars and reduction partials.
+struct CoupledBufs {
+  cplx<double> *bz = nullptr, *V = nullptr, *Z = nullptr, *partials = nullptr;
+  GmresScalars *S = nullptr;
+  int64_t ld = 0;
+};
+
+size_t plan_coupled(int nb, int64_t nn, int m, char *base, CoupledBufs *B) {
+  Carver cv(base);
+  const int64_t N = nb * nn;
+  B->ld = (N + 31) & ~int64_t(31);
+  B->bz = cv.take<cplx<double>>(N);
+  B->V = cv.take<cplx<double>>((size_t)(m + 1) * B->ld);
+  B->Z = cv.take<cplx<double>>((size_t)m * B->ld);
+  B->S = cv.take<GmresScalars>(1);
+  B->partials = cv.take<cplx<double>>((size_t)kRedBlocks * (kMaxRestart + 2));
+  return cv.off;
+}
+
+// y = A x for the stacked vector: A_ii x_i per block, then the coupling
+// -k2c_ij x_j; with b, y = b - A x
+void coupled_apply(int nb, ecs_ctx *const *ctx, const double *k2c, const cplx<double> *x, cplx<double> *y,
+                   const cplx<double> *b, hipStream_t s) {
+  const int64_t nn = nn_of(ctx[0]);
+  for (int i = 0; i < nb; i++) launch_apply<double, double, double>(grid_A(ctx[i]), x + i * nn, y + i * nn, s);
+  if (k2c || b) launch_couple(k2c ? nb : 1, k2c ? nn : nb * nn, k2c, x, y, b, s);
+}
+
+ecs_status coupled_check(int nb, ecs_ctx *const *ctx, const ecs_solve_desc *outer, const ecs_solve_desc *inner) {
+  if (nb < 1 || nb > kMaxBlocks || !ctx || !outer) return ECS_EINVAL;
+  for (int i = 0; i < nb; i++) {
+    if (!ctx[i]) return ECS_EINVAL;
+    ecs_status st = check_ready(ctx[i]);
+    if (st != ECS_OK) return st;
+    if (ctx[i]->dim != ctx[0]->dim || ctx[i]->device != ctx[0]->device)
+      return fail(ctx[0], ECS_EINVAL, "coupled blocks must share the dimension and the device");
+    for (int a = 0; a < 3; a++)
+      if (ctx[i]->n[a] != ctx[0]->n[a]) return fail(ctx[0], ECS_EINVAL, "coupled blocks must share the grid");
+  }
+  if (outer->krylov != ECS_KRYLOV_FGMRES) return fail(ctx[0], ECS_EINVAL, "the outer method is FGMRES");
+  if (outer->restart < 1 || outer->restart > kMaxRestart) return fail(ctx[0], ECS_EINVAL, "restart must be in [1, 64]");
+  if (!(outer->rtol > 0) || outer->maxit < 0) return fail(ctx[0], ECS_EINVAL, "rtol must be > 0 and maxit >= 0");
+  if (inner && (inner->krylov != ECS_KRYLOV_BICGSTAB || !(inner->rtol > 0) || inner->maxit < 1))
+    return fail(ctx[0], ECS_EINVAL, "the block solves use Bi-CGSTAB with rtol > 0, maxit >= 1");
+  return ECS_OK;
+}
+
+// Right-preconditioned FGMRES(m) over the stacked vector; the preconditioner
+// solves every diagonal block with its own context, all blocks at once through
+// the batched Bi-CGSTAB driver (inner == NULL: one multigrid cycle per block).
+ecs_status coupled_fgmres(int nb, ecs_ctx *const *ctx, const double *k2c, const ecs_solve_desc *d,
+                          const ecs_solve_desc *inner, const CoupledBufs &B, const cplx<double> *b, cplx<double> *x,
+                          ecs_stats *st) {
+  ecs_ctx *C = ctx[0];
+  const int64_t nn = nn_of(C), N = nb * nn;
+  const int m = d->restart;
+  hipStream_t s = C->stream;
+  GmresScalars *S = B.S;
+  const int64_t ld = B.ld;
+  const HostLevel &F = C->hl[0];
+  for (int i = 0; i < nb; i++) launch_mask_boundary(F.n[0], F.n[1], F.n[2], b + i * nn, B.bz + i * nn, s);
+  launch_nrm2sq<double>(B.bz, N, B.partials, &S->nrm2, s);
+  const double bnorm = std::sqrt(read_scalar(C, &S->nrm2.re));
+  if (!(bnorm == bnorm) || std::isinf(bnorm)) return fail(C, ECS_EBREAKDOWN, "right-hand side contains NaN/Inf");
+  if (!d->x_is_guess) launch_zero<double>(x, N, s);
+  if (bnorm == 0) {
+    launch_zero<double>(x, N, s);
+    st->rel_residual = 0;
+    HIP_OK(hipStreamSynchronize(s));
+    return ECS_OK;
+  }
+  HIP_OK(hipMemcpyAsync(&S->bnorm, &bnorm, sizeof(double), hipMemcpyHostToDevice, s));
+  std::vector<ecs_stats> bst(nb);
+  std::vector<const void *> bp(nb);
+  std::vector<void *> xp(nb);
+  std::vector<int> ones(nb, 1);
+  int it = 0;
+  ecs_status status = ECS_NOT_CONVERGED;
+  for (;;) {
+    coupled_apply(nb, ctx, k2c, x, B.V, B.bz, s);  // r = b - A x
+    launch_nrm2sq<double>(B.V, N, B.partials, &S->nrm2, s);
+    launch_gmres_start(S, m, s);
+    launch_scale_dev(B.V, N, &S->inv, s);
+    const double rt = read_scalar(C, &S->resid_true);
+    st->rel_residual = rt;
+    if (!(rt == rt) || std::isinf(rt)) { status = fail(C, ECS_EBREAKDOWN, "coupled FGMRES: residual is NaN/Inf"); break; }
+    if (rt <= d->rtol) { status = ECS_OK; break; }
+    if (it >= d->maxit) { status = ECS_NOT_CONVERGED; break; }
+    int k = 0;
+    bool bad = false;
+    for (int j = 0; j < m && it < d->maxit; j++) {
+      cplx<double> *vj = B.V + (int64_t)j * ld, *w = B.V + (int64_t)(j + 1) * ld, *zj = B.Z + (int64_t)j * ld;
+      // z_j = blockdiag(A_ii)^{-1} v_j, approximately
+      if (inner) {
+        for (int i = 0; i < nb; i++) {
+          bp[i] = vj + i * nn;
+          xp[i] = zj + i * nn;
+        }
+        HIP_OK(hipStreamSynchronize(s));
+        const ecs_status ist = batch_solve_impl(nb, ctx, inner, bp.data(), xp.data(), ones.data(), bst.data());
+        if (ist < 0) { status = ist; bad = true; break; }
+        for (int i = 0; i < nb; i++) {
+          st->vcycles += bst[i].vcycles;
+          st->inner_iterations += bst[i].iterations;
+          if (ctx[i]->stream != s) HIP_OK(hipStreamSynchronize(ctx[i]->stream));
+        }
+      } else {
+        HIP_OK(hipStreamSynchronize(s));
+        for (int i = 0; i < nb; i++) {
+          ecs_ctx *Ci = ctx[i];
+          if (Ci->prec.vcycle_dtype == ECS_F64) {
+            vcycle<double>(Ci, vj + i * nn, zj + i * nn);
+          } else {
+            KrylovBufs K;  // the block's own cycle-dtype scratch
+            plan_krylov(Ci, nullptr, Ci->ws + Ci->hier_bytes, &K);
+            cplx<float> *tz = reinterpret_cast<cplx<float> *>(K.tz);
+            precond<float>(Ci, vj + i * nn, tz);
+            launch_cast<float, double>(tz, zj + i * nn, nn, Ci->stream);
+          }
+        }
+        for (int i = 0; i < nb; i++)
+          if (ctx[i]->stream != s) HIP_OK(hipStreamSynchronize(ctx[i]->stream));
+        st->vcycles += nb;
+      }
+      coupled_apply(nb, ctx, k2c, zj, w, nullptr, s);
+      launch_mdot_partial<double, double>(B.V, ld, j + 1, w, N, B.partials, s);
+      launch_reduce_cols(B.partials, N, j + 1, S->H + (int64_t)j * (m + 1), s);
+      launch_mupdate_partial(B.V, ld, j + 1, S->H + (int64_t)j * (m + 1), w, N, B.partials, s);
+      launch_reduce_cols(B.partials, N, 1, &S->nrm2, s);
+      launch_gmres_givens(S, j, m, s);
+      launch_scale_dev(w, N, &S->inv, s);
+      it++;
+      k = j + 1;
+      if (!read_bytes(C, &S->est, 2 * sizeof(double) + 2 * sizeof(int))) { bad = true; break; }
+      double est;
+      int happy;
+      std::memcpy(&est, C->pinned, sizeof(double));
+      std::memcpy(&happy, reinterpret_cast<char *>(C->pinned) + 2 * sizeof(double) + sizeof(int), sizeof(int));
+      if (d->history && it - 1 < d->history_len) d->history[it - 1] = est;
+      if (!(est == est) || std::isinf(est)) { bad = true; break; }
+      if (est <= d->rtol || happy) break;
+    }
+    if (bad) {
+      if (status >= 0) status = fail(C, ECS_EBREAKDOWN, "coupled FGMRES: breakdown");
+      break;
+    }
+    launch_gmres_backsolve(S, k, m, s);
+    launch_lincomb<double>(B.Z, ld, k, S->y, x, N, s);
+    st->restarts++;
+  }
+  st->iterations = it;
+  HIP_OK(hipStreamSynchronize(s));
+  HIP_OK(hipGetLastError());
+  return status;
+}
+
 ecs_status solve_impl(ecs_ctx *C, const ecs_solve_desc *d, const cplx<double> *b, cplx<double> *x, ecs_stats *st) {
   if (d->restart < 1 || d->restart > kMaxRestart) return fail(C, ECS_EINVAL, "restart must be in [1, 64]");
   if (!(d->rtol > 0) || d->maxit < 0) return fail(C, ECS_EINVAL, "rtol must be > 0 and maxit >= 0");
@@ -1924,6 +2083,46 @@ ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *de
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats)
     for (int q = 0; q < n; q++) stats[q].seconds = secs;
+  return st;
+}
+
+ecs_status ecs_coupled_workspace_size(int nb, ecs_ctx *const *ctx, const ecs_solve_desc *outer, size_t *bytes) {
+  if (!bytes) return ECS_EINVAL;
+  ecs_status st = coupled_check(nb, ctx, outer, nullptr);
+  if (st != ECS_OK) return st;
+  CoupledBufs B;
+  *bytes = plan_coupled(nb, nn_of(ctx[0]), outer->restart, nullptr, &B) + 256;
+  return ECS_OK;
+}
+
+ecs_status ecs_coupled_solve(int nb, ecs_ctx *const *ctx, const double *k2c, const ecs_solve_desc *outer,
+                             const ecs_solve_desc *inner, void *workspace, size_t ws_bytes, const void *b, void *x,
+                             ecs_stats *stats) {
+  ecs_status st = coupled_check(nb, ctx, outer, inner);
+  if (st != ECS_OK) return st;
+  if (!b || !x || !workspace) return fail(ctx[0], ECS_EINVAL, "null argument");
+  if (((uintptr_t)workspace % 256) != 0) return fail(ctx[0], ECS_EINVAL, "workspace must be 256-byte aligned");
+  CoupledBufs B;
+  if (plan_coupled(nb, nn_of(ctx[0]), outer->restart, nullptr, &B) > ws_bytes)
+    return fail(ctx[0], ECS_ENOMEM, "workspace too small for the coupled solve");
+  plan_coupled(nb, nn_of(ctx[0]), outer->restart, reinterpret_cast<char *>(workspace), &B);
+  if (!inner)
+    for (int i = 0; i < nb; i++)
+      if (ctx[i]->prec.kind == ECS_PREC_NONE) return fail(ctx[0], ECS_EINVAL, "block without a preconditioner");
+  ecs_solve_desc in{};
+  if (inner) {  // block solves start from zero and keep no history
+    in = *inner;
+    in.x_is_guess = 0;
+    in.history = nullptr;
+    in.history_len = 0;
+  }
+  ecs_stats local{};
+  auto t0 = std::chrono::steady_clock::now();
+  st = coupled_fgmres(nb, ctx, k2c, outer, inner ? &in : nullptr, B, reinterpret_cast<const cplx<double> *>(b),
+                      reinterpret_cast<cplx<double> *>(x), &local);
+  local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  local.status = st;
+  if (stats) *stats = local;
   return st;
 }
 

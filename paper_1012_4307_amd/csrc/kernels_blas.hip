@@ -368,6 +368,28 @@ __global__ __launch_bounds__(BS) void k_mask_boundary(int n0, int n1, int n2, co
     y[p] = in ? x[p] : mk<double>(0, 0);
   }
 }
+// Coupling of the block system: y_i <- y_i - sum_{j != i} k2c[i nb + j] x_j at
+// every node (blocks of nn nodes stacked); with b: y_i <- b_i - (that), the
+// residual of the coupled system.  The nb values of x at a node stay in
+// registers across the i loop.
+template <int NB>
+__global__ __launch_bounds__(BS) void k_couple(int64_t nn, const double *__restrict__ k2c,
+                                               const cplx<double> *__restrict__ x, cplx<double> *y,
+                                               const cplx<double> *__restrict__ b) {
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < nn; p += (int64_t)gridDim.x * BS) {
+    cplx<double> xv[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) xv[j] = x[j * nn + p];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+      cplx<double> acc = y[i * nn + p];
+#pragma unroll
+      for (int j = 0; j < NB; j++)
+        if (j != i) acc = acc - k2c[(int64_t)(i * NB + j) * nn + p] * xv[j];
+      y[i * nn + p] = b ? b[i * nn + p] - acc : acc;
+    }
+  }
+}
 __global__ __launch_bounds__(BS) void k_grad_k2(const cplx<double> *__restrict__ lam,
                                                 const cplx<double> *__restrict__ u, double *__restrict__ g,
                                                 int64_t n) {
@@ -508,6 +530,24 @@ void launch_scale_w(int n0, int n1, int n2, const cplx<double> *w0, const cplx<d
 void launch_mask_boundary(int n0, int n1, int n2, const cplx<double> *x, cplx<double> *y, hipStream_t s) {
   int64_t n = (int64_t)n0 * n1 * n2;
   launch_k(k_mask_boundary, dim3(grid_for(n)), dim3(BS), 0, s, n0, n1, n2, x, y);
+}
+template <int NB>
+void launch_couple_nb(int64_t nn, const double *k2c, const cplx<double> *x, cplx<double> *y, const cplx<double> *b,
+                      hipStream_t s) {
+  launch_k((k_couple<NB>), dim3(grid_for(nn)), dim3(BS), 0, s, nn, k2c, x, y, b);
+}
+void launch_couple(int nb, int64_t nn, const double *k2c, const cplx<double> *x, cplx<double> *y,
+                   const cplx<double> *b, hipStream_t s) {
+  switch (nb) {
+    case 1: launch_couple_nb<1>(nn, k2c, x, y, b, s); break;
+    case 2: launch_couple_nb<2>(nn, k2c, x, y, b, s); break;
+    case 3: launch_couple_nb<3>(nn, k2c, x, y, b, s); break;
+    case 4: launch_couple_nb<4>(nn, k2c, x, y, b, s); break;
+    case 5: launch_couple_nb<5>(nn, k2c, x, y, b, s); break;
+    case 6: launch_couple_nb<6>(nn, k2c, x, y, b, s); break;
+    case 7: launch_couple_nb<7>(nn, k2c, x, y, b, s); break;
+    default: launch_couple_nb<8>(nn, k2c, x, y, b, s); break;
+  }
 }
 void launch_grad_k2(const cplx<double> *lam, const cplx<double> *u, double *g, int64_t n, hipStream_t s) {
   launch_k(k_grad_k2, dim3(grid_for(n)), dim3(BS), 0, s, lam, u, g, n);

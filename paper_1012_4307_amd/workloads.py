@@ -27,6 +27,12 @@ Workloads (sizes are nodes per axis including both Dirichlet end nodes):
   sampling sub-grid and data from a +5% Gaussian bump of k^2.
 * ``cube_constant_k(n)`` -- 3D [-1,1]^3, ECS from 0.75 at pi/6, k = 12,
   Gaussian source.
+* ``coupled_blocks(nb, n)`` -- a coupled block system of the kind Sec. 2
+  derives from the partial-wave expansion: nb soft-Coulomb channels on
+  [-10,10]^2 (ECS from 8 at pi/6) with thresholds, k^2_ii = 2(E - eps_i +
+  1/sqrt(r^2+1)), eps_i = 0.5 i, coupled by short-range symmetric potentials
+  k^2_ij = 2 c_ij exp(-r^2/2), c_ij ~ U[0.1, 0.3] (seeded); the entrance
+  channel 0 is driven by phi0 V, the others start empty.
 * ``paper_mp1`` / ``paper_mp2`` / ``paper_mp3`` -- the model problems of
   Sec. 5 with the grids of Tables 1-4: MP1 (-Lap - k^2, k = 160, unit
   source at the centre node, interior [0,1]^2 with 64-cell layers on all
@@ -47,6 +53,7 @@ import numpy as np
 SEED_RANDOM_RHS = 1012
 SEED_BATCH = 20101012
 SEED_ADJOINT = 4307
+SEED_COUPLED = 1012430
 
 
 @dataclasses.dataclass
@@ -308,3 +315,31 @@ def paper_mp3(k: float = 2.0, L: float = 50.0, n_int: int = 512, n_layer: int = 
     if k == 2.0:
         return w, _paper_setups((-1.0, -0.6), math.pi / 13, -4.19, 2, 2, 0.8, 1.05, c)
     return w, _paper_setups((-1.0, -0.6), math.pi / 13, -16.18, 4, 3, 0.8, 1.05, c)
+
+
+# ------------------------------------------------------------ coupled blocks
+def coupled_blocks(nb: int = 4, n: int = 257, E: float = 2.0, L: float = 10.0, coarsest: int = 5,
+                   seed: int = SEED_COUPLED):
+    """(blocks, k2c, rhs): nb channel workloads (QD, V(1,1) red-black), the
+    coupling potentials k2c[i, j] (nb x nb x shape, symmetric, zero diagonal)
+    and the stacked right-hand side (nb x shape)."""
+    rng = np.random.default_rng(seed)
+    X, Y = _grid2(n, -L, L)
+    r2 = X * X + Y * Y
+    blocks = []
+    for i in range(nb):
+        w = coulomb(E=E - 0.5 * i, n=n, L=L, coarsest=coarsest)
+        w.name = f"channel{i}"
+        blocks.append(w)
+    c = rng.uniform(0.1, 0.3, size=(nb, nb))
+    c = np.triu(c, 1)
+    c = c + c.T
+    g = np.exp(-r2 / 2.0)
+    k2c = np.zeros((nb, nb) + X.shape)
+    for i in range(nb):
+        for j in range(nb):
+            if i != j:
+                k2c[i, j] = 2.0 * c[i, j] * g
+    rhs = np.zeros((nb,) + X.shape, np.complex128)
+    rhs[0] = blocks[0].rhs[0]
+    return blocks, k2c, rhs
