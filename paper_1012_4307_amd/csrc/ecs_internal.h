@@ -82,6 +82,9 @@ template <typename T>
 __device__ __forceinline__ uint32_t row_off(int q, int n0) {
   return (uint32_t)(q * n0 * (int)sizeof(T));
 }
+// Loaded values are bit-cast as a whole: with this compiler, indexing the
+// elements of the vector the load builtins return narrows the access to its
+// first dword.
 __device__ __forceinline__ cplx<float> ld_c(__amdgpu_buffer_rsrc_t r, uint32_t off, cplx<float>) {
   return __builtin_bit_cast(cplx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
