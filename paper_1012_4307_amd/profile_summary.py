@@ -10,15 +10,14 @@ run once per level, so the grid size names the level).  ``traffic`` reads
 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the finest-level fused down and
 up kernels and of the copy probe, scales each counter by what it reads for the
 copy probe of known size (bytes moved / counter bytes), and records the
-scaled bytes per launch together with a digest of the kernel sources, so a
-reader can tell when the figures no longer describe the code.
+scaled bytes per launch together with a digest of those kernels' sources, so
+a reader can tell when the figures no longer describe the code.
 """
 from __future__ import annotations
 
 import argparse
 import collections
 import csv
-import glob
 import hashlib
 import json
 import os
@@ -26,7 +25,9 @@ import re
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = sorted(glob.glob(os.path.join(ROOT, "paper_1012_4307_amd", "csrc", "kernels_*.hip")))
+# the sources of the kernels whose counters are recorded (the fused cycle
+# kernels and the device helpers they use)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1012_4307_amd", "csrc", f) for f in ("kernels_vcycle.hip", "ecs_internal.h")]
 COPY_BYTES = 512 << 20   # the copy probe moves 512 MiB each way
 
 
