@@ -108,6 +108,7 @@ struct ecs_ctx {
   GmresScalars *gs = nullptr;
   BicgScalars *bs = nullptr, *bs_in = nullptr;
   double *pinned = nullptr;  // host-pinned scalars for readback
+  hipEvent_t step_ev = nullptr;  // completion of the batched driver's last step on this context
 
   Timer timers[kTClasses];
   std::string err;
@@ -1374,97 +1375,127 @@ void batch_finish_rhs(BatchItem &I, ecs_status st, const ecs_solve_desc *d) {
   I.phase = I.r < I.nrhs ? 0 : 3;
 }
 
+// Enqueues the next step of one system (phase 0: right-hand side norm;
+// 1: restart and true residual; 2: one Bi-CGSTAB iteration), each ending in a
+// readback into the context's pinned buffer.
+void batch_enqueue(BatchItem &I, const ecs_solve_desc *d) {
+  ecs_ctx *C = I.C;
+  const int64_t nn = nn_of(C);
+  const HostLevel &F = C->hl[0];
+  cplx<double> *xr = I.x0 + (int64_t)I.r * nn;
+  if (I.phase == 0) {
+    launch_mask_boundary(F.n[0], F.n[1], F.n[2], I.b0 + (int64_t)I.r * nn, I.K.bz, C->stream);
+    if (d->x_is_guess) launch_mask_boundary(F.n[0], F.n[1], F.n[2], xr, xr, C->stream);
+    else launch_zero<double>(xr, nn, C->stream);
+    launch_nrm2sq<double>(I.K.bz, nn, C->partials, &C->gs->nrm2, C->stream);
+    (void)hipMemcpyAsync(C->pinned, &C->gs->nrm2.re, sizeof(double), hipMemcpyDeviceToHost, C->stream);
+  } else if (I.phase == 1) {
+    bicg_enqueue_restart(C, I.K, I.K.bz, xr);
+    bicg_enqueue_readback(C);
+  } else {
+    if (C->prec.vcycle_dtype == ECS_F32) bicg_enqueue_step<float>(C, I.K, xr);
+    else bicg_enqueue_step<double>(C, I.K, xr);
+    bicg_enqueue_readback(C);
+  }
+}
+
+// Consumes the readback of the finished step and moves the system on.
+void batch_process(BatchItem &I, const ecs_solve_desc *d) {
+  ecs_ctx *C = I.C;
+  if (I.phase == 0) {
+    double bn2;
+    std::memcpy(&bn2, C->pinned, sizeof(double));
+    const double bn = std::sqrt(bn2);
+    if (!(bn == bn) || std::isinf(bn)) {
+      batch_finish_rhs(I, ECS_EBREAKDOWN, d);
+    } else if (bn == 0) {
+      I.rt = 0;
+      launch_zero<double>(I.x0 + (int64_t)I.r * nn_of(C), nn_of(C), C->stream);  // A x = 0 -> x = 0
+      batch_finish_rhs(I, ECS_OK, d);
+    } else {
+      C->pinned[2] = bn;  // H2D source stays untouched by the {est, bad} readbacks
+      (void)hipMemcpyAsync(&C->bs->bnorm, &C->pinned[2], sizeof(double), hipMemcpyHostToDevice, C->stream);
+      I.phase = 1;
+    }
+    return;
+  }
+  double est;
+  int bad;
+  bicg_take_readback(C, &est, &bad);
+  if (I.phase == 1) {
+    I.rt = est;
+    if (!(est == est) || std::isinf(est)) {
+      batch_finish_rhs(I, ECS_EBREAKDOWN, d);
+    } else if (est <= d->rtol) {
+      batch_finish_rhs(I, ECS_OK, d);
+    } else if (I.it >= d->maxit) {
+      batch_finish_rhs(I, ECS_NOT_CONVERGED, d);
+    } else if (est >= I.last_restart && ++I.stalls >= 3) {
+      batch_finish_rhs(I, ECS_NOT_CONVERGED, d);
+    } else {
+      if (I.last_restart < INFINITY) I.restarts++;
+      I.last_restart = est;
+      I.phase = 2;
+    }
+  } else {
+    I.it++;
+    I.agg.vcycles += 2;
+    if (bad || est <= d->rtol || I.it >= d->maxit) I.phase = 1;
+  }
+}
+
+// Many independent Bi-CGSTAB solves, each system on its context's stream.  A
+// system's next step is enqueued as soon as its previous one has completed
+// (an event per context, polled by the host), so systems of different sizes
+// progress independently and the device holds work from every stream.  Each
+// system runs exactly the kernel sequence of its single solve.
 ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *d, const void *const *b,
                             void *const *x, const int *nrhs, ecs_stats *stats) {
   std::vector<BatchItem> items(n);
-  std::vector<hipStream_t> streams;
   for (int q = 0; q < n; q++) {
     ecs_ctx *C = ctxs[q];
     ecs_status st = check_ready(C);
     if (st != ECS_OK) return st;
+    for (int p = 0; p < q; p++)
+      if (ctxs[p] == C) return fail(C, ECS_EINVAL, "a context appears twice in the batch");
     if (nrhs[q] < 0) return fail(C, ECS_EINVAL, "negative right-hand side count");
     const size_t need = C->hier_bytes + plan_krylov(C, d, nullptr, &items[q].K);
     if (need > C->ws_bytes) return fail(C, ECS_ENOMEM, "workspace too small for the batched solve");
+    if (!C->step_ev && hipEventCreateWithFlags(&C->step_ev, hipEventDisableTiming) != hipSuccess) {
+      C->step_ev = nullptr;
+      return fail(C, ECS_EDEVICE, "event creation failed");
+    }
     plan_krylov(C, d, C->ws + C->hier_bytes, &items[q].K);
     items[q].C = C;
     items[q].b0 = reinterpret_cast<const cplx<double> *>(b[q]);
     items[q].x0 = reinterpret_cast<cplx<double> *>(x[q]);
     items[q].nrhs = nrhs[q];
     items[q].phase = nrhs[q] > 0 ? 0 : 3;
-    if (std::find(streams.begin(), streams.end(), C->stream) == streams.end()) streams.push_back(C->stream);
   }
-  for (;;) {
-    bool any = false;
+  int active = 0;
+  for (auto &I : items) {
+    if (I.phase == 3) continue;
+    batch_enqueue(I, d);
+    if (hipEventRecord(I.C->step_ev, I.C->stream) != hipSuccess) return ECS_EDEVICE;
+    active++;
+  }
+  while (active > 0) {
     for (auto &I : items) {
       if (I.phase == 3) continue;
-      any = true;
-      ecs_ctx *C = I.C;
-      const int64_t nn = nn_of(C);
-      const HostLevel &F = C->hl[0];
-      cplx<double> *xr = I.x0 + (int64_t)I.r * nn;
-      if (I.phase == 0) {
-        launch_mask_boundary(F.n[0], F.n[1], F.n[2], I.b0 + (int64_t)I.r * nn, I.K.bz, C->stream);
-        if (d->x_is_guess) launch_mask_boundary(F.n[0], F.n[1], F.n[2], xr, xr, C->stream);
-        else launch_zero<double>(xr, nn, C->stream);
-        launch_nrm2sq<double>(I.K.bz, nn, C->partials, &C->gs->nrm2, C->stream);
-        (void)hipMemcpyAsync(C->pinned, &C->gs->nrm2.re, sizeof(double), hipMemcpyDeviceToHost, C->stream);
-      } else if (I.phase == 1) {
-        bicg_enqueue_restart(C, I.K, I.K.bz, xr);
-        bicg_enqueue_readback(C);
-      } else {
-        if (C->prec.vcycle_dtype == ECS_F32) bicg_enqueue_step<float>(C, I.K, xr);
-        else bicg_enqueue_step<double>(C, I.K, xr);
-        bicg_enqueue_readback(C);
-      }
-    }
-    if (!any) break;
-    for (hipStream_t s : streams)
-      if (hipStreamSynchronize(s) != hipSuccess) return ECS_EDEVICE;
-    for (auto &I : items) {
-      if (I.phase == 3) continue;
-      ecs_ctx *C = I.C;
-      if (I.phase == 0) {
-        double bn2;
-        std::memcpy(&bn2, C->pinned, sizeof(double));
-        const double bn = std::sqrt(bn2);
-        if (!(bn == bn) || std::isinf(bn)) {
-          batch_finish_rhs(I, ECS_EBREAKDOWN, d);
-        } else if (bn == 0) {
-          I.rt = 0;
-          launch_zero<double>(I.x0 + (int64_t)I.r * nn_of(C), nn_of(C), C->stream);  // A x = 0 -> x = 0
-          batch_finish_rhs(I, ECS_OK, d);
-        } else {
-          C->pinned[2] = bn;  // H2D source stays untouched by the {est, bad} readbacks
-          (void)hipMemcpyAsync(&C->bs->bnorm, &C->pinned[2], sizeof(double), hipMemcpyHostToDevice, C->stream);
-          I.phase = 1;
-        }
+      const hipError_t q = hipEventQuery(I.C->step_ev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return fail(I.C, ECS_EDEVICE, std::string("batched solve: ") + hipGetErrorString(q));
+      batch_process(I, d);
+      if (I.phase == 3) {
+        active--;
         continue;
       }
-      double est;
-      int bad;
-      bicg_take_readback(C, &est, &bad);
-      if (I.phase == 1) {
-        I.rt = est;
-        if (!(est == est) || std::isinf(est)) {
-          batch_finish_rhs(I, ECS_EBREAKDOWN, d);
-        } else if (est <= d->rtol) {
-          batch_finish_rhs(I, ECS_OK, d);
-        } else if (I.it >= d->maxit) {
-          batch_finish_rhs(I, ECS_NOT_CONVERGED, d);
-        } else if (est >= I.last_restart && ++I.stalls >= 3) {
-          batch_finish_rhs(I, ECS_NOT_CONVERGED, d);
-        } else {
-          if (I.last_restart < INFINITY) I.restarts++;
-          I.last_restart = est;
-          I.phase = 2;
-        }
-      } else {
-        I.it++;
-        I.agg.vcycles += 2;
-        if (bad || est <= d->rtol || I.it >= d->maxit) I.phase = 1;
-      }
+      batch_enqueue(I, d);
+      if (hipEventRecord(I.C->step_ev, I.C->stream) != hipSuccess) return ECS_EDEVICE;
     }
   }
+  for (auto &I : items)
+    if (hipStreamSynchronize(I.C->stream) != hipSuccess) return ECS_EDEVICE;
   ecs_status worst = ECS_OK;
   for (int q = 0; q < n; q++) {
     items[q].agg.status = items[q].worst;
@@ -1473,7 +1504,6 @@ ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *d
   }
   return worst;
 }
-
 
 // ------------------------------------------------------- coupled blocks
 // Storage of the outer FGMRES of a coupled block system (caller's workspace):
@@ -2169,6 +2199,7 @@ void ecs_destroy(ecs_ctx *C) {
   for (auto &T : C->timers)
     for (auto &e : T.ev) (void)hipEventDestroy(e);
   if (C->pinned) (void)hipHostFree(C->pinned);
+  if (C->step_ev) (void)hipEventDestroy(C->step_ev);
   delete C;
 }
 

@@ -80,21 +80,77 @@ __device__ __forceinline__ bool interior(const int i, const int j, const int n0,
   return i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2;
 }
 
-// stage the level's 1D weights over region A's columns and rows (0 off the
-// interior, where they are never used)
+// The level's 1D weights over region A's columns and rows (0 off the
+// interior, where they are never used), w + h <= NP, one entry per thread:
+// read into registers first, written to LDS once the other staging loads of
+// the block have been issued.
 template <typename R>
-__device__ __forceinline__ void load_weights(const Grid<R> &g, const Region<R> &A) {
-  for (int q = threadIdx.x; q < A.w + A.h; q += NP) {
-    if (q < A.w) {
-      const int i = A.ox + q;
-      const bool in = i >= 1 && i <= g.n0 - 2;
-      A.xm[q] = in ? g.cm0[i] : zc<R>();
-      A.xp[q] = in ? g.cp0[i] : zc<R>();
-    } else {
-      const int j = A.oy + q - A.w;
-      const bool in = j >= 1 && j <= g.n1 - 2;
-      A.ym[q - A.w] = in ? g.cm1[j] : zc<R>();
-      A.yp[q - A.w] = in ? g.cp1[j] : zc<R>();
+struct WeightRead {
+  cplx<R> m, p;
+  bool in;
+};
+
+template <typename R>
+__device__ __forceinline__ WeightRead<R> read_weights(const Grid<R> &g, const Region<R> &A) {
+  const int q = threadIdx.x;
+  const bool col = q < A.w;
+  const int v = col ? A.ox + q : A.oy + q - A.w;
+  const int n = col ? g.n0 : g.n1;
+  const bool in = q < A.w + A.h && v >= 1 && v <= n - 2;
+  const int vc = in ? v : 1;
+  WeightRead<R> w;
+  w.m = col ? g.cm0[vc] : g.cm1[vc];
+  w.p = col ? g.cp0[vc] : g.cp1[vc];
+  w.in = in;  // applied at the write, so no use follows the loads here
+  return w;
+}
+
+template <typename R>
+__device__ __forceinline__ void write_weights(const Region<R> &A, const WeightRead<R> &w) {
+  const int q = threadIdx.x;
+  const cplx<R> m = w.in ? w.m : zc<R>(), p = w.in ? w.p : zc<R>();
+  if (q < A.w) {
+    A.xm[q] = m;
+    A.xp[q] = p;
+  } else if (q < A.w + A.h) {
+    A.ym[q - A.w] = m;
+    A.yp[q - A.w] = p;
+  }
+}
+
+// Stages one level over a region of WH nodes into LDS: t and b (when wanted)
+// and the inverse diagonal of every node, 0 off the interior.  The loop runs
+// a fixed number of slots per thread with clamped, unconditional loads, so
+// all loads of the block are in flight before the first is used.
+template <typename R, int WH, bool T, bool B>
+__device__ __forceinline__ void stage_level(const Grid<R> &g, const Region<R> &A, const cplx<R> *t, const cplx<R> *b,
+                                            cplx<R> *at, cplx<R> *ab, cplx<R> *ad) {
+  constexpr int S = (WH + NP - 1) / NP;
+  cplx<R> tv[S], bv[S], wx[S], wy[S];
+  R kv[S];
+  bool in[S];
+#pragma unroll
+  for (int s = 0; s < S; s++) {
+    const int q = threadIdx.x + s * NP;
+    int x, y;
+    xy_of(q, A.w, A.invw, x, y);
+    const int i = A.ox + x, j = A.oy + y;
+    in[s] = q < WH && interior(i, j, g.n0, g.n1);
+    const int ic = in[s] ? i : 1, jc = in[s] ? j : 1;
+    const int64_t p = (int64_t)jc * g.n0 + ic;
+    if (T) tv[s] = t[p];
+    if (B) bv[s] = b[p];
+    kv[s] = g.k2[p];
+    wx[s] = g.cm0[ic] + g.cp0[ic];
+    wy[s] = g.cm1[jc] + g.cp1[jc];
+  }
+#pragma unroll
+  for (int s = 0; s < S; s++) {
+    const int q = threadIdx.x + s * NP;
+    if (q < WH) {
+      if (T) at[q] = in[s] ? tv[s] : zc<R>();
+      if (B) ab[q] = in[s] ? bv[s] : zc<R>();
+      ad[q] = in[s] ? inv_p(wx[s] + wy[s] + (kv[s] * g.beta + g.c)) : zc<R>();
     }
   }
 }
@@ -194,39 +250,19 @@ __global__ __launch_bounds__(NP) void k_down2_rb(Grid<R> f, Grid<R> m, Grid<R> c
   __shared__ cplx<R> Aw[2 * (AW + AH)], Mw[2 * (MW + MH)];
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
-  const int tid = threadIdx.x;
   const int I0 = (tile % tiles_x) * C, J0 = (tile / tiles_x) * CY;
   const Region<R> M = make_region(2 * I0 - 3, 2 * J0 - 3, MW, MH, Mw);
   const Region<R> A = make_region(2 * M.ox - 3, 2 * M.oy - 3, AW, AH, Aw);
-  load_weights(f, A);
-  load_weights(m, M);
-
-  // one memory round trip: b and the inverse diagonal of the fine region,
-  // the inverse diagonal of the mid region
-  for (int q = tid; q < AW * AH; q += NP) {
-    int x, y;
-    xy_of(q, AW, A.invw, x, y);
-    const int i = A.ox + x, j = A.oy + y;
-    cplx<R> bv = zc<R>(), dv = zc<R>();
-    if (interior(i, j, f.n0, f.n1)) {
-      const int64_t p = (int64_t)j * f.n0 + i;
-      bv = b[p];
-      dv = inv_p(f.cm0[i] + f.cp0[i] + f.cm1[j] + f.cp1[j] + (f.k2[p] * f.beta + f.c));
-    }
-    Ab[q] = bv;
-    Ad[q] = dv;
-  }
-  for (int q = tid; q < MW * MH; q += NP) {
-    int x, y;
-    xy_of(q, MW, M.invw, x, y);
-    const int i = M.ox + x, j = M.oy + y;
-    cplx<R> dv = zc<R>();
-    if (interior(i, j, m.n0, m.n1)) {
-      const int64_t p = (int64_t)j * m.n0 + i;
-      dv = inv_p(m.cm0[i] + m.cp0[i] + m.cm1[j] + m.cp1[j] + (m.k2[p] * m.beta + m.c));
-    }
-    Md[q] = dv;
-  }
+  static_assert(AW + AH <= NP && MW + MH <= NP, "weights are staged one entry per thread");
+  // one memory round trip: the weights of both levels, b and the inverse
+  // diagonal of the fine region, the inverse diagonal of the mid region (fixed
+  // trip counts and clamped, unconditional loads: every load is issued before
+  // the first use)
+  const WeightRead<R> wa = read_weights(f, A), wm = read_weights(m, M);
+  stage_level<R, AW * AH, false, true>(f, A, nullptr, b, nullptr, Ab, Ad);
+  stage_level<R, MW * MH, false, false>(m, M, nullptr, nullptr, nullptr, nullptr, Md);
+  write_weights(A, wa);
+  write_weights(M, wm);
   __syncthreads();
   // level l; owned fine nodes [4 I0, 4 I0 + 4C) -> relative [9, 9 + 4C)
   down_sweep(f, A, Ab, Ad, At, Ar, omega, t_f, 9, 9 + 4 * C, 9, 9 + 4 * CY);
@@ -301,26 +337,6 @@ __device__ void up_sweep(const Grid<R> &g, const Region<R> &A, const cplx<R> *ab
 
 // load t, b and the inverse diagonal of region A of level g (0 off the
 // interior)
-template <typename R>
-__device__ __forceinline__ void load_level(const Grid<R> &g, const Region<R> &A, const cplx<R> *t, const cplx<R> *b,
-                                           cplx<R> *at, cplx<R> *ab, cplx<R> *ad) {
-  for (int q = threadIdx.x; q < A.w * A.h; q += NP) {
-    int x, y;
-    xy_of(q, A.w, A.invw, x, y);
-    const int i = A.ox + x, j = A.oy + y;
-    cplx<R> tv = zc<R>(), bv = zc<R>(), dv = zc<R>();
-    if (interior(i, j, g.n0, g.n1)) {
-      const int64_t p = (int64_t)j * g.n0 + i;
-      tv = t[p];
-      bv = b[p];
-      dv = inv_p(g.cm0[i] + g.cp0[i] + g.cm1[j] + g.cp1[j] + (g.k2[p] * g.beta + g.c));
-    }
-    at[q] = tv;
-    ab[q] = bv;
-    ad[q] = dv;
-  }
-}
-
 // Block tile: TX x TY nodes of level l at (x0, y0), x0 and y0 even.  Fine
 // region: (x0 - 2, y0 - 2), (TX + 4) x (TY + 4).  Its nodes interpolate from
 // mid nodes E = (x0/2 - 1, y0/2 - 1), (TX/2 + 3) x (TY/2 + 3), whose final
@@ -349,19 +365,26 @@ __global__ __launch_bounds__(NP) void k_up2_rb(Grid<R> f, Grid<R> m, Grid<R> c, 
   const Region<R> F = make_region(x0 / 2 - 3, y0 / 2 - 3, FW, FH, Fw);
   // coarse nodes under F: from floor(F.ox / 2) (F.ox may be odd or negative)
   const Region<R> G = make_region(F.ox >> 1, F.oy >> 1, GW, GH, (cplx<R> *)nullptr);
-  load_weights(f, A);
-  load_weights(m, F);
-
-  // one memory round trip: the coarse correction over G, t, b and the
-  // inverse diagonals of both levels
-  for (int q = tid; q < GW * GH; q += NP) {
+  static_assert(AW + AH <= NP && FW + FH <= NP && GW * GH <= NP, "staged one entry per thread");
+  // one memory round trip: the weights of both levels, the coarse correction
+  // over G, t, b and the inverse diagonals of both levels (clamped,
+  // unconditional loads, all issued before the first use)
+  const WeightRead<R> wa = read_weights(f, A), wf = read_weights(m, F);
+  cplx<R> ge;
+  bool ge_in;
+  {
     int x, y;
-    xy_of(q, GW, G.invw, x, y);
+    xy_of(tid, GW, G.invw, x, y);
     const int I = G.ox + x, J = G.oy + y;
-    Ge[q] = (I >= 0 && I < c.n0 && J >= 0 && J < c.n1) ? ec[(int64_t)J * c.n0 + I] : zc<R>();
+    const bool in = tid < GW * GH && I >= 0 && I < c.n0 && J >= 0 && J < c.n1;
+    ge_in = in;
+    ge = ec[in ? (int64_t)J * c.n0 + I : 0];
   }
-  load_level(m, F, t_m, b_m, Ft, Fb, Fd);
-  load_level(f, A, t_f, b_f, At, Ab, Ad);
+  stage_level<R, FW * FH, true, true>(m, F, t_m, b_m, Ft, Fb, Fd);
+  stage_level<R, AW * AH, true, true>(f, A, t_f, b_f, At, Ab, Ad);
+  write_weights(A, wa);
+  write_weights(F, wf);
+  if (tid < GW * GH) Ge[tid] = ge_in ? ge : zc<R>();
   __syncthreads();
   // level l + 1 over F; its final values on E (relative [2, 2 + EW)) into Ge's
   // successor: stored in Fv itself (the up sweep leaves them there)
