@@ -65,6 +65,26 @@ __device__ __forceinline__ cplx<R> offd_at(const Grid<R> &g, const cplx<RI> *__r
   return o;
 }
 
+// The same two quantities with the dimension fixed at compile time (no
+// branches between the loads, so a thread's loads are all in flight together).
+template <typename R, int DIM>
+__device__ __forceinline__ cplx<R> diag_d(const Grid<R> &g, int i, int j, int k, int64_t p) {
+  cplx<R> d = g.cm0[i] + g.cp0[i] + g.cm1[j] + g.cp1[j];
+  if constexpr (DIM == 3) d = d + g.cm2[k] + g.cp2[k];
+  return d + (g.k2[p] * g.beta + g.c);
+}
+template <typename R, int DIM>
+__device__ __forceinline__ cplx<R> offd_d(const Grid<R> &g, const cplx<R> *__restrict__ u, int i, int j, int k,
+                                          int64_t p) {
+  const int64_t s1 = g.n0;
+  cplx<R> o = g.cm0[i] * u[p - 1] + g.cp0[i] * u[p + 1] + g.cm1[j] * u[p - s1] + g.cp1[j] * u[p + s1];
+  if constexpr (DIM == 3) {
+    const int64_t s2 = (int64_t)g.n0 * g.n1;
+    o = o + g.cm2[k] * u[p - s2] + g.cp2[k] * u[p + s2];
+  }
+  return o;
+}
+
 template <typename R>
 dim3 grid_of(const Grid<R> &g) {
   return dim3(xcd_padded(((g.n0 + TX - 1) / TX) * ((g.n1 + TY - 1) / TY) * g.n2));
@@ -108,13 +128,22 @@ __global__ __launch_bounds__(256) void k_jacobi(Grid<R> g, const cplx<R> *__rest
     out[q.p] = mk<R>(0, 0);
     return;
   }
-  cplx<R> d = diag_at(g, q.i, q.j, q.k, q.p);
+  // uniform branches first, then every load of the path, then the arithmetic
   if (zero_guess) {
-    out[q.p] = omega * cdiv(b[q.p], d);
+    const cplx<R> bv = b[q.p];
+    const cplx<R> d = g.n2 > 1 ? diag_d<R, 3>(g, q.i, q.j, q.k, q.p) : diag_d<R, 2>(g, q.i, q.j, q.k, q.p);
+    out[q.p] = omega * cdiv(bv, d);
   } else {
-    cplx<R> u0 = u[q.p];
-    cplx<R> res = b[q.p] - (d * u0 - offd_at<R, R>(g, u, q.i, q.j, q.k, q.p));
-    out[q.p] = u0 + omega * cdiv(res, d);
+    const cplx<R> bv = b[q.p], u0 = u[q.p];
+    cplx<R> d, o;
+    if (g.n2 > 1) {
+      d = diag_d<R, 3>(g, q.i, q.j, q.k, q.p);
+      o = offd_d<R, 3>(g, u, q.i, q.j, q.k, q.p);
+    } else {
+      d = diag_d<R, 2>(g, q.i, q.j, q.k, q.p);
+      o = offd_d<R, 2>(g, u, q.i, q.j, q.k, q.p);
+    }
+    out[q.p] = u0 + omega * cdiv(bv - (d * u0 - o), d);
   }
 }
 
@@ -133,10 +162,16 @@ __global__ __launch_bounds__(256) void k_rb_colour(Grid<R> g, const cplx<R> *__r
     return;
   }
   if (!mine) return;
-  cplx<R> d = diag_at(g, q.i, q.j, q.k, q.p);
-  cplx<R> u0 = u[q.p];
-  cplx<R> res = b[q.p] - (d * u0 - offd_at<R, R>(g, u, q.i, q.j, q.k, q.p));
-  u[q.p] = u0 + omega * cdiv(res, d);
+  const cplx<R> bv = b[q.p], u0 = u[q.p];
+  cplx<R> d, o;
+  if (g.n2 > 1) {
+    d = diag_d<R, 3>(g, q.i, q.j, q.k, q.p);
+    o = offd_d<R, 3>(g, u, q.i, q.j, q.k, q.p);
+  } else {
+    d = diag_d<R, 2>(g, q.i, q.j, q.k, q.p);
+    o = offd_d<R, 2>(g, u, q.i, q.j, q.k, q.p);
+  }
+  u[q.p] = u0 + omega * cdiv(bv - (d * u0 - o), d);
 }
 
 // full weighting of a fine-grid vector onto the coarse interior, index space
@@ -168,7 +203,33 @@ __global__ __launch_bounds__(256) void k_restrict(Grid<R> f, Grid<R> c, const cp
 }
 
 // fused residual + full weighting: the 3^d fine residuals under the coarse
-// node are recomputed from u (no fine residual vector is stored)
+// node are recomputed from u (no fine residual vector is stored).  Under an
+// interior coarse node every one of them is a fine interior node, so the
+// loops need no tests: fixed trip counts, all loads in flight together.
+template <typename R, int DIM>
+__device__ __forceinline__ cplx<R> fw_residual(const Grid<R> &f, const cplx<R> *__restrict__ b,
+                                               const cplx<R> *__restrict__ u, int I, int J, int K) {
+  const R wgt[3] = {R(0.25), R(0.5), R(0.25)};
+  cplx<R> acc = mk<R>(0, 0);
+#pragma unroll
+  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); dz++) {
+    const int fk = DIM == 3 ? 2 * K + dz : 0;
+    const R wz = DIM == 3 ? wgt[dz + 1] : R(1);
+#pragma unroll
+    for (int dy = -1; dy <= 1; dy++) {
+      const int fj = 2 * J + dy;
+#pragma unroll
+      for (int dx = -1; dx <= 1; dx++) {
+        const int fi = 2 * I + dx;
+        const int64_t p = ((int64_t)fk * f.n1 + fj) * f.n0 + fi;
+        const cplx<R> r = b[p] - (diag_d<R, DIM>(f, fi, fj, fk, p) * u[p] - offd_d<R, DIM>(f, u, fi, fj, fk, p));
+        acc = acc + (wz * wgt[dy + 1] * wgt[dx + 1]) * r;
+      }
+    }
+  }
+  return acc;
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_residual_restrict(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
                                                            const cplx<R> *__restrict__ u, cplx<R> *__restrict__ rc) {
@@ -178,25 +239,7 @@ __global__ __launch_bounds__(256) void k_residual_restrict(Grid<R> f, Grid<R> c,
     rc[q.p] = mk<R>(0, 0);
     return;
   }
-  const R wgt[3] = {R(0.25), R(0.5), R(0.25)};
-  const int kz = f.n2 > 1 ? 1 : 0;
-  cplx<R> acc = mk<R>(0, 0);
-  for (int dz = -kz; dz <= kz; dz++) {
-    int fk = kz ? 2 * q.k + dz : 0;
-    R wz = kz ? wgt[dz + 1] : R(1);
-    bool zint = !kz || (fk >= 1 && fk <= f.n2 - 2);
-    for (int dy = -1; dy <= 1; dy++) {
-      int fj = 2 * q.j + dy;
-      for (int dx = -1; dx <= 1; dx++) {
-        int fi = 2 * q.i + dx;
-        if (!zint || fj < 1 || fj > f.n1 - 2 || fi < 1 || fi > f.n0 - 2) continue;
-        int64_t p = ((int64_t)fk * f.n1 + fj) * f.n0 + fi;
-        cplx<R> r = b[p] - (diag_at(f, fi, fj, fk, p) * u[p] - offd_at<R, R>(f, u, fi, fj, fk, p));
-        acc = acc + (wz * wgt[dy + 1] * wgt[dx + 1]) * r;
-      }
-    }
-  }
-  rc[q.p] = acc;
+  rc[q.p] = f.n2 > 1 ? fw_residual<R, 3>(f, b, u, q.i, q.j, q.k) : fw_residual<R, 2>(f, b, u, q.i, q.j, q.k);
 }
 
 // u_out = u_in + P ec on the fine interior (bilinear / trilinear in index
@@ -234,14 +277,14 @@ __global__ __launch_bounds__(256) void k_prolong_add(Grid<R> f, Grid<R> c, const
 }
 
 // (P ec) at fine node (i, j) of a 2D level: bilinear in index space; zero on
-// the fine boundary because ec is zero on the coarse boundary
+// the fine boundary because ec is zero on the coarse boundary.  Branch-free:
+// the mean of the four coarse nodes (I0 or I0 + 1) x (J0 or J0 + 1), where an
+// even index takes the same coarse node twice (never outside the level).
 template <typename R>
 __device__ __forceinline__ cplx<R> prolong_at(const cplx<R> *__restrict__ ec, int c0, int i, int j) {
-  const cplx<R> *e0 = ec + (int64_t)(j >> 1) * c0 + (i >> 1);
-  if ((i & 1) == 0 && (j & 1) == 0) return e0[0];
-  if ((j & 1) == 0) return R(0.5) * (e0[0] + e0[1]);
-  if ((i & 1) == 0) return R(0.5) * (e0[0] + e0[c0]);
-  return R(0.25) * (e0[0] + e0[1] + e0[c0] + e0[c0 + 1]);
+  const int I0 = i >> 1, J0 = j >> 1, I1 = I0 + (i & 1), J1 = J0 + (j & 1);
+  const cplx<R> *r0 = ec + (int64_t)J0 * c0, *r1 = ec + (int64_t)J1 * c0;
+  return R(0.25) * ((r0[I0] + r0[I1]) + (r1[I0] + r1[I1]));
 }
 
 // 2D coarse-grid correction fused with the first omega-Jacobi post-sweep, out
