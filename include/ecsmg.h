@@ -235,7 +235,10 @@ ecs_status ecs_coarse_solve(ecs_ctx *ctx, const void *b_dev, void *x_dev);
 ecs_status ecs_level_info(ecs_ctx *ctx, int level, int *nlevels, int64_t *nodes);
 
 /* Kernel timing for measurement: when enabled, HIP events are recorded on the
- * context's stream around every launch of kernel class `kclass`:
+ * context's stream around launches of kernel class `kclass` -- enable = 1:
+ * every launch; enable = n > 1: one launch in n (the 1st, (n+1)-th, ...),
+ * which keeps the events' own cost (a few microseconds per timed launch) off
+ * most launches of a timed solve; 0: off; negative: ECS_EINVAL.  Classes:
  *   0 finest-level smoothing sweep      5 finest-level residual + restriction
  *   1 Arnoldi multi-dot (partials)      6 finest-level prolongation + correction
  *   2 FP64 operator A (matvec)          7 finest-level fused down kernel
@@ -260,7 +263,7 @@ ecs_status ecs_timing_calibrate(ecs_ctx *ctx, int launches);
 /* Launch schedule of the fused 2D V(1,1) red-black cycle (performance only;
  * results do not depend on it):
  *   down_rows   coarse rows per block of the fused pre-smoothing/restriction
- *               kernel on grids above small_grid: 2, 4, 6, 8 (16 in FP32)
+ *               kernel on grids above small_grid: 2 to 6, 8 (16 in FP32)
  *   up_rows     fine rows per block of the fused prolongation/post-smoothing
  *               kernel on grids above small_grid: 4, 8, 12, 16 or 32
  *   small_grid  grids with at most this many nodes per axis use 2 / 4 rows
@@ -280,10 +283,20 @@ typedef struct {
 ecs_status ecs_set_tuning(ecs_ctx *ctx, const ecs_tuning *tuning);
 ecs_status ecs_get_tuning(ecs_ctx *ctx, ecs_tuning *tuning);
 
-/* Replay the V(1,1) red-black cycle from captured HIP graphs (default on):
- * the cycle is recorded once per (input, output) buffer pair and replayed
- * with one launch.  0 launches every kernel eagerly (same results). */
-ecs_status ecs_set_graphs(ecs_ctx *ctx, int enable);
+/* How the preconditioner cycle is launched (results are the same in every
+ * mode):
+ *   ECS_GRAPHS_NEVER   every kernel eagerly on the context's stream
+ *   ECS_GRAPHS_ALWAYS  the cycle is captured once per (input, output) buffer
+ *                      pair as a HIP graph and replayed with one launch
+ *   ECS_GRAPHS_AUTO    (default) graphs for general cycles, whose many small
+ *                      launches would make the host the bottleneck; eager
+ *                      launches for the fused 2D V(1,1) red-black cycle
+ *                      (about two launches per level), where the device-side
+ *                      completion of a graph launch costs more than the host
+ *                      launches it saves
+ * Any other value: ECS_EINVAL. */
+enum { ECS_GRAPHS_NEVER = 0, ECS_GRAPHS_ALWAYS = 1, ECS_GRAPHS_AUTO = 2 };
+ecs_status ecs_set_graphs(ecs_ctx *ctx, int mode);
 
 /* Batched solve of n independent problems (Bi-CGSTAB; desc->krylov must be
  * ECS_KRYLOV_BICGSTAB).  Each context is fully set up with its own workspace

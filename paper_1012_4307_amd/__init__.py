@@ -422,13 +422,20 @@ class Solver:
         self._check(lib().ecs_get_tuning(self._h, ctypes.byref(t)))
         return t.as_dict()
 
-    def set_graphs(self, enable: bool):
-        """Replay the V(1,1) red-black cycle from captured HIP graphs (default)."""
-        self._check(lib().ecs_set_graphs(self._h, 1 if enable else 0))
+    def set_graphs(self, mode):
+        """Launch mode of the cycle: True (HIP graph replay), False (eager) or
+        "auto" (the default: graphs for general cycles, eager launches for
+        the fused 2D V(1,1) red-black cycle)."""
+        code = {False: 0, True: 1, "auto": 2}[mode]
+        self._check(lib().ecs_set_graphs(self._h, code))
 
     # ----------------------------------------------------------- timing
-    def timing(self, kclass: str, enable: bool = True):
-        self._check(lib().ecs_timing_enable(self._h, TIMER[kclass], 1 if enable else 0))
+    def timing(self, kclass: str, enable: bool = True, every: int = 1):
+        """Time launches of one kernel class with HIP events: every launch, or
+        one in ``every``."""
+        if every < 1:
+            raise ValueError("every must be >= 1")
+        self._check(lib().ecs_timing_enable(self._h, TIMER[kclass], every if enable else 0))
 
     def timing_calibrate(self, launches: int = 200) -> float:
         """Mean timed duration (us) of an empty kernel: the fixed part of every

@@ -51,6 +51,8 @@ struct Timer {
   std::vector<hipEvent_t> ev;  // start/stop pairs
   size_t used = 0;
   bool on = false;
+  int every = 1;               // time one launch in `every` of the class
+  int64_t seen = 0;            // launch scopes of the class since enabling
   double bytes = 0;            // algorithmic bytes of the timed launches
 };
 
@@ -123,7 +125,7 @@ struct ecs_ctx {
   };
   std::vector<GraphEntry> graphs;
   hipStream_t capture = nullptr;
-  bool use_graphs = true;
+  int graph_mode = ECS_GRAPHS_AUTO;
 
   // launch schedule of the fused V(1,1) cycle (autotuned per grid and dtype)
   ecs_tuning tune{4, 8, 513, 33, 129};
@@ -350,6 +352,7 @@ struct TimedScope {
   double bytes = 0;
   TimedScope(ecs_ctx *c, int cls, double b) : C(c), T(&c->timers[cls]) {
     if (!T->on) return;
+    if (T->seen++ % T->every != 0) return;
     if (T->used + 2 > T->ev.size()) {
       if (T->ev.size() >= 2 * 65536) return;
       size_t old = T->ev.size();
@@ -913,11 +916,6 @@ void drop_graphs(ecs_ctx *C) {
   C->graphs.clear();
 }
 
-// The fused cycle is ~2 launches per level; below ~257^2 nodes a level is a
-// few microseconds of work, so host launch overhead would dominate.  The
-// whole cycle is captured once per (input, output) pair and replayed as one
-// graph launch.  Per-kernel timing needs eager launches, so graphs are
-// bypassed while any cycle timer is on.
 // launches of one general cycle (capped): cycles with very many coarse
 // visits (large gamma over many levels) are not captured
 int64_t cycle_launches(const ecs_ctx *C, int l, int gf, int gc, int64_t cap) {
@@ -930,12 +928,25 @@ int64_t cycle_launches(const ecs_ctx *C, int l, int gf, int gc, int64_t cap) {
   return n;
 }
 
+// A general cycle is several launches per level, most of them a few
+// microseconds of work on the coarse levels, so host launch overhead would
+// dominate: the whole cycle is captured once per (input, output) pair and
+// replayed as one graph launch.  The fused cycle is about two launches per
+// level; there the device-side completion of a graph launch (about 12 us
+// before the next kernel on the stream) costs more than the host launches it
+// saves, so the automatic mode launches it eagerly.  Per-kernel timing needs
+// eager launches, so graphs are bypassed while any cycle timer is on.
+// Returns false when the caller should launch the cycle eagerly.
 template <typename R>
 bool vcycle_graph(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
   for (int k : {kTSmooth, kTCoarse, kTRestrict, kTProlong, kTDown, kTUp})
     if (C->timers[k].on) return false;
-  if (!C->use_graphs) return false;
-  if (!fused_vcycle(C) && cycle_launches(C, 0, C->prec.gamma_f, C->prec.gamma_c, 4096) >= 4096) return false;
+  if (C->graph_mode == ECS_GRAPHS_NEVER) return false;
+  if (fused_vcycle(C)) {
+    if (C->graph_mode == ECS_GRAPHS_AUTO) return false;
+  } else if (cycle_launches(C, 0, C->prec.gamma_f, C->prec.gamma_c, 4096) >= 4096) {
+    return false;
+  }
   for (auto &g : C->graphs)
     if (g.b == b0 && g.u == u0 && g.real_bytes == (int)sizeof(R))
       return hipGraphLaunch(g.exec, C->stream) == hipSuccess;
@@ -2066,8 +2077,11 @@ ecs_status ecs_level_info(ecs_ctx *C, int level, int *nlevels, int64_t *nodes) {
 }
 
 ecs_status ecs_timing_enable(ecs_ctx *C, int kclass, int enable) {
-  if (!C || kclass < 0 || kclass >= kTClasses) return ECS_EINVAL;
-  C->timers[kclass].on = enable != 0;
+  if (!C || kclass < 0 || kclass >= kTClasses || enable < 0) return ECS_EINVAL;
+  Timer &T = C->timers[kclass];
+  T.on = enable != 0;
+  T.every = enable > 1 ? enable : 1;
+  T.seen = 0;
   return ECS_OK;
 }
 
@@ -2159,8 +2173,7 @@ ecs_status ecs_coupled_solve(int nb, ecs_ctx *const *ctx, const double *k2c, con
 ecs_status ecs_set_tuning(ecs_ctx *C, const ecs_tuning *t) {
   if (!C || !t) return ECS_EINVAL;
   const bool f32 = C->have_prec && C->prec.vcycle_dtype == ECS_F32;
-  const bool down_ok = t->down_rows == 2 || t->down_rows == 4 || t->down_rows == 6 || t->down_rows == 8 ||
-                       (t->down_rows == 16 && f32);
+  const bool down_ok = (t->down_rows >= 2 && t->down_rows <= 6) || t->down_rows == 8 || (t->down_rows == 16 && f32);
   const bool up_ok = t->up_rows == 4 || t->up_rows == 8 || t->up_rows == 12 || t->up_rows == 16 || t->up_rows == 32;
   if (!down_ok || !up_ok) return fail(C, ECS_EINVAL, "unsupported tile height");
   if (t->tail_nodes < 3 || t->tail_nodes > kTailNodes) return fail(C, ECS_EINVAL, "tail_nodes must be in [3, 33]");
@@ -2177,10 +2190,10 @@ ecs_status ecs_get_tuning(ecs_ctx *C, ecs_tuning *t) {
   return ECS_OK;
 }
 
-ecs_status ecs_set_graphs(ecs_ctx *C, int enable) {
-  if (!C) return ECS_EINVAL;
-  C->use_graphs = enable != 0;
-  if (!C->use_graphs) drop_graphs(C);
+ecs_status ecs_set_graphs(ecs_ctx *C, int mode) {
+  if (!C || mode < ECS_GRAPHS_NEVER || mode > ECS_GRAPHS_AUTO) return ECS_EINVAL;
+  C->graph_mode = mode;
+  if (mode == ECS_GRAPHS_NEVER) drop_graphs(C);
   return ECS_OK;
 }
 

@@ -615,8 +615,8 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
 
 // The tile height of the fused kernels is a launch parameter chosen by the
 // host (autotuned per grid size and dtype): coarse rows per down block in
-// {2, 4, 8, 16} (16 only in FP32, whose tile fits the LDS), fine rows per up
-// block in {4, 8, 16, 32}.
+// {2, ..., 6, 8, 16} (16 only in FP32, whose tile fits the LDS), fine rows
+// per up block in {4, 8, 12, 16, 32}.
 template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *u, cplx<R> *rc, R omega,
                     int rows, hipStream_t s) {
@@ -626,7 +626,9 @@ void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b
   const dim3 grid(xcd_padded(tiles)), block(NT);
   switch (rows) {
     case 2: launch_k((k_down_rb<R, 2>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
+    case 3: launch_k((k_down_rb<R, 3>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
     case 4: launch_k((k_down_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
+    case 5: launch_k((k_down_rb<R, 5>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
     case 6: launch_k((k_down_rb<R, 6>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
     case 16:
       if constexpr (sizeof(R) == 4) {

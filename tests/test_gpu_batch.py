@@ -81,4 +81,4 @@ def test_autotune_schedule_keeps_results(tmp_path, monkeypatch):
         S2 = gpu_for(w, dt)
         assert autotune.autotune(S2) == best   # from the cache
     with pytest.raises(E.EcsError):
-        S.set_tuning(down_rows=3)
+        S.set_tuning(down_rows=7)

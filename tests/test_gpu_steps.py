@@ -167,6 +167,23 @@ def test_vcycle_two_level_kernels(dt):
                 assert relerr(to_np(S.vcycle(to_gpu(v))), ref) < CYCLE_TOL[dt], (w.name, w.n, pg, tn)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_vcycle_tile_heights(dt):
+    """Every tile height of the fused down and up kernels (coarse rows per
+    block 2..6, 8, and 16 in FP32; fine rows 4..32), applied on every level
+    above the tail of a ragged grid, against the oracle's cycle."""
+    w = ragged_workload(n=193, coarsest=7)
+    P = oracle_for(w)
+    S = gpu_for(w, dt)
+    v = W.random_complex(w.shape, np.random.default_rng(16))
+    ref = P.mg_apply(v)
+    downs = (2, 3, 4, 5, 6, 8) + ((16,) if dt == "f32" else ())
+    for d in downs:
+        for u in (4, 8, 12, 16, 32):
+            S.set_tuning(down_rows=d, up_rows=u, small_grid=3, tail_nodes=33, pair_grid=0)
+            assert relerr(to_np(S.vcycle(to_gpu(v))), ref) < CYCLE_TOL[dt], (d, u)
+
+
 @pytest.mark.parametrize("gf,gc,smoother,omega,nu", [(2, 2, "rbgs", 1.05, 1), (1, 2, "jacobi", 0.8, 1),
                                                       (1, 4, "jacobi", 0.5, 2), (1, 1, "rbgs", 1.0, 2)])
 def test_general_cycles(gf, gc, smoother, omega, nu):
@@ -267,3 +284,6 @@ def test_vcycle_graph_replay_matches_eager():
             torch.cuda.synchronize()
             assert torch.equal(z, ref), (dt, r)
         assert torch.isfinite(y.abs()).all()
+        # the default mode launches this fused cycle eagerly
+        S.set_graphs("auto")
+        assert torch.equal(S.vcycle(v), ref), dt
