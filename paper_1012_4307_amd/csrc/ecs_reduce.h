@@ -28,6 +28,28 @@ __device__ __forceinline__ cplx<double> block_sum(cplx<double> v, cplx<double> *
   return s;
 }
 
+// This thread's share of a second-stage reduction: x[t] + x[t + B] + ... over
+// the entries below n (t = threadIdx.x, B = kRedThreads), added in that order.
+// The loads of a chunk are all issued before the first add: a plain strided
+// loop waits for each load before issuing the next, one memory round trip
+// per entry.
+__device__ __forceinline__ cplx<double> strided_sum(const cplx<double> *x, int n) {
+  constexpr int U = 8;
+  cplx<double> s = mk<double>(0, 0);
+  for (int b0 = threadIdx.x; b0 < n; b0 += U * kRedThreads) {
+    cplx<double> v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int b = b0 + u * kRedThreads;
+      v[u] = x[b < n ? b : b0];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (b0 + u * kRedThreads < n) s = s + v[u];
+  }
+  return s;
+}
+
 // Bi-CGSTAB scalar recurrence on the reduced dot products d0, d1.
 __device__ inline void bicg_update(BicgScalars *S, int mode, cplx<double> d0, cplx<double> d1) {
   const cplx<double> zero = mk<double>(0, 0);

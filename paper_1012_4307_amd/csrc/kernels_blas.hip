@@ -86,8 +86,7 @@ __global__ __launch_bounds__(BS) void k_reduce_cols(const cplx<double> *__restri
                                                     cplx<double> *__restrict__ out) {
   __shared__ cplx<double> lds[BS / 64];
   const int c = blockIdx.x;
-  cplx<double> s = mk<double>(0, 0);
-  for (int b = threadIdx.x; b < nblocks; b += BS) s = s + partials[(int64_t)c * nblocks + b];
+  cplx<double> s = strided_sum(partials + (int64_t)c * nblocks, nblocks);
   s = block_sum(s, lds);
   if (threadIdx.x == 0) out[c] = s;
 }
@@ -269,8 +268,7 @@ __global__ __launch_bounds__(BS) void k_bicg_final(const cplx<double> *__restric
   __shared__ cplx<double> lds[BS / 64];
   cplx<double> d[2] = {mk<double>(0, 0), mk<double>(0, 0)};
   for (int q = 0; q < npairs; q++) {
-    cplx<double> s = mk<double>(0, 0);
-    for (int b = threadIdx.x; b < nblocks; b += BS) s = s + partials[(int64_t)q * nblocks + b];
+    cplx<double> s = strided_sum(partials + (int64_t)q * nblocks, nblocks);
     d[q] = block_sum(s, lds);
     __syncthreads();
   }
