@@ -68,18 +68,24 @@ __device__ __forceinline__ int row_of(int p, float inv) { return (int)(((float)p
 template <typename R, typename M>
 __device__ __forceinline__ void dense_solve(int nu, int tpr, const M *mi, const cplx<R> *b, cplx<R> *x, int n0) {
   const int tid = threadIdx.x, ni = n0 - 2, rows = ST / tpr;
+  // node of unknown c from a float reciprocal (exact: c < 1024)
+  const float inv = 1.0f / (float)ni;
+  auto node = [&](int c) {
+    const int r = (int)(((float)c + 0.5f) * inv);
+    return (r + 1) * n0 + (c - r * ni) + 1;
+  };
   for (int r0 = 0; r0 < nu; r0 += rows) {
     const int r = r0 + tid / tpr;
     cplx<R> acc = mk<R>(0, 0);
     if (r < nu) {
 #pragma unroll 4
-      for (int c = tid % tpr; c < nu; c += tpr) acc = acc + mi[(int64_t)c * nu + r] * b[(c / ni + 1) * n0 + c % ni + 1];
+      for (int c = tid % tpr; c < nu; c += tpr) acc = acc + mi[(int64_t)c * nu + r] * b[node(c)];
     }
     for (int m = tpr >> 1; m >= 1; m >>= 1) {
       acc.re += __shfl_xor(acc.re, m, 64);
       acc.im += __shfl_xor(acc.im, m, 64);
     }
-    if (r < nu && tid % tpr == 0) x[(r / ni + 1) * n0 + r % ni + 1] = acc;
+    if (r < nu && tid % tpr == 0) x[node(r)] = acc;
   }
 }
 

@@ -393,23 +393,29 @@ struct TailLds {
 
 // rows of the dense coarsest solve: tpr lanes per row, partial sums combined
 // across the row's lanes; the interior unknowns are the interior nodes in
-// row-major order
+// row-major order.  The node of unknown c (interior row c / ni, column
+// c % ni) comes from a float reciprocal, not an integer division: exact here
+// (c < 1024, so the product stays more than 0.5 / ni away from an integer).
 template <typename R, typename M>
 __device__ __forceinline__ void tail_dense(int nu, int tpr, const M *mi, const cplx<R> *b, cplx<R> *x, int n0) {
   const int tid = threadIdx.x, ni = n0 - 2, rows_per_pass = TT / tpr;
+  const float inv = 1.0f / (float)ni;
+  auto node = [&](int c) {
+    const int r = (int)(((float)c + 0.5f) * inv);
+    return (r + 1) * n0 + (c - r * ni) + 1;
+  };
   for (int r0 = 0; r0 < nu; r0 += rows_per_pass) {
     const int rr = r0 + tid / tpr;
     cplx<R> acc = zero_c<R>();
     if (rr < nu) {
 #pragma unroll 4
-      for (int c = tid % tpr; c < nu; c += tpr)
-        acc = acc + mi[(int64_t)c * nu + rr] * b[(c / ni + 1) * n0 + c % ni + 1];
+      for (int c = tid % tpr; c < nu; c += tpr) acc = acc + mi[(int64_t)c * nu + rr] * b[node(c)];
     }
     for (int m = tpr >> 1; m >= 1; m >>= 1) {
       acc.re += __shfl_xor(acc.re, m, 64);
       acc.im += __shfl_xor(acc.im, m, 64);
     }
-    if (rr < nu && tid % tpr == 0) x[(rr / ni + 1) * n0 + rr % ni + 1] = acc;
+    if (rr < nu && tid % tpr == 0) x[node(rr)] = acc;
   }
 }
 
@@ -548,12 +554,17 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
     __syncthreads();
   }
 
-  // dense solve on the coarsest level
+  // dense solve on the coarsest level; its boundary nodes (read as 0 by the
+  // prolongation) are cleared by other threads in the same phase: the solve
+  // writes only interior nodes
   {
     const Grid<R> &g = a.g[last];
     const int nn = g.n0 * g.n1, no = a.noff[last];
-    for (int p = tid; p < nn; p += TT) S.w[no + p] = zero_c<R>();
-    __syncthreads();
+    const float inv0 = 1.0f / (float)g.n0;
+    for (int p = tid; p < nn; p += TT) {
+      const int j = (int)(((float)p + 0.5f) * inv0), i = p - j * g.n0;
+      if (i == 0 || i == g.n0 - 1 || j == 0 || j == g.n1 - 1) S.w[no + p] = zero_c<R>();
+    }
     if (minv_lds) tail_dense(a.nunk, a.tpr, S.mi, S.b + no, S.w + no, g.n0);
     else tail_dense(a.nunk, a.tpr, a.minvT, S.b + no, S.w + no, g.n0);
     __syncthreads();
