@@ -455,7 +455,8 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
       const Grid<R> &g = a.g[k];
       const int nn = g.n0 * g.n1;
       const int p0 = P - a.poff[k], p = p0 < nn ? p0 : nn - 1;
-      const int i = p % g.n0, j = p / g.n0;
+      // row from a float reciprocal (exact: p < kTailCap)
+      const int j = (int)(((float)p + 0.5f) * (1.0f / (float)g.n0)), i = p - j * g.n0;
       lv[sl] = P < a.poff[a.nl] && p0 < nn ? k : -1;
       pv[sl] = p;
       cxm[sl] = g.cm0[i];
@@ -491,7 +492,8 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
       if (k < 0) continue;
       const int kk = __builtin_amdgcn_readfirstlane(k < 0 ? 0 : k);
       const Grid<R> &g = a.g[kk];
-      const int p = pv[sl], i = p % g.n0, j = p / g.n0, P = a.noff[kk] + p;
+      const int p = pv[sl], j = (int)(((float)p + 0.5f) * (1.0f / (float)g.n0)), i = p - j * g.n0;
+      const int P = a.noff[kk] + p;
       const bool in = i >= 1 && i <= g.n0 - 2 && j >= 1 && j <= g.n1 - 2;
       const cplx<R> dv = in ? inv_c(cxm[sl] + cxp[sl] + cym[sl] + cyp[sl] + (kv[sl] * g.beta + g.c)) : zero_c<R>();
       S.d[P] = dv;
