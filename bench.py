@@ -77,8 +77,8 @@ def vcycle_algorithmic_bytes(n, nlev, real_bytes):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the solver has no multi-GPU path in this "
-              f"build; the slab decomposition it would use is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the solver runs on a single GPU and has no "
+              f"multi-GPU path (a split into horizontal slabs with halo exchange is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1012_4307_amd as E
