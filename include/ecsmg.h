@@ -301,9 +301,13 @@ ecs_status ecs_set_graphs(ecs_ctx *ctx, int mode);
 /* Batched solve of n independent problems (Bi-CGSTAB; desc->krylov must be
  * ECS_KRYLOV_BICGSTAB).  Each context is fully set up with its own workspace
  * (sized for a Bi-CGSTAB desc) and should have its own stream: the driver
- * advances all systems in rounds -- one phase (||b||, true residual and
- * restart, or one iteration) per unconverged system per round, enqueued on
- * that system's stream -- and synchronises once per round.  b[s], x[s] point
+ * enqueues one phase of a system at a time (||b||, true residual and restart,
+ * or one iteration) on that system's stream, records an event after it, and
+ * polls the events from the host; a system's next phase is enqueued as soon
+ * as its own previous phase has completed, so systems of different sizes
+ * progress independently.  Each system runs exactly the kernel sequence of
+ * its single solve (same results).  Returns after every stream has been
+ * synchronised; a context given twice is ECS_EINVAL.  b[s], x[s] point
  * to nrhs[s] contiguous complex128 vectors of system s, solved one after the
  * other.  stats[s] aggregates the system's right-hand sides: summed
  * iterations, restarts and cycles, the largest final true residual, the worst
