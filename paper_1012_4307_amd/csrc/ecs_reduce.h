@@ -34,7 +34,7 @@ __device__ __forceinline__ cplx<double> block_sum(cplx<double> v, cplx<double> *
 // loop waits for each load before issuing the next, one memory round trip
 // per entry.
 __device__ __forceinline__ cplx<double> strided_sum(const cplx<double> *x, int n) {
-  constexpr int U = 8;
+  constexpr int U = 16;
   cplx<double> s = mk<double>(0, 0);
   for (int b0 = threadIdx.x; b0 < n; b0 += U * kRedThreads) {
     cplx<double> v[U];

@@ -287,3 +287,32 @@ def test_vcycle_graph_replay_matches_eager():
         # the default mode launches this fused cycle eagerly
         S.set_graphs("auto")
         assert torch.equal(S.vcycle(v), ref), dt
+
+
+def test_sampled_timing_and_launch_mode_arguments():
+    """Kernel timing of one launch in `every` (the 1st, (every+1)-th, ...):
+    ten cycles timed one in four give three timed fine-level down launches,
+    all with the same algorithmic bytes; launch modes outside
+    never/always/auto and negative timing arguments are rejected."""
+    import torch
+    import paper_1012_4307_amd as E
+    w = W.coulomb(E=2.0, n=257)
+    S = gpu_for(w, "f32")
+    v = to_gpu(w.rhs[0]).to(torch.complex64)
+    S.timing("down", True, every=4)
+    for _ in range(10):
+        S.vcycle_native(v)
+    n, ms, by = S.timing_read("down")
+    S.timing("down", False)
+    assert n == 3 and ms > 0, (n, ms)
+    assert by == pytest.approx(3 * 257 * 257 * 4 * 5.5)
+    S.timing("down", True)
+    for _ in range(5):
+        S.vcycle_native(v)
+    n, _, _ = S.timing_read("down")
+    S.timing("down", False)
+    assert n == 5
+    assert E.lib().ecs_set_graphs(S._h, 3) == -1
+    assert E.lib().ecs_timing_enable(S._h, 7, -1) == -1
+    with pytest.raises(ValueError):
+        S.timing("down", True, every=0)
