@@ -73,8 +73,8 @@ def batched(args):
     tuned = {}
     for q, d in enumerate(descs):
         w = W.batch_inputs(d)
-        S = _solver(w, "f64", kr, streams[q % len(streams)])
-        key = (d["n"], "f64")
+        S = _solver(w, args.batch_cycle, kr, streams[q % len(streams)])
+        key = (d["n"], args.batch_cycle)
         if key not in tuned:
             tuned[key] = autotune(S)
         else:
@@ -104,7 +104,7 @@ def batched(args):
                sequential_solves_per_s=round(seq_total / seq_secs, 3), sequential_sample_rhs=seq_total,
                speedup_vs_sequential=round((total / secs) / (seq_total / seq_secs), 3),
                tuning={f"{k[0]}_{k[1]}": v for k, v in tuned.items()}, by_size=by_size,
-               dtype="f64", data="synthetic"))
+               dtype="f64" if args.batch_cycle == "f64" else "f32 cycle + f64 Krylov", data="synthetic"))
 
 
 def adjoint(args):
