@@ -69,11 +69,12 @@ def level_nodes(n, nlev, dim=2):
 
 def vcycle_algorithmic_bytes(n, nlev, real_bytes):
     """Minimum HBM traffic of one V(1,1) red-black cycle from a zero guess, per
-    level l < coarsest: down pass reads b (2 reals), k^2 (1) and writes u (2)
-    and the coarse residual (2/4); up pass reads u (2), the coarse correction
-    (2/4), b (2), k^2 (1) and writes u (2): 13 reals per node."""
+    level l < coarsest: down pass reads b (2 reals), k^2 (1) and writes the
+    coarse residual (2/4); up pass reads the coarse correction (2/4), b (2),
+    k^2 (1) and writes u (2): 9 reals per node.  The pre-smoothed iterate
+    need not travel: the up pass can recompute it from b."""
     nodes = level_nodes(n, nlev)
-    return sum(nodes[:-1]) * 13 * real_bytes
+    return sum(nodes[:-1]) * 9 * real_bytes
 
 
 def main():
@@ -149,7 +150,6 @@ def main():
                                  rel_residual=st["rel_residual"])
             del S
 
-    # V-cycle bandwidth (algorithmic bytes of a V(1,1) RB cycle / cycle time)
     # V-cycle rate (algorithmic bytes of a V(1,1) RB cycle / cycle time), on
     # vectors in the cycle's dtype: warm (back to back) and cold (a 512 MiB
     # write between cycles evicts the 256 MB last-level cache)
@@ -260,7 +260,7 @@ def main():
                    "fp32_ms": round(vc32_ms, 4), "fp32_algo_gbs": round(vc32_gbs, 1),
                    "fp64_cold_ms": round(vc64_cold, 4), "fp64_cold_algo_gbs": round(vc64_cold_gbs, 1),
                    "fp32_cold_ms": round(vc32_cold, 4), "fp32_cold_algo_gbs": round(vc32_cold_gbs, 1),
-                   "bytes_model": "13 reals/node/level above the coarsest",
+                   "bytes_model": "9 reals/node/level above the coarsest",
                    "vectors": "in the cycle's dtype (no conversion passes)"},
         "copy_probe_gbs": round(copy_gbs, 1),
         "kernels_in_timed_region": kernels,

@@ -171,15 +171,16 @@ void launch_prolong_jacobi(const Grid<R> &fine, const Grid<R> &coarse, const cpl
 template <typename R>
 void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, int n1, int n2, const cplx<R> *b,
                          cplx<R> *x, hipStream_t s);
-// fused V(1,1) red-black kernels (2D): zero-guess pre-sweep + residual + FW,
-// and prolongation + correction + post-sweep (out of place)
+// fused V(1,1) red-black kernels (2D): zero-guess pre-sweep + residual + FW
+// (the pre-smoothed iterate is not stored), and the pre-sweep recomputed from
+// b + prolongation + correction + post-sweep into u_out
 // (rows: tile height, see ecs_tuning)
 template <typename R>
-void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *u, cplx<R> *rc, R omega,
-                    int rows, hipStream_t s);
+void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *rc, R omega, int rows,
+                    hipStream_t s);
 template <typename R>
-void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
-                  const cplx<R> *ec, cplx<R> *u_out, R omega, int rows, hipStream_t s);
+void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *ec, cplx<R> *u_out,
+                  R omega, int rows, hipStream_t s);
 // two levels of the fused cycle in one kernel (small levels): down over
 // levels l, l+1 (writes u_l, u_{l+1}, b_{l+1} and b_{l+2}); up over levels
 // l+1, l (reads the correction u_{l+2}, writes u_l)

@@ -851,10 +851,9 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
       l += 2;
       continue;
     }
-    // reads b, k^2; writes u and the coarse residual
-    TimedScope ts(C, l == 0 ? kTDown : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 5.5);
-    launch_down_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.b, om, small(l) ? 2 : T.down_rows,
-                      C->stream);
+    // reads b, k^2; writes the coarse residual (3.5 reals per node)
+    TimedScope ts(C, l == 0 ? kTDown : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 3.5);
+    launch_down_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, Dc.b, om, small(l) ? 2 : T.down_rows, C->stream);
     l++;
   }
   if (lt == lc) {
@@ -903,10 +902,9 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
     DevLevel<R> &Dc = dev_level<R>(C, l + 1);
     const cplx<R> *b = l == 0 ? b0 : D.b;
     cplx<R> *out = l == 0 ? u0 : D.u;
-    // reads u, the coarse correction, b, k^2; writes u
-    TimedScope ts(C, l == 0 ? kTUp : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 7.5);
-    launch_up_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, D.t, Dc.u, out, om, small(l) ? 4 : T.up_rows,
-                    C->stream);
+    // reads the coarse correction, b, k^2; writes u (5.5 reals per node)
+    TimedScope ts(C, l == 0 ? kTUp : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 5.5);
+    launch_up_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, Dc.u, out, om, small(l) ? 4 : T.up_rows, C->stream);
     l--;
   }
 }

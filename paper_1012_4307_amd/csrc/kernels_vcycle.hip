@@ -83,8 +83,7 @@ __device__ __forceinline__ cplx<R> sel(bool c, cplx<R> a, cplx<R> b) {
 // one further still.
 template <typename R, int CY>
 __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
-                                                cplx<R> *__restrict__ u_out, cplx<R> *__restrict__ rc, R omega,
-                                                int tiles_x, int tiles) {
+                                                cplx<R> *__restrict__ rc, R omega, int tiles_x, int tiles) {
   constexpr int CX = 61;
   constexpr int WX = 2 * CX + 5;          // 127 staged columns
   constexpr int WY = 2 * CY + 5;
@@ -175,18 +174,12 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
   __syncthreads();
   // red residual (1 - w) b + o from the relaxed black neighbours: own black
   // and the black of pair lane - side (red in column a: left = black of
-  // lane - 1, right = own black); zero off the interior.  Residuals to LDS;
-  // owned iterates to global memory.
+  // lane - 1, right = own black); zero off the interior.  Residuals to LDS.
+  // The relaxed iterate itself is not stored: the up kernel recomputes it.
   const int qs = lane - side;
   const bool qin = qs >= 0 && qs < 64;
   const int pq = qin ? qs : lane;
   const cplx<R> wRo = ared ? xpR : xmR, wRn = ared ? xmR : xpR;
-  // stores: owned rows and owned columns only
-  const int xr = iR - gx0, xb = iBk - gx0;
-  const uint32_t osR = col_off<cplx<R>>(xr >= 3 && xr < 3 + 2 * CX && iR < n0, iR);
-  const uint32_t osB = col_off<cplx<R>>(xb >= 3 && xb < 3 + 2 * CX && iBk < n0, iBk);
-  const int jo = gy0 + 3;
-  const __amdgpu_buffer_rsrc_t ru = rows_rsrc(u_out, jo, min(jo + 2 * CY, n1), n0);
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
@@ -197,10 +190,6 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
     if (yin && inR && qin && ly >= 1 && ly <= WY - 2)
       resR = om1 * bR[r] +
              (wRo * sB[ly][lane] + wRn * sB[ly][pq] + cym[r] * sB[ly - 1][lane] + cyp[r] * sB[ly + 1][lane]);
-    // owned nodes to global memory (the others fall outside the window)
-    const uint32_t qo = row_off<cplx<R>>(j - jo, n0);
-    st_c(ru, osR + qo, sR[ly][lane]);
-    st_c(ru, osB + qo, tB[r]);
     rR[ly][lane] = resR;
     rB[ly][lane] = (yin && inBk) ? resB[r] : zero_c<R>();
   }
@@ -225,31 +214,35 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
 }
 
 // ------------------------------------------------------------------- up
-// Block tile: TX = 124 x TY fine nodes at (x0, y0), both even; staged fine
-// region: columns x0 - 2 + [0, 128) (pairs 1..62 owned, pairs 0 and 63 halo),
-// rows y0 - 2 + [0, TY + 4) (halo 2: red nodes one outside the tile are
-// relaxed and read black neighbours two outside), and the coarse correction
-// under it.  Column a = x0 - 2 + 2 lane is even, so both columns of pair l
-// interpolate from coarse column x0/2 - 1 + l (= staged coarse column l).
+// Block tile: TX = 120 x TY fine nodes at (x0, y0), both even.  The
+// pre-smoothed iterate t of the down pass is not stored: it is recomputed
+// here from b (the zero-guess red relaxation, then the black one), which
+// costs one phase and a wider halo but saves writing and re-reading a fine
+// vector.  Staged fine region: columns x0 - 4 + [0, 128) (pairs 2..61 owned),
+// rows y0 - 3 + [0, TY + 6): red t on ring 3 feeds black t on ring 2, the red
+// relaxation on ring 1 reads black values on ring 2, and the black relaxation
+// on the tile reads red values on ring 1.  Column a = x0 - 4 + 2 lane is even,
+// so both columns of pair l interpolate from coarse column x0/2 - 2 + l
+// (= staged coarse column l).
 template <typename R, int TY>
 __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
-                                              const cplx<R> *__restrict__ u_in, const cplx<R> *__restrict__ ec,
-                                              cplx<R> *__restrict__ u_out, R omega, int tiles_x, int tiles) {
-  constexpr int TX = 124;
-  constexpr int WY = TY + 4;
+                                              const cplx<R> *__restrict__ ec, cplx<R> *__restrict__ u_out, R omega,
+                                              int tiles_x, int tiles) {
+  constexpr int TX = 120;
+  constexpr int WY = TY + 6;
   constexpr int RPW = (WY + 3) / 4;
-  constexpr int CWX = TX / 2 + 3, CWY = TY / 2 + 3;
+  constexpr int CWX = TX / 2 + 5, CWY = TY / 2 + 3;
   __shared__ cplx<R> sR[WY][64], sB[WY][64];
   __shared__ cplx<R> se[CWY][CWX];
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
   const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
-  const int gx0 = x0 - 2, gy0 = y0 - 2;
-  const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1;  // coarse staging origin
+  const int gx0 = x0 - 4, gy0 = y0 - 3;
+  const int cx0 = x0 / 2 - 2, cy0 = y0 / 2 - 1;  // coarse staging origin
   const int n0 = f.n0, n1 = f.n1;
   const R om1 = R(1) - omega;
-  const int ia = gx0 + 2 * lane, ib = ia + 1;     // ia even
+  const int ia = gx0 + 2 * lane, ib = ia + 1;  // ia even
   const bool ina = ia >= 1 && ia <= n0 - 2;
   const bool inb = ib >= 1 && ib <= n0 - 2;
   // column a (even) is red in this wave's rows iff j is even
@@ -262,8 +255,7 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
   // interior rows of the staged window through buffer resources: halo and
   // boundary nodes read as 0
   const int jl = min(max(gy0, 1), n1 - 1), jh = min(max(gy0 + WY, 1), n1 - 1);
-  const __amdgpu_buffer_rsrc_t ru = rows_rsrc(u_in, jl, jh, n0), rb = rows_rsrc(b, jl, jh, n0),
-                               rk = rows_rsrc(f.k2, jl, jh, n0);
+  const __amdgpu_buffer_rsrc_t rb = rows_rsrc(b, jl, jh, n0), rk = rows_rsrc(f.k2, jl, jh, n0);
   const uint32_t obR = col_off<cplx<R>>(inR, iR), obB = col_off<cplx<R>>(inBk, iBk);
   const uint32_t okR = col_off<R>(inR, iR), okB = col_off<R>(inBk, iBk);
 
@@ -278,8 +270,6 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
     cym[r] = yin ? f.cm1[jc] : zero_c<R>();
     cyp[r] = yin ? f.cp1[jc] : zero_c<R>();
     const uint32_t qb = row_off<cplx<R>>(j - jl, n0), qk = row_off<R>(j - jl, n0);
-    vR[r] = ld_c(ru, obR + qb, cplx<R>());
-    vB[r] = ld_c(ru, obB + qb, cplx<R>());
     bR[r] = ld_c(rb, obR + qb, cplx<R>());
     bB[r] = ld_c(rb, obB + qb, cplx<R>());
     kR[r] = ld_r(rk, okR + qk, R());
@@ -290,17 +280,44 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
     const int I = cx0 + cx, J = cy0 + cy;
     se[cy][cx] = (I >= 0 && I < c.n0 && J >= 0 && J < c.n1) ? ec[(int64_t)J * c.n0 + I] : zero_c<R>();
   }
-  __syncthreads();
-  // v = u + P ec (bilinear in index space) and the inverse diagonals.  Column
-  // a is even: its correction is se[cj][lane] (j even) or the mean over
-  // rows cj, cj + 1 (j odd); column b (odd) adds the neighbour column.
+  // inverse diagonals and the down pass's zero-guess red relaxation
+  // t = w b / D (0 off the interior)
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     if (ly >= WY) break;
     const int j = gy0 + ly;
     const bool yin = j >= 1 && j <= n1 - 2;
-    dR[r] = dB[r] = zero_c<R>();
+    dR[r] = (yin && inR) ? inv_cycle(xmR + xpR + cym[r] + cyp[r] + (kR[r] * f.beta + f.c)) : zero_c<R>();
+    dB[r] = (yin && inBk) ? inv_cycle(xmB + xpB + cym[r] + cyp[r] + (kB[r] * f.beta + f.c)) : zero_c<R>();
+    vR[r] = omega * (bR[r] * dR[r]);
+    sR[ly][lane] = vR[r];
+  }
+  __syncthreads();
+  // the down pass's black relaxation t = w (b + o) / D on rings 2 and
+  // closer (its red neighbours: own pair, the pair on the other side, own
+  // pair one row up and down), then v = t + P ec (bilinear in index space;
+  // column a is even: its correction is se[cj][lane] (j even) or the mean
+  // over rows cj, cj + 1 (j odd); column b adds the neighbour column).
+  // Black values to LDS; red ones stay in registers.
+  const int side = ared ? 1 : -1;  // pair holding a node's neighbour of the other colour across the pair
+  const int ps = lane + side;
+  const bool pin = ps >= 0 && ps < 64;
+  const int psc = pin ? ps : lane;
+  const cplx<R> wBo = ared ? xmB : xpB, wBn = ared ? xpB : xmB;  // black node: own-pair / other-pair weights
+#pragma unroll
+  for (int r = 0; r < RPW; r++) {
+    const int ly = wv + 4 * r;
+    vB[r] = zero_c<R>();
+    if (ly >= WY) break;
+    if (ly < 1 || ly > WY - 2) continue;  // ring 3: red t only
+    const int j = gy0 + ly;
+    const bool yin = j >= 1 && j <= n1 - 2;
+    if (pin) {
+      const cplx<R> tb =
+          bB[r] + (wBo * sR[ly][lane] + wBn * sR[ly][psc] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane]);
+      vB[r] = omega * (tb * dB[r]);
+    }
     if (yin) {
       const int cj = (j >> 1) - cy0;
       cplx<R> pa, pb;
@@ -311,23 +328,15 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
         pa = R(0.5) * (se[cj][lane] + se[cj + 1][lane]);
         pb = R(0.25) * (se[cj][lane] + se[cj][lane + 1] + se[cj + 1][lane] + se[cj + 1][lane + 1]);
       }
-      if (inR) {
-        vR[r] = vR[r] + (ared ? pa : pb);
-        dR[r] = inv_cycle(xmR + xpR + cym[r] + cyp[r] + (kR[r] * f.beta + f.c));
-      }
-      if (inBk) {
-        vB[r] = vB[r] + (ared ? pb : pa);
-        dB[r] = inv_cycle(xmB + xpB + cym[r] + cyp[r] + (kB[r] * f.beta + f.c));
-      }
+      if (inR) vR[r] = vR[r] + (ared ? pa : pb);
+      if (inBk) vB[r] = vB[r] + (ared ? pb : pa);
     }
-    sR[ly][lane] = vR[r];
     sB[ly][lane] = vB[r];
   }
   __syncthreads();
   // red relaxation on the tile plus a one-node ring.  The red node's black
   // neighbours: own black and the black of pair lane - side in its row (red
   // in column a: left = black of lane - 1), own black one row up and down.
-  const int side = ared ? 1 : -1;
   const int qs = lane - side;
   const bool qin = qs >= 0 && qs < 64;
   const int pq = qin ? qs : lane;
@@ -337,17 +346,15 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
     const int ly = wv + 4 * r;
     if (ly >= WY) break;
     const int j = gy0 + ly;
-    if (ly < 1 || ly > WY - 2 || !qin || !inR || j < 1 || j > n1 - 2) continue;
+    if (ly < 2 || ly > WY - 3 || !qin || !inR || j < 1 || j > n1 - 2) continue;
     const cplx<R> o = wRo * sB[ly][lane] + wRn * sB[ly][pq] + cym[r] * sB[ly - 1][lane] + cyp[r] * sB[ly + 1][lane];
     vR[r] = om1 * vR[r] + omega * ((bR[r] + o) * dR[r]);
     sR[ly][lane] = vR[r];
   }
   __syncthreads();
-  // black relaxation on the owned tile (pairs 1..62, rows 2..TY+1); write
+  // black relaxation on the owned tile (pairs 2..61, rows 3..TY+2); write
   // both nodes of every owned pair
-  const int ps = lane + side;
-  const bool own_x = lane >= 1 && lane <= 62;
-  const cplx<R> wBo = ared ? xmB : xpB, wBn = ared ? xpB : xmB;
+  const bool own_x = lane >= 2 && lane <= 61;
   const uint32_t osR = col_off<cplx<R>>(own_x && iR < n0, iR), osB = col_off<cplx<R>>(own_x && iBk < n0, iBk);
   const __amdgpu_buffer_rsrc_t ro = rows_rsrc(u_out, y0, min(y0 + TY, n1), n0);
 #pragma unroll
@@ -355,10 +362,11 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
     const int ly = wv + 4 * r;
     if (ly >= WY) break;
     const int j = gy0 + ly;
-    if (ly < 2 || ly >= TY + 2 || j >= n1) continue;
+    if (ly < 3 || ly >= TY + 3 || j >= n1) continue;
     cplx<R> outB = vB[r];
     if (own_x && inBk && j >= 1 && j <= n1 - 2) {
-      const cplx<R> o = wBo * sR[ly][lane] + wBn * sR[ly][ps] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane];
+      const cplx<R> o =
+          wBo * sR[ly][lane] + wBn * sR[ly][psc] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane];
       outB = om1 * outB + omega * ((bB[r] + o) * dB[r]);
     }
     const uint32_t qo = row_off<cplx<R>>(j - y0, n0);
@@ -631,41 +639,41 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
 // {2, ..., 6, 8, 16} (16 only in FP32, whose tile fits the LDS), fine rows
 // per up block in {4, 8, 12, 16, 32}.
 template <typename R>
-void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *u, cplx<R> *rc, R omega,
-                    int rows, hipStream_t s) {
+void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *rc, R omega, int rows,
+                    hipStream_t s) {
   constexpr int CX = 61;
   const int tx = (coarse.n0 + CX - 1) / CX;
   const int tiles = tx * ((coarse.n1 + rows - 1) / rows);
   const dim3 grid(xcd_padded(tiles)), block(NT);
   switch (rows) {
-    case 2: launch_k((k_down_rb<R, 2>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
-    case 3: launch_k((k_down_rb<R, 3>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
-    case 4: launch_k((k_down_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
-    case 5: launch_k((k_down_rb<R, 5>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
-    case 6: launch_k((k_down_rb<R, 6>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
+    case 2: launch_k((k_down_rb<R, 2>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
+    case 3: launch_k((k_down_rb<R, 3>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
+    case 4: launch_k((k_down_rb<R, 4>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
+    case 5: launch_k((k_down_rb<R, 5>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
+    case 6: launch_k((k_down_rb<R, 6>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
     case 16:
       if constexpr (sizeof(R) == 4) {
-        launch_k((k_down_rb<R, 16>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles);
+        launch_k((k_down_rb<R, 16>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles);
         break;
       }
       [[fallthrough]];
-    default: launch_k((k_down_rb<R, 8>), grid, block, 0, s, fine, coarse, b, u, rc, omega, tx, tiles); break;
+    default: launch_k((k_down_rb<R, 8>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
   }
 }
 
 template <typename R>
-void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *u_in,
-                  const cplx<R> *ec, cplx<R> *u_out, R omega, int rows, hipStream_t s) {
-  constexpr int TX = 124;
+void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *ec, cplx<R> *u_out,
+                  R omega, int rows, hipStream_t s) {
+  constexpr int TX = 120;
   const int tx = (fine.n0 + TX - 1) / TX;
   const int tiles = tx * ((fine.n1 + rows - 1) / rows);
   const dim3 grid(xcd_padded(tiles)), block(NT);
   switch (rows) {
-    case 4: launch_k((k_up_rb<R, 4>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
-    case 8: launch_k((k_up_rb<R, 8>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
-    case 12: launch_k((k_up_rb<R, 12>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
-    case 32: launch_k((k_up_rb<R, 32>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
-    default: launch_k((k_up_rb<R, 16>), grid, block, 0, s, fine, coarse, b, u_in, ec, u_out, omega, tx, tiles); break;
+    case 4: launch_k((k_up_rb<R, 4>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
+    case 8: launch_k((k_up_rb<R, 8>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
+    case 12: launch_k((k_up_rb<R, 12>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
+    case 32: launch_k((k_up_rb<R, 32>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
+    default: launch_k((k_up_rb<R, 16>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
   }
 }
 
@@ -675,15 +683,14 @@ void launch_tail(const TailArgs<R> &a, hipStream_t s) {
 }
 
 template void launch_down_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *, cplx<double> *,
-                                     cplx<double> *, double, int, hipStream_t);
+                                     double, int, hipStream_t);
 template void launch_down_rb<float>(const Grid<float> &, const Grid<float> &, const cplx<float> *, cplx<float> *,
-                                    cplx<float> *, float, int, hipStream_t);
+                                    float, int, hipStream_t);
 template void launch_up_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *,
-                                   const cplx<double> *, const cplx<double> *, cplx<double> *, double, int,
-                                   hipStream_t);
+                                   const cplx<double> *, cplx<double> *, double, int, hipStream_t);
 template void launch_tail<double>(const TailArgs<double> &, hipStream_t);
 template void launch_tail<float>(const TailArgs<float> &, hipStream_t);
 template void launch_up_rb<float>(const Grid<float> &, const Grid<float> &, const cplx<float> *, const cplx<float> *,
-                                  const cplx<float> *, cplx<float> *, float, int, hipStream_t);
+                                  cplx<float> *, float, int, hipStream_t);
 
 }  // namespace ecs

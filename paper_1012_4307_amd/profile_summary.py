@@ -132,8 +132,11 @@ def main():
         stats(a.trace, a.out, a.cmd)
     else:
         nodes = a.n * a.n
+        # FP32 complex: down reads b, k^2 and writes the coarse quarter (3.5
+        # reals = 14 B per fine node); up reads the coarse quarter, b, k^2 and
+        # writes u (5.5 reals = 22 B)
         traffic(a.fetch, a.write, a.out, a.json, a.cmd_fetch, a.cmd_write,
-                algo=dict(down=nodes * 22, up=nodes * 30))
+                algo=dict(down=nodes * 14, up=nodes * 22))
 
 
 if __name__ == "__main__":

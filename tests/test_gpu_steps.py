@@ -305,7 +305,7 @@ def test_sampled_timing_and_launch_mode_arguments():
     n, ms, by = S.timing_read("down")
     S.timing("down", False)
     assert n == 3 and ms > 0, (n, ms)
-    assert by == pytest.approx(3 * 257 * 257 * 4 * 5.5)
+    assert by == pytest.approx(3 * 257 * 257 * 4 * 3.5)  # read b, k^2; write the coarse quarter
     S.timing("down", True)
     for _ in range(5):
         S.vcycle_native(v)
