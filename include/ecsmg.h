@@ -265,7 +265,7 @@ ecs_status ecs_timing_calibrate(ecs_ctx *ctx, int launches);
  *   down_rows   coarse rows per block of the fused pre-smoothing/restriction
  *               kernel on grids above small_grid: 2 to 6, 8 (16 in FP32)
  *   up_rows     fine rows per block of the fused prolongation/post-smoothing
- *               kernel on grids above small_grid: 4, 8, 12, 16 or 32
+ *               kernel on grids above small_grid: 4, 8, 10, 12, 16 or 32
  *   small_grid  grids with at most this many nodes per axis use 2 / 4 rows
  *   tail_nodes  levels with at most this many nodes per axis (3..33) run in
  *               the single-workgroup kernel that ends the cycle

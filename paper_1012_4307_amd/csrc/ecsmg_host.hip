@@ -2172,7 +2172,8 @@ ecs_status ecs_set_tuning(ecs_ctx *C, const ecs_tuning *t) {
   if (!C || !t) return ECS_EINVAL;
   const bool f32 = C->have_prec && C->prec.vcycle_dtype == ECS_F32;
   const bool down_ok = (t->down_rows >= 2 && t->down_rows <= 6) || t->down_rows == 8 || (t->down_rows == 16 && f32);
-  const bool up_ok = t->up_rows == 4 || t->up_rows == 8 || t->up_rows == 12 || t->up_rows == 16 || t->up_rows == 32;
+  const bool up_ok = t->up_rows == 4 || t->up_rows == 8 || t->up_rows == 10 || t->up_rows == 12 || t->up_rows == 16 ||
+                     t->up_rows == 32;
   if (!down_ok || !up_ok) return fail(C, ECS_EINVAL, "unsupported tile height");
   if (t->tail_nodes < 3 || t->tail_nodes > kTailNodes) return fail(C, ECS_EINVAL, "tail_nodes must be in [3, 33]");
   if (t->small_grid < 3) return fail(C, ECS_EINVAL, "small_grid must be >= 3");

@@ -637,7 +637,7 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
 // The tile height of the fused kernels is a launch parameter chosen by the
 // host (autotuned per grid size and dtype): coarse rows per down block in
 // {2, ..., 6, 8, 16} (16 only in FP32, whose tile fits the LDS), fine rows
-// per up block in {4, 8, 12, 16, 32}.
+// per up block in {4, 8, 10, 12, 16, 32}.
 template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *rc, R omega, int rows,
                     hipStream_t s) {
@@ -671,6 +671,7 @@ void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, 
   switch (rows) {
     case 4: launch_k((k_up_rb<R, 4>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
     case 8: launch_k((k_up_rb<R, 8>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
+    case 10: launch_k((k_up_rb<R, 10>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
     case 12: launch_k((k_up_rb<R, 12>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
     case 32: launch_k((k_up_rb<R, 32>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
     default: launch_k((k_up_rb<R, 16>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;

@@ -179,7 +179,7 @@ def test_vcycle_tile_heights(dt):
     ref = P.mg_apply(v)
     downs = (2, 3, 4, 5, 6, 8) + ((16,) if dt == "f32" else ())
     for d in downs:
-        for u in (4, 8, 12, 16, 32):
+        for u in (4, 8, 10, 12, 16, 32):
             S.set_tuning(down_rows=d, up_rows=u, small_grid=3, tail_nodes=33, pair_grid=0)
             assert relerr(to_np(S.vcycle(to_gpu(v))), ref) < CYCLE_TOL[dt], (d, u)
 
