@@ -25,9 +25,13 @@ import re
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-# the sources of the kernels whose counters are recorded (the fused cycle
-# kernels and the device helpers they use)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1012_4307_amd", "csrc", f) for f in ("kernels_vcycle.hip", "ecs_internal.h")]
+# the sources of the kernels whose counters are recorded: the device helpers
+# (ecs_internal.h) and the part of kernels_vcycle.hip that defines the fused
+# down and up kernels and their helpers (everything before the tail section;
+# the tail kernel and the host launchers follow it)
+CSRC = os.path.join(ROOT, "paper_1012_4307_amd", "csrc")
+KERNEL_SOURCES = [os.path.join(CSRC, "ecs_internal.h"), os.path.join(CSRC, "kernels_vcycle.hip")]
+TAIL_MARKER = b"\n// ----------------------------------------------------------------- tail\n"
 COPY_BYTES = 512 << 20   # the copy probe moves 512 MiB each way
 
 
@@ -35,7 +39,13 @@ def sources_digest() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(f, "rb") as fh:
-            h.update(fh.read())
+            text = fh.read()
+        if f.endswith("kernels_vcycle.hip"):
+            cut = text.find(TAIL_MARKER)
+            if cut < 0:
+                raise SystemExit("kernels_vcycle.hip: tail section marker not found")
+            text = text[:cut]
+        h.update(text)
     return h.hexdigest()[:16]
 
 
