@@ -4,9 +4,9 @@
 // interpolation).  Each level is visited by exactly two kernels:
 //
 //   down: u = S_rb(0; b) (zero-guess sweep), rc = FW(b - M u)
-//         reads b, k^2 once, writes u and the coarse residual
-//   up:   v = u + P ec, u_out = S_rb(v; b) (post-sweep, out of place)
-//         reads u, ec, b, k^2 once, writes u_out
+//         reads b, k^2 once, writes the coarse residual (u is not stored)
+//   up:   u = S_rb(0; b) again, v = u + P ec, u_out = S_rb(v; b) (post-sweep,
+//         out of place); reads ec, b, k^2 once, writes u_out
 //
 // against four (pre-sweep, residual+FW, prolongation, post-sweep) in the
 // generic path whose sweeps make two passes over the grid.  A block owns a tile
