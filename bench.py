@@ -54,6 +54,7 @@ def parse():
                     choices=["mixed2049", "batched", "adjoint", "cube", "coulomb513", "small65", "paper_mp", "coupled"],
                     help="mixed2049 (default): the headline line; the others report the secondary workloads")
     ap.add_argument("--batch-count", type=int, default=96)
+    ap.add_argument("--batch-streams", type=int, default=32, help="HIP streams the batched systems are spread over")
     ap.add_argument("--batch-cycle", choices=("f64", "f32"), default="f64",
                     help="dtype of the multigrid cycle of the batched systems (the Krylov vectors stay FP64)")
     return ap.parse_args()

@@ -68,7 +68,7 @@ def batched(args):
     from .autotune import autotune
     descs = W.batch_systems(count=args.batch_count)
     kr = Krylov(method="bicgstab", rtol=1e-8, maxit=20000)
-    streams = [torch.cuda.Stream() for _ in range(8)]
+    streams = [torch.cuda.Stream() for _ in range(max(1, args.batch_streams))]
     solvers, rhs = [], []
     tuned = {}
     for q, d in enumerate(descs):
