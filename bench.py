@@ -112,7 +112,7 @@ def main():
     S64 = make("f64", "fgmres", 0)
     nlev = S64.nlev
 
-    timed_classes = ("down", "up", "mdot", "mupdate", "apply_A")
+    timed_classes = ("down", "up", "down_p", "down_s", "mdot", "mupdate", "apply_A")
 
     def timed_solves(S, k, timers=()):
         for cls in timers:

@@ -33,7 +33,7 @@ KRYLOV = {"gmres": 0, "fgmres": 1, "bicgstab": 2}
 OP = {"A": 0, "AT": 1, "M": 2}
 STATUS = {0: "ok", 1: "not_converged", -1: "einval", -2: "enomem", -3: "edevice", -4: "ebreakdown", -5: "estate"}
 TIMER = {"smooth": 0, "mdot": 1, "apply_A": 2, "coarse": 3, "mupdate": 4, "restrict": 5, "prolong": 6, "down": 7,
-         "up": 8, "empty": 9}
+         "up": 8, "empty": 9, "down_p": 10, "down_s": 11}
 
 
 class EcsError(RuntimeError):
@@ -57,7 +57,7 @@ class SolveDesc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("down_rows", ctypes.c_int), ("up_rows", ctypes.c_int), ("small_grid", ctypes.c_int),
-                ("tail_nodes", ctypes.c_int), ("pair_grid", ctypes.c_int)]
+                ("tail_nodes", ctypes.c_int), ("pair_grid", ctypes.c_int), ("fuse_updates", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -412,9 +412,11 @@ class Solver:
         self._check(lib().ecs_coarse_solve(self._h, _ptr(b), _ptr(x)))
         return x
 
-    def set_tuning(self, down_rows=4, up_rows=8, small_grid=513, tail_nodes=33, pair_grid=129):
-        """Launch schedule of the fused V(1,1) cycle (performance only)."""
-        t = Tuning(down_rows, up_rows, small_grid, tail_nodes, pair_grid)
+    def set_tuning(self, down_rows=4, up_rows=8, small_grid=513, tail_nodes=33, pair_grid=129, fuse_updates=1):
+        """Launch schedule of the fused V(1,1) cycle, and whether the nested
+        FP32 Bi-CGSTAB forms its updates inside the finest down kernel
+        (performance only)."""
+        t = Tuning(down_rows, up_rows, small_grid, tail_nodes, pair_grid, int(fuse_updates))
         self._check(lib().ecs_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self):

@@ -178,6 +178,24 @@ void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, 
 template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *rc, R omega, int rows,
                     hipStream_t s);
+// The down kernel can form its right-hand side while staging it, from the
+// vectors of a Bi-CGSTAB step (FP32 only): kDownSrcP b = r + beta (p - omega v),
+// kDownSrcS b = r - alpha v (the step's scalars read from S), each with the
+// expression of the separate update kernels, so the values are the same.  The
+// formed vector is stored at every node of the grid (out must not alias r, p
+// or v: neighbouring blocks read them as their halo).
+struct BicgScalars;
+enum { kDownSrcB = 0, kDownSrcP = 1, kDownSrcS = 2 };
+template <typename R>
+struct DownSrc {
+  int mode;                    // kDownSrcP or kDownSrcS
+  const cplx<R> *r, *p, *v;    // p unused for kDownSrcS
+  cplx<R> *out;
+  const BicgScalars *S;
+};
+template <typename R>
+void launch_down_rb_src(const Grid<R> &fine, const Grid<R> &coarse, const DownSrc<R> &src, cplx<R> *rc, R omega,
+                        int rows, hipStream_t s);
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *ec, cplx<R> *u_out,
                   R omega, int rows, hipStream_t s);

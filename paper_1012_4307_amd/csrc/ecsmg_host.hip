@@ -58,7 +58,7 @@ struct Timer {
 
 // timing classes (see ecs_timing_enable in ecsmg.h)
 enum { kTSmooth = 0, kTMdot = 1, kTApply = 2, kTCoarse = 3, kTMupdate = 4, kTRestrict = 5, kTProlong = 6,
-       kTDown = 7, kTUp = 8, kTEmpty = 9, kTClasses = 10 };
+       kTDown = 7, kTUp = 8, kTEmpty = 9, kTDownP = 10, kTDownS = 11, kTClasses = 12 };
 
 // bump allocator over the caller's workspace (256 B alignment); with a null
 // base it only measures
@@ -128,7 +128,7 @@ struct ecs_ctx {
   int graph_mode = ECS_GRAPHS_AUTO;
 
   // launch schedule of the fused V(1,1) cycle (autotuned per grid and dtype)
-  ecs_tuning tune{4, 8, 513, 33, 129};
+  ecs_tuning tune{4, 8, 513, 33, 129, 1};
 
   // coarse end of the general cycle in one workgroup (2D): packed weights and
   // inverse diagonals of the levels that may form it (levels sfirst .. coarsest,
@@ -301,6 +301,7 @@ struct KrylovBufs {
   void *ph = nullptr, *sh = nullptr;
   cplx<float> *fr = nullptr, *frh = nullptr, *fp = nullptr, *fv = nullptr, *fs = nullptr, *ft = nullptr,
               *fph = nullptr, *fsh = nullptr;
+  cplx<float> *fp2 = nullptr;  // second p buffer: the fused update writes p beside the old one
   cplx<double> *a1 = nullptr, *a2 = nullptr;  // adjoint scaling buffers
   cplx<double> *bz = nullptr;                 // right-hand side with its boundary entries zeroed
   int64_t ld = 0;
@@ -339,6 +340,7 @@ size_t plan_krylov(const ecs_ctx *C, const ecs_solve_desc *d, char *base, Krylov
       K->ft = cv.take<cplx<float>>(n);
       K->fph = cv.take<cplx<float>>(n);
       K->fsh = cv.take<cplx<float>>(n);
+      K->fp2 = cv.take<cplx<float>>(n);
     }
   }
   return cv.off;
@@ -816,11 +818,18 @@ bool fused_vcycle(const ecs_ctx *C) {
          P.gamma_c == 1 && C->nlev > 1;
 }
 
-template <typename R>
-void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
+// Which kernel runs each level of the fused cycle: levels from lt on run in
+// the single-workgroup tail; above it, pair_start[l] marks levels l, l+1 run
+// by one two-level kernel; every other level has its own down and up kernel.
+struct FusedPlan {
+  int lt;
+  bool pair_start[kMaxLev + 1];
+};
+
+FusedPlan fused_plan(const ecs_ctx *C) {
   const int lc = C->nlev - 1;
-  const R om = (R)C->prec.omega;
   const ecs_tuning &T = C->tune;
+  FusedPlan P{};
   // first level handled by the tail: the coarsest levels that are small
   int lt = lc;
   int64_t tail_nn = C->hl[lc].nn;
@@ -829,19 +838,51 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
     lt--;
     tail_nn += C->hl[lt].nn;
   }
-  auto small = [&](int l) { return C->hl[l].n[0] <= T.small_grid && C->hl[l].n[1] <= T.small_grid; };
+  P.lt = lt;
   // the levels above the tail with at most pair_grid nodes per axis run two
-  // per kernel, pairs counted from the tail up; pair_start[l]: levels l, l+1
-  bool pair_start[kMaxLev + 1] = {};
-  {
-    int ls = lt;
-    while (ls > 0 && C->hl[ls - 1].n[0] <= T.pair_grid && C->hl[ls - 1].n[1] <= T.pair_grid) ls--;
-    for (int l = lt - 2; l >= ls; l -= 2) pair_start[l] = true;
-  }
+  // per kernel, pairs counted from the tail up
+  int ls = lt;
+  while (ls > 0 && C->hl[ls - 1].n[0] <= T.pair_grid && C->hl[ls - 1].n[1] <= T.pair_grid) ls--;
+  for (int l = lt - 2; l >= ls; l -= 2) P.pair_start[l] = true;
+  return P;
+}
+
+// The inner FP32 Bi-CGSTAB can form each cycle's right-hand side (its p and
+// s updates) inside the finest level's down kernel when that level has one
+// and the cycle is launched eagerly.
+bool fused_updates(const ecs_ctx *C) {
+  if (!C->tune.fuse_updates || !fused_vcycle(C) || C->graph_mode == ECS_GRAPHS_ALWAYS) return false;
+  const FusedPlan P = fused_plan(C);
+  return P.lt > 0 && !P.pair_start[0];
+}
+
+// src (FP32, finest level by its own down kernel): the right-hand side b0 is
+// formed by that kernel from src and stored in b0 == src->out
+template <typename R>
+void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0, const DownSrc<R> *src = nullptr) {
+  const int lc = C->nlev - 1;
+  const R om = (R)C->prec.omega;
+  const ecs_tuning &T = C->tune;
+  const FusedPlan plan = fused_plan(C);
+  const int lt = plan.lt;
+  const bool *pair_start = plan.pair_start;
+  auto small = [&](int l) { return C->hl[l].n[0] <= T.small_grid && C->hl[l].n[1] <= T.small_grid; };
   for (int l = 0; l < lt;) {
     DevLevel<R> &D = dev_level<R>(C, l);
     DevLevel<R> &Dc = dev_level<R>(C, l + 1);
     const cplx<R> *b = l == 0 ? b0 : D.b;
+    if constexpr (sizeof(R) == 4) {
+      if (l == 0 && src) {
+        // reads the vectors b is formed from (r, p, v or r, v) and k^2;
+        // writes b and the coarse residual
+        const bool pm = src->mode == kDownSrcP;
+        TimedScope ts(C, pm ? kTDownP : kTDownS, (double)C->hl[0].nn * sizeof(R) * (pm ? 9.5 : 7.5));
+        launch_down_rb_src<R>(grid_M<R>(C, 0), grid_M<R>(C, 1), *src, Dc.b, om, small(0) ? 2 : T.down_rows,
+                              C->stream);
+        l++;
+        continue;
+      }
+    }
     if (pair_start[l]) {
       // reads b, k^2 of both levels; writes u of both, b of level l+1, the
       // residual restricted to level l+2
@@ -937,7 +978,7 @@ int64_t cycle_launches(const ecs_ctx *C, int l, int gf, int gc, int64_t cap) {
 // Returns false when the caller should launch the cycle eagerly.
 template <typename R>
 bool vcycle_graph(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
-  for (int k : {kTSmooth, kTCoarse, kTRestrict, kTProlong, kTDown, kTUp})
+  for (int k : {kTSmooth, kTCoarse, kTRestrict, kTProlong, kTDown, kTUp, kTDownP, kTDownS})
     if (C->timers[k].on) return false;
   if (C->graph_mode == ECS_GRAPHS_NEVER) return false;
   if (fused_vcycle(C)) {
@@ -1119,12 +1160,27 @@ void inner_bicgstab(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *v, cplx
   launch_zero<float>(K.fv, n, s);
   launch_pairdot<float>(K.fr, K.fr, nullptr, nullptr, 1, n, C->partials, S, kBicgInit, s);
   const Grid<float> gA = grid_A32(C);
+  // fused: the finest down kernel forms p (into the other p buffer: blocks
+  // read the old p around their tiles) and s; the same values either way
+  const bool fuse = fused_updates(C);
+  cplx<float> *p_old = K.fp, *p_new = K.fp2;
   for (int it = 0; it < iters; it++) {
-    launch_bicg_p<float>(K.fp, K.fr, K.fv, n, S, s);
-    vcycle<float>(C, K.fp, K.fph);
+    if (fuse) {
+      const DownSrc<float> sp{kDownSrcP, K.fr, p_old, K.fv, p_new, S};
+      vcycle_fused<float>(C, p_new, K.fph, &sp);
+      std::swap(p_old, p_new);
+    } else {
+      launch_bicg_p<float>(K.fp, K.fr, K.fv, n, S, s);
+      vcycle<float>(C, K.fp, K.fph);
+    }
     launch_apply_dot<float, float>(gA, K.fph, K.fv, K.frh, kBicgAlpha, C->partials, S, s);
-    launch_bicg_s<float>(K.fs, K.fr, K.fv, n, S, s);
-    vcycle<float>(C, K.fs, K.fsh);
+    if (fuse) {
+      const DownSrc<float> ss{kDownSrcS, K.fr, nullptr, K.fv, K.fs, S};
+      vcycle_fused<float>(C, K.fs, K.fsh, &ss);
+    } else {
+      launch_bicg_s<float>(K.fs, K.fr, K.fv, n, S, s);
+      vcycle<float>(C, K.fs, K.fsh);
+    }
     launch_apply_dot<float, float>(gA, K.fsh, K.ft, K.fs, kBicgOmega, C->partials, S, s);
     launch_bicg_xr<float, float>(x, K.fph, K.fsh, K.fr, K.fs, K.ft, K.frh, n, C->partials, S, s);
   }
@@ -2178,6 +2234,7 @@ ecs_status ecs_set_tuning(ecs_ctx *C, const ecs_tuning *t) {
   if (t->tail_nodes < 3 || t->tail_nodes > kTailNodes) return fail(C, ECS_EINVAL, "tail_nodes must be in [3, 33]");
   if (t->small_grid < 3) return fail(C, ECS_EINVAL, "small_grid must be >= 3");
   if (t->pair_grid < 0) return fail(C, ECS_EINVAL, "pair_grid must be >= 0");
+  if (t->fuse_updates != 0 && t->fuse_updates != 1) return fail(C, ECS_EINVAL, "fuse_updates must be 0 or 1");
   C->tune = *t;
   drop_graphs(C);
   return ECS_OK;

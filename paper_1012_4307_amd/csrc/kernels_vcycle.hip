@@ -17,6 +17,7 @@
 // and no grid-wide synchronisation is needed.  Rows are loaded with
 // consecutive lanes on consecutive x (unit stride, interleaved complex).
 #include "ecs_internal.h"
+#include "ecs_krylov.h"
 
 namespace ecs {
 
@@ -81,9 +82,15 @@ __device__ __forceinline__ cplx<R> sel(bool c, cplx<R> a, cplx<R> b) {
 // the tile's coarse nodes reads residuals one node out, a residual reads the
 // relaxed iterate one further out, and a relaxed black node reads red values
 // one further still.
-template <typename R, int CY>
+//
+// SRC selects the right-hand side: kDownSrcB reads b; kDownSrcP and kDownSrcS
+// stage the Bi-CGSTAB vectors it is formed from instead (r, p, v or r, v),
+// form it per staged node and store it at the owned nodes (boundary nodes,
+// read as 0, get 0).
+template <typename R, int CY, int SRC>
 __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
-                                                cplx<R> *__restrict__ rc, R omega, int tiles_x, int tiles) {
+                                                const DownSrc<R> src, cplx<R> *__restrict__ rc, R omega,
+                                                int tiles_x, int tiles) {
   constexpr int CX = 61;
   constexpr int WX = 2 * CX + 5;          // 127 staged columns
   constexpr int WY = 2 * CY + 5;
@@ -120,6 +127,10 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
 
   cplx<R> bR[RPW], bB[RPW], dR[RPW], dB[RPW], cym[RPW], cyp[RPW];
   R kR[RPW], kB[RPW];
+  // the vectors the right-hand side is formed from (SRC != kDownSrcB)
+  const __amdgpu_buffer_rsrc_t rr = rows_rsrc(src.r, jl, jh, n0), rv = rows_rsrc(src.v, jl, jh, n0),
+                               rp = rows_rsrc(SRC == kDownSrcP ? src.p : src.r, jl, jh, n0);
+  cplx<R> xR[RPW], xB[RPW], vR[RPW], vB[RPW], pR[RPW], pB[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
@@ -129,10 +140,51 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
     cym[r] = yin ? f.cm1[jc] : zero_c<R>();
     cyp[r] = yin ? f.cp1[jc] : zero_c<R>();
     const uint32_t qb = row_off<cplx<R>>(j - jl, n0), qk = row_off<R>(j - jl, n0);
-    bR[r] = ld_c(rb, obR + qb, cplx<R>());
-    bB[r] = ld_c(rb, obB + qb, cplx<R>());
+    if constexpr (SRC == kDownSrcB) {
+      bR[r] = ld_c(rb, obR + qb, cplx<R>());
+      bB[r] = ld_c(rb, obB + qb, cplx<R>());
+    } else {
+      xR[r] = ld_c(rr, obR + qb, cplx<R>());
+      xB[r] = ld_c(rr, obB + qb, cplx<R>());
+      vR[r] = ld_c(rv, obR + qb, cplx<R>());
+      vB[r] = ld_c(rv, obB + qb, cplx<R>());
+      if constexpr (SRC == kDownSrcP) {
+        pR[r] = ld_c(rp, obR + qb, cplx<R>());
+        pB[r] = ld_c(rp, obB + qb, cplx<R>());
+      }
+    }
     kR[r] = ld_r(rk, okR + qk, R());
     kB[r] = ld_r(rk, okB + qk, R());
+  }
+  if constexpr (SRC != kDownSrcB) {
+    // the same expressions as the separate update kernels
+    if constexpr (SRC == kDownSrcP) {
+      const cplx<R> beta = cvt<R>(src.S->beta), om_s = cvt<R>(src.S->omega);
+#pragma unroll
+      for (int r = 0; r < RPW; r++) {
+        bR[r] = xR[r] + beta * (pR[r] - om_s * vR[r]);
+        bB[r] = xB[r] + beta * (pB[r] - om_s * vB[r]);
+      }
+    } else {
+      const cplx<R> alpha = cvt<R>(src.S->alpha);
+#pragma unroll
+      for (int r = 0; r < RPW; r++) {
+        bR[r] = xR[r] - alpha * vR[r];
+        bB[r] = xB[r] - alpha * vB[r];
+      }
+    }
+    // owned nodes: staged columns [3, 3 + 2 CX), rows [3, 3 + 2 CY)
+    const int ca = 2 * lane;
+    const bool owna = ca >= 3 && ca < 3 + 2 * CX && ia < n0;
+    const bool ownb = ca + 1 >= 3 && ca + 1 < 3 + 2 * CX && ib < n0;
+#pragma unroll
+    for (int r = 0; r < RPW; r++) {
+      const int ly = wv + 4 * r, j = gy0 + ly;
+      if (ly < 3 || ly >= 3 + 2 * CY || j >= n1) continue;
+      cplx<R> *row = src.out + (int64_t)j * n0;
+      if (owna) row[ia] = ared ? bR[r] : bB[r];
+      if (ownb) row[ib] = ared ? bB[r] : bR[r];
+    }
   }
   // inverse diagonals; red relaxation from zero: omega b / D
 #pragma unroll
@@ -638,27 +690,40 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
 // host (autotuned per grid size and dtype): coarse rows per down block in
 // {2, ..., 6, 8, 16} (16 only in FP32, whose tile fits the LDS), fine rows
 // per up block in {4, 8, 10, 12, 16, 32}.
-template <typename R>
-void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *rc, R omega, int rows,
-                    hipStream_t s) {
+template <typename R, int SRC>
+void launch_down(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const DownSrc<R> &src, cplx<R> *rc,
+                 R omega, int rows, hipStream_t s) {
   constexpr int CX = 61;
   const int tx = (coarse.n0 + CX - 1) / CX;
   const int tiles = tx * ((coarse.n1 + rows - 1) / rows);
   const dim3 grid(xcd_padded(tiles)), block(NT);
   switch (rows) {
-    case 2: launch_k((k_down_rb<R, 2>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
-    case 3: launch_k((k_down_rb<R, 3>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
-    case 4: launch_k((k_down_rb<R, 4>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
-    case 5: launch_k((k_down_rb<R, 5>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
-    case 6: launch_k((k_down_rb<R, 6>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
+    case 2: launch_k((k_down_rb<R, 2, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
+    case 3: launch_k((k_down_rb<R, 3, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
+    case 4: launch_k((k_down_rb<R, 4, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
+    case 5: launch_k((k_down_rb<R, 5, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
+    case 6: launch_k((k_down_rb<R, 6, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
     case 16:
       if constexpr (sizeof(R) == 4) {
-        launch_k((k_down_rb<R, 16>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles);
+        launch_k((k_down_rb<R, 16, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles);
         break;
       }
       [[fallthrough]];
-    default: launch_k((k_down_rb<R, 8>), grid, block, 0, s, fine, coarse, b, rc, omega, tx, tiles); break;
+    default: launch_k((k_down_rb<R, 8, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
   }
+}
+
+template <typename R>
+void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *rc, R omega, int rows,
+                    hipStream_t s) {
+  launch_down<R, kDownSrcB>(fine, coarse, b, DownSrc<R>{}, rc, omega, rows, s);
+}
+
+template <typename R>
+void launch_down_rb_src(const Grid<R> &fine, const Grid<R> &coarse, const DownSrc<R> &src, cplx<R> *rc, R omega,
+                        int rows, hipStream_t s) {
+  if (src.mode == kDownSrcP) launch_down<R, kDownSrcP>(fine, coarse, nullptr, src, rc, omega, rows, s);
+  else launch_down<R, kDownSrcS>(fine, coarse, nullptr, src, rc, omega, rows, s);
 }
 
 template <typename R>
@@ -689,6 +754,8 @@ template void launch_down_rb<float>(const Grid<float> &, const Grid<float> &, co
                                     float, int, hipStream_t);
 template void launch_up_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *,
                                    const cplx<double> *, cplx<double> *, double, int, hipStream_t);
+template void launch_down_rb_src<float>(const Grid<float> &, const Grid<float> &, const DownSrc<float> &, cplx<float> *,
+                                        float, int, hipStream_t);
 template void launch_tail<double>(const TailArgs<double> &, hipStream_t);
 template void launch_tail<float>(const TailArgs<float> &, hipStream_t);
 template void launch_up_rb<float>(const Grid<float> &, const Grid<float> &, const cplx<float> *, const cplx<float> *,

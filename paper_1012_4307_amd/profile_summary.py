@@ -7,11 +7,13 @@ measurements, and the per-launch HBM traffic of the fused cycle kernels.
 
 ``stats`` tabulates kernel time by kernel and launch grid (the fused kernels
 run once per level, so the grid size names the level).  ``traffic`` reads
-FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the finest-level fused down and
-up kernels and of the copy probe, scales each counter by what it reads for the
-copy probe of known size (bytes moved / counter bytes), and records the
-scaled bytes per launch together with a digest of those kernels' sources, so
-a reader can tell when the figures no longer describe the code.
+FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the finest-level fused
+kernels (the FP32 up kernel, the FP32 down kernels that form the nested
+Bi-CGSTAB's p and s, the FP64 down and up kernels) and of the copy probe,
+scales each counter by what it reads for the copy probe of known size (bytes
+moved / counter bytes), and records the scaled bytes per launch together with
+a digest of those kernels' sources, so a reader can tell when the figures no
+longer describe the code.
 """
 from __future__ import annotations
 
@@ -33,6 +35,18 @@ CSRC = os.path.join(ROOT, "paper_1012_4307_amd", "csrc")
 KERNEL_SOURCES = [os.path.join(CSRC, "ecs_internal.h"), os.path.join(CSRC, "kernels_vcycle.hip")]
 TAIL_MARKER = b"\n// ----------------------------------------------------------------- tail\n"
 COPY_BYTES = 512 << 20   # the copy probe moves 512 MiB each way
+# class (as bench.py's timing classes) and kernel name pattern; the finest
+# grid of each is the one recorded
+CLASSES = (("up", r"k_up_rb<float, \d+>"), ("down_p", r"k_down_rb<float, \d+, 1>"),
+           ("down_s", r"k_down_rb<float, \d+, 2>"), ("down_f64", r"k_down_rb<double, \d+, 0>"),
+           ("up_f64", r"k_up_rb<double, \d+>"))
+# algorithmic bytes per fine node: every input read once, every output written
+# once.  FP32 complex 8 B, real 4 B: up reads the coarse correction (a quarter
+# node), b, k^2 and writes u (5.5 reals = 22 B); the p-forming down kernel
+# reads r, p, v, k^2 and writes p and the coarse residual (9.5 reals = 38 B);
+# the s-forming one reads r, v, k^2 and writes s and the coarse residual
+# (7.5 reals = 30 B).  FP64: down 3.5 reals = 28 B, up 5.5 reals = 44 B.
+ALGO_BYTES_PER_NODE = dict(up=22, down_p=38, down_s=30, down_f64=28, up_f64=44)
 
 
 def sources_digest() -> str:
@@ -104,15 +118,15 @@ def traffic(fetch_csv: str, write_csv: str, out_txt: str, out_json: str, cmd_fet
     lines = [f"command (FETCH_SIZE): {cmd_fetch}", f"command (WRITE_SIZE): {cmd_write}", "",
              f"copy probe ({COPY_BYTES} B read + written): FETCH_SIZE {copy_fetch:.1f} KiB -> scale "
              f"{fetch_scale:.4f}; WRITE_SIZE {copy_write:.1f} KiB -> scale {write_scale:.4f}", "",
-             f"{'class':6s} {'kernel':24s} {'grid':>8s} {'FETCH KiB':>11s} {'WRITE KiB':>11s} {'HBM bytes':>12s} "
+             f"{'class':8s} {'kernel':26s} {'grid':>8s} {'FETCH KiB':>11s} {'WRITE KiB':>11s} {'HBM bytes':>12s} "
              f"{'algorithmic':>12s} {'ratio':>6s}"]
-    for cls, pat in (("down", r"k_down_rb<float, \d+>"), ("up", r"k_up_rb<float, \d+>")):
+    for cls, pat in CLASSES:
         (name, grid), f_kib = _finest(fe, pat)
         w_kib = statistics.median(wr[(name, grid)])
         hbm = f_kib * 1024 * fetch_scale + w_kib * 1024 * write_scale
         kernels[cls] = dict(kernel=name, grid_threads=grid, fetch_kib=f_kib, write_kib=w_kib,
                             hbm_bytes_per_launch=round(hbm), algorithmic_bytes_per_launch=algo[cls])
-        lines.append(f"{cls:6s} {name:24s} {grid:8d} {f_kib:11.1f} {w_kib:11.1f} {hbm:12.0f} {algo[cls]:12d} "
+        lines.append(f"{cls:8s} {name:26s} {grid:8d} {f_kib:11.1f} {w_kib:11.1f} {hbm:12.0f} {algo[cls]:12d} "
                      f"{hbm / algo[cls]:6.3f}")
     with open(out_txt, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -142,11 +156,8 @@ def main():
         stats(a.trace, a.out, a.cmd)
     else:
         nodes = a.n * a.n
-        # FP32 complex: down reads b, k^2 and writes the coarse quarter (3.5
-        # reals = 14 B per fine node); up reads the coarse quarter, b, k^2 and
-        # writes u (5.5 reals = 22 B)
         traffic(a.fetch, a.write, a.out, a.json, a.cmd_fetch, a.cmd_write,
-                algo=dict(down=nodes * 14, up=nodes * 22))
+                algo={c: nodes * b for c, b in ALGO_BYTES_PER_NODE.items()})
 
 
 if __name__ == "__main__":

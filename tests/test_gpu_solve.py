@@ -102,6 +102,49 @@ def test_mixed_fgmres_vs_fp64_oracle():
         assert st["rel_residual"] <= 1e-12
 
 
+@pytest.mark.parametrize("case", ["coulomb257", "ragged193"])
+def test_nested_updates_fused_equal_separate(case):
+    """The nested FP32 Bi-CGSTAB with its p and s updates formed inside the
+    finest down kernel gives the same solve as with the separate update
+    kernels: same iteration counts, equal iterates (the per-node expressions
+    are the same); also when graph launches switch the fusion off."""
+    import torch
+    w = W.large_coulomb(n=257, coarsest=9) if case == "coulomb257" else ragged_workload(n=193, coarsest=7)
+    kr = E.Krylov(method="fgmres", restart=40, rtol=1e-10, maxit=20000, inner=4)
+    S = gpu_for(w, "f32", krylov=kr)
+    b = to_gpu(w.rhs[0])
+    out = {}
+    nn = w.shape[0] * w.shape[1]
+    for label, fuse, graphs in (("separate", 0, "auto"), ("fused", 1, "auto"), ("graphs", 1, True)):
+        S.set_tuning(fuse_updates=fuse)
+        S.set_graphs(graphs)
+        timed = label != "graphs"
+        for cls in ("down", "down_p", "down_s"):
+            S.timing(cls, timed)
+        x, st = S.solve(b)
+        assert st["status"] == 0, (label, st)
+        out[label] = (x.clone(), st["iterations"], st["inner_iterations"])
+        if timed:
+            # the finest down kernel of every cycle, in its own class
+            got = {cls: S.timing_read(cls) for cls in ("down", "down_p", "down_s")}
+            ni = st["inner_iterations"]
+            if fuse:
+                assert got["down_p"][0] == ni and got["down_s"][0] == ni, got
+                assert got["down_p"][2] == ni * nn * 4 * 9.5 and got["down_s"][2] == ni * nn * 4 * 7.5
+                assert got["down"][0] == 0, got
+            else:
+                assert got["down"][0] == 2 * ni and got["down_p"][0] == got["down_s"][0] == 0, got
+            for cls in ("down", "down_p", "down_s"):
+                S.timing(cls, False)
+    x0, it0, in0 = out["separate"]
+    for label in ("fused", "graphs"):
+        x1, it1, in1 = out[label]
+        assert (it1, in1) == (it0, in0), label
+        assert torch.equal(x1, x0), (label, relerr(to_np(x1), to_np(x0)))
+    with pytest.raises(E.EcsError):
+        S.set_tuning(fuse_updates=2)
+
+
 def test_status_paths():
     w = W.small_constant_k(n=33)
     S = gpu_for(w, "f64")
