@@ -145,6 +145,24 @@ def test_nested_updates_fused_equal_separate(case):
         S.set_tuning(fuse_updates=2)
 
 
+def test_nested_updates_fused_full_size():
+    """The same at the benchmark's size and launch configuration (2049^2,
+    h = 0.25, 9 levels, 16 inner iterations), over two outer FGMRES(40)
+    iterations: equal iterates with and without the fused updates."""
+    import torch
+    w = W.large_coulomb(n=2049)
+    kr = E.Krylov(method="fgmres", restart=40, rtol=1e-8, maxit=2, inner=16)
+    S = gpu_for(w, "f32", krylov=kr)
+    b = to_gpu(w.rhs[0])
+    xs = []
+    for fuse in (0, 1):
+        S.set_tuning(fuse_updates=fuse)
+        x, st = S.solve(b)
+        assert st["status"] == 1 and st["iterations"] == 2 and st["inner_iterations"] == 32, st
+        xs.append(x)
+    assert torch.equal(xs[0], xs[1])
+
+
 def test_status_paths():
     w = W.small_constant_k(n=33)
     S = gpu_for(w, "f64")
