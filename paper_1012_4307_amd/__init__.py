@@ -217,8 +217,11 @@ class Solver:
         nodes = (ctypes.c_int64 * 3)(*(list(self.n) + [1] * (3 - self.dim)))
         lo3 = (ctypes.c_double * 3)(*(list(lo) + [0.0] * (3 - self.dim)))
         hi3 = (ctypes.c_double * 3)(*(list(hi) + [1.0] * (3 - self.dim)))
+        # the context enqueues all its work on the stream current at creation
+        self.stream = torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
-            self._check(L.ecs_create(ctypes.byref(h), self.dim, nodes, lo3, hi3, _stream_ptr(self.device)), None)
+            self._check(L.ecs_create(ctypes.byref(h), self.dim, nodes, lo3, hi3,
+                                     ctypes.c_void_p(self.stream.cuda_stream)), None)
         self._h = h
         for a in range(self.dim):
             for side in (0, 1):

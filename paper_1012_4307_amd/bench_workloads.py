@@ -65,22 +65,22 @@ def batched(args):
     import torch
     from . import Krylov, batch_solve
     from . import workloads as W
-    from .autotune import autotune
+    from .autotune import autotune_group
     descs = W.batch_systems(count=args.batch_count)
     kr = Krylov(method="bicgstab", rtol=1e-8, maxit=20000)
     streams = [torch.cuda.Stream() for _ in range(max(1, args.batch_streams))]
     solvers, rhs = [], []
-    tuned = {}
     for q, d in enumerate(descs):
         w = W.batch_inputs(d)
-        S = _solver(w, args.batch_cycle, kr, streams[q % len(streams)])
-        key = (d["n"], args.batch_cycle)
-        if key not in tuned:
-            tuned[key] = autotune(S)
-        else:
-            S.set_tuning(**tuned[key])
-        solvers.append(S)
+        solvers.append(_solver(w, args.batch_cycle, kr, streams[q % len(streams)]))
         rhs.append(torch.stack([torch.from_numpy(b).to("cuda") for b in w.rhs]))
+    torch.cuda.synchronize()
+    # one schedule per grid size, tuned for the throughput of concurrent
+    # cycles (the systems of that size on their own streams)
+    groups = {}
+    for q, d in enumerate(descs):
+        groups.setdefault((d["n"], args.batch_cycle), []).append(solvers[q])
+    tuned = {key: autotune_group(group) for key, group in groups.items()}
     torch.cuda.synchronize()
     total = sum(int(b.shape[0]) for b in rhs)
     batch_solve(solvers, rhs, kr)   # warm-up (also fills the graph caches)

@@ -82,3 +82,58 @@ def test_autotune_schedule_keeps_results(tmp_path, monkeypatch):
         assert autotune.autotune(S2) == best   # from the cache
     with pytest.raises(E.EcsError):
         S.set_tuning(down_rows=7)
+
+
+def test_autotune_group_one_schedule_for_the_batch(tmp_path, monkeypatch):
+    """The throughput tuner for batches: one schedule from the candidate list,
+    applied to every solver of the group, cached; solvers of another size are
+    refused; the batched solve under that schedule still equals the single
+    solves (a schedule changes no arithmetic)."""
+    import torch
+    from paper_1012_4307_amd import autotune
+    monkeypatch.setenv("ECSMG_TUNING_CACHE", str(tmp_path / "tune.json"))
+    descs = [d for d in W.batch_systems(count=12, sizes=(129, 257)) if d["n"] == 129][:3]
+    ws = [W.batch_inputs(d) for d in descs]
+    kr = E.Krylov(method="bicgstab", rtol=1e-8, maxit=5000)
+    streams = [torch.cuda.Stream() for _ in ws]
+    solvers, rhs = [], []
+    for st, w in zip(streams, ws):
+        with torch.cuda.stream(st):
+            solvers.append(gpu_for(w, "f64", krylov=kr))
+        rhs.append(torch.stack([to_gpu(b) for b in w.rhs]))
+    torch.cuda.synchronize()
+    best = autotune.autotune_group(solvers, reps=2)
+    assert best in list(autotune.candidates("f64"))
+    assert all(S.get_tuning() == best for S in solvers)
+    assert (tmp_path / "tune.json").exists()
+    assert autotune.autotune_group(solvers) == best   # from the cache
+    other = gpu_for(W.coulomb(E=1.0, n=65), "f64", krylov=kr)
+    with pytest.raises(ValueError):
+        autotune.autotune_group([solvers[0], other])
+    xs, stats = E.batch_solve(solvers, rhs, kr)
+    torch.cuda.synchronize()
+    for q, w in enumerate(ws):
+        assert stats[q]["status"] == 0, stats[q]
+        with torch.cuda.stream(streams[q]):
+            x1, _ = solvers[q].solve(to_gpu(w.rhs[0]), krylov=kr)
+        torch.cuda.synchronize()
+        assert torch.equal(xs[q][0], x1), q
+
+
+def test_cycle_timer_times_the_solvers_own_stream():
+    """The single-cycle tuner's timer brackets the cycles on the stream they
+    run on: a solver made under a side stream times like one made on the
+    current stream (2049^2 FP64, where a cycle's device time is several times
+    the host's launch time)."""
+    import torch
+    from paper_1012_4307_amd import autotune
+    w = W.large_coulomb(n=2049)
+    v = to_gpu(w.rhs[0])
+    S0 = gpu_for(w, "f64")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        S1 = gpu_for(w, "f64")
+    assert S1.stream == side and S0.stream == torch.cuda.current_stream()
+    t0 = min(autotune.time_cycles(S0, v, reps=10) for _ in range(3))
+    t1 = min(autotune.time_cycles(S1, v, reps=10) for _ in range(3))
+    assert 0.8 < t1 / t0 < 1.25, (t0, t1)
