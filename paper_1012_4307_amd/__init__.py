@@ -150,6 +150,38 @@ def _stream_ptr(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+class _StreamOrder:
+    """Orders the library's streams (each context enqueues on the stream that
+    was current when it was made) with the caller's current stream around one
+    call: before it, each of them waits for the caller's stream, so inputs
+    written there are complete when the library reads them; after it, the
+    caller's stream waits for each of them, so outputs can be used there, and
+    the outputs' memory is marked in use on them, so torch's allocator does not
+    hand it out again before they are done.  Nothing happens for a context on
+    the caller's current stream."""
+
+    def __init__(self, streams, outs=()):
+        self.streams = list(streams)
+        self.outs = outs
+
+    def __enter__(self):
+        torch = _torch()
+        self.cur = torch.cuda.current_stream(self.streams[0].device) if self.streams else None
+        for st in self.streams:
+            if st != self.cur:
+                st.wait_stream(self.cur)
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        if exc_type is None:
+            for st in self.streams:
+                if st != self.cur:
+                    for t in self.outs:
+                        t.record_stream(st)
+                    self.cur.wait_stream(st)
+        return False
+
+
 @dataclass
 class Precond:
     """Preconditioner and cycle (Sec. 4-5).  kind: none | laplace | csl | csg | qd."""
@@ -261,6 +293,8 @@ class Solver:
         if self.ws is not None and self.ws.numel() >= need.value:
             return
         self.ws = torch.empty(need.value + 256, dtype=torch.uint8, device=self.device)
+        if self.stream != torch.cuda.current_stream(self.device):
+            self.ws.record_stream(self.stream)   # in use on the context's stream
         base = self.ws.data_ptr()
         off = (-base) % 256
         self._check(L.ecs_set_workspace(self._h, ctypes.c_void_p(base + off), need.value + 256 - off))
@@ -271,7 +305,8 @@ class Solver:
             raise ValueError("bad k2")
         self.k2 = k2
         L = lib()
-        self._check(L.ecs_set_k2(self._h, _ptr(k2)))
+        with _StreamOrder([self.stream]):
+            self._check(L.ecs_set_k2(self._h, _ptr(k2)))
         base = self.ws.data_ptr()
         off = (-base) % 256
         self._check(L.ecs_set_workspace(self._h, ctypes.c_void_p(base + off), self.ws.numel() - off))
@@ -310,7 +345,8 @@ class Solver:
         x = x0.clone() if x0 is not None else torch.empty_like(b)
         st = Stats()
         d = kr.to_c(x0 is not None, history)
-        rc = lib().ecs_solve(self._h, ctypes.byref(d), _ptr(b), _ptr(x), ctypes.byref(st))
+        with _StreamOrder([self.stream], (x,)):
+            rc = lib().ecs_solve(self._h, ctypes.byref(d), _ptr(b), _ptr(x), ctypes.byref(st))
         if rc < 0:
             self._check(rc)
         out = st.as_dict()
@@ -328,8 +364,10 @@ class Solver:
         x = x0.clone() if x0 is not None else torch.empty_like(b)
         hist = np.zeros(maxcycles + 1)
         st = Stats()
-        rc = lib().ecs_mg_solve(self._h, _ptr(b), _ptr(x), float(rtol), int(maxcycles), 1 if x0 is not None else 0,
-                                hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist.size, ctypes.byref(st))
+        with _StreamOrder([self.stream], (x,)):
+            rc = lib().ecs_mg_solve(self._h, _ptr(b), _ptr(x), float(rtol), int(maxcycles),
+                                    1 if x0 is not None else 0, hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    hist.size, ctypes.byref(st))
         if rc < 0:
             self._check(rc)
         out = st.as_dict()
@@ -345,7 +383,8 @@ class Solver:
         lam = torch.empty_like(g)
         st = Stats()
         d = kr.to_c()
-        rc = lib().ecs_solve_adjoint(self._h, ctypes.byref(d), _ptr(g), _ptr(lam), ctypes.byref(st))
+        with _StreamOrder([self.stream], (lam,)):
+            rc = lib().ecs_solve_adjoint(self._h, ctypes.byref(d), _ptr(g), _ptr(lam), ctypes.byref(st))
         if rc < 0:
             self._check(rc)
         out = st.as_dict()
@@ -357,7 +396,8 @@ class Solver:
         lam = self._vec(lam)
         u = self._vec(u)
         g = torch.empty(self.shape, dtype=torch.float64, device=self.device)
-        self._check(lib().ecs_grad_k2(self._h, _ptr(lam), _ptr(u), _ptr(g)))
+        with _StreamOrder([self.stream], (g,)):
+            self._check(lib().ecs_grad_k2(self._h, _ptr(lam), _ptr(u), _ptr(g)))
         return g
 
     # ------------------------------------------------------- single steps
@@ -365,7 +405,8 @@ class Solver:
         torch = _torch()
         x = self._vec(x)
         y = torch.empty_like(x)
-        self._check(lib().ecs_apply(self._h, OP[op], _ptr(x), _ptr(y)))
+        with _StreamOrder([self.stream], (y,)):
+            self._check(lib().ecs_apply(self._h, OP[op], _ptr(x), _ptr(y)))
         return y
 
     def vcycle(self, v):
@@ -373,7 +414,8 @@ class Solver:
         torch = _torch()
         v = self._vec(v)
         z = torch.empty_like(v)
-        self._check(lib().ecs_vcycle(self._h, _ptr(v), _ptr(z)))
+        with _StreamOrder([self.stream], (z,)):
+            self._check(lib().ecs_vcycle(self._h, _ptr(v), _ptr(z)))
         return z
 
     def vcycle_native(self, v):
@@ -382,14 +424,16 @@ class Solver:
         torch = _torch()
         v = self._vec(v, self.cycle_dtype)
         z = torch.empty_like(v)
-        self._check(lib().ecs_vcycle_native(self._h, _ptr(v), _ptr(z)))
+        with _StreamOrder([self.stream], (z,)):
+            self._check(lib().ecs_vcycle_native(self._h, _ptr(v), _ptr(z)))
         return z
 
     def smooth(self, b, u, level=0, nsweeps=1):
         shape = self.level_shape(level)
         b = self._vec(b, self.cycle_dtype, shape)
         u = self._vec(u, self.cycle_dtype, shape).clone()
-        self._check(lib().ecs_smooth(self._h, level, _ptr(b), _ptr(u), nsweeps))
+        with _StreamOrder([self.stream], (u,)):
+            self._check(lib().ecs_smooth(self._h, level, _ptr(b), _ptr(u), nsweeps))
         return u
 
     def residual_restrict(self, b, u, level=0):
@@ -398,13 +442,15 @@ class Solver:
         b = self._vec(b, self.cycle_dtype, shape)
         u = self._vec(u, self.cycle_dtype, shape)
         rc = torch.empty(self.level_shape(level + 1), dtype=self.cycle_dtype, device=self.device)
-        self._check(lib().ecs_residual_restrict(self._h, level, _ptr(b), _ptr(u), _ptr(rc)))
+        with _StreamOrder([self.stream], (rc,)):
+            self._check(lib().ecs_residual_restrict(self._h, level, _ptr(b), _ptr(u), _ptr(rc)))
         return rc
 
     def prolong_correct(self, ec, u, level=0):
         ec = self._vec(ec, self.cycle_dtype, self.level_shape(level + 1))
         u = self._vec(u, self.cycle_dtype, self.level_shape(level)).clone()
-        self._check(lib().ecs_prolong_correct(self._h, level, _ptr(ec), _ptr(u)))
+        with _StreamOrder([self.stream], (u,)):
+            self._check(lib().ecs_prolong_correct(self._h, level, _ptr(ec), _ptr(u)))
         return u
 
     def coarse_solve(self, b):
@@ -412,7 +458,8 @@ class Solver:
         shape = self.level_shape(self.nlev - 1)
         b = self._vec(b, self.cycle_dtype, shape)
         x = torch.empty_like(b)
-        self._check(lib().ecs_coarse_solve(self._h, _ptr(b), _ptr(x)))
+        with _StreamOrder([self.stream], (x,)):
+            self._check(lib().ecs_coarse_solve(self._h, _ptr(b), _ptr(x)))
         return x
 
     def set_tuning(self, down_rows=4, up_rows=8, small_grid=513, tail_nodes=33, pair_grid=129, fuse_updates=1):
@@ -473,7 +520,8 @@ def batch_solve(solvers, rhs, krylov: Krylov):
     nr = (ctypes.c_int * n)(*[int(b.shape[0]) for b in rhs])
     st = (Stats * n)()
     d = krylov.to_c()
-    rc = lib().ecs_batch_solve(n, ctxs, ctypes.byref(d), bs, xp, nr, st)
+    with _StreamOrder([S.stream for S in solvers], tuple(xs)):
+        rc = lib().ecs_batch_solve(n, ctxs, ctypes.byref(d), bs, xp, nr, st)
     if rc < 0:
         raise EcsError(rc, "batched solve failed")
     return xs, [s.as_dict() for s in st]
@@ -511,9 +559,10 @@ def coupled_solve(solvers, k2c, b, x0=None, outer: Optional[Krylov] = None, inne
     off = (-ws.data_ptr()) % 256
     x = x0.clone() if x0 is not None else torch.empty_like(b)
     st = Stats()
-    rc = L.ecs_coupled_solve(nb, hs, _ptr(k2c) if k2c is not None else None, ctypes.byref(do),
-                             None if cycles_only else ctypes.byref(di), ctypes.c_void_p(ws.data_ptr() + off),
-                             need.value + 256 - off, _ptr(b), _ptr(x), ctypes.byref(st))
+    with _StreamOrder([S.stream for S in solvers], (x, ws)):
+        rc = L.ecs_coupled_solve(nb, hs, _ptr(k2c) if k2c is not None else None, ctypes.byref(do),
+                                 None if cycles_only else ctypes.byref(di), ctypes.c_void_p(ws.data_ptr() + off),
+                                 need.value + 256 - off, _ptr(b), _ptr(x), ctypes.byref(st))
     if rc < 0:
         raise EcsError(rc, L.ecs_last_error(solvers[0]._h).decode())
     out = st.as_dict()

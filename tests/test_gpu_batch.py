@@ -137,3 +137,33 @@ def test_cycle_timer_times_the_solvers_own_stream():
     t0 = min(autotune.time_cycles(S0, v, reps=10) for _ in range(3))
     t1 = min(autotune.time_cycles(S1, v, reps=10) for _ in range(3))
     assert 0.8 < t1 / t0 < 1.25, (t0, t1)
+
+
+def test_side_stream_solver_is_ordered_with_the_callers_stream():
+    """A solver made under a side stream reads inputs the caller's stream has
+    just written (behind a long FP64 product) and its outputs are read on the
+    caller's stream, with no explicit synchronisation: the results equal those
+    of a solver made on the caller's stream."""
+    import torch
+    w = W.coulomb(E=2.0, n=513)
+    kr = E.Krylov(method="bicgstab", rtol=1e-8, maxit=5000)
+    S0 = gpu_for(w, "f64", krylov=kr)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        S1 = gpu_for(w, "f64", krylov=kr)
+    ref = to_gpu(w.rhs[0])
+    z0, y0 = S0.vcycle(ref), S0.apply(ref)
+    x0, _ = S0.solve(ref)
+    a = torch.randn(4096, 4096, device="cuda", dtype=torch.float64)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        b = torch.zeros_like(ref)
+        _ = a @ a                      # keeps the caller's stream busy for milliseconds
+        b.copy_(ref)
+        z1, y1 = S1.vcycle(b), S1.apply(b)
+        assert float((z1 - z0).abs().max()) == 0 and float((y1 - y0).abs().max()) == 0
+        b2 = torch.zeros_like(ref)
+        _ = a @ a
+        b2.copy_(ref)
+        x1, st = S1.solve(b2)
+        assert st["status"] == 0 and torch.equal(x1, x0)
