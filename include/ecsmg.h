@@ -133,9 +133,18 @@ ecs_status ecs_create(ecs_ctx **out, int dim, const int64_t *nodes, const double
  * homogeneous Dirichlet node.  ECS_BC_DIRICHLET removes the layer. */
 ecs_status ecs_set_ecs(ecs_ctx *ctx, int axis, int side, int kind, double start, double theta);
 
-/* k^2 at the real node coordinates, FP64 device array of prod(nodes) entries
- * (borrowed, read at every solve).  Invalidates the preconditioner setup. */
-ecs_status ecs_set_k2(ecs_ctx *ctx, const double *k2_dev);
+/* k^2 at the real node coordinates (the k^2(x) of the model problem, Sec. 2;
+ * Sec. 3.2 evaluates it at the nodes): a device array of prod(nodes) reals,
+ * node-major, of real_dtype ECS_F64 (double) or ECS_F32 (float).
+ *   ECS_F64: borrowed and read by every later call (apply, cycle, solve) until
+ *            the next ecs_set_k2 or ecs_destroy.
+ *   ECS_F32: read once, by ecs_set_workspace, which widens it exactly into
+ *            FP64 storage inside the workspace (ecs_workspace_size counts it,
+ *            so call ecs_set_k2 first); later changes to the array take effect
+ *            at the next ecs_set_workspace.
+ * Invalidates the preconditioner setup (call ecs_set_workspace again).
+ * Errors: ECS_EINVAL for a null pointer or another dtype. */
+ecs_status ecs_set_k2(ecs_ctx *ctx, const void *k2_dev, int real_dtype);
 
 ecs_status ecs_set_precond(ecs_ctx *ctx, const ecs_prec_desc *desc);
 
@@ -308,9 +317,12 @@ ecs_status ecs_get_tuning(ecs_ctx *ctx, ecs_tuning *tuning);
 enum { ECS_GRAPHS_NEVER = 0, ECS_GRAPHS_ALWAYS = 1, ECS_GRAPHS_AUTO = 2 };
 ecs_status ecs_set_graphs(ecs_ctx *ctx, int mode);
 
-/* Batched solve of n independent problems (Bi-CGSTAB; desc->krylov must be
- * ECS_KRYLOV_BICGSTAB).  Each context is fully set up with its own workspace
- * (sized for a Bi-CGSTAB desc) and should have its own stream: the driver
+/* Batched solve of n independent problems (Bi-CGSTAB), the many independent
+ * Helmholtz blocks of Sec. 2 at once.  desc[s] holds system s's Krylov
+ * settings (desc[s]->krylov must be ECS_KRYLOV_BICGSTAB; rtol, maxit and
+ * x_is_guess may differ between systems).  Each context is fully set up with
+ * its own workspace (sized for its Bi-CGSTAB desc) and should have its own
+ * stream: the driver
  * enqueues one phase of a system at a time (||b||, true residual and restart,
  * or one iteration) on that system's stream, records an event after it, and
  * polls the events from the host; a system's next phase is enqueued as soon
@@ -322,7 +334,7 @@ ecs_status ecs_set_graphs(ecs_ctx *ctx, int mode);
  * other.  stats[s] aggregates the system's right-hand sides: summed
  * iterations, restarts and cycles, the largest final true residual, the worst
  * status, and the wall time of the whole batch. */
-ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *desc, const void *const *b,
+ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *const *desc, const void *const *b,
                            void *const *x, const int *nrhs, ecs_stats *stats);
 
 /* Plain device copy of `bytes` bytes (bandwidth probe), on `stream`. */

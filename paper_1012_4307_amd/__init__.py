@@ -88,7 +88,7 @@ def lib():
     sig = {
         "ecs_create": [pP, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D), P],
         "ecs_set_ecs": [P, I, I, I, D, D],
-        "ecs_set_k2": [P, P],
+        "ecs_set_k2": [P, P, I],
         "ecs_set_precond": [P, ctypes.POINTER(PrecDesc)],
         "ecs_workspace_size": [P, ctypes.POINTER(SolveDesc), ctypes.POINTER(Z)],
         "ecs_set_workspace": [P, P, Z],
@@ -104,7 +104,8 @@ def lib():
         "ecs_level_info": [P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_int64)],
         "ecs_timing_enable": [P, I, I],
         "ecs_timing_read": [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D)],
-        "ecs_batch_solve": [I, pP, ctypes.POINTER(SolveDesc), pP, pP, ctypes.POINTER(I), ctypes.POINTER(Stats)],
+        "ecs_batch_solve": [I, pP, ctypes.POINTER(ctypes.POINTER(SolveDesc)), pP, pP, ctypes.POINTER(I),
+                            ctypes.POINTER(Stats)],
         "ecs_copy_probe": [P, P, Z, P],
         "ecs_timing_calibrate": [P, I],
         "ecs_vcycle_native": [P, P, P],
@@ -227,7 +228,8 @@ class Solver:
 
     dim, n, lo, hi : grid (nodes per axis incl. both Dirichlet ends)
     ecs            : per axis (lo_side, hi_side), each None or (layer start, theta)
-    k2             : float64 CUDA tensor of k^2 at the nodes, shape reversed(n)
+    k2             : float64 or float32 CUDA tensor of k^2 at the nodes, shape
+                     reversed(n) (float32 is widened once, at set-up)
     precond        : Precond
     krylov         : Krylov settings used to size the workspace (larger ones
                      reallocate it on demand)
@@ -239,8 +241,8 @@ class Solver:
         self.dim = int(dim)
         self.n = tuple(int(v) for v in n)
         self.shape = tuple(reversed(self.n))
-        if not (k2.is_cuda and k2.dtype == torch.float64 and k2.is_contiguous() and tuple(k2.shape) == self.shape):
-            raise ValueError("k2 must be a contiguous float64 CUDA tensor of shape %s" % (self.shape,))
+        self.device = None
+        self._k2_dtype(k2)
         self.device = k2.device
         self.k2 = k2
         self.precond = precond
@@ -260,7 +262,7 @@ class Solver:
                 spec = ecs[a][side]
                 if spec is not None:
                     self._check(L.ecs_set_ecs(h, a, side, ECS, float(spec[0]), float(spec[1])))
-        self._check(L.ecs_set_k2(h, _ptr(k2)))
+        self._check(L.ecs_set_k2(h, _ptr(k2), self._k2_dtype(k2)))
         self._pd = precond.to_c()
         self._check(L.ecs_set_precond(h, ctypes.byref(self._pd)))
         self.nlev = self.level_count()
@@ -284,6 +286,30 @@ class Solver:
             L.ecs_destroy(h)
             self._h = None
 
+    def _k2_dtype(self, k2):
+        """The library's dtype code of a k^2 tensor; raises ValueError unless it
+        is a contiguous float64 / float32 CUDA tensor of the grid's shape on the
+        solver's device."""
+        torch = _torch()
+        ok = (isinstance(k2, torch.Tensor) and k2.is_cuda and k2.dtype in (torch.float64, torch.float32)
+              and k2.is_contiguous() and tuple(k2.shape) == self.shape
+              and (self.device is None or k2.device == self.device))
+        if not ok:
+            desc = f"{k2.dtype} {tuple(k2.shape)} on {k2.device}" if isinstance(k2, torch.Tensor) else type(k2).__name__
+            raise ValueError(f"k2 must be a contiguous float64 or float32 CUDA tensor of shape {self.shape}"
+                             f"{'' if self.device is None else ' on ' + str(self.device)}, got {desc}")
+        return F64 if k2.dtype == torch.float64 else F32
+
+    def _set_workspace(self, ws, nbytes):
+        """Hand `ws` to the library, which builds the hierarchy in it on the
+        context's stream: that stream first waits for the caller's, so memory
+        the caller's stream used before (torch may hand out a block freed
+        there) is not overwritten early."""
+        base = ws.data_ptr()
+        off = (-base) % 256
+        with _StreamOrder([self.stream], (ws,)):
+            self._check(lib().ecs_set_workspace(self._h, ctypes.c_void_p(base + off), nbytes - off))
+
     def _ensure_workspace(self, kr: Krylov):
         torch = _torch()
         L = lib()
@@ -293,23 +319,23 @@ class Solver:
         if self.ws is not None and self.ws.numel() >= need.value:
             return
         self.ws = torch.empty(need.value + 256, dtype=torch.uint8, device=self.device)
-        if self.stream != torch.cuda.current_stream(self.device):
-            self.ws.record_stream(self.stream)   # in use on the context's stream
-        base = self.ws.data_ptr()
-        off = (-base) % 256
-        self._check(L.ecs_set_workspace(self._h, ctypes.c_void_p(base + off), need.value + 256 - off))
+        self._set_workspace(self.ws, self.ws.numel())
 
     def reset_k2(self, k2):
-        """Replace k^2 (same shape) and rebuild the hierarchy."""
-        if tuple(k2.shape) != self.shape or not k2.is_contiguous():
-            raise ValueError("bad k2")
-        self.k2 = k2
+        """Replace k^2 (same shape and device; float64 or float32) and rebuild
+        the hierarchy."""
+        code = self._k2_dtype(k2)
         L = lib()
         with _StreamOrder([self.stream]):
-            self._check(L.ecs_set_k2(self._h, _ptr(k2)))
-        base = self.ws.data_ptr()
-        off = (-base) % 256
-        self._check(L.ecs_set_workspace(self._h, ctypes.c_void_p(base + off), self.ws.numel() - off))
+            self._check(L.ecs_set_k2(self._h, _ptr(k2), code))
+        self.k2 = k2
+        need = ctypes.c_size_t()
+        self._check(L.ecs_workspace_size(self._h, None, ctypes.byref(need)))
+        if self.ws.numel() < need.value + 256:   # an FP32 field needs room for its FP64 copy
+            self.ws = None
+            self._ensure_workspace(self.krylov)
+        else:
+            self._set_workspace(self.ws, self.ws.numel())
 
     def level_count(self):
         nl = ctypes.c_int()
@@ -506,24 +532,42 @@ class Solver:
         return n.value, ms.value, by.value
 
 
-def batch_solve(solvers, rhs, krylov: Krylov):
-    """Solve every right-hand side of every system: rhs[s] is a complex128 CUDA
-    tensor of shape (nrhs_s, *solvers[s].shape).  Returns (solutions, stats)."""
+def batch_solve(solvers, rhs, krylov):
+    """Solve every right-hand side of every system by Bi-CGSTAB: rhs[s] is a
+    contiguous complex128 CUDA tensor of shape (nrhs_s, *solvers[s].shape) on
+    that solver's device; krylov is one Krylov for all systems or a list with
+    one per system.  Returns (solutions, stats)."""
     torch = _torch()
     n = len(solvers)
-    for S in solvers:
-        S._ensure_workspace(krylov)
+    krs = list(krylov) if isinstance(krylov, (list, tuple)) else [krylov] * n
+    if len(rhs) != n or len(krs) != n:
+        raise ValueError(f"{n} solvers need {n} right-hand side tensors and Krylov settings "
+                         f"(got {len(rhs)} and {len(krs)})")
+    if len({id(S) for S in solvers}) != n:
+        raise ValueError("a solver appears twice in the batch")
+    for q, (S, b, kr) in enumerate(zip(solvers, rhs, krs)):
+        if kr.method != "bicgstab":
+            raise ValueError(f"system {q}: the batched solve uses Bi-CGSTAB, got {kr.method}")
+        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.complex128 and b.is_contiguous()
+                and b.dim() == len(S.shape) + 1 and tuple(b.shape[1:]) == S.shape and b.device == S.device):
+            desc = f"{b.dtype} {tuple(b.shape)}" if isinstance(b, torch.Tensor) else type(b).__name__
+            raise ValueError(f"system {q}: rhs must be a contiguous complex128 CUDA tensor of shape "
+                             f"(nrhs, {', '.join(map(str, S.shape))}) on {S.device}, got {desc}")
+    for S, kr in zip(solvers, krs):
+        S._ensure_workspace(kr)
     xs = [torch.empty_like(b) for b in rhs]
     ctxs = (ctypes.c_void_p * n)(*[S._h.value for S in solvers])
     bs = (ctypes.c_void_p * n)(*[b.data_ptr() for b in rhs])
     xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
     nr = (ctypes.c_int * n)(*[int(b.shape[0]) for b in rhs])
     st = (Stats * n)()
-    d = krylov.to_c()
+    descs = [kr.to_c() for kr in krs]
+    dp = (ctypes.POINTER(SolveDesc) * n)(*[ctypes.pointer(d) for d in descs])
     with _StreamOrder([S.stream for S in solvers], tuple(xs)):
-        rc = lib().ecs_batch_solve(n, ctxs, ctypes.byref(d), bs, xp, nr, st)
+        rc = lib().ecs_batch_solve(n, ctxs, dp, bs, xp, nr, st)
     if rc < 0:
-        raise EcsError(rc, "batched solve failed")
+        msg = "; ".join(lib().ecs_last_error(S._h).decode() for S in solvers if lib().ecs_last_error(S._h))
+        raise EcsError(rc, msg or "batched solve failed")
     return xs, [s.as_dict() for s in st]
 
 

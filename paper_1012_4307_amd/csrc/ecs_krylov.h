@@ -81,6 +81,8 @@ void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cpl
 template <typename RI, typename RO>
 void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s);
 void launch_cast_real(const double *x, float *y, int64_t n, hipStream_t s);
+// FP32 -> FP64 real array (exact)
+void launch_widen_real(const float *x, double *y, int64_t n, hipStream_t s);
 template <typename R>
 void launch_zero(cplx<R> *x, int64_t n, hipStream_t s);
 void launch_scale_w(int n0, int n1, int n2, const cplx<double> *w0, const cplx<double> *w1, const cplx<double> *w2,

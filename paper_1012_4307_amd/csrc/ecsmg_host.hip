@@ -84,7 +84,12 @@ struct ecs_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   Side side[3][2];
+  // k^2 as handed over (borrowed), its dtype, and the FP64 array the kernels
+  // read: the caller's own array for FP64, else a copy widened at set-up
+  const void *k2_user = nullptr;
+  int k2_dtype = ECS_F64;
   const double *k2 = nullptr;
+  double *k2_wide = nullptr;
   bool have_prec = false;
   ecs_prec_desc prec{};
   int nlev = 0;
@@ -224,6 +229,7 @@ void build_host_levels(ecs_ctx *C) {
 // ------------------------------------------------------ workspace plan
 size_t plan_layout(ecs_ctx *C, Carver &cv) {
   const bool f32 = C->prec.vcycle_dtype == ECS_F32;
+  C->k2_wide = C->k2_dtype == ECS_F32 ? cv.take<double>(C->hl[0].nn) : nullptr;
   for (int a = 0; a < C->dim; a++) {
     C->Acm[a] = cv.take<cplx<double>>(C->hl[0].n[a]);
     C->Acp[a] = cv.take<cplx<double>>(C->hl[0].n[a]);
@@ -283,6 +289,7 @@ size_t plan_hierarchy(ecs_ctx *C, char *base) {
     probe.dim = C->dim;
     probe.nlev = C->nlev;
     probe.prec = C->prec;
+    probe.k2_dtype = C->k2_dtype;
     probe.hl = C->hl;
     Carver cv(nullptr);
     return plan_layout(&probe, cv);
@@ -508,6 +515,13 @@ ecs_status setup(ecs_ctx *C) {
   const bool f32 = C->prec.vcycle_dtype == ECS_F32;
   hipStream_t s = C->stream;
   const int64_t nn0 = nn_of(C);
+  // the kernels read k^2 in FP64: an FP32 field is widened (exactly) once here
+  if (C->k2_dtype == ECS_F32) {
+    launch_widen_real(reinterpret_cast<const float *>(C->k2_user), C->k2_wide, nn0, s);
+    C->k2 = C->k2_wide;
+  } else {
+    C->k2 = reinterpret_cast<const double *>(C->k2_user);
+  }
   // operator scalars of M (Sec. 5)
   const ecs_prec_desc &P = C->prec;
   double lam0 = 0;
@@ -1416,6 +1430,7 @@ ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, co
 // taken one after the other (its workspace holds one solve's vectors).
 struct BatchItem {
   ecs_ctx *C = nullptr;
+  const ecs_solve_desc *d = nullptr;  // this system's Krylov settings
   KrylovBufs K;
   const cplx<double> *b0 = nullptr;
   cplx<double> *x0 = nullptr;
@@ -1514,13 +1529,18 @@ void batch_process(BatchItem &I, const ecs_solve_desc *d) {
 // (an event per context, polled by the host), so systems of different sizes
 // progress independently and the device holds work from every stream.  Each
 // system runs exactly the kernel sequence of its single solve.
-ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *d, const void *const *b,
+ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *const *descs, const void *const *b,
                             void *const *x, const int *nrhs, ecs_stats *stats) {
   std::vector<BatchItem> items(n);
   for (int q = 0; q < n; q++) {
     ecs_ctx *C = ctxs[q];
     ecs_status st = check_ready(C);
     if (st != ECS_OK) return st;
+    const ecs_solve_desc *d = descs[q];
+    if (!d) return fail(C, ECS_EINVAL, "null solve descriptor");
+    if (d->krylov != ECS_KRYLOV_BICGSTAB) return fail(C, ECS_EINVAL, "the batched solve uses Bi-CGSTAB");
+    if (!(d->rtol > 0) || d->maxit < 0) return fail(C, ECS_EINVAL, "rtol must be > 0, maxit >= 0");
+    if (nrhs[q] > 0 && (!b[q] || !x[q])) return fail(C, ECS_EINVAL, "null right-hand side or solution pointer");
     for (int p = 0; p < q; p++)
       if (ctxs[p] == C) return fail(C, ECS_EINVAL, "a context appears twice in the batch");
     if (nrhs[q] < 0) return fail(C, ECS_EINVAL, "negative right-hand side count");
@@ -1532,6 +1552,7 @@ ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *d
     }
     plan_krylov(C, d, C->ws + C->hier_bytes, &items[q].K);
     items[q].C = C;
+    items[q].d = d;
     items[q].b0 = reinterpret_cast<const cplx<double> *>(b[q]);
     items[q].x0 = reinterpret_cast<cplx<double> *>(x[q]);
     items[q].nrhs = nrhs[q];
@@ -1540,7 +1561,7 @@ ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *d
   int active = 0;
   for (auto &I : items) {
     if (I.phase == 3) continue;
-    batch_enqueue(I, d);
+    batch_enqueue(I, I.d);
     if (hipEventRecord(I.C->step_ev, I.C->stream) != hipSuccess) return ECS_EDEVICE;
     active++;
   }
@@ -1550,12 +1571,12 @@ ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *d
       const hipError_t q = hipEventQuery(I.C->step_ev);
       if (q == hipErrorNotReady) continue;
       if (q != hipSuccess) return fail(I.C, ECS_EDEVICE, std::string("batched solve: ") + hipGetErrorString(q));
-      batch_process(I, d);
+      batch_process(I, I.d);
       if (I.phase == 3) {
         active--;
         continue;
       }
-      batch_enqueue(I, d);
+      batch_enqueue(I, I.d);
       if (hipEventRecord(I.C->step_ev, I.C->stream) != hipSuccess) return ECS_EDEVICE;
     }
   }
@@ -1649,6 +1670,7 @@ ecs_status coupled_fgmres(int nb, ecs_ctx *const *ctx, const double *k2c, const 
   std::vector<const void *> bp(nb);
   std::vector<void *> xp(nb);
   std::vector<int> ones(nb, 1);
+  std::vector<const ecs_solve_desc *> inner_descs(nb, inner);
   int it = 0;
   ecs_status status = ECS_NOT_CONVERGED;
   for (;;) {
@@ -1672,7 +1694,8 @@ ecs_status coupled_fgmres(int nb, ecs_ctx *const *ctx, const double *k2c, const 
           xp[i] = zj + i * nn;
         }
         HIP_OK(hipStreamSynchronize(s));
-        const ecs_status ist = batch_solve_impl(nb, ctx, inner, bp.data(), xp.data(), ones.data(), bst.data());
+        const ecs_status ist =
+            batch_solve_impl(nb, ctx, inner_descs.data(), bp.data(), xp.data(), ones.data(), bst.data());
         if (ist < 0) { status = ist; bad = true; break; }
         for (int i = 0; i < nb; i++) {
           st->vcycles += bst[i].vcycles;
@@ -1802,10 +1825,13 @@ ecs_status ecs_set_ecs(ecs_ctx *C, int axis, int side, int kind, double start, d
   return ECS_OK;
 }
 
-ecs_status ecs_set_k2(ecs_ctx *C, const double *k2_dev) {
+ecs_status ecs_set_k2(ecs_ctx *C, const void *k2_dev, int real_dtype) {
   if (!C) return ECS_EINVAL;
   if (!k2_dev) return fail(C, ECS_EINVAL, "k2 is null");
-  C->k2 = k2_dev;
+  if (real_dtype != ECS_F64 && real_dtype != ECS_F32) return fail(C, ECS_EINVAL, "k2 dtype must be F64 or F32");
+  C->k2_user = k2_dev;
+  C->k2_dtype = real_dtype;
+  C->k2 = nullptr;
   C->ready = false;
   return ECS_OK;
 }
@@ -1856,7 +1882,7 @@ ecs_status ecs_workspace_size(ecs_ctx *C, const ecs_solve_desc *d, size_t *bytes
 
 ecs_status ecs_set_workspace(ecs_ctx *C, void *dev, size_t bytes) {
   if (!C) return ECS_EINVAL;
-  if (!C->have_prec || !C->k2) return fail(C, ECS_ESTATE, "set k2 and the preconditioner first");
+  if (!C->have_prec || !C->k2_user) return fail(C, ECS_ESTATE, "set k2 and the preconditioner first");
   if (!dev || ((uintptr_t)dev % 256) != 0) return fail(C, ECS_EINVAL, "workspace must be 256-byte aligned");
   build_host_levels(C);
   size_t hb = plan_hierarchy(C, nullptr);
@@ -2170,12 +2196,12 @@ ecs_status ecs_timing_read(ecs_ctx *C, int kclass, int64_t *launches, double *to
   return ECS_OK;
 }
 
-ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *desc, const void *const *b,
+ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *const *desc, const void *const *b,
                            void *const *x, const int *nrhs, ecs_stats *stats) {
   if (n < 0 || (n > 0 && (!ctxs || !desc || !b || !x || !nrhs))) return ECS_EINVAL;
   if (n == 0) return ECS_OK;
-  if (desc->krylov != ECS_KRYLOV_BICGSTAB) return fail(ctxs[0], ECS_EINVAL, "the batched solve uses Bi-CGSTAB");
-  if (!(desc->rtol > 0) || desc->maxit < 0) return fail(ctxs[0], ECS_EINVAL, "rtol must be > 0, maxit >= 0");
+  for (int q = 0; q < n; q++)
+    if (!ctxs[q]) return ECS_EINVAL;
   auto t0 = std::chrono::steady_clock::now();
   ecs_status st = batch_solve_impl(n, ctxs, desc, b, x, nrhs, stats);
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

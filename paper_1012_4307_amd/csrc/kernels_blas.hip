@@ -328,6 +328,9 @@ __global__ __launch_bounds__(BS) void k_cast(const cplx<RI> *__restrict__ x, cpl
 __global__ __launch_bounds__(BS) void k_cast_real(const double *__restrict__ x, float *__restrict__ y, int64_t n) {
   for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) y[p] = (float)x[p];
 }
+__global__ __launch_bounds__(BS) void k_widen_real(const float *__restrict__ x, double *__restrict__ y, int64_t n) {
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) y[p] = (double)x[p];
+}
 template <typename R>
 __global__ __launch_bounds__(BS) void k_zero(cplx<R> *__restrict__ x, int64_t n) {
   for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) x[p] = mk<R>(0, 0);
@@ -515,6 +518,9 @@ void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s) {
 }
 void launch_cast_real(const double *x, float *y, int64_t n, hipStream_t s) {
   launch_k(k_cast_real, dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
+}
+void launch_widen_real(const float *x, double *y, int64_t n, hipStream_t s) {
+  launch_k(k_widen_real, dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
 }
 template <typename R>
 void launch_zero(cplx<R> *x, int64_t n, hipStream_t s) {

@@ -47,7 +47,7 @@ def test_create_rejects_bad_arguments_without_a_device():
 
 def test_null_context_is_rejected():
     lib = E.lib()
-    assert lib.ecs_set_k2(None, None) == -1
+    assert lib.ecs_set_k2(None, None, 0) == -1
     assert lib.ecs_apply(None, 0, None, None) == -1
     assert lib.ecs_solve(None, None, None, None, None) == -1
     assert lib.ecs_last_error(None) == b"null context"

@@ -208,6 +208,37 @@ def test_qd_constant_k_equals_scaled_csl():
     assert np.abs(zq - k2 * zc).max() < 1e-10 * np.abs(zq).max()
 
 
+@pytest.mark.parametrize("E_,maxk2,minre", [(0.5, 3.0, 1.874), (4.0, 10.0, 8.874)])
+def test_qd_automatic_lambda0(E_, maxk2, minre):
+    """Sec. 5: without a better estimate, |Re lambda0| is taken as the largest
+    wavenumber squared on the grid.  For the soft-Coulomb field
+    k^2 = 2(E + 1/sqrt(r^2+1)) on [-10,10]^2 the maximum sits at the origin,
+    2(E+1), a grid node at 33^2.  The rough rule over-estimates the most
+    negative real eigenvalue of the discrete Z (dense eig: -1.874 and -8.874),
+    and then the Sec. 4.1 disk |mu - c| <= |c| still holds for M_QD^{-1} Z."""
+    w = W.coulomb(E=E_, n=33)
+    P = oracle.Problem(2, w.n, w.lo, w.hi, w.ecs, w.k2, 1)
+    lam = P.set_operator("qd", 0.0)
+    assert lam == pytest.approx(maxk2, abs=1e-12)
+    A, _ = P.dense("A")
+    ev = np.linalg.eigvals(A)
+    assert ev.real.min() == pytest.approx(-minre, abs=5e-4)
+    assert lam >= -ev.real.min()
+    M, _ = P.dense("M")
+    mu = np.linalg.eigvals(np.linalg.solve(M, A))
+    c = lam * (1 - 1j) / 2
+    assert np.max(np.abs(mu - c) / abs(c)) <= 1 + 1e-9
+    # the rule reads every fine node, also layer and Dirichlet-edge nodes, at
+    # odd indices (not on any coarser grid): a maximum only there is found
+    for (j, i) in [(16, 31), (0, 15), (21, 0), (32, 7)]:
+        k2 = w.k2.copy()
+        k2[j, i] = 7.0 * maxk2
+        Q = oracle.Problem(2, w.n, w.lo, w.hi, w.ecs, k2, 2)
+        assert Q.set_operator("qd", 0.0) == 7.0 * maxk2, (j, i)
+    # an explicit Re lambda0 is used by magnitude, whatever its sign
+    assert P.set_operator("qd", -2.5) == 2.5 and P.set_operator("qd", 2.5) == 2.5
+
+
 def test_csg_is_rotated_laplacian():
     """Sec. 5: Z on the grid rotated by e^{i theta_a}.  Every difference weight
     is homogeneous of degree -2 in the mesh widths, so L_rot = e^{-2 i theta_a} L."""
