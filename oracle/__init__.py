@@ -74,6 +74,8 @@ def _load():
     lib.ora_solve.argtypes = [P, Ii, Ii, Ii, Ii, D, Ii, P, P, P]
     lib.ora_solve.restype = Ii
     lib.ora_num_threads.restype = Ii
+    lib.ora_set_threads.argtypes = [Ii]
+    lib.ora_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -84,6 +86,11 @@ def _ptr(a: np.ndarray):
 
 def num_threads() -> int:
     return int(_load().ora_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (timing only)."""
+    _load().ora_set_threads(int(n))
 
 
 def zmap(n: int, lo: float, hi: float, ecs_lo=None, ecs_hi=None) -> np.ndarray:

@@ -875,3 +875,13 @@ int ora_num_threads(void) {
   return 1;
 #endif
 }
+
+/* threads of the parallel loops from now on (timing only; the reductions'
+ * summation order, and so their last bits, depends on the count) */
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -27,6 +27,7 @@ class HelmholtzSolve(torch.autograd.Function):
         if st["status"] != 0:
             raise RuntimeError(f"forward solve did not converge: {st}")
         ctx.solver = solver
+        ctx.k2_dtype = k2.dtype
         ctx.adjoint_krylov = adjoint_krylov or krylov
         ctx.save_for_backward(u)
         ctx.stats = st
@@ -39,13 +40,14 @@ class HelmholtzSolve(torch.autograd.Function):
         lam, st = S.solve_adjoint(torch.conj(grad_u).resolve_conj().contiguous(), krylov=ctx.adjoint_krylov)
         if st["status"] != 0:
             raise RuntimeError(f"adjoint solve did not converge: {st}")
-        grad_k2 = S.grad_k2(lam, u) if ctx.needs_input_grad[0] else None
+        # the gradient is formed in FP64 and returned in k2's own dtype
+        grad_k2 = S.grad_k2(lam, u).to(ctx.k2_dtype) if ctx.needs_input_grad[0] else None
         grad_f = torch.conj(lam).resolve_conj() if ctx.needs_input_grad[1] else None
         return grad_k2, grad_f, None, None, None
 
 
 def helmholtz_solve(solver: Solver, k2: torch.Tensor, f: torch.Tensor, krylov: Optional[Krylov] = None,
                     adjoint_krylov: Optional[Krylov] = None) -> torch.Tensor:
-    """u = A(k2)^{-1} f on the solver's grid, differentiable in k2 (float64)
-    and f (complex128).  The solver is re-pointed at k2 when it changes."""
+    """u = A(k2)^{-1} f on the solver's grid, differentiable in k2 (float64 or
+    float32) and f (complex128).  The solver is re-pointed at k2 when it changes."""
     return HelmholtzSolve.apply(k2, f, solver, krylov, adjoint_krylov)

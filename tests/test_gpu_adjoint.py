@@ -91,6 +91,48 @@ def test_autograd_gradient_vs_oracle():
     assert relerr(to_np(u.detach()), uo) < 1e-9
 
 
+def test_autograd_gradient_vs_oracle_1025():
+    """The adjoint workload at its full size, 1025^2 (E = 2, 64 x 64 sampler,
+    data from the +5% bump): the GPU gradient (forward and adjoint FGMRES(40)
+    solves at 1e-12) against the oracle's, whose A^T is assembled explicitly,
+    both oracle solves at 1e-11.  At this size central differences with
+    eps = 1e-6 sit at the loss's rounding floor, so the oracle gradient is the
+    full-size reference; FD is checked at 129^2 above."""
+    import time
+    import torch
+    from paper_1012_4307_amd.autograd import helmholtz_solve
+    tight = E.Krylov(method="fgmres", restart=40, rtol=1e-12, maxit=40000)
+    w, k2_true, idx, _ = W.adjoint_case(n=1025)
+    S = gpu_for(w, "f64", krylov=tight)
+    f = to_gpu(w.rhs[0])
+    St = gpu_for(W.Workload(w.name, 2, w.n, w.lo, w.hi, w.ecs, k2_true, w.rhs, w.precond, w.cycle, w.krylov,
+                            w.nlev), "f64", krylov=tight)
+    u_true, st = St.solve(f)
+    assert st["status"] == 0
+    del St
+    ii = torch.as_tensor(idx, device="cuda")
+    d = u_true[ii][:, ii]
+    k2 = to_gpu(w.k2).requires_grad_(True)
+    u = helmholtz_solve(S, k2, f, krylov=tight)
+    r = u[ii][:, ii] - d
+    (g,) = torch.autograd.grad(0.5 * (r.real ** 2 + r.imag ** 2).sum(), k2)
+    g, un, dn = to_np(g), to_np(u.detach()), to_np(d)
+    t0 = time.perf_counter()
+    P = oracle_for(w)
+    uo, sto = P.solve(w.rhs[0], "gmres", 40, 1e-11, 40000)
+    assert sto["status"] == 0, sto
+    gg = np.zeros(w.shape, complex)
+    gg[np.ix_(idx, idx)] = uo[np.ix_(idx, idx)] - dn
+    lam, sta = P.solve(np.conj(gg), "gmres", 40, 1e-11, 40000, transpose=True)
+    assert sta["status"] == 0, sta
+    go = (lam * uo).real
+    err_u, err_g = relerr(un, uo), relerr(g, go)
+    print(f"1025^2 oracle: {sto['iterations']} + {sta['iterations']} iterations in {time.perf_counter() - t0:.1f} s; "
+          f"relerr u {err_u:.2e}, gradient {err_g:.2e}", flush=True)
+    assert err_u < 1e-8
+    assert err_g < 1e-7
+
+
 def test_autograd_gradient_wrt_rhs():
     """dL/df = conj(lam): checked by central differences along random complex
     directions of f."""

@@ -86,9 +86,9 @@ def test_coulomb_513():
 
 
 def test_mixed_fgmres_vs_fp64_oracle():
-    """Mixed form (FP32 cycle inside FP64 FGMRES(40)) on the benchmark operator
-    family at a reduced size (513^2, h = 0.25): both sides at 1e-12, relative
-    error <= 1e-6."""
+    """Mixed form (FP32 cycle inside FP64 FGMRES(40), with 0 or 2 nested FP32
+    Bi-CGSTAB iterations) on the benchmark operator family at a reduced size
+    (257^2, h = 0.25): both sides at 1e-12, relative error <= 1e-6."""
     w = W.large_coulomb(n=257, coarsest=9)
     P = oracle_for(w)
     xo, sto = P.solve(w.rhs[0], "fgmres", 40, 1e-12, 20000)
@@ -100,6 +100,74 @@ def test_mixed_fgmres_vs_fp64_oracle():
         assert st["status"] == 0, (dt, inner, st)
         assert relerr(to_np(x), xo) < 1e-6, (dt, inner)
         assert st["rel_residual"] <= 1e-12
+
+
+def test_headline_mixed_inner16_vs_fp64_oracle():
+    """The benchmark's solver configuration -- FP64 FGMRES(40) around 16
+    nested complex-FP32 Bi-CGSTAB iterations of the FP32 V(1,1) cycle, QD,
+    9 levels -- on the benchmark operator family at 513^2 (h = 0.25, domain
+    [-64, 64]^2): against the oracle's FP64 FGMRES(40) solution at 1e-12, at
+    the benchmark's tolerance 1e-8 and at 1e-12 (relative error <= 1e-6 both;
+    the true residual of each recomputed with the oracle's operator)."""
+    w = W.large_coulomb(n=513, coarsest=9)
+    P = oracle_for(w)
+    b = w.rhs[0]
+    xo, sto = P.solve(b, "fgmres", 40, 1e-12, 20000)
+    assert sto["status"] == 0, sto
+    for rtol in (1e-8, 1e-12):
+        kr = E.Krylov(method="fgmres", restart=40, rtol=rtol, maxit=20000, inner=16)
+        S = gpu_for(w, "f32", krylov=kr)
+        x, st = S.solve(to_gpu(b))
+        assert st["status"] == 0, (rtol, st)
+        x = to_np(x)
+        err = relerr(x, xo)
+        res = oracle_resid(P, x, b)
+        print(f"rtol {rtol:g}: outer {st['iterations']} inner {st['inner_iterations']} "
+              f"relerr vs oracle {err:.3e} oracle residual {res:.3e}", flush=True)
+        assert res <= 1.05 * rtol, (rtol, res)
+        assert err < 1e-6, (rtol, err)
+
+
+def test_automatic_lambda0_matches_oracle():
+    """QD with |Re lambda0| left to the rule of Sec. 5 (the largest k^2 over
+    every fine node): with the maximum placed on a Dirichlet edge row and at a
+    layer node at odd indices, the GPU cycle equals the oracle's cycle with
+    the same automatic value."""
+    w = ragged_workload(n=97, coarsest=4)
+    for (j, i) in [(0, 37), (49, 95)]:
+        k2 = w.k2.copy()
+        k2[j, i] = 3.0 * w.k2.max()
+        w2 = W.Workload(w.name, 2, w.n, w.lo, w.hi, w.ecs, k2, w.rhs, w.precond, w.cycle, w.krylov, w.nlev)
+        P = oracle_for(w2)
+        assert P.lam0 == k2[j, i]
+        S = gpu_for(w2, "f64")
+        assert relerr(to_np(S.vcycle(to_gpu(w.rhs[0]))), P.mg_apply(w.rhs[0])) < 1e-12, (j, i)
+
+
+def test_fp32_k2_equals_widened_fp64():
+    """ecs_set_k2 with an FP32 field: the library widens it exactly, so the
+    solve equals the one given the same values in FP64 (bit for bit), and the
+    oracle on those values confirms the residual."""
+    import torch
+    w = W.coulomb(E=1.0, n=257)
+    k2_32 = w.k2.astype(np.float32)
+    k2_64 = k2_32.astype(np.float64)
+    w64 = W.Workload(w.name, 2, w.n, w.lo, w.hi, w.ecs, k2_64, w.rhs, w.precond, w.cycle, w.krylov, w.nlev)
+    S64 = gpu_for(w64, "f64")
+    x64, st64 = S64.solve(to_gpu(w.rhs[0]))
+    S32 = gpu_for(w64, "f64")
+    S32.reset_k2(torch.from_numpy(k2_32).to("cuda"))
+    x32, st32 = S32.solve(to_gpu(w.rhs[0]))
+    assert st32["status"] == 0 and st32["iterations"] == st64["iterations"]
+    assert torch.equal(x32, x64)
+    P = oracle_for(w64)
+    assert oracle_resid(P, to_np(x32), w.rhs[0]) <= 1.05e-8
+    # and a solver made from the FP32 field directly, FP32 cycle
+    pc = E.Precond(kind="qd", smoother="rbgs", omega=1.0, coarsest_nodes=5, vcycle_dtype="f32")
+    S = E.Solver(2, w.n, w.lo, w.hi, w.ecs, torch.from_numpy(k2_32).to("cuda"), pc,
+                 E.Krylov(method="bicgstab", rtol=1e-8, maxit=2000))
+    x, st = S.solve(to_gpu(w.rhs[0]))
+    assert st["status"] == 0 and oracle_resid(P, to_np(x), w.rhs[0]) <= 1.05e-8
 
 
 @pytest.mark.parametrize("case", ["coulomb257", "ragged193"])
@@ -224,8 +292,11 @@ def test_adjoint_solve_and_gradient():
         assert abs(fd - grad[j, i]) <= 1e-5 * abs(fd) + 1e-12, (j, i, fd, grad[j, i])
 
 
-def test_3d_solve():
-    w = W.cube_constant_k(n=17, k=6.0)
+@pytest.mark.parametrize("n,k", [(17, 6.0), (65, 12.0)])
+def test_3d_solve(n, k):
+    """3D 7-point solves (QD, V(1,1) red-black, FGMRES(30) to 1e-8) against
+    the oracle's 1e-13 solution; 65^3 spans two x-tiles of the 3D kernels."""
+    w = W.cube_constant_k(n=n, k=k)
     P = oracle_for(w)
     S = gpu_for(w, "f64")
     x, st = S.solve(to_gpu(w.rhs[0]))
@@ -233,3 +304,17 @@ def test_3d_solve():
     xo, _ = P.solve(w.rhs[0], "fgmres", 30, 1e-13, 3000)
     assert relerr(to_np(x), xo) < 1e-5
     assert oracle_resid(P, to_np(x), w.rhs[0]) <= 1.05e-8
+
+
+def test_3d_solve_129_residual_by_oracle():
+    """The 3D case of the benchmark set: 129^3 at constant k = 12, QD + V(1,1)
+    red-black over 6 levels, FGMRES(30) to 1e-8; the true residual of the GPU
+    solution recomputed with the oracle's operator."""
+    w = W.cube_constant_k(n=129)
+    P = oracle_for(w)
+    S = gpu_for(w, "f64")
+    x, st = S.solve(to_gpu(w.rhs[0]))
+    assert st["status"] == 0, st
+    res = oracle_resid(P, to_np(x), w.rhs[0])
+    print(f"129^3: {st['iterations']} iterations, oracle residual {res:.3e}", flush=True)
+    assert res <= 1.05e-8

@@ -251,6 +251,32 @@ def test_3d_steps_and_cycle():
     assert relerr(to_np(S32.vcycle(to_gpu(b))), P.mg_apply(b)) < 2e-4
 
 
+@pytest.mark.parametrize("n,coarsest", [(97, 4), (65, 5)])
+def test_3d_steps_and_cycle_wide(n, coarsest):
+    """3D grids wider than one 64-node x-tile of the 3D kernels (97^3 ragged,
+    unsymmetric layers, random k^2; 65^3 one node over the tile): every step
+    and one cycle (both dtypes) against the oracle."""
+    w = ragged_workload(n=n, coarsest=coarsest, dim=3, seed=33)
+    P = oracle_for(w)
+    S = gpu_for(w, "f64")
+    rng = np.random.default_rng(11)
+    x = W.random_complex(w.shape, rng)
+    for op in ("A", "M", "AT"):
+        y = to_np(S.apply(to_gpu(x), op))
+        assert relerr(y, P.apply(x, which=op)) < 1e-13, op
+        assert np.all(y[0] == 0) and np.all(y[:, :, -1] == 0)
+    b = W.random_complex(w.shape, rng)
+    assert relerr(to_np(S.smooth(to_gpu(b), to_gpu(x))), P.smooth(b, x)) < 1e-13
+    rc = to_np(S.residual_restrict(to_gpu(b), to_gpu(x)))
+    assert relerr(rc, P.restrict(P.residual(b, x))) < 1e-13
+    ec = W.random_complex(S.level_shape(1), rng)
+    assert relerr(to_np(S.prolong_correct(to_gpu(ec), to_gpu(x))), P.prolong_add(ec, x)) < 1e-13
+    ref = P.mg_apply(b)
+    assert relerr(to_np(S.vcycle(to_gpu(b))), ref) < 1e-12
+    S32 = gpu_for(w, "f32")
+    assert relerr(to_np(S32.vcycle(to_gpu(b))), ref) < 2e-4
+
+
 def test_full_size_vcycle_sampled():
     """The benchmark grid (2049^2, h = 0.25, 9 levels): one FP64 cycle checked
     against the oracle on the whole grid (one oracle cycle takes seconds)."""
