@@ -161,6 +161,23 @@ ecs_status ecs_set_workspace(ecs_ctx *ctx, void *dev, size_t bytes);
 /* Solve A x = b (Sec. 5).  b, x: complex128 device arrays. */
 ecs_status ecs_solve(ecs_ctx *ctx, const ecs_solve_desc *desc, const void *b_dev, void *x_dev, ecs_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): ecs_solve with
+ * the Krylov vectors in the library's static device scratch instead of the
+ * workspace.  Same arguments, method, results and statuses as ecs_solve; the
+ * call itself allocates nothing (no hipMalloc/hipFree, no graph, no event):
+ * the cycle is launched eagerly whatever ecs_set_graphs says, and kernel
+ * timers are not recorded.  The context's workspace need only hold the
+ * hierarchy (ecs_workspace_size with desc = NULL).  Limit: the Krylov storage
+ * of the solve must fit the scratch, 64 MiB per device (Bi-CGSTAB up to about
+ * 513^2 nodes, GMRES(30) up to about 257^2); larger ones return ECS_ENOMEM
+ * with the size in ecs_last_error.  Every call on one GPU shares that GPU's
+ * scratch (it keeps the last call's contents; each solve initialises what it
+ * reads): calls that overlap on one GPU, from different streams or threads,
+ * race and must be serialised by the caller. */
+ecs_status ecs_solve_static(ecs_ctx *ctx, const ecs_solve_desc *desc, const void *b_dev, void *x_dev,
+                            ecs_stats *stats);
+
 /* Solve A^T lam = g (plain transpose, no conjugation) with the same
  * preconditioner, through the similarity A^T = W A W^{-1}, W = diag of the
  * products of the dual cell widths w_i = (h_{i-1} + h_i)/2. */

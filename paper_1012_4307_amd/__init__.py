@@ -93,6 +93,7 @@ def lib():
         "ecs_workspace_size": [P, ctypes.POINTER(SolveDesc), ctypes.POINTER(Z)],
         "ecs_set_workspace": [P, P, Z],
         "ecs_solve": [P, ctypes.POINTER(SolveDesc), P, P, ctypes.POINTER(Stats)],
+        "ecs_solve_static": [P, ctypes.POINTER(SolveDesc), P, P, ctypes.POINTER(Stats)],
         "ecs_solve_adjoint": [P, ctypes.POINTER(SolveDesc), P, P, ctypes.POINTER(Stats)],
         "ecs_grad_k2": [P, P, P, P],
         "ecs_apply": [P, I, P, P],
@@ -134,7 +135,8 @@ EXPORTED = ["ecs_create", "ecs_set_ecs", "ecs_set_k2", "ecs_set_precond", "ecs_w
             "ecs_residual_restrict", "ecs_prolong_correct", "ecs_coarse_solve", "ecs_level_info",
             "ecs_timing_enable", "ecs_timing_read", "ecs_batch_solve", "ecs_copy_probe", "ecs_last_error",
             "ecs_destroy", "ecs_set_graphs", "ecs_set_tuning", "ecs_get_tuning", "ecs_timing_calibrate",
-            "ecs_vcycle_native", "ecs_mg_solve", "ecs_coupled_workspace_size", "ecs_coupled_solve"]
+            "ecs_vcycle_native", "ecs_mg_solve", "ecs_coupled_workspace_size", "ecs_coupled_solve",
+            "ecs_solve_static"]
 
 
 def _torch():
@@ -233,9 +235,12 @@ class Solver:
     precond        : Precond
     krylov         : Krylov settings used to size the workspace (larger ones
                      reallocate it on demand)
+    hierarchy_only : size the workspace for the hierarchy alone (enough for
+                     the single-step calls and solve_static)
     """
 
-    def __init__(self, dim, n, lo, hi, ecs, k2, precond: Precond, krylov: Optional[Krylov] = None):
+    def __init__(self, dim, n, lo, hi, ecs, k2, precond: Precond, krylov: Optional[Krylov] = None,
+                 hierarchy_only: bool = False):
         torch = _torch()
         L = lib()
         self.dim = int(dim)
@@ -267,7 +272,7 @@ class Solver:
         self._check(L.ecs_set_precond(h, ctypes.byref(self._pd)))
         self.nlev = self.level_count()
         self.ws = None
-        self._ensure_workspace(self.krylov)
+        self._ensure_workspace(None if hierarchy_only else self.krylov)
 
     # ------------------------------------------------------------------
     def _check(self, rc, h="self"):
@@ -310,12 +315,12 @@ class Solver:
         with _StreamOrder([self.stream], (ws,)):
             self._check(lib().ecs_set_workspace(self._h, ctypes.c_void_p(base + off), nbytes - off))
 
-    def _ensure_workspace(self, kr: Krylov):
+    def _ensure_workspace(self, kr: Optional[Krylov]):
         torch = _torch()
         L = lib()
         need = ctypes.c_size_t()
-        d = kr.to_c()
-        self._check(L.ecs_workspace_size(self._h, ctypes.byref(d), ctypes.byref(need)))
+        d = kr.to_c() if kr is not None else None
+        self._check(L.ecs_workspace_size(self._h, ctypes.byref(d) if d is not None else None, ctypes.byref(need)))
         if self.ws is not None and self.ws.numel() >= need.value:
             return
         self.ws = torch.empty(need.value + 256, dtype=torch.uint8, device=self.device)
@@ -373,6 +378,25 @@ class Solver:
         d = kr.to_c(x0 is not None, history)
         with _StreamOrder([self.stream], (x,)):
             rc = lib().ecs_solve(self._h, ctypes.byref(d), _ptr(b), _ptr(x), ctypes.byref(st))
+        if rc < 0:
+            self._check(rc)
+        out = st.as_dict()
+        out["status_name"] = STATUS.get(rc, rc)
+        return x, out
+
+    def solve_static(self, b, x0=None, krylov: Optional[Krylov] = None, history=None):
+        """Solve A x = b through ecs_solve_static: the Krylov vectors live in
+        the library's static device scratch, so the call allocates nothing on
+        the device beyond the output tensor (the workspace is not grown);
+        returns (x, stats dict)."""
+        torch = _torch()
+        kr = krylov or self.krylov
+        b = self._vec(b)
+        x = x0.clone() if x0 is not None else torch.empty_like(b)
+        st = Stats()
+        d = kr.to_c(x0 is not None, history)
+        with _StreamOrder([self.stream], (x,)):
+            rc = lib().ecs_solve_static(self._h, ctypes.byref(d), _ptr(b), _ptr(x), ctypes.byref(st))
         if rc < 0:
             self._check(rc)
         out = st.as_dict()

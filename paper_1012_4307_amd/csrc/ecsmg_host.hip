@@ -12,6 +12,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -23,9 +24,39 @@ using cd = std::complex<double>;
 
 thread_local KernelEvents ecs::g_kernel_events;
 
+// Device scratch of ecs_solve_static: the Krylov vectors of a solve for
+// callers that cannot allocate device memory.  Every GPU the library runs on
+// holds its own copy until the process ends.  In host code the array's name
+// stands for no device address: kernels and copies take the per-device
+// address looked up once (scratch_address) instead.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
 
 constexpr int kMaxLev = 16;
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch array (the current device), looked up on
+// the first call per device; null (and the HIP error in *err) on failure.
+char *scratch_address(int device, hipError_t *err) {
+  *err = hipSuccess;
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_ptr[device] = reinterpret_cast<char *>(p);
+  }
+  return g_scratch_ptr[device];
+}
 
 struct Side {
   int kind = ECS_BC_DIRICHLET;
@@ -119,6 +150,12 @@ struct ecs_ctx {
 
   Timer timers[kTClasses];
   std::string err;
+
+  // this device's ecs_solve_static scratch (looked up at creation); while
+  // no_alloc is set the cycle is launched eagerly (no graph is captured or
+  // instantiated) and no timer records
+  char *scratch = nullptr;
+  bool no_alloc = false;
 
   // replayable V-cycles: one instantiated graph per (input, output, dtype),
   // captured on a private stream and launched on `stream`
@@ -360,7 +397,7 @@ struct TimedScope {
   size_t slot = SIZE_MAX;
   double bytes = 0;
   TimedScope(ecs_ctx *c, int cls, double b) : C(c), T(&c->timers[cls]) {
-    if (!T->on) return;
+    if (!T->on || C->no_alloc) return;
     if (T->seen++ % T->every != 0) return;
     if (T->used + 2 > T->ev.size()) {
       if (T->ev.size() >= 2 * 65536) return;
@@ -994,7 +1031,7 @@ template <typename R>
 bool vcycle_graph(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0) {
   for (int k : {kTSmooth, kTCoarse, kTRestrict, kTProlong, kTDown, kTUp, kTDownP, kTDownS})
     if (C->timers[k].on) return false;
-  if (C->graph_mode == ECS_GRAPHS_NEVER) return false;
+  if (C->graph_mode == ECS_GRAPHS_NEVER || C->no_alloc) return false;
   if (fused_vcycle(C)) {
     if (C->graph_mode == ECS_GRAPHS_AUTO) return false;
   } else if (cycle_launches(C, 0, C->prec.gamma_f, C->prec.gamma_c, 4096) >= 4096) {
@@ -1752,7 +1789,24 @@ ecs_status coupled_fgmres(int nb, ecs_ctx *const *ctx, const double *k2c, const 
   return status;
 }
 
-ecs_status solve_impl(ecs_ctx *C, const ecs_solve_desc *d, const cplx<double> *b, cplx<double> *x, ecs_stats *st) {
+// Krylov storage of one solve: after the hierarchy in the caller's workspace,
+// or (kscratch) in this device's static scratch array.
+ecs_status plan_solve_storage(ecs_ctx *C, const ecs_solve_desc *d, char *kscratch, KrylovBufs *K) {
+  const size_t kb = plan_krylov(C, d, nullptr, K);
+  if (kscratch) {
+    if (kb > kScratchBytes)
+      return fail(C, ECS_ENOMEM, "solve needs " + std::to_string(kb >> 20) + " MiB of Krylov storage; the static "
+                                 "scratch holds " + std::to_string(kScratchBytes >> 20) + " MiB");
+    plan_krylov(C, d, kscratch, K);
+    return ECS_OK;
+  }
+  if (C->hier_bytes + kb > C->ws_bytes) return fail(C, ECS_ENOMEM, "workspace too small for this solve");
+  plan_krylov(C, d, C->ws + C->hier_bytes, K);
+  return ECS_OK;
+}
+
+ecs_status solve_impl(ecs_ctx *C, const ecs_solve_desc *d, const cplx<double> *b, cplx<double> *x, ecs_stats *st,
+                      char *kscratch = nullptr) {
   if (d->restart < 1 || d->restart > kMaxRestart) return fail(C, ECS_EINVAL, "restart must be in [1, 64]");
   if (!(d->rtol > 0) || d->maxit < 0) return fail(C, ECS_EINVAL, "rtol must be > 0 and maxit >= 0");
   if (d->krylov < 0 || d->krylov > 2) return fail(C, ECS_EINVAL, "unknown Krylov method");
@@ -1762,9 +1816,8 @@ ecs_status solve_impl(ecs_ctx *C, const ecs_solve_desc *d, const cplx<double> *b
   if (C->prec.kind == ECS_PREC_NONE && C->prec.vcycle_dtype == ECS_F32)
     return fail(C, ECS_EINVAL, "no preconditioner: use vcycle_dtype F64");
   KrylovBufs K;
-  size_t need = C->hier_bytes + plan_krylov(C, d, nullptr, &K);
-  if (need > C->ws_bytes) return fail(C, ECS_ENOMEM, "workspace too small for this solve");
-  plan_krylov(C, d, C->ws + C->hier_bytes, &K);
+  ecs_status pst = plan_solve_storage(C, d, kscratch, &K);
+  if (pst != ECS_OK) return pst;
   const bool f32 = C->prec.vcycle_dtype == ECS_F32;
   // boundary entries of b are ignored and those of a guess x are reset
   const HostLevel &F = C->hl[0];
@@ -1802,6 +1855,15 @@ ecs_status ecs_create(ecs_ctx **out, int dim, const int64_t *nodes, const double
   C->stream = reinterpret_cast<hipStream_t>(stream);
   if (hipGetDevice(&C->device) != hipSuccess ||
       hipHostMalloc((void **)&C->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+    delete C;
+    return ECS_EDEVICE;
+  }
+  // the library's set-up call on this device: look up its static scratch
+  // (with the device current) so that ecs_solve_static never has to
+  hipError_t se;
+  C->scratch = scratch_address(C->device, &se);
+  if (!C->scratch) {
+    (void)hipHostFree(C->pinned);
     delete C;
     return ECS_EDEVICE;
   }
@@ -1908,6 +1970,23 @@ ecs_status ecs_solve(ecs_ctx *C, const ecs_solve_desc *d, const void *b, void *x
   ecs_stats local{};
   auto t0 = std::chrono::steady_clock::now();
   st = solve_impl(C, d, reinterpret_cast<const cplx<double> *>(b), reinterpret_cast<cplx<double> *>(x), &local);
+  local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  local.status = st;
+  if (stats) *stats = local;
+  return st;
+}
+
+ecs_status ecs_solve_static(ecs_ctx *C, const ecs_solve_desc *d, const void *b, void *x, ecs_stats *stats) {
+  ecs_status st = check_ready(C);
+  if (st != ECS_OK) return st;
+  if (!d || !b || !x) return fail(C, ECS_EINVAL, "null argument");
+  if (!C->scratch) return fail(C, ECS_ESTATE, "no static scratch on this device");
+  ecs_stats local{};
+  auto t0 = std::chrono::steady_clock::now();
+  C->no_alloc = true;
+  st = solve_impl(C, d, reinterpret_cast<const cplx<double> *>(b), reinterpret_cast<cplx<double> *>(x), &local,
+                  C->scratch);
+  C->no_alloc = false;
   local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   local.status = st;
   if (stats) *stats = local;
