@@ -111,10 +111,10 @@ def main():
     k2 = torch.from_numpy(w.k2).to(dev)
     b = torch.from_numpy(w.rhs[0]).to(dev)
 
-    def make(dt, method, inner):
+    def make(dt, method, inner, orth="cgs2_selective"):
         pc = E.Precond(kind="qd", re_lambda0=0.0, smoother="rbgs", omega=1.0, nu1=1, nu2=1, gamma_f=1, gamma_c=1,
                        coarsest_nodes=9, vcycle_dtype=dt)
-        kr = E.Krylov(method=method, restart=args.restart, rtol=1e-8, maxit=20000, inner=inner)
+        kr = E.Krylov(method=method, restart=args.restart, rtol=1e-8, maxit=20000, inner=inner, orth=orth)
         return E.Solver(2, w.n, w.lo, w.hi, w.ecs, k2, pc, kr)
 
     Smix = make("f32", "fgmres", args.inner)
@@ -146,18 +146,29 @@ def main():
         Smix.solve(b)
         S64.solve(b)
     tmix, stmix, xmix, ktim = timed_solves(Smix, args.steps, timed_classes)
-    t64, st64, x64, _ = timed_solves(S64, args.steps)
+    # the comparison solves take longer: at most 5 timed runs each
+    t64, st64, x64, _ = timed_solves(S64, min(args.steps, 5))
     rel_diff = float((xmix - x64).abs().max() / x64.abs().max())
+    # the same nested algorithm with the FP64 cycle and FP64 inner Bi-CGSTAB:
+    # the mixed form's factor over it is the precision's share of the speedup
+    Sn64 = make("f64", "fgmres", args.inner)
+    Sn64.solve(b)
+    tn64, stn64, xn64, _ = timed_solves(Sn64, min(args.steps, 5))
+    del Sn64
 
     context = {}
     if not args.no_context:
-        for name, (dt, method, inner) in {"fgmres_fp32_cycle": ("f32", "fgmres", 0),
-                                          "bicgstab_fp64": ("f64", "bicgstab", 0)}.items():
-            S = make(dt, method, inner)
+        for name, (dt, method, inner, orth) in {
+                "fgmres_fp32_cycle": ("f32", "fgmres", 0, "cgs2_selective"),
+                "fgmres_fp64_cgs1": ("f64", "fgmres", 0, "cgs1"),
+                "fgmres_fp64_cgs2": ("f64", "fgmres", 0, "cgs2"),
+                "mixed_cgs1": ("f32", "fgmres", args.inner, "cgs1"),
+                "bicgstab_fp64": ("f64", "bicgstab", 0, "cgs2_selective")}.items():
+            S = make(dt, method, inner, orth)
             S.solve(b)
             tt, st, _, _ = timed_solves(S, 1)
             context[name] = dict(seconds=round(tt[0], 4), iterations=st["iterations"], vcycles=st["vcycles"],
-                                 rel_residual=st["rel_residual"])
+                                 rel_residual=st["rel_residual"], second_gram_schmidt_passes=st["reorthogonalisations"])
             del S
 
     # V-cycle rate (algorithmic bytes of a V(1,1) RB cycle / cycle time), on
@@ -263,7 +274,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, st64["iterations"], args.restart,
-                           {"mixed": xmix.cpu().numpy(), "fp64": x64.cpu().numpy()})
+                           {"mixed": xmix.cpu().numpy(), "fp64": x64.cpu().numpy(),
+                            "nested_fp64": xn64.cpu().numpy()})
 
     value = float(np.median(tmix))
     line = {
@@ -286,10 +298,17 @@ def main():
                    "inner_fp32_iterations": args.inner},
         "mixed": dict(seconds=round(value, 4), iterations=stmix["iterations"],
                       inner_iterations=stmix["inner_iterations"], vcycles=stmix["vcycles"],
-                      rel_residual=stmix["rel_residual"], rel_diff_vs_fp64_solution=rel_diff),
+                      rel_residual=stmix["rel_residual"], rel_diff_vs_fp64_solution=rel_diff,
+                      second_gram_schmidt_passes=stmix["reorthogonalisations"]),
         "fp64": dict(seconds=round(float(np.median(t64)), 4), iterations=st64["iterations"],
-                     vcycles=st64["vcycles"], rel_residual=st64["rel_residual"]),
+                     vcycles=st64["vcycles"], rel_residual=st64["rel_residual"],
+                     second_gram_schmidt_passes=st64["reorthogonalisations"]),
+        "nested_fp64": dict(seconds=round(float(np.median(tn64)), 4), iterations=stn64["iterations"],
+                            inner_iterations=stn64["inner_iterations"], vcycles=stn64["vcycles"],
+                            rel_residual=stn64["rel_residual"],
+                            second_gram_schmidt_passes=stn64["reorthogonalisations"]),
         "speedup_mixed_vs_fp64": round(float(np.median(t64)) / value, 3),
+        "speedup_mixed_vs_nested_fp64": round(float(np.median(tn64)) / value, 3),
         "context_solves": context,
         "vcycle": {"fp64": vc64, "fp32": vc32,
                    "bytes_models": {"method": "13 reals/node/level above the coarsest (down 5.5, up 7.5)",
@@ -309,16 +328,20 @@ GOLDEN_ORACLE = os.path.join(ROOT, "tests", "golden", "oracle_large_coulomb_2049
 
 def cpu_baseline(w, gpu_iterations, restart, solutions):
     """The CPU oracle (plain FP64 C with OpenMP) on a bounded sample of the same
-    solve: the first SAMPLE_ITERS iterations of its FGMRES(restart) with one FP64
-    V-cycle each, on the same 2049^2 inputs, timed three times at one thread and
-    three times at all threads (medians), then scaled to the iterations the
+    solve, on the same 2049^2 inputs:
+      * all threads: one complete restart cycle of its FGMRES(restart) (every
+        basis size 0 .. restart-1, one FP64 V-cycle each), timed once;
+      * the first 4 iterations, timed three times at all threads and three
+        times at one thread (medians): the one-thread restart cycle is the
+        all-thread one scaled by the ratio of the two short samples.
+    The per-iteration time of a restart cycle is scaled to the iterations the
     oracle's own solve needs to reach 1e-8 (stored by the oracle-only script
     tests/golden/make_oracle_large_coulomb.py; the FP64 GPU solve's count when
-    that file is absent).  Later iterations orthogonalise against up to
-    `restart` basis vectors, not the first few, so the scaled figure is a lower
-    bound of the oracle's solve time.  The same leg recomputes the true relative
-    residual of each GPU solution with the oracle's operator and, with the
-    stored samples of the oracle's 1e-12 solution, its relative error."""
+    that file is absent).  The first cycle also pays the first touch of the
+    basis (about 2.7 GB), which later cycles do not.  The same leg recomputes
+    the true relative residual of each GPU solution with the oracle's operator
+    and, with the stored samples of the oracle's 1e-12 solution, its relative
+    error."""
     import oracle
     P = oracle.Problem(w.dim, w.n, w.lo, w.hi, w.ecs, w.k2, w.nlev)
     P.set_operator("qd")
@@ -341,30 +364,32 @@ def cpu_baseline(w, gpu_iterations, restart, solutions):
             c["samples"] = int(ref.size)
         checks[name] = c
     allc = oracle.num_threads()
-    SAMPLE_ITERS = 4
+    SHORT = 4
 
-    def med(threads):
+    def run(threads, k):
         oracle.set_threads(threads)
-        ts = []
-        for _ in range(3):
-            t0 = time.perf_counter()
-            P.solve(b, "fgmres", restart, 1e-8, SAMPLE_ITERS)
-            ts.append(time.perf_counter() - t0)
-        return float(np.median(ts)), ts
+        t0 = time.perf_counter()
+        P.solve(b, "fgmres", restart, 1e-8, k)
+        return time.perf_counter() - t0
 
-    t_all, runs_all = med(allc)
-    t_one, runs_one = med(1)
+    t_cycle = run(allc, restart)
+    short_all = [run(allc, SHORT) for _ in range(3)]
+    short_one = [run(1, SHORT) for _ in range(3)]
     oracle.set_threads(allc)
+    m_all, m_one = float(np.median(short_all)), float(np.median(short_one))
+    per_all = t_cycle / restart
+    per_one = per_all * m_one / m_all
     iters = golden["fgmres_1e8"]["iterations"] if golden else gpu_iterations
     src = "the oracle's own FGMRES(40) solve to 1e-8" if golden else "the FP64 GPU solve (no stored oracle count)"
-    per_all, per_one = t_all / SAMPLE_ITERS, t_one / SAMPLE_ITERS
     out = dict(value=round(per_all * iters, 2), unit="s", cores=allc, kind="oracle",
-               sample=f"first {SAMPLE_ITERS} FGMRES({restart}) iterations (one FP64 V-cycle each) of the FP64 solve "
-                      f"on the same {w.n[0]}^2 inputs, median of 3 runs: {t_all:.2f} s at {allc} threads, "
-                      f"{t_one:.2f} s at 1 thread; scaled by the {iters} iterations of {src} (a lower bound: "
-                      f"later iterations orthogonalise against up to {restart} vectors)",
-               one_thread=dict(value=round(per_one * iters, 2), cores=1, runs_s=[round(t, 3) for t in runs_one]),
-               all_threads=dict(value=round(per_all * iters, 2), cores=allc, runs_s=[round(t, 3) for t in runs_all]),
+               sample=f"one restart cycle ({restart} iterations) of the oracle's FP64 FGMRES({restart}) on the same "
+                      f"{w.n[0]}^2 inputs at {allc} threads ({t_cycle:.1f} s), scaled to the {iters} iterations of "
+                      f"{src}; one thread: the same scaled by the medians of 3 runs of the first {SHORT} "
+                      f"iterations at 1 and at {allc} threads ({m_one:.2f} / {m_all:.2f} s)",
+               one_thread=dict(value=round(per_one * iters, 2), cores=1, seconds_per_iteration=round(per_one, 4),
+                               short_runs_s=[round(t, 3) for t in short_one]),
+               all_threads=dict(value=round(per_all * iters, 2), cores=allc, seconds_per_iteration=round(per_all, 4),
+                                restart_cycle_s=round(t_cycle, 3), short_runs_s=[round(t, 3) for t in short_all]),
                oracle_iterations=iters, solution_checks=checks)
     if golden:
         out["oracle_full_solve_reference"] = dict(seconds=golden["fgmres_1e8"]["seconds"],

@@ -59,6 +59,8 @@ enum { ECS_PREC_NONE = 0, ECS_PREC_LAPLACE = 1, ECS_PREC_CSL = 2, ECS_PREC_CSG =
 enum { ECS_SMOOTH_JACOBI = 0, ECS_SMOOTH_RBGS = 1 };
 enum { ECS_KRYLOV_GMRES = 0, ECS_KRYLOV_FGMRES = 1, ECS_KRYLOV_BICGSTAB = 2 };
 enum { ECS_OP_A = 0, ECS_OP_AT = 1, ECS_OP_M = 2 };
+/* Gram-Schmidt of the GMRES / FGMRES Arnoldi step (see ecs_solve_desc) */
+enum { ECS_ORTH_CGS2_SELECTIVE = 0, ECS_ORTH_CGS2 = 1, ECS_ORTH_CGS1 = 2 };
 
 /* Preconditioner M and the multigrid cycle that approximately inverts it
  * (Sec. 4.2, Algorithm 1; operators of Sec. 5):
@@ -93,12 +95,19 @@ typedef struct {
  *   GMRES(restart):  x = x0 + M^{-1} V y
  *   FGMRES(restart): x = x0 + Z y, z_j = M^{-1} v_j stored in vcycle_dtype;
  *                    inner > 0 makes the preconditioner `inner` iterations of
- *                    complex-FP32 Bi-CGSTAB around the FP32 cycle (nested
- *                    mixed form; requires vcycle_dtype = ECS_F32).
+ *                    Bi-CGSTAB (from zero, on A, right-preconditioned by the
+ *                    cycle) in the cycle's dtype: the nested mixed form with
+ *                    vcycle_dtype = ECS_F32, the same algorithm in FP64
+ *                    with ECS_F64.
  *   BICGSTAB:        van der Vorst's method, shadow residual r^ = r0.
  * maxit counts outer iterations (Arnoldi steps / Bi-CGSTAB iterations).
  * history: optional host array of history_len doubles receiving the
- * estimated relative residual after each iteration. */
+ * estimated relative residual after each iteration.
+ * orth: the Arnoldi step's Gram-Schmidt (GMRES, FGMRES; Hermitian inner
+ * products): classical Gram-Schmidt with a second pass -- always
+ * (ECS_ORTH_CGS2), when the first pass leaves less than 1/sqrt(2) of the new
+ * vector's norm (ECS_ORTH_CGS2_SELECTIVE, the default 0: the criterion of
+ * Daniel, Gragg, Kaufman and Stewart), or never (ECS_ORTH_CGS1). */
 typedef struct {
   int krylov;
   int restart;
@@ -108,16 +117,18 @@ typedef struct {
   int inner;
   double *history;
   int history_len;
+  int orth;
 } ecs_solve_desc;
 
 typedef struct {
   int iterations;          /* outer Krylov iterations                         */
   int restarts;            /* restart cycles (GMRES) / true-residual restarts */
   int64_t vcycles;         /* preconditioner applications (multigrid cycles)  */
-  int64_t inner_iterations;/* FP32 inner iterations (nested form)             */
+  int64_t inner_iterations;/* inner Bi-CGSTAB iterations (nested form)       */
   double rel_residual;     /* true ||b - A x|| / ||b|| at exit (FP64)         */
   double seconds;          /* host wall time inside the call                  */
   int status;              /* same value as returned                          */
+  int64_t reorthogonalisations; /* second Gram-Schmidt passes run (GMRES)     */
 } ecs_stats;
 
 /* Create a problem on the calling thread's current HIP device.

@@ -30,6 +30,7 @@ DIRICHLET, ECS = 0, 1
 PREC = {"none": 0, "laplace": 1, "csl": 2, "csg": 3, "qd": 4}
 SMOOTHER = {"jacobi": 0, "rbgs": 1}
 KRYLOV = {"gmres": 0, "fgmres": 1, "bicgstab": 2}
+ORTH = {"cgs2_selective": 0, "cgs2": 1, "cgs1": 2}
 OP = {"A": 0, "AT": 1, "M": 2}
 STATUS = {0: "ok", 1: "not_converged", -1: "einval", -2: "enomem", -3: "edevice", -4: "ebreakdown", -5: "estate"}
 TIMER = {"smooth": 0, "mdot": 1, "apply_A": 2, "coarse": 3, "mupdate": 4, "restrict": 5, "prolong": 6, "down": 7,
@@ -52,7 +53,8 @@ class PrecDesc(ctypes.Structure):
 class SolveDesc(ctypes.Structure):
     _fields_ = [("krylov", ctypes.c_int), ("restart", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("x_is_guess", ctypes.c_int), ("inner", ctypes.c_int),
-                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int),
+                ("orth", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -66,7 +68,7 @@ class Tuning(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("vcycles", ctypes.c_int64),
                 ("inner_iterations", ctypes.c_int64), ("rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("status", ctypes.c_int)]
+                ("seconds", ctypes.c_double), ("status", ctypes.c_int), ("reorthogonalisations", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -214,11 +216,12 @@ class Krylov:
     restart: int = 30
     rtol: float = 1e-8
     maxit: int = 2000
-    inner: int = 0             # nested FP32 Bi-CGSTAB iterations per FGMRES step
+    inner: int = 0             # nested Bi-CGSTAB iterations (cycle dtype) per FGMRES step
+    orth: str = "cgs2_selective"   # Arnoldi Gram-Schmidt: cgs2_selective | cgs2 | cgs1
 
     def to_c(self, x_is_guess=False, history=None):
         d = SolveDesc(KRYLOV[self.method], self.restart, self.rtol, self.maxit, 1 if x_is_guess else 0, self.inner,
-                      None, 0)
+                      None, 0, ORTH[self.orth])
         if history is not None:
             d.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             d.history_len = history.size

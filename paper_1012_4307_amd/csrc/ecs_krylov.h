@@ -18,6 +18,8 @@ struct GmresScalars {
   double est;                                          // |g_{j+1}| / ||b||  (Givens estimate)
   double resid_true;                                   // true residual / ||b|| at a restart
   int bad, happy;
+  int reorth;                                          // the second Gram-Schmidt pass of this step runs
+  int reorth_count;                                    // second passes run in this solve
   cplx<double> one;                                    // constant 1 (single-column updates)
   cplx<double> g[kMaxRestart + 1];
   cplx<double> cs[kMaxRestart], sn[kMaxRestart];
@@ -37,15 +39,20 @@ enum { kBicgAlpha = 1, kBicgOmega = 2, kBicgInit = 4, kBicgNormRho = 5 };
 
 int reduction_blocks(int64_t n);
 
+// The Arnoldi kernels take an optional gate: with gate != null they do
+// nothing unless *gate != 0 (a second Gram-Schmidt pass decided on the device).
 // multi-dot partials: partials[c][block] = block's share of sum_p conj(V_c[p]) w[p]
 template <typename RA, typename RB>
 void launch_mdot_partial(const cplx<RA> *V, int64_t ldv, int ncols, const cplx<RB> *w, int64_t n,
-                         cplx<double> *partials, hipStream_t s);
+                         cplx<double> *partials, hipStream_t s, const int *gate = nullptr);
 // out[c] = fixed-order sum of partials[c][*] (block count derived from n)
-void launch_reduce_cols(const cplx<double> *partials, int64_t n, int ncols, cplx<double> *out, hipStream_t s);
+void launch_reduce_cols(const cplx<double> *partials, int64_t n, int ncols, cplx<double> *out, hipStream_t s,
+                        const int *gate = nullptr);
 // w <- w - sum_c V_c h_c ; partials[block] = block's share of ||w||^2
 void launch_mupdate_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w,
-                            int64_t n, cplx<double> *partials, hipStream_t s);
+                            int64_t n, cplx<double> *partials, hipStream_t s, const int *gate = nullptr);
+// S->reorth = (||w'||^2 = S->nrm2 < eta2 ||w||^2 = H(j+1, j)); counts it
+void launch_reorth_gate(GmresScalars *S, int j, int m, double eta2, hipStream_t s);
 template <typename R>
 void launch_nrm2sq(const cplx<R> *x, int64_t n, cplx<double> *partials, cplx<double> *out, hipStream_t s);
 template <typename RZ>
@@ -55,7 +62,7 @@ void launch_scale_dev(cplx<double> *x, int64_t n, const double *scal, hipStream_
 void launch_gmres_start(GmresScalars *S, int m, hipStream_t s);
 void launch_gmres_givens(GmresScalars *S, int j, int m, hipStream_t s);
 void launch_gmres_backsolve(GmresScalars *S, int k, int m, hipStream_t s);
-void launch_add_h2(GmresScalars *S, int j, int m, hipStream_t s);
+void launch_add_h2(GmresScalars *S, int j, int m, hipStream_t s, const int *gate = nullptr);
 
 template <typename R>
 void launch_pairdot(const cplx<R> *x0, const cplx<R> *y0, const cplx<R> *x1, const cplx<R> *y1, int npairs, int64_t n,

@@ -343,9 +343,10 @@ struct KrylovBufs {
   void *tz = nullptr;         // n, cycle dtype
   cplx<double> *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *tt = nullptr;
   void *ph = nullptr, *sh = nullptr;
-  cplx<float> *fr = nullptr, *frh = nullptr, *fp = nullptr, *fv = nullptr, *fs = nullptr, *ft = nullptr,
-              *fph = nullptr, *fsh = nullptr;
-  cplx<float> *fp2 = nullptr;  // second p buffer: the fused update writes p beside the old one
+  // nested Bi-CGSTAB of the FGMRES preconditioner, in the cycle's dtype; fp2:
+  // second p buffer (the fused update writes p beside the old one)
+  void *fr = nullptr, *frh = nullptr, *fp = nullptr, *fv = nullptr, *fs = nullptr, *ft = nullptr, *fph = nullptr,
+       *fsh = nullptr, *fp2 = nullptr;
   cplx<double> *a1 = nullptr, *a2 = nullptr;  // adjoint scaling buffers
   cplx<double> *bz = nullptr;                 // right-hand side with its boundary entries zeroed
   int64_t ld = 0;
@@ -376,15 +377,15 @@ size_t plan_krylov(const ecs_ctx *C, const ecs_solve_desc *d, char *base, Krylov
     K->t = cv.take<cplx<double>>(n);
     if (d->krylov == ECS_KRYLOV_FGMRES) K->Z = cv.take<char>((size_t)K->ld * m * zs);
     if (d->inner > 0) {
-      K->fr = cv.take<cplx<float>>(n);
-      K->frh = cv.take<cplx<float>>(n);
-      K->fp = cv.take<cplx<float>>(n);
-      K->fv = cv.take<cplx<float>>(n);
-      K->fs = cv.take<cplx<float>>(n);
-      K->ft = cv.take<cplx<float>>(n);
-      K->fph = cv.take<cplx<float>>(n);
-      K->fsh = cv.take<cplx<float>>(n);
-      K->fp2 = cv.take<cplx<float>>(n);
+      K->fr = cv.take<char>(n * zs);
+      K->frh = cv.take<char>(n * zs);
+      K->fp = cv.take<char>(n * zs);
+      K->fv = cv.take<char>(n * zs);
+      K->fs = cv.take<char>(n * zs);
+      K->ft = cv.take<char>(n * zs);
+      K->fph = cv.take<char>(n * zs);
+      K->fsh = cv.take<char>(n * zs);
+      K->fp2 = cv.take<char>(n * zs);
     }
   }
   return cv.off;
@@ -1198,43 +1199,103 @@ double read_scalar(ecs_ctx *C, const double *dev) {
   return C->pinned[0];
 }
 
-// FP32 Bi-CGSTAB around the FP32 cycle, `iters` iterations from x = 0, all on
-// the device (nested mixed-precision preconditioner of FGMRES)
-void inner_bicgstab(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *v, cplx<float> *x, int iters) {
+template <typename R>
+Grid<R> grid_A_of(const ecs_ctx *C);
+template <>
+Grid<double> grid_A_of<double>(const ecs_ctx *C) { return grid_A(C); }
+template <>
+Grid<float> grid_A_of<float>(const ecs_ctx *C) { return grid_A32(C); }
+
+// Bi-CGSTAB in the cycle's dtype around the cycle, `iters` iterations from
+// x = 0, all on the device: the nested preconditioner of FGMRES (complex FP32
+// in the mixed form; FP64 gives the same algorithm at full precision)
+template <typename R>
+void inner_bicgstab(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *v, cplx<R> *x, int iters) {
   const int64_t n = nn_of(C);
   hipStream_t s = C->stream;
   BicgScalars *S = C->bs_in;
-  launch_cast<double, float>(v, K.fr, n, s);
-  (void)hipMemcpyAsync(K.frh, K.fr, n * sizeof(cplx<float>), hipMemcpyDeviceToDevice, s);
-  launch_zero<float>(x, n, s);
-  launch_zero<float>(K.fp, n, s);
-  launch_zero<float>(K.fv, n, s);
-  launch_pairdot<float>(K.fr, K.fr, nullptr, nullptr, 1, n, C->partials, S, kBicgInit, s);
-  const Grid<float> gA = grid_A32(C);
-  // fused: the finest down kernel forms p (into the other p buffer: blocks
-  // read the old p around their tiles) and s; the same values either way
-  const bool fuse = fused_updates(C);
-  cplx<float> *p_old = K.fp, *p_new = K.fp2;
+  cplx<R> *fr = reinterpret_cast<cplx<R> *>(K.fr), *frh = reinterpret_cast<cplx<R> *>(K.frh);
+  cplx<R> *fv = reinterpret_cast<cplx<R> *>(K.fv), *fs = reinterpret_cast<cplx<R> *>(K.fs);
+  cplx<R> *ft = reinterpret_cast<cplx<R> *>(K.ft), *fph = reinterpret_cast<cplx<R> *>(K.fph);
+  cplx<R> *fsh = reinterpret_cast<cplx<R> *>(K.fsh);
+  if constexpr (sizeof(R) == 4) launch_cast<double, float>(v, fr, n, s);
+  else (void)hipMemcpyAsync(fr, v, n * sizeof(cplx<R>), hipMemcpyDeviceToDevice, s);
+  (void)hipMemcpyAsync(frh, fr, n * sizeof(cplx<R>), hipMemcpyDeviceToDevice, s);
+  launch_zero<R>(x, n, s);
+  launch_zero<R>(reinterpret_cast<cplx<R> *>(K.fp), n, s);
+  launch_zero<R>(fv, n, s);
+  launch_pairdot<R>(fr, fr, nullptr, nullptr, 1, n, C->partials, S, kBicgInit, s);
+  const Grid<R> gA = grid_A_of<R>(C);
+  // fused (FP32): the finest down kernel forms p (into the other p buffer:
+  // blocks read the old p around their tiles) and s; the same values either way
+  const bool fuse = sizeof(R) == 4 && fused_updates(C);
+  cplx<R> *p_old = reinterpret_cast<cplx<R> *>(K.fp), *p_new = reinterpret_cast<cplx<R> *>(K.fp2);
   for (int it = 0; it < iters; it++) {
     if (fuse) {
-      const DownSrc<float> sp{kDownSrcP, K.fr, p_old, K.fv, p_new, S};
-      vcycle_fused<float>(C, p_new, K.fph, &sp);
+      const DownSrc<R> sp{kDownSrcP, fr, p_old, fv, p_new, S};
+      vcycle_fused<R>(C, p_new, fph, &sp);
       std::swap(p_old, p_new);
     } else {
-      launch_bicg_p<float>(K.fp, K.fr, K.fv, n, S, s);
-      vcycle<float>(C, K.fp, K.fph);
+      launch_bicg_p<R>(p_old, fr, fv, n, S, s);
+      vcycle<R>(C, p_old, fph);
     }
-    launch_apply_dot<float, float>(gA, K.fph, K.fv, K.frh, kBicgAlpha, C->partials, S, s);
+    launch_apply_dot<R, R>(gA, fph, fv, frh, kBicgAlpha, C->partials, S, s);
     if (fuse) {
-      const DownSrc<float> ss{kDownSrcS, K.fr, nullptr, K.fv, K.fs, S};
-      vcycle_fused<float>(C, K.fs, K.fsh, &ss);
+      const DownSrc<R> ss{kDownSrcS, fr, nullptr, fv, fs, S};
+      vcycle_fused<R>(C, fs, fsh, &ss);
     } else {
-      launch_bicg_s<float>(K.fs, K.fr, K.fv, n, S, s);
-      vcycle<float>(C, K.fs, K.fsh);
+      launch_bicg_s<R>(fs, fr, fv, n, S, s);
+      vcycle<R>(C, fs, fsh);
     }
-    launch_apply_dot<float, float>(gA, K.fsh, K.ft, K.fs, kBicgOmega, C->partials, S, s);
-    launch_bicg_xr<float, float>(x, K.fph, K.fsh, K.fr, K.fs, K.ft, K.frh, n, C->partials, S, s);
+    launch_apply_dot<R, R>(gA, fsh, ft, fs, kBicgOmega, C->partials, S, s);
+    launch_bicg_xr<R, R>(x, fph, fsh, fr, fs, ft, frh, n, C->partials, S, s);
   }
+}
+
+// Arnoldi step j (Sec. 5's GMRES): h = V_{0..j}^H w, w -= V h, ||w||^2 into
+// S->nrm2, classical Gram-Schmidt with the multi-dot and multi-update kernels.
+// A second pass h2 = V^H w, w -= V h2, H(:, j) += h2 restores the
+// orthogonality that one classical pass loses under cancellation: always
+// (ECS_ORTH_CGS2), never (ECS_ORTH_CGS1), or when ||w'|| < ||w|| / sqrt(2)
+// after the first pass (ECS_ORTH_CGS2_SELECTIVE, decided on the device: the
+// gated kernels of the second pass exit at once otherwise).  w is the basis
+// column V_{j+1}, so one more multi-dot column gives ||w||^2.
+void orthogonalise(ecs_ctx *C, const cplx<double> *V, int64_t ld, int j, cplx<double> *w, int64_t n,
+                   cplx<double> *partials, GmresScalars *S, int m, int orth, hipStream_t s) {
+  cplx<double> *h = S->H + (int64_t)j * (m + 1);
+  const bool sel = orth == ECS_ORTH_CGS2_SELECTIVE;
+  const int nc = j + 1 + (sel ? 1 : 0);
+  {
+    TimedScope ts(C, kTMdot, (double)n * 16 * (nc + 1));  // read v_0..v_j (and w as a column) and w
+    launch_mdot_partial<double, double>(V, ld, nc, w, n, partials, s);
+  }
+  launch_reduce_cols(partials, n, nc, h, s);
+  {
+    TimedScope ts(C, kTMupdate, (double)n * 16 * (j + 3));  // read v_0..v_j, w; write w
+    launch_mupdate_partial(V, ld, j + 1, h, w, n, partials, s);
+  }
+  launch_reduce_cols(partials, n, 1, &S->nrm2, s);
+  if (orth == ECS_ORTH_CGS1) return;
+  const int *gate = nullptr;
+  if (sel) {
+    launch_reorth_gate(S, j, m, 0.5, s);
+    gate = &S->reorth;
+  }
+  launch_mdot_partial<double, double>(V, ld, j + 1, w, n, partials, s, gate);
+  launch_reduce_cols(partials, n, j + 1, S->h2, s, gate);
+  launch_mupdate_partial(V, ld, j + 1, S->h2, w, n, partials, s, gate);
+  launch_reduce_cols(partials, n, 1, &S->nrm2, s, gate);
+  launch_add_h2(S, j, m, s, gate);
+}
+
+// second Gram-Schmidt passes of a solve: counted on the device when selective
+// (read through the context's pinned buffer on its stream)
+int64_t reorth_passes(ecs_ctx *C, GmresScalars *S, int orth, int64_t iterations) {
+  if (orth == ECS_ORTH_CGS1) return 0;
+  if (orth == ECS_ORTH_CGS2) return iterations;
+  int cnt = -1;
+  if (read_bytes(C, &S->reorth_count, sizeof(int))) std::memcpy(&cnt, C->pinned, sizeof(int));
+  return cnt;
 }
 
 template <typename RZ>
@@ -1250,6 +1311,7 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
   cplx<RZ> *tz = reinterpret_cast<cplx<RZ> *>(K.tz);
   const cplx<double> one = mk<double>(1, 0);
   HIP_OK(hipMemcpyAsync(&S->one, &one, sizeof(one), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemsetAsync(&S->reorth_count, 0, sizeof(int), s));
   launch_nrm2sq<double>(b, n, C->partials, &S->nrm2, s);
   const double bn2 = read_scalar(C, &S->nrm2.re);
   const double bnorm = std::sqrt(bn2);
@@ -1289,7 +1351,7 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
       cplx<double> *vj = K.V + (int64_t)j * ld;
       cplx<double> *w = K.V + (int64_t)(j + 1) * ld;
       cplx<RZ> *zj = flexible ? Z + (int64_t)j * ld : tz;
-      if (d->inner > 0) inner_bicgstab(C, K, vj, reinterpret_cast<cplx<float> *>(zj), d->inner);
+      if (d->inner > 0) inner_bicgstab<RZ>(C, K, vj, zj, d->inner);
       else precond<RZ>(C, vj, zj);
       st->vcycles += d->inner > 0 ? 2 * d->inner : 1;
       st->inner_iterations += d->inner;
@@ -1297,16 +1359,7 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
         TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 24));
         launch_apply<double, RZ, double>(grid_A(C), zj, w, s);
       }
-      {
-        TimedScope ts(C, kTMdot, (double)n * 16 * (j + 2));  // read v_0..v_j and w
-        launch_mdot_partial<double, double>(K.V, ld, j + 1, w, n, C->partials, s);
-      }
-      launch_reduce_cols(C->partials, n, j + 1, S->H + (int64_t)j * (m + 1), s);
-      {
-        TimedScope ts(C, kTMupdate, (double)n * 16 * (j + 3));  // read v_0..v_j, w; write w
-        launch_mupdate_partial(K.V, ld, j + 1, S->H + (int64_t)j * (m + 1), w, n, C->partials, s);
-      }
-      launch_reduce_cols(C->partials, n, 1, &S->nrm2, s);
+      orthogonalise(C, K.V, ld, j, w, n, C->partials, S, m, d->orth, s);
       launch_gmres_givens(S, j, m, s);
       launch_scale_dev(w, n, &S->inv, s);
       it++;
@@ -1338,6 +1391,7 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
     st->restarts++;
   }
   st->iterations = it;
+  st->reorthogonalisations = reorth_passes(C, S, d->orth, it);
   HIP_OK(hipGetLastError());
   return status;
 }
@@ -1673,6 +1727,8 @@ ecs_status coupled_check(int nb, ecs_ctx *const *ctx, const ecs_solve_desc *oute
   if (outer->krylov != ECS_KRYLOV_FGMRES) return fail(ctx[0], ECS_EINVAL, "the outer method is FGMRES");
   if (outer->restart < 1 || outer->restart > kMaxRestart) return fail(ctx[0], ECS_EINVAL, "restart must be in [1, 64]");
   if (!(outer->rtol > 0) || outer->maxit < 0) return fail(ctx[0], ECS_EINVAL, "rtol must be > 0 and maxit >= 0");
+  if (outer->orth < ECS_ORTH_CGS2_SELECTIVE || outer->orth > ECS_ORTH_CGS1)
+    return fail(ctx[0], ECS_EINVAL, "unknown orthogonalisation");
   if (inner && (inner->krylov != ECS_KRYLOV_BICGSTAB || !(inner->rtol > 0) || inner->maxit < 1))
     return fail(ctx[0], ECS_EINVAL, "the block solves use Bi-CGSTAB with rtol > 0, maxit >= 1");
   return ECS_OK;
@@ -1703,6 +1759,7 @@ ecs_status coupled_fgmres(int nb, ecs_ctx *const *ctx, const double *k2c, const 
     return ECS_OK;
   }
   HIP_OK(hipMemcpyAsync(&S->bnorm, &bnorm, sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemsetAsync(&S->reorth_count, 0, sizeof(int), s));
   std::vector<ecs_stats> bst(nb);
   std::vector<const void *> bp(nb);
   std::vector<void *> xp(nb);
@@ -1758,10 +1815,7 @@ ecs_status coupled_fgmres(int nb, ecs_ctx *const *ctx, const double *k2c, const 
         st->vcycles += nb;
       }
       coupled_apply(nb, ctx, k2c, zj, w, nullptr, s);
-      launch_mdot_partial<double, double>(B.V, ld, j + 1, w, N, B.partials, s);
-      launch_reduce_cols(B.partials, N, j + 1, S->H + (int64_t)j * (m + 1), s);
-      launch_mupdate_partial(B.V, ld, j + 1, S->H + (int64_t)j * (m + 1), w, N, B.partials, s);
-      launch_reduce_cols(B.partials, N, 1, &S->nrm2, s);
+      orthogonalise(C, B.V, ld, j, w, N, B.partials, S, m, d->orth, s);
       launch_gmres_givens(S, j, m, s);
       launch_scale_dev(w, N, &S->inv, s);
       it++;
@@ -1784,6 +1838,7 @@ ecs_status coupled_fgmres(int nb, ecs_ctx *const *ctx, const double *k2c, const 
     st->restarts++;
   }
   st->iterations = it;
+  st->reorthogonalisations = reorth_passes(C, S, d->orth, it);
   HIP_OK(hipStreamSynchronize(s));
   HIP_OK(hipGetLastError());
   return status;
@@ -1810,8 +1865,9 @@ ecs_status solve_impl(ecs_ctx *C, const ecs_solve_desc *d, const cplx<double> *b
   if (d->restart < 1 || d->restart > kMaxRestart) return fail(C, ECS_EINVAL, "restart must be in [1, 64]");
   if (!(d->rtol > 0) || d->maxit < 0) return fail(C, ECS_EINVAL, "rtol must be > 0 and maxit >= 0");
   if (d->krylov < 0 || d->krylov > 2) return fail(C, ECS_EINVAL, "unknown Krylov method");
-  if (d->inner > 0 && (d->krylov != ECS_KRYLOV_FGMRES || C->prec.vcycle_dtype != ECS_F32))
-    return fail(C, ECS_EINVAL, "inner iterations need FGMRES and an FP32 cycle");
+  if (d->orth < ECS_ORTH_CGS2_SELECTIVE || d->orth > ECS_ORTH_CGS1)
+    return fail(C, ECS_EINVAL, "unknown orthogonalisation");
+  if (d->inner > 0 && d->krylov != ECS_KRYLOV_FGMRES) return fail(C, ECS_EINVAL, "inner iterations need FGMRES");
   if (d->inner > 0 && C->prec.kind == ECS_PREC_NONE) return fail(C, ECS_EINVAL, "inner iterations need a cycle");
   if (C->prec.kind == ECS_PREC_NONE && C->prec.vcycle_dtype == ECS_F32)
     return fail(C, ECS_EINVAL, "no preconditioner: use vcycle_dtype F64");

@@ -35,7 +35,9 @@ constexpr int CG = 4;
 
 template <typename RA, typename RB>
 __global__ __launch_bounds__(BS) void k_mdot(const cplx<RA> *__restrict__ V, int64_t ldv, int ncols,
-                                             const cplx<RB> *__restrict__ w, int64_t n, cplx<double> *partials) {
+                                             const cplx<RB> *__restrict__ w, int64_t n, cplx<double> *partials,
+                                             const int *gate) {
+  if (gate && *gate == 0) return;  // a second Gram-Schmidt pass that is not needed
   constexpr int LDA = kMaxRestart + 2;
   __shared__ cplx<double> acc[BS / 64][LDA];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -83,7 +85,8 @@ __global__ __launch_bounds__(BS) void k_mdot(const cplx<RA> *__restrict__ V, int
 // out[c] = sum over blocks of partials[c][block] (fixed order); one block per
 // column.
 __global__ __launch_bounds__(BS) void k_reduce_cols(const cplx<double> *__restrict__ partials, int nblocks,
-                                                    cplx<double> *__restrict__ out) {
+                                                    cplx<double> *__restrict__ out, const int *gate) {
+  if (gate && *gate == 0) return;
   __shared__ cplx<double> lds[BS / 64];
   const int c = blockIdx.x;
   cplx<double> s = strided_sum(partials + (int64_t)c * nblocks, nblocks);
@@ -95,7 +98,8 @@ __global__ __launch_bounds__(BS) void k_reduce_cols(const cplx<double> *__restri
 // tiling as the multi-dot
 __global__ __launch_bounds__(BS) void k_mupdate(const cplx<double> *__restrict__ V, int64_t ldv, int ncols,
                                                 const cplx<double> *__restrict__ h, cplx<double> *__restrict__ w,
-                                                int64_t n, cplx<double> *partials) {
+                                                int64_t n, cplx<double> *partials, const int *gate) {
+  if (gate && *gate == 0) return;
   __shared__ cplx<double> hs[kMaxRestart + 2];
   __shared__ cplx<double> lds[BS / 64];
   for (int c = threadIdx.x; c < ncols; c += BS) hs[c] = h[c];
@@ -235,10 +239,24 @@ __global__ void k_gmres_backsolve(GmresScalars *S, int k, int m) {
   }
 }
 
-// second Gram-Schmidt pass: H(:, j) += h2
-__global__ void k_add_h2(GmresScalars *S, int j, int m) {
+// second Gram-Schmidt pass: H(:, j) += h2 (when the pass ran)
+__global__ void k_add_h2(GmresScalars *S, int j, int m, const int *gate) {
+  if (gate && *gate == 0) return;
   int q = threadIdx.x;
   if (q <= j) S->H[(int64_t)j * (m + 1) + q] = S->H[(int64_t)j * (m + 1) + q] + S->h2[q];
+}
+
+// Selective reorthogonalisation (the criterion of Daniel, Gragg, Kaufman and
+// Stewart): after the first pass, ||w'||^2 is in S->nrm2 and ||w||^2 before it
+// in H(j+1, j) (the multi-dot's extra column); a second pass runs when the
+// projection removed so much of w that ||w'|| < eta ||w||, where the computed
+// w' has lost orthogonality to the basis.
+__global__ void k_reorth_gate(GmresScalars *S, int j, int m, double eta2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double before = S->H[(int64_t)j * (m + 1) + j + 1].re;
+  const int need = S->nrm2.re < eta2 * before;
+  S->reorth = need;
+  S->reorth_count += need;
 }
 
 // ------------------------------------------------------ Bi-CGSTAB pieces
@@ -440,24 +458,29 @@ int reduction_blocks(int64_t n) { return red_blocks(n); }
 
 template <typename RA, typename RB>
 void launch_mdot_partial(const cplx<RA> *V, int64_t ldv, int ncols, const cplx<RB> *w, int64_t n,
-                         cplx<double> *partials, hipStream_t s) {
-  launch_k((k_mdot<RA, RB>), dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, w, n, partials);
+                         cplx<double> *partials, hipStream_t s, const int *gate) {
+  launch_k((k_mdot<RA, RB>), dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, w, n, partials, gate);
 }
 
-void launch_reduce_cols(const cplx<double> *partials, int64_t n, int ncols, cplx<double> *out, hipStream_t s) {
-  launch_k(k_reduce_cols, dim3(ncols), dim3(BS), 0, s, partials, red_blocks(n), out);
+void launch_reduce_cols(const cplx<double> *partials, int64_t n, int ncols, cplx<double> *out, hipStream_t s,
+                        const int *gate) {
+  launch_k(k_reduce_cols, dim3(ncols), dim3(BS), 0, s, partials, red_blocks(n), out, gate);
 }
 
 void launch_mupdate_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w,
-                            int64_t n, cplx<double> *partials, hipStream_t s) {
-  launch_k(k_mupdate, dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, h, w, n, partials);
+                            int64_t n, cplx<double> *partials, hipStream_t s, const int *gate) {
+  launch_k(k_mupdate, dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, h, w, n, partials, gate);
+}
+
+void launch_reorth_gate(GmresScalars *S, int j, int m, double eta2, hipStream_t s) {
+  launch_k(k_reorth_gate, dim3(1), dim3(1), 0, s, S, j, m, eta2);
 }
 
 template <typename R>
 void launch_nrm2sq(const cplx<R> *x, int64_t n, cplx<double> *partials, cplx<double> *out, hipStream_t s) {
   int nb = red_blocks(n);
   launch_k((k_nrm2sq<R>), dim3(nb), dim3(BS), 0, s, x, n, partials);
-  launch_k(k_reduce_cols, dim3(1), dim3(BS), 0, s, partials, nb, out);
+  launch_k(k_reduce_cols, dim3(1), dim3(BS), 0, s, partials, nb, out, (const int *)nullptr);
 }
 
 template <typename RZ>
@@ -479,8 +502,8 @@ void launch_gmres_backsolve(GmresScalars *S, int k, int m, hipStream_t s) {
   launch_k(k_gmres_backsolve, dim3(1), dim3(1), 0, s, S, k, m);
 }
 
-void launch_add_h2(GmresScalars *S, int j, int m, hipStream_t s) {
-  launch_k(k_add_h2, dim3(1), dim3(kMaxRestart + 2), 0, s, S, j, m);
+void launch_add_h2(GmresScalars *S, int j, int m, hipStream_t s, const int *gate) {
+  launch_k(k_add_h2, dim3(1), dim3(kMaxRestart + 2), 0, s, S, j, m, gate);
 }
 
 template <typename R>
@@ -577,7 +600,7 @@ void launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t s) 
 }
 
 template void launch_mdot_partial<double, double>(const cplx<double> *, int64_t, int, const cplx<double> *, int64_t,
-                                                  cplx<double> *, hipStream_t);
+                                                  cplx<double> *, hipStream_t, const int *);
 template void launch_nrm2sq<double>(const cplx<double> *, int64_t, cplx<double> *, cplx<double> *, hipStream_t);
 template void launch_nrm2sq<float>(const cplx<float> *, int64_t, cplx<double> *, cplx<double> *, hipStream_t);
 template void launch_lincomb<double>(const cplx<double> *, int64_t, int, const cplx<double> *, cplx<double> *, int64_t,

@@ -87,6 +87,7 @@ def test_coulomb_513():
 
 def test_mixed_fgmres_vs_fp64_oracle():
     """Mixed form (FP32 cycle inside FP64 FGMRES(40), with 0 or 2 nested FP32
+    Bi-CGSTAB iterations) and the FP64 cycle (plain, and with 4 nested FP64
     Bi-CGSTAB iterations) on the benchmark operator family at a reduced size
     (257^2, h = 0.25): both sides at 1e-12, relative error <= 1e-6."""
     w = W.large_coulomb(n=257, coarsest=9)
@@ -94,7 +95,7 @@ def test_mixed_fgmres_vs_fp64_oracle():
     xo, sto = P.solve(w.rhs[0], "fgmres", 40, 1e-12, 20000)
     assert sto["status"] == 0
     kr = E.Krylov(method="fgmres", restart=40, rtol=1e-12, maxit=20000)
-    for dt, inner in (("f32", 0), ("f32", 2), ("f64", 0)):
+    for dt, inner in (("f32", 0), ("f32", 2), ("f64", 0), ("f64", 4)):
         S = gpu_for(w, dt, krylov=E.Krylov(method="fgmres", restart=40, rtol=1e-12, maxit=20000, inner=inner))
         x, st = S.solve(to_gpu(w.rhs[0]))
         assert st["status"] == 0, (dt, inner, st)
@@ -126,6 +127,34 @@ def test_headline_mixed_inner16_vs_fp64_oracle():
               f"relerr vs oracle {err:.3e} oracle residual {res:.3e}", flush=True)
         assert res <= 1.05 * rtol, (rtol, res)
         assert err < 1e-6, (rtol, err)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_arnoldi_orthogonalisation_vs_oracle_mgs(dt):
+    """FGMRES(40) on the benchmark operator family at 513^2 (h = 0.25) with
+    each Gram-Schmidt variant of the Arnoldi step against the oracle, whose
+    Arnoldi is modified Gram-Schmidt: classical Gram-Schmidt with a second
+    pass (always, or selectively when the first pass cancels more than
+    1 - 1/sqrt(2) of the norm) needs the oracle's iteration count within 5%;
+    every variant's solution meets 1e-8 by the oracle's operator."""
+    w = W.large_coulomb(n=513, coarsest=9)
+    P = oracle_for(w)
+    b = w.rhs[0]
+    _, sto = P.solve(b, "fgmres", 40, 1e-8, 20000)
+    assert sto["status"] == 0
+    its = {}
+    for orth in ("cgs2_selective", "cgs2", "cgs1"):
+        kr = E.Krylov(method="fgmres", restart=40, rtol=1e-8, maxit=20000, orth=orth)
+        S = gpu_for(w, dt, krylov=kr)
+        x, st = S.solve(to_gpu(b))
+        assert st["status"] == 0, (orth, st)
+        assert oracle_resid(P, to_np(x), b) <= 1.05e-8, orth
+        its[orth] = (st["iterations"], st["reorthogonalisations"])
+    print(dt, "oracle MGS", sto["iterations"], "GPU (iterations, second passes)", its, flush=True)
+    for orth in ("cgs2_selective", "cgs2"):
+        assert abs(its[orth][0] - sto["iterations"]) <= 0.05 * sto["iterations"], (orth, its, sto["iterations"])
+    assert its["cgs2"][1] == its["cgs2"][0] and its["cgs1"][1] == 0
+    assert 0 <= its["cgs2_selective"][1] <= its["cgs2_selective"][0]
 
 
 def test_automatic_lambda0_matches_oracle():
