@@ -107,7 +107,10 @@ typedef struct {
  * products): classical Gram-Schmidt with a second pass -- always
  * (ECS_ORTH_CGS2), when the first pass leaves less than 1/sqrt(2) of the new
  * vector's norm (ECS_ORTH_CGS2_SELECTIVE, the default 0: the criterion of
- * Daniel, Gragg, Kaufman and Stewart), or never (ECS_ORTH_CGS1). */
+ * Daniel, Gragg, Kaufman and Stewart), or never (ECS_ORTH_CGS1).
+ * nrhs: Bi-CGSTAB right-hand sides of one system at once in ecs_batch_solve
+ * (1..8; 0: up to 8), and in ecs_workspace_size the batched solve's storage
+ * for that many (0 there sizes a single solve only); other calls ignore it. */
 typedef struct {
   int krylov;
   int restart;
@@ -118,6 +121,7 @@ typedef struct {
   double *history;
   int history_len;
   int orth;
+  int nrhs;
 } ecs_solve_desc;
 
 typedef struct {
@@ -230,7 +234,8 @@ ecs_status ecs_vcycle_native(ecs_ctx *ctx, const void *v_dev, void *z_dev);
  *        offset i * nodes; x is a guess when outer->x_is_guess.
  *   workspace: device memory of ecs_coupled_workspace_size bytes, 256-byte
  *        aligned, caller-owned; the contexts' own workspaces must be sized for
- *        `inner` (ecs_workspace_size with inner).
+ *        `inner` as one right-hand side of the batched solve
+ *        (ecs_workspace_size with inner, nrhs = 1).
  *   stats: iterations = outer iterations, inner_iterations and vcycles summed
  *        over all block solves.  Outer work runs on ctx[0]'s stream; the call
  *        returns after every stream involved has finished. */
@@ -348,18 +353,25 @@ ecs_status ecs_set_graphs(ecs_ctx *ctx, int mode);
 /* Batched solve of n independent problems (Bi-CGSTAB), the many independent
  * Helmholtz blocks of Sec. 2 at once.  desc[s] holds system s's Krylov
  * settings (desc[s]->krylov must be ECS_KRYLOV_BICGSTAB; rtol, maxit and
- * x_is_guess may differ between systems).  Each context is fully set up with
- * its own workspace (sized for its Bi-CGSTAB desc) and should have its own
- * stream: the driver
- * enqueues one phase of a system at a time (||b||, true residual and restart,
- * or one iteration) on that system's stream, records an event after it, and
- * polls the events from the host; a system's next phase is enqueued as soon
- * as its own previous phase has completed, so systems of different sizes
- * progress independently.  Each system runs exactly the kernel sequence of
- * its single solve (same results).  Returns after every stream has been
- * synchronised; a context given twice is ECS_EINVAL.  b[s], x[s] point
- * to nrhs[s] contiguous complex128 vectors of system s, solved one after the
- * other.  stats[s] aggregates the system's right-hand sides: summed
+ * x_is_guess may differ between systems).  b[s], x[s] point to nrhs[s]
+ * contiguous complex128 vectors of system s (x read as the initial guesses
+ * when x_is_guess).  Each context is fully set up with its own workspace and
+ * should have its own stream.
+ *   Right-hand sides: with the fused 2D V(1,1) red-black cycle (2D, RB-GS,
+ *   nu1 = nu2 = 1, V) a system's right-hand sides are solved together, up to
+ *   min(8, desc[s]->nrhs if > 0) at once, every kernel of an iteration serving
+ *   all of them in one launch (per right-hand side the same arithmetic as a
+ *   single solve); other set-ups take them one at a time.  The workspace must
+ *   hold that many at once (ecs_workspace_size with that nrhs; 1 for other
+ *   set-ups), else ECS_ENOMEM.
+ *   Scheduling: the driver enqueues one round of a system at a time on that
+ *   system's stream (the restarts -- true residuals -- of the right-hand sides
+ *   that need one, one iteration of the others, one readback), records an
+ *   event after it and polls the events from the host; a system's next round
+ *   is enqueued as soon as its own previous one has completed, so systems of
+ *   different sizes progress independently.
+ * Returns after every stream has been synchronised; a context given twice is
+ * ECS_EINVAL.  stats[s] aggregates the system's right-hand sides: summed
  * iterations, restarts and cycles, the largest final true residual, the worst
  * status, and the wall time of the whole batch. */
 ecs_status ecs_batch_solve(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *const *desc, const void *const *b,

@@ -16,6 +16,7 @@ raises.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import math
 import os
 from dataclasses import dataclass, field
@@ -54,7 +55,7 @@ class SolveDesc(ctypes.Structure):
     _fields_ = [("krylov", ctypes.c_int), ("restart", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("x_is_guess", ctypes.c_int), ("inner", ctypes.c_int),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int),
-                ("orth", ctypes.c_int)]
+                ("orth", ctypes.c_int), ("nrhs", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -218,10 +219,11 @@ class Krylov:
     maxit: int = 2000
     inner: int = 0             # nested Bi-CGSTAB iterations (cycle dtype) per FGMRES step
     orth: str = "cgs2_selective"   # Arnoldi Gram-Schmidt: cgs2_selective | cgs2 | cgs1
+    nrhs: int = 0              # Bi-CGSTAB workspace for the batched solve: right-hand sides at once (0: none)
 
     def to_c(self, x_is_guess=False, history=None):
         d = SolveDesc(KRYLOV[self.method], self.restart, self.rtol, self.maxit, 1 if x_is_guess else 0, self.inner,
-                      None, 0, ORTH[self.orth])
+                      None, 0, ORTH[self.orth], self.nrhs)
         if history is not None:
             d.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             d.history_len = history.size
@@ -559,17 +561,21 @@ class Solver:
         return n.value, ms.value, by.value
 
 
-def batch_solve(solvers, rhs, krylov):
+def batch_solve(solvers, rhs, krylov, x0=None, group=8):
     """Solve every right-hand side of every system by Bi-CGSTAB: rhs[s] is a
     contiguous complex128 CUDA tensor of shape (nrhs_s, *solvers[s].shape) on
     that solver's device; krylov is one Krylov for all systems or a list with
-    one per system.  Returns (solutions, stats)."""
+    one per system; x0 (optional) a list with each system's initial guesses
+    (a tensor like rhs[s], or None for zero guesses); group: right-hand sides
+    of a system solved at once (1..8; the fused 2D V(1,1) red-black cycle,
+    else one at a time).  Returns (solutions, stats)."""
     torch = _torch()
     n = len(solvers)
     krs = list(krylov) if isinstance(krylov, (list, tuple)) else [krylov] * n
-    if len(rhs) != n or len(krs) != n:
-        raise ValueError(f"{n} solvers need {n} right-hand side tensors and Krylov settings "
-                         f"(got {len(rhs)} and {len(krs)})")
+    x0s = list(x0) if x0 is not None else [None] * n
+    if len(rhs) != n or len(krs) != n or len(x0s) != n:
+        raise ValueError(f"{n} solvers need {n} right-hand side tensors, Krylov settings and guesses "
+                         f"(got {len(rhs)}, {len(krs)} and {len(x0s)})")
     if len({id(S) for S in solvers}) != n:
         raise ValueError("a solver appears twice in the batch")
     for q, (S, b, kr) in enumerate(zip(solvers, rhs, krs)):
@@ -580,15 +586,24 @@ def batch_solve(solvers, rhs, krylov):
             desc = f"{b.dtype} {tuple(b.shape)}" if isinstance(b, torch.Tensor) else type(b).__name__
             raise ValueError(f"system {q}: rhs must be a contiguous complex128 CUDA tensor of shape "
                              f"(nrhs, {', '.join(map(str, S.shape))}) on {S.device}, got {desc}")
-    for S, kr in zip(solvers, krs):
-        S._ensure_workspace(kr)
-    xs = [torch.empty_like(b) for b in rhs]
+        g = x0s[q]
+        if g is not None and not (isinstance(g, torch.Tensor) and g.is_cuda and g.dtype == torch.complex128
+                                  and g.is_contiguous() and tuple(g.shape) == tuple(b.shape) and g.device == b.device):
+            raise ValueError(f"system {q}: x0 must be a contiguous complex128 CUDA tensor like its rhs")
+    if not 1 <= int(group) <= 8:
+        raise ValueError("group must be in [1, 8]")
+    for S, kr, b in zip(solvers, krs, rhs):
+        # the fused 2D V(1,1) red-black cycle solves up to 8 right-hand sides at once
+        fused = (S.dim == 2 and S.precond.smoother == "rbgs" and S.precond.nu1 == 1 and S.precond.nu2 == 1
+                 and S.precond.gamma_f == 1 and S.precond.gamma_c == 1 and S.nlev > 1)
+        S._ensure_workspace(dataclasses.replace(kr, nrhs=max(1, min(int(b.shape[0]), int(group))) if fused else 1))
+    xs = [torch.empty_like(b) if g is None else g.clone() for b, g in zip(rhs, x0s)]
     ctxs = (ctypes.c_void_p * n)(*[S._h.value for S in solvers])
     bs = (ctypes.c_void_p * n)(*[b.data_ptr() for b in rhs])
     xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
     nr = (ctypes.c_int * n)(*[int(b.shape[0]) for b in rhs])
     st = (Stats * n)()
-    descs = [kr.to_c() for kr in krs]
+    descs = [dataclasses.replace(kr, nrhs=int(group)).to_c(g is not None) for kr, g in zip(krs, x0s)]
     dp = (ctypes.POINTER(SolveDesc) * n)(*[ctypes.pointer(d) for d in descs])
     with _StreamOrder([S.stream for S in solvers], tuple(xs)):
         rc = lib().ecs_batch_solve(n, ctxs, dp, bs, xp, nr, st)
@@ -617,7 +632,7 @@ def coupled_solve(solvers, k2c, b, x0=None, outer: Optional[Krylov] = None, inne
                                 and tuple(k2c.shape) == (nb, nb) + shape):
         raise ValueError(f"k2c must be a contiguous float64 CUDA tensor of shape {(nb, nb) + shape}")
     for S in solvers:
-        S._ensure_workspace(inner)
+        S._ensure_workspace(dataclasses.replace(inner, nrhs=1))   # one right-hand side per block solve
     hs = (ctypes.c_void_p * nb)(*[S._h.value for S in solvers])
     do = outer.to_c(x0 is not None)
     di = inner.to_c()

@@ -106,6 +106,26 @@ __device__ __forceinline__ void st_c(__amdgpu_buffer_rsrc_t r, uint32_t off, cpl
                                          0, 0);
 }
 
+// Several right-hand sides of one system per launch (the batched solve): row
+// y of the launch grid works on right-hand side slot[y] (rows = count).  The
+// copies of a per-right-hand-side array of a level lie rhs_stride(nodes)
+// elements apart; per-right-hand-side scalars are consecutive structs and
+// reduction partials kRhsPartials entries apart.  A single solve launches
+// one row with slot 0, so no pointer moves.
+constexpr int kMaxRhs = 8;
+constexpr int kRhsPartials = 8192;
+struct RhsSet {
+  int count;
+  int slot[kMaxRhs];
+};
+__host__ __device__ __forceinline__ int64_t rhs_stride(int64_t nodes) { return (nodes + 63) & ~int64_t(63); }
+__device__ __forceinline__ int64_t rhs_index(const RhsSet &rs) { return rs.slot[blockIdx.y]; }
+inline RhsSet one_rhs() {
+  RhsSet r{};
+  r.count = 1;
+  return r;
+}
+
 // XCD-aware tile order.  Workgroups are handed to the 8 XCDs of the chip in
 // round-robin order of their linear index, and each XCD has its own L2.  A 1D
 // launch of `padded` (a multiple of 8) blocks is mapped so that XCD x owns the
@@ -170,14 +190,14 @@ void launch_prolong_jacobi(const Grid<R> &fine, const Grid<R> &coarse, const cpl
                            const cplx<R> *u, cplx<R> *out, R omega, hipStream_t s);
 template <typename R>
 void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, int n1, int n2, const cplx<R> *b,
-                         cplx<R> *x, hipStream_t s);
+                         cplx<R> *x, hipStream_t s, const RhsSet &rs = one_rhs());
 // fused V(1,1) red-black kernels (2D): zero-guess pre-sweep + residual + FW
 // (the pre-smoothed iterate is not stored), and the pre-sweep recomputed from
 // b + prolongation + correction + post-sweep into u_out
 // (rows: tile height, see ecs_tuning)
 template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *rc, R omega, int rows,
-                    hipStream_t s);
+                    hipStream_t s, const RhsSet &rs = one_rhs());
 // The down kernel can form its right-hand side while staging it, from the
 // vectors of a Bi-CGSTAB step (FP32 only): kDownSrcP b = r + beta (p - omega v),
 // kDownSrcS b = r - alpha v (the step's scalars read from S), each with the
@@ -198,17 +218,17 @@ void launch_down_rb_src(const Grid<R> &fine, const Grid<R> &coarse, const DownSr
                         int rows, hipStream_t s);
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *ec, cplx<R> *u_out,
-                  R omega, int rows, hipStream_t s);
+                  R omega, int rows, hipStream_t s, const RhsSet &rs = one_rhs());
 // two levels of the fused cycle in one kernel (small levels): down over
 // levels l, l+1 (writes u_l, u_{l+1}, b_{l+1} and b_{l+2}); up over levels
 // l+1, l (reads the correction u_{l+2}, writes u_l)
 template <typename R>
 void launch_down2_rb(const Grid<R> &f, const Grid<R> &m, const Grid<R> &c, const cplx<R> *b, cplx<R> *t_f,
-                     cplx<R> *b_m, cplx<R> *t_m, cplx<R> *rc, R omega, hipStream_t s);
+                     cplx<R> *b_m, cplx<R> *t_m, cplx<R> *rc, R omega, hipStream_t s, const RhsSet &rs = one_rhs());
 template <typename R>
 void launch_up2_rb(const Grid<R> &f, const Grid<R> &m, const Grid<R> &c, const cplx<R> *b_f, const cplx<R> *t_f,
                    const cplx<R> *b_m, const cplx<R> *t_m, const cplx<R> *ec, cplx<R> *u_out, R omega,
-                   hipStream_t s);
+                   hipStream_t s, const RhsSet &rs = one_rhs());
 // the coarsest levels of a 2D V(1,1) red-black cycle in one workgroup, every
 // level vector resident in LDS: levels with at most kTailNodes nodes per axis,
 // at least two of them (the last is the coarsest, solved densely), kTailCap
@@ -232,7 +252,7 @@ struct TailArgs {
   R omega;
 };
 template <typename R>
-void launch_tail(const TailArgs<R> &a, hipStream_t s);
+void launch_tail(const TailArgs<R> &a, hipStream_t s, const RhsSet &rs = one_rhs());
 
 // The coarse end of a general cycle (any gamma_f, gamma_c, nu1, nu2,
 // omega-Jacobi or red-black) in one workgroup, driven by a schedule that the

@@ -67,26 +67,31 @@ void launch_add_h2(GmresScalars *S, int j, int m, hipStream_t s, const int *gate
 template <typename R>
 void launch_pairdot(const cplx<R> *x0, const cplx<R> *y0, const cplx<R> *x1, const cplx<R> *y1, int npairs, int64_t n,
                     cplx<double> *partials, BicgScalars *S, int mode, hipStream_t s);
+// With an RhsSet (the batched solve) the vectors of slot q start q
+// rhs_stride(n) elements in, the scalars at S + q and the partials
+// q kRhsPartials entries in.
 template <typename R>
-void launch_bicg_p(cplx<R> *p, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s);
+void launch_bicg_p(cplx<R> *p, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s,
+                   const RhsSet &rs = one_rhs());
 template <typename R>
-void launch_bicg_s(cplx<R> *sv, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s);
+void launch_bicg_s(cplx<R> *sv, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s,
+                   const RhsSet &rs = one_rhs());
 // x += alpha ph + omega sh; r = s - omega t; then ||r||^2 and (r^, r) reduce
 // (fixed-order second stage) into est and the next step's beta
 template <typename R, typename RZ>
 void launch_bicg_xr(cplx<R> *x, const cplx<RZ> *ph, const cplx<RZ> *sh, cplx<R> *r, const cplx<R> *sv,
                     const cplx<R> *t, const cplx<R> *rh, int64_t n, cplx<double> *partials, BicgScalars *S,
-                    hipStream_t s);
+                    hipStream_t s, const RhsSet &rs = one_rhs());
 // y = A x with a fused dot product: kBicgAlpha -> (d0, y) gives alpha;
 // kBicgOmega -> (y, d0) and (y, y) give omega (multigrid side, kernels_mg.hip)
 void launch_bicg_final(const cplx<double> *partials, int nblocks, int npairs, BicgScalars *S, int mode,
-                       hipStream_t s);
+                       hipStream_t s, const RhsSet &rs = one_rhs());
 template <typename R, typename RI>
 void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cplx<R> *d0, int mode,
-                      cplx<double> *partials, BicgScalars *S, hipStream_t s);
+                      cplx<double> *partials, BicgScalars *S, hipStream_t s, const RhsSet &rs = one_rhs());
 
 template <typename RI, typename RO>
-void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s);
+void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s, const RhsSet &rs = one_rhs());
 void launch_cast_real(const double *x, float *y, int64_t n, hipStream_t s);
 // FP32 -> FP64 real array (exact)
 void launch_widen_real(const float *x, double *y, int64_t n, hipStream_t s);

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -36,6 +37,10 @@ namespace {
 
 constexpr int kMaxLev = 16;
 constexpr int kMaxDevices = 64;
+// host-pinned scalars per context: readbacks in [0, kPinnedStage), host-to-
+// device staging above
+constexpr size_t kPinnedBytes = 1024;
+constexpr size_t kPinnedStage = 768;
 
 std::mutex g_scratch_mu;
 char *g_scratch_ptr[kMaxDevices] = {};
@@ -313,7 +318,7 @@ size_t plan_layout(ecs_ctx *C, Carver &cv) {
   C->partials = cv.take<cplx<double>>((size_t)kRedBlocks * (kMaxRestart + 2));
   C->dscal = cv.take<double>(kRedBlocks + 8);
   C->gs = cv.take<GmresScalars>(1);
-  C->bs = cv.take<BicgScalars>(1);
+  C->bs = cv.take<BicgScalars>(kMaxRhs);  // one per right-hand side slot of the batched solve
   C->bs_in = cv.take<BicgScalars>(1);
   return cv.off;
 }
@@ -350,7 +355,43 @@ struct KrylovBufs {
   cplx<double> *a1 = nullptr, *a2 = nullptr;  // adjoint scaling buffers
   cplx<double> *bz = nullptr;                 // right-hand side with its boundary entries zeroed
   int64_t ld = 0;
+  // batched Bi-CGSTAB (plan_batch): slots copies of every vector, rhs_stride(n)
+  // apart (r .. sh, bz above, the iterates bx), the FP32 cycle's input per slot
+  // and the cycle's level buffers per slot (void: the cycle's dtype)
+  int slots = 0;
+  cplx<double> *bx = nullptr;
+  void *b32 = nullptr;
+  void *lb[kMaxLev] = {}, *lt[kMaxLev] = {}, *lu[kMaxLev] = {};
 };
+
+// Storage of the batched Bi-CGSTAB for `slots` right-hand sides at once (one
+// group of a system's right-hand sides; see batch_solve_impl).
+size_t plan_batch(const ecs_ctx *C, int slots, char *base, KrylovBufs *K) {
+  Carver cv(base);
+  const int64_t n = nn_of(C), sn = rhs_stride(n) * slots;
+  const bool f32 = C->prec.vcycle_dtype == ECS_F32;
+  const size_t zs = f32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+  K->slots = slots;
+  K->ld = rhs_stride(n);
+  K->bz = cv.take<cplx<double>>(sn);
+  K->bx = cv.take<cplx<double>>(sn);
+  K->r = cv.take<cplx<double>>(sn);
+  K->rh = cv.take<cplx<double>>(sn);
+  K->p = cv.take<cplx<double>>(sn);
+  K->v = cv.take<cplx<double>>(sn);
+  K->s = cv.take<cplx<double>>(sn);
+  K->tt = cv.take<cplx<double>>(sn);
+  K->ph = cv.take<char>(sn * zs);
+  K->sh = cv.take<char>(sn * zs);
+  K->b32 = f32 ? cv.take<char>(sn * zs) : nullptr;
+  for (int l = 0; l < C->nlev; l++) {
+    const int64_t sl = rhs_stride(C->hl[l].nn) * slots;
+    K->lt[l] = cv.take<char>(sl * zs);
+    K->lb[l] = l == 0 ? nullptr : cv.take<char>(sl * zs);
+    K->lu[l] = l == 0 ? nullptr : cv.take<char>(sl * zs);
+  }
+  return cv.off;
+}
 
 size_t plan_krylov(const ecs_ctx *C, const ecs_solve_desc *d, char *base, KrylovBufs *K) {
   Carver cv(base);
@@ -705,7 +746,7 @@ ecs_status setup(ecs_ctx *C) {
   }
   // Krylov scalars start cleared
   HIP_OK(hipMemsetAsync(C->gs, 0, sizeof(GmresScalars), s));
-  HIP_OK(hipMemsetAsync(C->bs, 0, sizeof(BicgScalars), s));
+  HIP_OK(hipMemsetAsync(C->bs, 0, kMaxRhs * sizeof(BicgScalars), s));
   HIP_OK(hipMemsetAsync(C->bs_in, 0, sizeof(BicgScalars), s));
   HIP_OK(hipStreamSynchronize(s));
   HIP_OK(hipGetLastError());
@@ -908,28 +949,51 @@ bool fused_updates(const ecs_ctx *C) {
   return P.lt > 0 && !P.pair_start[0];
 }
 
-// src (FP32, finest level by its own down kernel): the right-hand side b0 is
-// formed by that kernel from src and stored in b0 == src->out
+// Level buffers of the fused cycle: the hierarchy's own (one right-hand
+// side), or for the batched solve arrays holding one copy per right-hand side
+// slot, rhs_stride(level nodes) elements apart.
 template <typename R>
-void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0, const DownSrc<R> *src = nullptr) {
+struct CycleBufs {
+  cplx<R> *b[kMaxLev] = {}, *t[kMaxLev] = {}, *u[kMaxLev] = {};
+};
+
+template <typename R>
+CycleBufs<R> hierarchy_bufs(ecs_ctx *C) {
+  CycleBufs<R> B;
+  for (int l = 0; l < C->nlev; l++) {
+    DevLevel<R> &D = dev_level<R>(C, l);
+    B.b[l] = D.b;
+    B.t[l] = D.t;
+    B.u[l] = D.u;
+  }
+  return B;
+}
+
+// src (FP32, finest level by its own down kernel): the right-hand side b0 is
+// formed by that kernel from src and stored in b0 == src->out.  cb / rs (the
+// batched solve): the cycle of every right-hand side slot in rs at once, b0
+// and u0 holding one vector per slot rhs_stride(nodes) apart.
+template <typename R>
+void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0, const DownSrc<R> *src = nullptr,
+                  const CycleBufs<R> *cb = nullptr, const RhsSet &rs = one_rhs()) {
   const int lc = C->nlev - 1;
   const R om = (R)C->prec.omega;
   const ecs_tuning &T = C->tune;
   const FusedPlan plan = fused_plan(C);
   const int lt = plan.lt;
   const bool *pair_start = plan.pair_start;
+  const CycleBufs<R> B = cb ? *cb : hierarchy_bufs<R>(C);
+  const double nr = rs.count;  // algorithmic bytes scale with the right-hand sides of a launch
   auto small = [&](int l) { return C->hl[l].n[0] <= T.small_grid && C->hl[l].n[1] <= T.small_grid; };
   for (int l = 0; l < lt;) {
-    DevLevel<R> &D = dev_level<R>(C, l);
-    DevLevel<R> &Dc = dev_level<R>(C, l + 1);
-    const cplx<R> *b = l == 0 ? b0 : D.b;
+    const cplx<R> *b = l == 0 ? b0 : B.b[l];
     if constexpr (sizeof(R) == 4) {
       if (l == 0 && src) {
         // reads the vectors b is formed from (r, p, v or r, v) and k^2;
         // writes b and the coarse residual
         const bool pm = src->mode == kDownSrcP;
         TimedScope ts(C, pm ? kTDownP : kTDownS, (double)C->hl[0].nn * sizeof(R) * (pm ? 9.5 : 7.5));
-        launch_down_rb_src<R>(grid_M<R>(C, 0), grid_M<R>(C, 1), *src, Dc.b, om, small(0) ? 2 : T.down_rows,
+        launch_down_rb_src<R>(grid_M<R>(C, 0), grid_M<R>(C, 1), *src, B.b[1], om, small(0) ? 2 : T.down_rows,
                               C->stream);
         l++;
         continue;
@@ -938,23 +1002,25 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0, const DownSrc<R> *
     if (pair_start[l]) {
       // reads b, k^2 of both levels; writes u of both, b of level l+1, the
       // residual restricted to level l+2
-      TimedScope ts(C, kTCoarse, (double)(C->hl[l].nn + C->hl[l + 1].nn) * sizeof(R) * 5.5);
-      launch_down2_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), grid_M<R>(C, l + 2), b, D.t, Dc.b, Dc.t,
-                         dev_level<R>(C, l + 2).b, om, C->stream);
+      TimedScope ts(C, kTCoarse, nr * (C->hl[l].nn + C->hl[l + 1].nn) * sizeof(R) * 5.5);
+      launch_down2_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), grid_M<R>(C, l + 2), b, B.t[l], B.b[l + 1],
+                         B.t[l + 1], B.b[l + 2], om, C->stream, rs);
       l += 2;
       continue;
     }
     // reads b, k^2; writes the coarse residual (3.5 reals per node)
-    TimedScope ts(C, l == 0 ? kTDown : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 3.5);
-    launch_down_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, Dc.b, om, small(l) ? 2 : T.down_rows, C->stream);
+    TimedScope ts(C, l == 0 ? kTDown : kTCoarse, nr * C->hl[l].nn * sizeof(R) * 3.5);
+    launch_down_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, B.b[l + 1], om, small(l) ? 2 : T.down_rows,
+                      C->stream, rs);
     l++;
   }
   if (lt == lc) {
     // no small levels above the coarsest: dense solve only
-    const cplx<R> *b = lc == 0 ? b0 : dev_level<R>(C, lc).b;
-    cplx<R> *u = lc == 0 ? u0 : dev_level<R>(C, lc).u;
+    const cplx<R> *b = lc == 0 ? b0 : B.b[lc];
+    cplx<R> *u = lc == 0 ? u0 : B.u[lc];
     TimedScope ts(C, kTCoarse, 0.0);
-    coarse_solve<R>(C, b, u);
+    const HostLevel &L = C->hl[lc];
+    launch_coarse_solve<R>(C->nunk, minv_of<R>(C), C->unk, L.n[0], L.n[1], L.n[2], b, u, C->stream, rs);
   } else {
     TailArgs<R> a{};
     a.nl = lc - lt + 1;
@@ -966,38 +1032,35 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0, const DownSrc<R> *
       a.poff[k + 1] = a.poff[k] + ((int)C->hl[l].nn + 63) / 64 * 64;
       a.woff[k + 1] = a.woff[k] + (int)std::max(C->hl[l].n[0], C->hl[l].n[1]);
     }
-    a.b0 = lt == 0 ? b0 : dev_level<R>(C, lt).b;
-    a.u0 = lt == 0 ? u0 : dev_level<R>(C, lt).u;
+    a.b0 = lt == 0 ? b0 : B.b[lt];
+    a.u0 = lt == 0 ? u0 : B.u[lt];
     a.minvT = minv_of<R>(C);
     a.nunk = C->nunk;
     a.tpr = 64;
     while (a.tpr > 1 && a.tpr * C->nunk > 1024) a.tpr >>= 1;
     a.omega = om;
     TimedScope ts(C, kTCoarse, 0.0);
-    launch_tail<R>(a, C->stream);
+    launch_tail<R>(a, C->stream, rs);
   }
   for (int l = lt - 1; l >= 0;) {
     if (l >= 1 && pair_start[l - 1]) {
       // levels l - 1 and l: reads u, b, k^2 of both and the correction from
       // level l + 1; writes u of level l - 1
       const int lf = l - 1;
-      DevLevel<R> &D = dev_level<R>(C, lf);
-      DevLevel<R> &Dm = dev_level<R>(C, lf + 1);
-      const cplx<R> *b = lf == 0 ? b0 : D.b;
-      cplx<R> *out = lf == 0 ? u0 : D.u;
-      TimedScope ts(C, kTCoarse, (double)(C->hl[lf].nn + C->hl[lf + 1].nn) * sizeof(R) * 7.5);
-      launch_up2_rb<R>(grid_M<R>(C, lf), grid_M<R>(C, lf + 1), grid_M<R>(C, lf + 2), b, D.t, Dm.b, Dm.t,
-                       dev_level<R>(C, lf + 2).u, out, om, C->stream);
+      const cplx<R> *b = lf == 0 ? b0 : B.b[lf];
+      cplx<R> *out = lf == 0 ? u0 : B.u[lf];
+      TimedScope ts(C, kTCoarse, nr * (C->hl[lf].nn + C->hl[lf + 1].nn) * sizeof(R) * 7.5);
+      launch_up2_rb<R>(grid_M<R>(C, lf), grid_M<R>(C, lf + 1), grid_M<R>(C, lf + 2), b, B.t[lf], B.b[lf + 1],
+                       B.t[lf + 1], B.u[lf + 2], out, om, C->stream, rs);
       l -= 2;
       continue;
     }
-    DevLevel<R> &D = dev_level<R>(C, l);
-    DevLevel<R> &Dc = dev_level<R>(C, l + 1);
-    const cplx<R> *b = l == 0 ? b0 : D.b;
-    cplx<R> *out = l == 0 ? u0 : D.u;
+    const cplx<R> *b = l == 0 ? b0 : B.b[l];
+    cplx<R> *out = l == 0 ? u0 : B.u[l];
     // reads the coarse correction, b, k^2; writes u (5.5 reals per node)
-    TimedScope ts(C, l == 0 ? kTUp : kTCoarse, (double)C->hl[l].nn * sizeof(R) * 5.5);
-    launch_up_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, Dc.u, out, om, small(l) ? 4 : T.up_rows, C->stream);
+    TimedScope ts(C, l == 0 ? kTUp : kTCoarse, nr * C->hl[l].nn * sizeof(R) * 5.5);
+    launch_up_rb<R>(grid_M<R>(C, l), grid_M<R>(C, l + 1), b, B.u[l + 1], out, om, small(l) ? 4 : T.up_rows,
+                    C->stream, rs);
     l--;
   }
 }
@@ -1512,114 +1575,233 @@ ecs_status bicgstab(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, co
 }
 
 // ------------------------------------------------------------- batched
-// Many independent systems (each context with its own workspace and, ideally,
-// its own stream), every right-hand side solved by Bi-CGSTAB.  The driver
-// advances all systems in rounds: each round enqueues one phase per active
-// system (start: ||b||; verify: true residual and restart scalars; step: one
-// iteration) followed by the 12-byte readback, then synchronises once and
-// moves every system's state machine on.  A system's right-hand sides are
-// taken one after the other (its workspace holds one solve's vectors).
+// Many independent systems (Sec. 2's blocks), every right-hand side solved by
+// Bi-CGSTAB.  Each system takes its right-hand sides in groups of up to
+// kMaxRhs (one group when the fused 2D V(1,1) red-black cycle runs: every
+// kernel of an iteration then serves the whole group in one launch, a slot
+// per right-hand side; one right-hand side per group otherwise).  A system
+// advances in rounds on its own stream: a round enqueues the restarts (true
+// residual) of the slots that need one, one batched iteration of the slots
+// that iterate, and the readback of every slot's scalars; an event per
+// context marks the round's end, and the host polls the events, so systems of
+// different sizes progress independently.  Per slot the arithmetic is that of
+// the single solve, kernel for kernel, so results equal single solves.
+static_assert(kMaxRhs * sizeof(BicgScalars) <= kPinnedStage, "slot scalars fit the pinned readback area");
+
+struct BatchSlot {
+  int phase = 0;  // 1 verify (true residual, restart), 2 iterate, 3 finished
+  int it = 0, stalls = 0, restarts = 0;
+  double last_restart = INFINITY, rt = 0;
+};
+
 struct BatchItem {
   ecs_ctx *C = nullptr;
   const ecs_solve_desc *d = nullptr;  // this system's Krylov settings
   KrylovBufs K;
-  const cplx<double> *b0 = nullptr;
+  const cplx<double> *b0 = nullptr;   // the caller's right-hand sides and solutions
   cplx<double> *x0 = nullptr;
-  int nrhs = 0, r = 0;
-  int phase = 0;  // 0 start, 1 verify, 2 iterate, 3 finished
-  int it = 0, stalls = 0, restarts = 0;
-  double last_restart = INFINITY, rt = 0;
+  int nrhs = 0, group = 1;            // right-hand sides; slots per group
+  int first = 0, count = 0;           // the current group: right-hand sides [first, first + count)
+  bool started = false;               // the group's norms are in
+  bool done = false;
+  BatchSlot slot[kMaxRhs];
+  RhsSet ver{}, itr{};                // slots restarted / iterated in the round in flight
   ecs_stats agg{};
   ecs_status worst = ECS_OK;
 };
 
-void batch_finish_rhs(BatchItem &I, ecs_status st, const ecs_solve_desc *d) {
-  I.agg.iterations += I.it;
-  I.agg.restarts += I.restarts;
-  I.agg.rel_residual = std::max(I.agg.rel_residual, I.rt);
+void batch_note(BatchItem &I, ecs_status st) {
   if (st != ECS_OK && (I.worst == ECS_OK || st < 0)) I.worst = st;
-  (void)d;
-  I.r++;
-  I.it = I.stalls = I.restarts = 0;
-  I.last_restart = INFINITY;
-  I.rt = 0;
-  I.phase = I.r < I.nrhs ? 0 : 3;
 }
 
-// Enqueues the next step of one system (phase 0: right-hand side norm;
-// 1: restart and true residual; 2: one Bi-CGSTAB iteration), each ending in a
-// readback into the context's pinned buffer.
-void batch_enqueue(BatchItem &I, const ecs_solve_desc *d) {
-  ecs_ctx *C = I.C;
-  const int64_t nn = nn_of(C);
-  const HostLevel &F = C->hl[0];
-  cplx<double> *xr = I.x0 + (int64_t)I.r * nn;
-  if (I.phase == 0) {
-    launch_mask_boundary(F.n[0], F.n[1], F.n[2], I.b0 + (int64_t)I.r * nn, I.K.bz, C->stream);
-    if (d->x_is_guess) launch_mask_boundary(F.n[0], F.n[1], F.n[2], xr, xr, C->stream);
-    else launch_zero<double>(xr, nn, C->stream);
-    launch_nrm2sq<double>(I.K.bz, nn, C->partials, &C->gs->nrm2, C->stream);
-    (void)hipMemcpyAsync(C->pinned, &C->gs->nrm2.re, sizeof(double), hipMemcpyDeviceToHost, C->stream);
-  } else if (I.phase == 1) {
-    bicg_enqueue_restart(C, I.K, I.K.bz, xr);
-    bicg_enqueue_readback(C);
-  } else {
-    if (C->prec.vcycle_dtype == ECS_F32) bicg_enqueue_step<float>(C, I.K, xr);
-    else bicg_enqueue_step<double>(C, I.K, xr);
-    bicg_enqueue_readback(C);
+void batch_finish_slot(BatchItem &I, int q, ecs_status st) {
+  BatchSlot &S = I.slot[q];
+  I.agg.iterations += S.it;
+  I.agg.restarts += S.restarts;
+  I.agg.rel_residual = std::max(I.agg.rel_residual, S.rt);
+  batch_note(I, st);
+  S.phase = 3;
+}
+
+// a slot's vector of the batched layout
+template <typename T>
+T *slot_of(void *base, const KrylovBufs &K, int q) {
+  return reinterpret_cast<T *>(base) + (int64_t)q * K.ld;
+}
+
+template <typename RZ>
+CycleBufs<RZ> batch_bufs(ecs_ctx *C, const KrylovBufs &K) {
+  CycleBufs<RZ> B;
+  for (int l = 0; l < C->nlev; l++) {
+    B.b[l] = reinterpret_cast<cplx<RZ> *>(K.lb[l]);
+    B.t[l] = reinterpret_cast<cplx<RZ> *>(K.lt[l]);
+    B.u[l] = reinterpret_cast<cplx<RZ> *>(K.lu[l]);
   }
+  return B;
 }
 
-// Consumes the readback of the finished step and moves the system on.
-void batch_process(BatchItem &I, const ecs_solve_desc *d) {
-  ecs_ctx *C = I.C;
-  if (I.phase == 0) {
-    double bn2;
-    std::memcpy(&bn2, C->pinned, sizeof(double));
-    const double bn = std::sqrt(bn2);
-    if (!(bn == bn) || std::isinf(bn)) {
-      batch_finish_rhs(I, ECS_EBREAKDOWN, d);
-    } else if (bn == 0) {
-      I.rt = 0;
-      launch_zero<double>(I.x0 + (int64_t)I.r * nn_of(C), nn_of(C), C->stream);  // A x = 0 -> x = 0
-      batch_finish_rhs(I, ECS_OK, d);
-    } else {
-      C->pinned[2] = bn;  // H2D source stays untouched by the {est, bad} readbacks
-      (void)hipMemcpyAsync(&C->bs->bnorm, &C->pinned[2], sizeof(double), hipMemcpyHostToDevice, C->stream);
-      I.phase = 1;
-    }
+// z = M^{-1} v for every slot in rs (FP64 in, cycle dtype out)
+template <typename RZ>
+void batch_precond(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *v, cplx<RZ> *z, const RhsSet &rs) {
+  const int64_t n = nn_of(C);
+  if (!fused_vcycle(C)) {  // one slot, slot 0: the single solve's cycle
+    precond<RZ>(C, v, z);
     return;
   }
-  double est;
-  int bad;
-  bicg_take_readback(C, &est, &bad);
-  if (I.phase == 1) {
-    I.rt = est;
-    if (!(est == est) || std::isinf(est)) {
-      batch_finish_rhs(I, ECS_EBREAKDOWN, d);
-    } else if (est <= d->rtol) {
-      batch_finish_rhs(I, ECS_OK, d);
-    } else if (I.it >= d->maxit) {
-      batch_finish_rhs(I, ECS_NOT_CONVERGED, d);
-    } else if (est >= I.last_restart && ++I.stalls >= 3) {
-      batch_finish_rhs(I, ECS_NOT_CONVERGED, d);
-    } else {
-      if (I.last_restart < INFINITY) I.restarts++;
-      I.last_restart = est;
-      I.phase = 2;
-    }
+  const CycleBufs<RZ> B = batch_bufs<RZ>(C, K);
+  if constexpr (sizeof(RZ) == 4) {
+    cplx<float> *b = reinterpret_cast<cplx<float> *>(K.b32);
+    launch_cast<double, float>(v, b, n, C->stream, rs);
+    vcycle_fused<float>(C, b, z, nullptr, &B, rs);
   } else {
-    I.it++;
-    I.agg.vcycles += 2;
-    if (bad || est <= d->rtol || I.it >= d->maxit) I.phase = 1;
+    vcycle_fused<double>(C, v, z, nullptr, &B, rs);
   }
 }
 
-// Many independent Bi-CGSTAB solves, each system on its context's stream.  A
-// system's next step is enqueued as soon as its previous one has completed
-// (an event per context, polled by the host), so systems of different sizes
-// progress independently and the device holds work from every stream.  Each
-// system runs exactly the kernel sequence of its single solve.
+// one Bi-CGSTAB iteration of every slot in rs (bicg_enqueue_step per slot)
+template <typename RZ>
+void batch_step(ecs_ctx *C, const KrylovBufs &K, const RhsSet &rs) {
+  const int64_t n = nn_of(C);
+  hipStream_t s = C->stream;
+  BicgScalars *S = C->bs;
+  cplx<RZ> *ph = reinterpret_cast<cplx<RZ> *>(K.ph);
+  cplx<RZ> *sh = reinterpret_cast<cplx<RZ> *>(K.sh);
+  launch_bicg_p<double>(K.p, K.r, K.v, n, S, s, rs);
+  batch_precond<RZ>(C, K, K.p, ph, rs);
+  launch_apply_dot<double, RZ>(grid_A(C), ph, K.v, K.rh, kBicgAlpha, C->partials, S, s, rs);
+  launch_bicg_s<double>(K.s, K.r, K.v, n, S, s, rs);
+  batch_precond<RZ>(C, K, K.s, sh, rs);
+  launch_apply_dot<double, RZ>(grid_A(C), sh, K.tt, K.s, kBicgOmega, C->partials, S, s, rs);
+  launch_bicg_xr<double, RZ>(K.bx, ph, sh, K.r, K.s, K.tt, K.rh, n, C->partials, S, s, rs);
+}
+
+// restart of slot q: r = b - A x, (r, r) -> the restart scalars, r^ = r, p = v = 0
+void batch_restart(ecs_ctx *C, const KrylovBufs &K, int q) {
+  const int64_t n = nn_of(C);
+  hipStream_t s = C->stream;
+  cplx<double> *r = slot_of<cplx<double>>(K.r, K, q);
+  launch_residual<double>(grid_A(C), slot_of<cplx<double>>(K.bz, K, q), slot_of<cplx<double>>(K.bx, K, q), r, s);
+  launch_pairdot<double>(r, r, nullptr, nullptr, 1, n, C->partials + (int64_t)q * kRhsPartials, C->bs + q, kBicgInit,
+                         s);
+  (void)hipMemcpyAsync(slot_of<cplx<double>>(K.rh, K, q), r, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, s);
+  launch_zero<double>(slot_of<cplx<double>>(K.p, K, q), n, s);
+  launch_zero<double>(slot_of<cplx<double>>(K.v, K, q), n, s);
+}
+
+// Enqueues the system's next round, ending in a readback into the pinned
+// buffer: a new group's right-hand side norms, or every slot's scalars.
+void batch_enqueue(BatchItem &I) {
+  ecs_ctx *C = I.C;
+  const ecs_solve_desc *d = I.d;
+  const int64_t nn = nn_of(C);
+  const HostLevel &F = C->hl[0];
+  hipStream_t s = C->stream;
+  if (!I.started) {
+    for (int q = 0; q < I.count; q++) {
+      const int64_t r = I.first + q;
+      cplx<double> *bz = slot_of<cplx<double>>(I.K.bz, I.K, q), *x = slot_of<cplx<double>>(I.K.bx, I.K, q);
+      launch_mask_boundary(F.n[0], F.n[1], F.n[2], I.b0 + r * nn, bz, s);
+      if (d->x_is_guess) launch_mask_boundary(F.n[0], F.n[1], F.n[2], I.x0 + r * nn, x, s);
+      else launch_zero<double>(x, nn, s);
+      launch_nrm2sq<double>(bz, nn, C->partials, &C->gs->g[q], s);
+    }
+    (void)hipMemcpyAsync(C->pinned, C->gs->g, I.count * sizeof(cplx<double>), hipMemcpyDeviceToHost, s);
+    return;
+  }
+  I.ver.count = I.itr.count = 0;
+  for (int q = 0; q < I.count; q++) {
+    if (I.slot[q].phase == 1) I.ver.slot[I.ver.count++] = q;
+    else if (I.slot[q].phase == 2) I.itr.slot[I.itr.count++] = q;
+  }
+  for (int k = 0; k < I.ver.count; k++) batch_restart(C, I.K, I.ver.slot[k]);
+  if (I.itr.count > 0) {
+    if (C->prec.vcycle_dtype == ECS_F32) batch_step<float>(C, I.K, I.itr);
+    else batch_step<double>(C, I.K, I.itr);
+  }
+  (void)hipMemcpyAsync(C->pinned, C->bs, I.count * sizeof(BicgScalars), hipMemcpyDeviceToHost, s);
+}
+
+void batch_next_group(BatchItem &I) {
+  I.first += I.count;
+  I.count = std::min(I.group, I.nrhs - I.first);
+  I.started = false;
+  for (int q = 0; q < kMaxRhs; q++) I.slot[q] = BatchSlot();
+  if (I.count <= 0) I.done = true;
+}
+
+// Consumes the round's readback and moves every slot on.
+void batch_process(BatchItem &I) {
+  ecs_ctx *C = I.C;
+  const ecs_solve_desc *d = I.d;
+  const int64_t nn = nn_of(C);
+  if (!I.started) {
+    double *stage = reinterpret_cast<double *>(reinterpret_cast<char *>(C->pinned) + kPinnedStage);
+    for (int q = 0; q < I.count; q++) {
+      cplx<double> g;
+      std::memcpy(&g, reinterpret_cast<const char *>(C->pinned) + q * sizeof(cplx<double>), sizeof g);
+      const double bn = std::sqrt(g.re);
+      if (!(bn == bn) || std::isinf(bn)) {
+        batch_finish_slot(I, q, ECS_EBREAKDOWN);
+      } else if (bn == 0) {
+        launch_zero<double>(slot_of<cplx<double>>(I.K.bx, I.K, q), nn, C->stream);  // A x = 0 -> x = 0
+        I.slot[q].rt = 0;
+        batch_finish_slot(I, q, ECS_OK);
+      } else {
+        // the staging area is not written again before this copy has run
+        stage[q] = bn;
+        (void)hipMemcpyAsync(&C->bs[q].bnorm, &stage[q], sizeof(double), hipMemcpyHostToDevice, C->stream);
+        I.slot[q].phase = 1;
+      }
+    }
+    I.started = true;
+  } else {
+    auto scal = [&](int q, double *est, int *bad) {
+      const char *p = reinterpret_cast<const char *>(C->pinned) + q * sizeof(BicgScalars);
+      std::memcpy(est, p + offsetof(BicgScalars, est), sizeof(double));
+      std::memcpy(bad, p + offsetof(BicgScalars, bad), sizeof(int));
+    };
+    for (int k = 0; k < I.ver.count; k++) {
+      const int q = I.ver.slot[k];
+      BatchSlot &S = I.slot[q];
+      double est;
+      int bad;
+      scal(q, &est, &bad);
+      S.rt = est;
+      if (!(est == est) || std::isinf(est)) {
+        batch_finish_slot(I, q, ECS_EBREAKDOWN);
+      } else if (est <= d->rtol) {
+        batch_finish_slot(I, q, ECS_OK);
+      } else if (S.it >= d->maxit) {
+        batch_finish_slot(I, q, ECS_NOT_CONVERGED);
+      } else if (est >= S.last_restart && ++S.stalls >= 3) {
+        batch_finish_slot(I, q, ECS_NOT_CONVERGED);
+      } else {
+        if (S.last_restart < INFINITY) S.restarts++;
+        S.last_restart = est;
+        S.phase = 2;
+      }
+    }
+    for (int k = 0; k < I.itr.count; k++) {
+      const int q = I.itr.slot[k];
+      BatchSlot &S = I.slot[q];
+      double est;
+      int bad;
+      scal(q, &est, &bad);
+      S.it++;
+      I.agg.vcycles += 2;
+      if (bad || est <= d->rtol || S.it >= d->maxit) S.phase = 1;
+    }
+  }
+  bool all = true;
+  for (int q = 0; q < I.count; q++) all = all && I.slot[q].phase == 3;
+  if (!all) return;
+  // the group is finished: its iterates go to the caller's solutions
+  for (int q = 0; q < I.count; q++)
+    (void)hipMemcpyAsync(I.x0 + (int64_t)(I.first + q) * nn, slot_of<cplx<double>>(I.K.bx, I.K, q),
+                         nn * sizeof(cplx<double>), hipMemcpyDeviceToDevice, C->stream);
+  batch_next_group(I);
+}
+
 ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *const *descs, const void *const *b,
                             void *const *x, const int *nrhs, ecs_stats *stats) {
   std::vector<BatchItem> items(n);
@@ -1635,44 +1817,52 @@ ecs_status batch_solve_impl(int n, ecs_ctx *const *ctxs, const ecs_solve_desc *c
     for (int p = 0; p < q; p++)
       if (ctxs[p] == C) return fail(C, ECS_EINVAL, "a context appears twice in the batch");
     if (nrhs[q] < 0) return fail(C, ECS_EINVAL, "negative right-hand side count");
-    const size_t need = C->hier_bytes + plan_krylov(C, d, nullptr, &items[q].K);
-    if (need > C->ws_bytes) return fail(C, ECS_ENOMEM, "workspace too small for the batched solve");
+    BatchItem &I = items[q];
+    // right-hand sides at once: up to kMaxRhs (or the desc's nrhs) with the fused cycle
+    const int cap = d->nrhs > 0 ? std::min(d->nrhs, kMaxRhs) : kMaxRhs;
+    I.group = fused_vcycle(C) ? std::max(1, std::min(nrhs[q], cap)) : 1;
+    const size_t need = C->hier_bytes + plan_batch(C, I.group, nullptr, &I.K);
+    if (need > C->ws_bytes)
+      return fail(C, ECS_ENOMEM, "workspace too small for the batched solve (size it with nrhs = " +
+                                     std::to_string(I.group) + " right-hand sides at once)");
     if (!C->step_ev && hipEventCreateWithFlags(&C->step_ev, hipEventDisableTiming) != hipSuccess) {
       C->step_ev = nullptr;
       return fail(C, ECS_EDEVICE, "event creation failed");
     }
-    plan_krylov(C, d, C->ws + C->hier_bytes, &items[q].K);
-    items[q].C = C;
-    items[q].d = d;
-    items[q].b0 = reinterpret_cast<const cplx<double> *>(b[q]);
-    items[q].x0 = reinterpret_cast<cplx<double> *>(x[q]);
-    items[q].nrhs = nrhs[q];
-    items[q].phase = nrhs[q] > 0 ? 0 : 3;
+    plan_batch(C, I.group, C->ws + C->hier_bytes, &I.K);
+    I.C = C;
+    I.d = d;
+    I.b0 = reinterpret_cast<const cplx<double> *>(b[q]);
+    I.x0 = reinterpret_cast<cplx<double> *>(x[q]);
+    I.nrhs = nrhs[q];
+    I.first = 0;
+    I.count = std::min(I.group, I.nrhs);
+    I.done = I.nrhs == 0;
   }
   int active = 0;
   for (auto &I : items) {
-    if (I.phase == 3) continue;
-    batch_enqueue(I, I.d);
+    if (I.done) continue;
+    batch_enqueue(I);
     if (hipEventRecord(I.C->step_ev, I.C->stream) != hipSuccess) return ECS_EDEVICE;
     active++;
   }
   while (active > 0) {
     for (auto &I : items) {
-      if (I.phase == 3) continue;
-      const hipError_t q = hipEventQuery(I.C->step_ev);
-      if (q == hipErrorNotReady) continue;
-      if (q != hipSuccess) return fail(I.C, ECS_EDEVICE, std::string("batched solve: ") + hipGetErrorString(q));
-      batch_process(I, I.d);
-      if (I.phase == 3) {
+      if (I.done) continue;
+      const hipError_t e = hipEventQuery(I.C->step_ev);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) return fail(I.C, ECS_EDEVICE, std::string("batched solve: ") + hipGetErrorString(e));
+      batch_process(I);
+      if (I.done) {
         active--;
         continue;
       }
-      batch_enqueue(I, I.d);
+      batch_enqueue(I);
       if (hipEventRecord(I.C->step_ev, I.C->stream) != hipSuccess) return ECS_EDEVICE;
     }
   }
   for (auto &I : items)
-    if (hipStreamSynchronize(I.C->stream) != hipSuccess) return ECS_EDEVICE;
+    if (I.C && hipStreamSynchronize(I.C->stream) != hipSuccess) return ECS_EDEVICE;
   ecs_status worst = ECS_OK;
   for (int q = 0; q < n; q++) {
     items[q].agg.status = items[q].worst;
@@ -1910,7 +2100,7 @@ ecs_status ecs_create(ecs_ctx **out, int dim, const int64_t *nodes, const double
   }
   C->stream = reinterpret_cast<hipStream_t>(stream);
   if (hipGetDevice(&C->device) != hipSuccess ||
-      hipHostMalloc((void **)&C->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void **)&C->pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
     delete C;
     return ECS_EDEVICE;
   }
@@ -1992,9 +2182,12 @@ ecs_status ecs_workspace_size(ecs_ctx *C, const ecs_solve_desc *d, size_t *bytes
   if (!C || !bytes) return ECS_EINVAL;
   if (!C->have_prec) return fail(C, ECS_ESTATE, "set the preconditioner first");
   if (d && (d->restart < 1 || d->restart > kMaxRestart)) return fail(C, ECS_EINVAL, "restart must be in [1, 64]");
+  if (d && (d->nrhs < 0 || d->nrhs > kMaxRhs)) return fail(C, ECS_EINVAL, "nrhs must be in [0, 8]");
   build_host_levels(C);
-  KrylovBufs K;
-  *bytes = plan_hierarchy(C, nullptr) + 256 + plan_krylov(C, d, nullptr, &K) + 256;
+  KrylovBufs K, KB;
+  size_t kb = plan_krylov(C, d, nullptr, &K);
+  if (d && d->krylov == ECS_KRYLOV_BICGSTAB && d->nrhs > 0) kb = std::max(kb, plan_batch(C, d->nrhs, nullptr, &KB));
+  *bytes = plan_hierarchy(C, nullptr) + 256 + kb + 256;
   return ECS_OK;
 }
 

@@ -280,10 +280,16 @@ __global__ __launch_bounds__(BS) void k_pairdot(const cplx<R> *__restrict__ x0, 
   }
 }
 
-// final reduction of pair dots and the Bi-CGSTAB scalar recurrence
+// final reduction of pair dots and the Bi-CGSTAB scalar recurrence (one
+// block per right-hand side)
 __global__ __launch_bounds__(BS) void k_bicg_final(const cplx<double> *__restrict__ partials, int nblocks,
-                                                   int npairs, BicgScalars *S, int mode) {
+                                                   int npairs, BicgScalars *S, int mode, RhsSet rs) {
   __shared__ cplx<double> lds[BS / 64];
+  {
+    const int64_t q = rhs_index(rs);
+    partials += q * kRhsPartials;
+    S += q;
+  }
   cplx<double> d[2] = {mk<double>(0, 0), mk<double>(0, 0)};
   for (int q = 0; q < npairs; q++) {
     cplx<double> s = strided_sum(partials + (int64_t)q * nblocks, nblocks);
@@ -296,7 +302,15 @@ __global__ __launch_bounds__(BS) void k_bicg_final(const cplx<double> *__restric
 // p = r + beta (p - omega v)
 template <typename R>
 __global__ __launch_bounds__(BS) void k_bicg_p(cplx<R> *__restrict__ p, const cplx<R> *__restrict__ r,
-                                               const cplx<R> *__restrict__ v, int64_t n, const BicgScalars *S) {
+                                               const cplx<R> *__restrict__ v, int64_t n, const BicgScalars *S,
+                                               RhsSet rs) {
+  {
+    const int64_t q = rhs_index(rs), sn = rhs_stride(n);
+    p += q * sn;
+    r += q * sn;
+    v += q * sn;
+    S += q;
+  }
   const cplx<R> beta = cvt<R>(S->beta), omega = cvt<R>(S->omega);
   for (int64_t q = (int64_t)blockIdx.x * BS + threadIdx.x; q < n; q += (int64_t)gridDim.x * BS)
     p[q] = r[q] + beta * (p[q] - omega * v[q]);
@@ -305,7 +319,15 @@ __global__ __launch_bounds__(BS) void k_bicg_p(cplx<R> *__restrict__ p, const cp
 // s = r - alpha v
 template <typename R>
 __global__ __launch_bounds__(BS) void k_bicg_s(cplx<R> *__restrict__ s, const cplx<R> *__restrict__ r,
-                                               const cplx<R> *__restrict__ v, int64_t n, const BicgScalars *S) {
+                                               const cplx<R> *__restrict__ v, int64_t n, const BicgScalars *S,
+                                               RhsSet rs) {
+  {
+    const int64_t q = rhs_index(rs), sn = rhs_stride(n);
+    s += q * sn;
+    r += q * sn;
+    v += q * sn;
+    S += q;
+  }
   const cplx<R> alpha = cvt<R>(S->alpha);
   for (int64_t q = (int64_t)blockIdx.x * BS + threadIdx.x; q < n; q += (int64_t)gridDim.x * BS)
     s[q] = r[q] - alpha * v[q];
@@ -318,8 +340,20 @@ __global__ __launch_bounds__(BS) void k_bicg_xr(cplx<R> *__restrict__ x, const c
                                                 const cplx<RZ> *__restrict__ sh, cplx<R> *__restrict__ r,
                                                 const cplx<R> *__restrict__ s, const cplx<R> *__restrict__ t,
                                                 const cplx<R> *__restrict__ rh, int64_t n, BicgScalars *S,
-                                                cplx<double> *partials) {
+                                                cplx<double> *partials, RhsSet rs) {
   __shared__ cplx<double> lds[BS / 64];
+  {
+    const int64_t q = rhs_index(rs), sn = rhs_stride(n);
+    x += q * sn;
+    ph += q * sn;
+    sh += q * sn;
+    r += q * sn;
+    s += q * sn;
+    t += q * sn;
+    rh += q * sn;
+    S += q;
+    partials += q * kRhsPartials;
+  }
   const cplx<R> alpha = cvt<R>(S->alpha), omega = cvt<R>(S->omega);
   double nrm = 0;
   cplx<double> rr = mk<double>(0, 0);
@@ -340,7 +374,13 @@ __global__ __launch_bounds__(BS) void k_bicg_xr(cplx<R> *__restrict__ x, const c
 
 // ----------------------------------------------------------- utilities
 template <typename RI, typename RO>
-__global__ __launch_bounds__(BS) void k_cast(const cplx<RI> *__restrict__ x, cplx<RO> *__restrict__ y, int64_t n) {
+__global__ __launch_bounds__(BS) void k_cast(const cplx<RI> *__restrict__ x, cplx<RO> *__restrict__ y, int64_t n,
+                                             RhsSet rs) {
+  {
+    const int64_t q = rhs_index(rs) * rhs_stride(n);
+    x += q;
+    y += q;
+  }
   for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) y[p] = cvt<RO>(x[p]);
 }
 __global__ __launch_bounds__(BS) void k_cast_real(const double *__restrict__ x, float *__restrict__ y, int64_t n) {
@@ -511,33 +551,35 @@ void launch_pairdot(const cplx<R> *x0, const cplx<R> *y0, const cplx<R> *x1, con
                     cplx<double> *partials, BicgScalars *S, int mode, hipStream_t s) {
   int nb = red_blocks(n);
   launch_k((k_pairdot<R>), dim3(nb), dim3(BS), 0, s, x0, y0, x1, y1, npairs, n, partials);
-  launch_k(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, npairs, S, mode);
+  launch_k(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, npairs, S, mode, one_rhs());
 }
 template <typename R>
-void launch_bicg_p(cplx<R> *p, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s) {
-  launch_k((k_bicg_p<R>), dim3(grid_for(n)), dim3(BS), 0, s, p, r, v, n, S);
+void launch_bicg_p(cplx<R> *p, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s,
+                   const RhsSet &rs) {
+  launch_k((k_bicg_p<R>), dim3(grid_for(n), rs.count), dim3(BS), 0, s, p, r, v, n, S, rs);
 }
 template <typename R>
-void launch_bicg_s(cplx<R> *sv, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s) {
-  launch_k((k_bicg_s<R>), dim3(grid_for(n)), dim3(BS), 0, s, sv, r, v, n, S);
+void launch_bicg_s(cplx<R> *sv, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s,
+                   const RhsSet &rs) {
+  launch_k((k_bicg_s<R>), dim3(grid_for(n), rs.count), dim3(BS), 0, s, sv, r, v, n, S, rs);
 }
 template <typename R, typename RZ>
 void launch_bicg_xr(cplx<R> *x, const cplx<RZ> *ph, const cplx<RZ> *sh, cplx<R> *r, const cplx<R> *sv,
                     const cplx<R> *t, const cplx<R> *rh, int64_t n, cplx<double> *partials, BicgScalars *S,
-                    hipStream_t s) {
+                    hipStream_t s, const RhsSet &rs) {
   const int nb = red_blocks(n);
-  launch_k((k_bicg_xr<R, RZ>), dim3(nb), dim3(BS), 0, s, x, ph, sh, r, sv, t, rh, n, S, partials);
-  launch_k(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, 2, S, (int)kBicgNormRho);
+  launch_k((k_bicg_xr<R, RZ>), dim3(nb, rs.count), dim3(BS), 0, s, x, ph, sh, r, sv, t, rh, n, S, partials, rs);
+  launch_k(k_bicg_final, dim3(1, rs.count), dim3(BS), 0, s, partials, nb, 2, S, (int)kBicgNormRho, rs);
 }
 
 void launch_bicg_final(const cplx<double> *partials, int nblocks, int npairs, BicgScalars *S, int mode,
-                       hipStream_t s) {
-  launch_k(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nblocks, npairs, S, mode);
+                       hipStream_t s, const RhsSet &rs) {
+  launch_k(k_bicg_final, dim3(1, rs.count), dim3(BS), 0, s, partials, nblocks, npairs, S, mode, rs);
 }
 
 template <typename RI, typename RO>
-void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s) {
-  launch_k((k_cast<RI, RO>), dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
+void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s, const RhsSet &rs) {
+  launch_k((k_cast<RI, RO>), dim3(grid_for(n), rs.count), dim3(BS), 0, s, x, y, n, rs);
 }
 void launch_cast_real(const double *x, float *y, int64_t n, hipStream_t s) {
   launch_k(k_cast_real, dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
@@ -613,24 +655,24 @@ template void launch_pairdot<double>(const cplx<double> *, const cplx<double> *,
 template void launch_pairdot<float>(const cplx<float> *, const cplx<float> *, const cplx<float> *,
                                     const cplx<float> *, int, int64_t, cplx<double> *, BicgScalars *, int, hipStream_t);
 template void launch_bicg_p<double>(cplx<double> *, const cplx<double> *, const cplx<double> *, int64_t,
-                                    const BicgScalars *, hipStream_t);
+                                    const BicgScalars *, hipStream_t, const RhsSet &);
 template void launch_bicg_p<float>(cplx<float> *, const cplx<float> *, const cplx<float> *, int64_t,
-                                   const BicgScalars *, hipStream_t);
+                                   const BicgScalars *, hipStream_t, const RhsSet &);
 template void launch_bicg_s<double>(cplx<double> *, const cplx<double> *, const cplx<double> *, int64_t,
-                                    const BicgScalars *, hipStream_t);
+                                    const BicgScalars *, hipStream_t, const RhsSet &);
 template void launch_bicg_s<float>(cplx<float> *, const cplx<float> *, const cplx<float> *, int64_t,
-                                   const BicgScalars *, hipStream_t);
+                                   const BicgScalars *, hipStream_t, const RhsSet &);
 template void launch_bicg_xr<double, double>(cplx<double> *, const cplx<double> *, const cplx<double> *, cplx<double> *,
                                              const cplx<double> *, const cplx<double> *, const cplx<double> *, int64_t,
-                                             cplx<double> *, BicgScalars *, hipStream_t);
+                                             cplx<double> *, BicgScalars *, hipStream_t, const RhsSet &);
 template void launch_bicg_xr<double, float>(cplx<double> *, const cplx<float> *, const cplx<float> *, cplx<double> *,
                                             const cplx<double> *, const cplx<double> *, const cplx<double> *, int64_t,
-                                            cplx<double> *, BicgScalars *, hipStream_t);
+                                            cplx<double> *, BicgScalars *, hipStream_t, const RhsSet &);
 template void launch_bicg_xr<float, float>(cplx<float> *, const cplx<float> *, const cplx<float> *, cplx<float> *,
                                            const cplx<float> *, const cplx<float> *, const cplx<float> *, int64_t,
-                                           cplx<double> *, BicgScalars *, hipStream_t);
-template void launch_cast<double, float>(const cplx<double> *, cplx<float> *, int64_t, hipStream_t);
-template void launch_cast<float, double>(const cplx<float> *, cplx<double> *, int64_t, hipStream_t);
+                                           cplx<double> *, BicgScalars *, hipStream_t, const RhsSet &);
+template void launch_cast<double, float>(const cplx<double> *, cplx<float> *, int64_t, hipStream_t, const RhsSet &);
+template void launch_cast<float, double>(const cplx<float> *, cplx<double> *, int64_t, hipStream_t, const RhsSet &);
 template void launch_zero<double>(cplx<double> *, int64_t, hipStream_t);
 template void launch_zero<float>(cplx<float> *, int64_t, hipStream_t);
 

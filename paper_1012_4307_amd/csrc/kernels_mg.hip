@@ -320,9 +320,15 @@ __global__ __launch_bounds__(256) void k_prolong_jacobi(Grid<R> f, Grid<R> c, co
 template <typename R>
 __global__ __launch_bounds__(1024) void k_coarse_solve(int nunk, const cplx<R> *__restrict__ minvT,
                                                        const int *__restrict__ unk, int n0, int n1, int n2,
-                                                       const cplx<R> *__restrict__ b, cplx<R> *__restrict__ x) {
+                                                       const cplx<R> *__restrict__ b, cplx<R> *__restrict__ x,
+                                                       RhsSet rs) {
   __shared__ cplx<R> sb[2048];
   const int nn = n0 * n1 * n2;
+  {
+    const int64_t q = rhs_index(rs) * rhs_stride(nn);  // one block per right-hand side
+    b += q;
+    x += q;
+  }
   for (int t = threadIdx.x; t < nunk; t += blockDim.x) sb[t] = b[unk[t]];
   for (int t = threadIdx.x; t < nn; t += blockDim.x) {
     const int i = t % n0, j = (t / n0) % n1, k = t / (n0 * n1);
@@ -393,10 +399,19 @@ constexpr int SX = 62;
 template <typename R, typename RI, typename RO, int MODE, int SY>
 __global__ __launch_bounds__(256) void k_apply2d(Grid<R> g, const cplx<RI> *__restrict__ x, cplx<RO> *__restrict__ y,
                                                  const cplx<R> *__restrict__ d0, cplx<double> *partials, int tiles_x,
-                                                 int tiles) {
+                                                 int tiles, RhsSet rs) {
   __shared__ cplx<double> lds[4];
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n0 = g.n0, n1 = g.n1;
+  {
+    const int64_t q = rhs_index(rs), sn = rhs_stride((int64_t)n0 * n1);
+    x += q * sn;
+    y += q * sn;
+    if (MODE != 0) {
+      d0 += q * sn;
+      partials += q * kRhsPartials;
+    }
+  }
   const int padded = gridDim.x, b = blockIdx.x;
   const int local = (b % kXcds) * (padded / kXcds) + b / kXcds;  // XCD-aware order within a pass
   cplx<double> a0 = mk<double>(0, 0);
@@ -491,11 +506,13 @@ __global__ void k_inject_k2(int n0, int n1, int n2, const double *__restrict__ k
 
 // 2D launches of the strip kernel: one block (4 waves, 62 x 4 SY nodes) per
 // tile while the tile count fits the reduction buffer, grid-stride beyond
+// blocks: one per strip tile while the partials (two per block) fit the
+// reduction buffer, or a right-hand side's share of it in a batched launch
 template <typename R>
-void strip_grid(const Grid<R> &g, int sy, int *tiles_x, int *tiles, int *blocks) {
+void strip_grid(const Grid<R> &g, int sy, int *tiles_x, int *tiles, int *blocks, bool batched = false) {
   *tiles_x = (g.n0 - 1 + SX - 1) / SX;
   *tiles = *tiles_x * ((g.n1 + 4 * sy - 1) / (4 * sy));
-  const int cap = kRedBlocks * (kMaxRestart + 2) / 2;
+  const int cap = batched ? kRhsPartials / 2 : kRedBlocks * (kMaxRestart + 2) / 2;
   *blocks = xcd_padded(*tiles < cap ? *tiles : cap);
 }
 
@@ -506,7 +523,7 @@ void launch_apply(const Grid<R> &g, const cplx<RI> *x, cplx<RO> *y, hipStream_t 
     int tx, tiles, nb;
     strip_grid(g, sy, &tx, &tiles, &nb);
     launch_k((k_apply2d<R, RI, RO, 0, sy>), dim3(nb), dim3(256), 0, s, g, x, y,
-                       (const cplx<R> *)nullptr, (cplx<double> *)nullptr, tx, tiles);
+                       (const cplx<R> *)nullptr, (cplx<double> *)nullptr, tx, tiles, one_rhs());
     return;
   }
   launch_k((k_apply<R, RI, RO>), grid_of(g), dim3(TX, TY), 0, s, g, x, y);
@@ -550,25 +567,25 @@ void launch_prolong_jacobi(const Grid<R> &fine, const Grid<R> &coarse, const cpl
 }
 template <typename R>
 void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, int n1, int n2, const cplx<R> *b,
-                         cplx<R> *x, hipStream_t s) {
-  launch_k((k_coarse_solve<R>), dim3(1), dim3(1024), 0, s, nunk, minv, unk, n0, n1, n2, b, x);
+                         cplx<R> *x, hipStream_t s, const RhsSet &rs) {
+  launch_k((k_coarse_solve<R>), dim3(1, rs.count), dim3(1024), 0, s, nunk, minv, unk, n0, n1, n2, b, x, rs);
 }
 template <typename R, typename RI>
 void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cplx<R> *d0, int mode,
-                      cplx<double> *partials, BicgScalars *S, hipStream_t s) {
+                      cplx<double> *partials, BicgScalars *S, hipStream_t s, const RhsSet &rs) {
   // one block per 64 x 4 tile while the partials (two per block) fit the
-  // reduction buffer (kRedBlocks x (kMaxRestart + 2) entries)
+  // reduction buffer (kRedBlocks x (kMaxRestart + 2) entries); batched
+  // launches (2D only) give every right-hand side kRhsPartials of them
   if (g.n2 == 1) {
     constexpr int sy = strip_rows<R, 1>();
     int tx, tiles, nb;
-    strip_grid(g, sy, &tx, &tiles, &nb);
+    strip_grid(g, sy, &tx, &tiles, &nb, rs.count > 1);
+    const dim3 grid(nb, rs.count);
     if (mode == kBicgAlpha)
-      launch_k((k_apply2d<R, RI, R, kBicgAlpha, sy>), dim3(nb), dim3(256), 0, s, g, x, y, d0, partials, tx,
-                         tiles);
+      launch_k((k_apply2d<R, RI, R, kBicgAlpha, sy>), grid, dim3(256), 0, s, g, x, y, d0, partials, tx, tiles, rs);
     else
-      launch_k((k_apply2d<R, RI, R, kBicgOmega, sy>), dim3(nb), dim3(256), 0, s, g, x, y, d0, partials, tx,
-                         tiles);
-    launch_bicg_final(partials, nb, mode == kBicgAlpha ? 1 : 2, S, mode, s);
+      launch_k((k_apply2d<R, RI, R, kBicgOmega, sy>), grid, dim3(256), 0, s, g, x, y, d0, partials, tx, tiles, rs);
+    launch_bicg_final(partials, nb, mode == kBicgAlpha ? 1 : 2, S, mode, s, rs);
     return;
   }
   const int ntiles = ((g.n0 + TX - 1) / TX) * ((g.n1 + TY - 1) / TY) * g.n2;
@@ -599,18 +616,21 @@ void launch_inject_k2(int n0, int n1, int n2, const double *k2_fine, int f0, int
   template void launch_prolong_to<R>(const Grid<R> &, const Grid<R> &, const cplx<R> *, const cplx<R> *,         \
                                      cplx<R> *, hipStream_t);                                                   \
   template void launch_coarse_solve<R>(int, const cplx<R> *, const int *, int, int, int, const cplx<R> *,      \
-                                       cplx<R> *, hipStream_t);                                                 \
+                                       cplx<R> *, hipStream_t, const RhsSet &);                                 \
   template void launch_inject_k2<R>(int, int, int, const double *, int, int, R *, hipStream_t);
 
 ECS_INST_MG(double)
 ECS_INST_MG(float)
 
 template void launch_apply_dot<double, double>(const Grid<double> &, const cplx<double> *, cplx<double> *,
-                                               const cplx<double> *, int, cplx<double> *, BicgScalars *, hipStream_t);
+                                               const cplx<double> *, int, cplx<double> *, BicgScalars *, hipStream_t,
+                                               const RhsSet &);
 template void launch_apply_dot<double, float>(const Grid<double> &, const cplx<float> *, cplx<double> *,
-                                              const cplx<double> *, int, cplx<double> *, BicgScalars *, hipStream_t);
+                                              const cplx<double> *, int, cplx<double> *, BicgScalars *, hipStream_t,
+                                              const RhsSet &);
 template void launch_apply_dot<float, float>(const Grid<float> &, const cplx<float> *, cplx<float> *,
-                                             const cplx<float> *, int, cplx<double> *, BicgScalars *, hipStream_t);
+                                             const cplx<float> *, int, cplx<double> *, BicgScalars *, hipStream_t,
+                                             const RhsSet &);
 template void launch_apply<double, double, double>(const Grid<double> &, const cplx<double> *, cplx<double> *,
                                                    hipStream_t);
 template void launch_apply<double, float, double>(const Grid<double> &, const cplx<float> *, cplx<double> *,

@@ -90,7 +90,7 @@ __device__ __forceinline__ cplx<R> sel(bool c, cplx<R> a, cplx<R> b) {
 template <typename R, int CY, int SRC>
 __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
                                                 const DownSrc<R> src, cplx<R> *__restrict__ rc, R omega,
-                                                int tiles_x, int tiles) {
+                                                int tiles_x, int tiles, RhsSet rs) {
   constexpr int CX = 61;
   constexpr int WX = 2 * CX + 5;          // 127 staged columns
   constexpr int WY = 2 * CY + 5;
@@ -104,6 +104,12 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
+  {
+    // this block's right-hand side (the formed-b variants run one only)
+    const int64_t q = rhs_index(rs);
+    b += q * rhs_stride((int64_t)f.n0 * f.n1);
+    rc += q * rhs_stride((int64_t)c.n0 * c.n1);
+  }
   const int I0 = (tile % tiles_x) * CX, J0 = (tile / tiles_x) * CY;
   const int gx0 = 2 * I0 - 3, gy0 = 2 * J0 - 3;
   const int n0 = f.n0, n1 = f.n1;
@@ -279,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
 template <typename R, int TY>
 __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
                                               const cplx<R> *__restrict__ ec, cplx<R> *__restrict__ u_out, R omega,
-                                              int tiles_x, int tiles) {
+                                              int tiles_x, int tiles, RhsSet rs) {
   constexpr int TX = 120;
   constexpr int WY = TY + 6;
   constexpr int RPW = (WY + 3) / 4;
@@ -289,6 +295,12 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
+  {
+    const int64_t q = rhs_index(rs), sf = rhs_stride((int64_t)f.n0 * f.n1);
+    b += q * sf;
+    u_out += q * sf;
+    ec += q * rhs_stride((int64_t)c.n0 * c.n1);
+  }
   const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
   const int gx0 = x0 - 4, gy0 = y0 - 3;
   const int cx0 = x0 / 2 - 2, cy0 = y0 / 2 - 1;  // coarse staging origin
@@ -480,9 +492,13 @@ __device__ __forceinline__ void tail_dense(int nu, int tpr, const M *mi, const c
 }
 
 template <typename R>
-__global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
+__global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a, RhsSet rs) {
   __shared__ TailLds<R> S;
   const int tid = threadIdx.x;
+  // one workgroup per right-hand side (the kernel argument block is not written)
+  const int64_t rq = rhs_index(rs) * rhs_stride((int64_t)a.g[0].n0 * a.g[0].n1);
+  const cplx<R> *const b0 = a.b0 + rq;
+  cplx<R> *const u0 = a.u0 + rq;
   const R om = a.omega, om1 = R(1) - a.omega;
   const int last = a.nl - 1;
   const bool minv_lds = a.nunk * a.nunk <= kTailMinv;
@@ -524,7 +540,7 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
       cym[sl] = g.cm1[j];
       cyp[sl] = g.cp1[j];
       kv[sl] = g.k2[p];
-      bv[sl] = a.b0[k == 0 ? p : 0];
+      bv[sl] = b0[k == 0 ? p : 0];
     }
     constexpr int kMiSlots = (kTailMinv + TT - 1) / TT;
     const int nmi = a.nunk * a.nunk;
@@ -675,8 +691,8 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
         }
         if (k == 0 && colour == 1) {
           const int pp = j * n0 + h2;  // both nodes of the pair (the red one is final)
-          a.u0[pp] = w[pp];
-          if (h2 + 1 < n0) a.u0[pp + 1] = w[pp + 1];
+          u0[pp] = w[pp];
+          if (h2 + 1 < n0) u0[pp + 1] = w[pp + 1];
         }
       }
       __syncthreads();
@@ -692,73 +708,75 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a) {
 // per up block in {4, 8, 10, 12, 16, 32}.
 template <typename R, int SRC>
 void launch_down(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const DownSrc<R> &src, cplx<R> *rc,
-                 R omega, int rows, hipStream_t s) {
+                 R omega, int rows, hipStream_t s, const RhsSet &rs) {
   constexpr int CX = 61;
   const int tx = (coarse.n0 + CX - 1) / CX;
   const int tiles = tx * ((coarse.n1 + rows - 1) / rows);
-  const dim3 grid(xcd_padded(tiles)), block(NT);
+  const dim3 grid(xcd_padded(tiles), rs.count), block(NT);
   switch (rows) {
-    case 2: launch_k((k_down_rb<R, 2, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
-    case 3: launch_k((k_down_rb<R, 3, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
-    case 4: launch_k((k_down_rb<R, 4, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
-    case 5: launch_k((k_down_rb<R, 5, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
-    case 6: launch_k((k_down_rb<R, 6, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
+    case 2: launch_k((k_down_rb<R, 2, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
+    case 3: launch_k((k_down_rb<R, 3, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
+    case 4: launch_k((k_down_rb<R, 4, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
+    case 5: launch_k((k_down_rb<R, 5, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
+    case 6: launch_k((k_down_rb<R, 6, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
     case 16:
       if constexpr (sizeof(R) == 4) {
-        launch_k((k_down_rb<R, 16, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles);
+        launch_k((k_down_rb<R, 16, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs);
         break;
       }
       [[fallthrough]];
-    default: launch_k((k_down_rb<R, 8, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles); break;
+    default:
+      launch_k((k_down_rb<R, 8, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs);
+      break;
   }
 }
 
 template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *rc, R omega, int rows,
-                    hipStream_t s) {
-  launch_down<R, kDownSrcB>(fine, coarse, b, DownSrc<R>{}, rc, omega, rows, s);
+                    hipStream_t s, const RhsSet &rs) {
+  launch_down<R, kDownSrcB>(fine, coarse, b, DownSrc<R>{}, rc, omega, rows, s, rs);
 }
 
 template <typename R>
 void launch_down_rb_src(const Grid<R> &fine, const Grid<R> &coarse, const DownSrc<R> &src, cplx<R> *rc, R omega,
                         int rows, hipStream_t s) {
-  if (src.mode == kDownSrcP) launch_down<R, kDownSrcP>(fine, coarse, nullptr, src, rc, omega, rows, s);
-  else launch_down<R, kDownSrcS>(fine, coarse, nullptr, src, rc, omega, rows, s);
+  if (src.mode == kDownSrcP) launch_down<R, kDownSrcP>(fine, coarse, nullptr, src, rc, omega, rows, s, one_rhs());
+  else launch_down<R, kDownSrcS>(fine, coarse, nullptr, src, rc, omega, rows, s, one_rhs());
 }
 
 template <typename R>
 void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *ec, cplx<R> *u_out,
-                  R omega, int rows, hipStream_t s) {
+                  R omega, int rows, hipStream_t s, const RhsSet &rs) {
   constexpr int TX = 120;
   const int tx = (fine.n0 + TX - 1) / TX;
   const int tiles = tx * ((fine.n1 + rows - 1) / rows);
-  const dim3 grid(xcd_padded(tiles)), block(NT);
+  const dim3 grid(xcd_padded(tiles), rs.count), block(NT);
   switch (rows) {
-    case 4: launch_k((k_up_rb<R, 4>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
-    case 8: launch_k((k_up_rb<R, 8>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
-    case 10: launch_k((k_up_rb<R, 10>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
-    case 12: launch_k((k_up_rb<R, 12>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
-    case 32: launch_k((k_up_rb<R, 32>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
-    default: launch_k((k_up_rb<R, 16>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles); break;
+    case 4: launch_k((k_up_rb<R, 4>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    case 8: launch_k((k_up_rb<R, 8>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    case 10: launch_k((k_up_rb<R, 10>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    case 12: launch_k((k_up_rb<R, 12>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    case 32: launch_k((k_up_rb<R, 32>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    default: launch_k((k_up_rb<R, 16>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
   }
 }
 
 template <typename R>
-void launch_tail(const TailArgs<R> &a, hipStream_t s) {
-  launch_k((k_tail<R>), dim3(1), dim3(TT), 0, s, a);
+void launch_tail(const TailArgs<R> &a, hipStream_t s, const RhsSet &rs) {
+  launch_k((k_tail<R>), dim3(1, rs.count), dim3(TT), 0, s, a, rs);
 }
 
 template void launch_down_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *, cplx<double> *,
-                                     double, int, hipStream_t);
+                                     double, int, hipStream_t, const RhsSet &);
 template void launch_down_rb<float>(const Grid<float> &, const Grid<float> &, const cplx<float> *, cplx<float> *,
-                                    float, int, hipStream_t);
+                                    float, int, hipStream_t, const RhsSet &);
 template void launch_up_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *,
-                                   const cplx<double> *, cplx<double> *, double, int, hipStream_t);
+                                   const cplx<double> *, cplx<double> *, double, int, hipStream_t, const RhsSet &);
 template void launch_down_rb_src<float>(const Grid<float> &, const Grid<float> &, const DownSrc<float> &, cplx<float> *,
                                         float, int, hipStream_t);
-template void launch_tail<double>(const TailArgs<double> &, hipStream_t);
-template void launch_tail<float>(const TailArgs<float> &, hipStream_t);
+template void launch_tail<double>(const TailArgs<double> &, hipStream_t, const RhsSet &);
+template void launch_tail<float>(const TailArgs<float> &, hipStream_t, const RhsSet &);
 template void launch_up_rb<float>(const Grid<float> &, const Grid<float> &, const cplx<float> *, const cplx<float> *,
-                                  cplx<float> *, float, int, hipStream_t);
+                                  cplx<float> *, float, int, hipStream_t, const RhsSet &);
 
 }  // namespace ecs

@@ -242,7 +242,7 @@ template <typename R, int C, int CY>
 __global__ __launch_bounds__(NP) void k_down2_rb(Grid<R> f, Grid<R> m, Grid<R> c, const cplx<R> *__restrict__ b,
                                                  cplx<R> *__restrict__ t_f, cplx<R> *__restrict__ b_m,
                                                  cplx<R> *__restrict__ t_m, cplx<R> *__restrict__ rc, R omega,
-                                                 int tiles_x, int tiles) {
+                                                 int tiles_x, int tiles, RhsSet rs) {
   constexpr int MW = 2 * C + 5, MH = 2 * CY + 5;
   constexpr int AW = 2 * MW + 5, AH = 2 * MH + 5;
   __shared__ cplx<R> Ab[AW * AH], Ad[AW * AH], At[AW * AH], Ar[AW * AH];
@@ -250,6 +250,14 @@ __global__ __launch_bounds__(NP) void k_down2_rb(Grid<R> f, Grid<R> m, Grid<R> c
   __shared__ cplx<R> Aw[2 * (AW + AH)], Mw[2 * (MW + MH)];
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
+  {
+    const int64_t q = rhs_index(rs), sf = rhs_stride((int64_t)f.n0 * f.n1), sm = rhs_stride((int64_t)m.n0 * m.n1);
+    b += q * sf;
+    t_f += q * sf;
+    b_m += q * sm;
+    t_m += q * sm;
+    rc += q * rhs_stride((int64_t)c.n0 * c.n1);
+  }
   const int I0 = (tile % tiles_x) * C, J0 = (tile / tiles_x) * CY;
   const Region<R> M = make_region(2 * I0 - 3, 2 * J0 - 3, MW, MH, Mw);
   const Region<R> A = make_region(2 * M.ox - 3, 2 * M.oy - 3, AW, AH, Aw);
@@ -346,7 +354,8 @@ template <typename R, int TX, int TY>
 __global__ __launch_bounds__(NP) void k_up2_rb(Grid<R> f, Grid<R> m, Grid<R> c, const cplx<R> *__restrict__ b_f,
                                                const cplx<R> *__restrict__ t_f, const cplx<R> *__restrict__ b_m,
                                                const cplx<R> *__restrict__ t_m, const cplx<R> *__restrict__ ec,
-                                               cplx<R> *__restrict__ u_out, R omega, int tiles_x, int tiles) {
+                                               cplx<R> *__restrict__ u_out, R omega, int tiles_x, int tiles,
+                                               RhsSet rs) {
   constexpr int AW = TX + 4, AH = TY + 4;
   constexpr int EW = TX / 2 + 3, EH = TY / 2 + 3;
   constexpr int FW = EW + 4, FH = EH + 4;
@@ -357,6 +366,15 @@ __global__ __launch_bounds__(NP) void k_up2_rb(Grid<R> f, Grid<R> m, Grid<R> c, 
   __shared__ cplx<R> Aw[2 * (AW + AH)], Fw[2 * (FW + FH)];
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
+  {
+    const int64_t q = rhs_index(rs), sf = rhs_stride((int64_t)f.n0 * f.n1), sm = rhs_stride((int64_t)m.n0 * m.n1);
+    b_f += q * sf;
+    t_f += q * sf;
+    u_out += q * sf;
+    b_m += q * sm;
+    t_m += q * sm;
+    ec += q * rhs_stride((int64_t)c.n0 * c.n1);
+  }
   const int tid = threadIdx.x;
   const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
   const Region<R> A = make_region(x0 - 2, y0 - 2, AW, AH, Aw);
@@ -403,37 +421,38 @@ __global__ __launch_bounds__(NP) void k_up2_rb(Grid<R> f, Grid<R> m, Grid<R> c, 
 
 template <typename R>
 void launch_down2_rb(const Grid<R> &f, const Grid<R> &m, const Grid<R> &c, const cplx<R> *b, cplx<R> *t_f,
-                     cplx<R> *b_m, cplx<R> *t_m, cplx<R> *rc, R omega, hipStream_t s) {
+                     cplx<R> *b_m, cplx<R> *t_m, cplx<R> *rc, R omega, hipStream_t s, const RhsSet &rs) {
   constexpr int C = 8, CY = sizeof(R) == 4 ? 4 : 2;
   const int tx = (c.n0 + C - 1) / C;
   const int tiles = tx * ((c.n1 + CY - 1) / CY);
-  launch_k((k_down2_rb<R, C, CY>), dim3(xcd_padded(tiles)), dim3(NP), 0, s, f, m, c, b, t_f, b_m, t_m, rc, omega,
-           tx, tiles);
+  launch_k((k_down2_rb<R, C, CY>), dim3(xcd_padded(tiles), rs.count), dim3(NP), 0, s, f, m, c, b, t_f, b_m, t_m,
+           rc, omega, tx, tiles, rs);
 }
 
 template <typename R>
 void launch_up2_rb(const Grid<R> &f, const Grid<R> &m, const Grid<R> &c, const cplx<R> *b_f, const cplx<R> *t_f,
                    const cplx<R> *b_m, const cplx<R> *t_m, const cplx<R> *ec, cplx<R> *u_out, R omega,
-                   hipStream_t s) {
+                   hipStream_t s, const RhsSet &rs) {
   constexpr int TX = 32, TY = sizeof(R) == 4 ? 16 : 8;
   const int tx = (f.n0 + TX - 1) / TX;
   const int tiles = tx * ((f.n1 + TY - 1) / TY);
-  launch_k((k_up2_rb<R, TX, TY>), dim3(xcd_padded(tiles)), dim3(NP), 0, s, f, m, c, b_f, t_f, b_m, t_m, ec, u_out,
-           omega, tx, tiles);
+  launch_k((k_up2_rb<R, TX, TY>), dim3(xcd_padded(tiles), rs.count), dim3(NP), 0, s, f, m, c, b_f, t_f, b_m, t_m,
+           ec, u_out, omega, tx, tiles, rs);
 }
 
 template void launch_down2_rb<double>(const Grid<double> &, const Grid<double> &, const Grid<double> &,
                                       const cplx<double> *, cplx<double> *, cplx<double> *, cplx<double> *,
-                                      cplx<double> *, double, hipStream_t);
+                                      cplx<double> *, double, hipStream_t, const RhsSet &);
 template void launch_down2_rb<float>(const Grid<float> &, const Grid<float> &, const Grid<float> &,
                                      const cplx<float> *, cplx<float> *, cplx<float> *, cplx<float> *,
-                                     cplx<float> *, float, hipStream_t);
+                                     cplx<float> *, float, hipStream_t, const RhsSet &);
 template void launch_up2_rb<double>(const Grid<double> &, const Grid<double> &, const Grid<double> &,
                                     const cplx<double> *, const cplx<double> *, const cplx<double> *,
                                     const cplx<double> *, const cplx<double> *, cplx<double> *, double,
-                                    hipStream_t);
+                                    hipStream_t, const RhsSet &);
 template void launch_up2_rb<float>(const Grid<float> &, const Grid<float> &, const Grid<float> &,
                                    const cplx<float> *, const cplx<float> *, const cplx<float> *,
-                                   const cplx<float> *, const cplx<float> *, cplx<float> *, float, hipStream_t);
+                                   const cplx<float> *, const cplx<float> *, cplx<float> *, float, hipStream_t,
+                                   const RhsSet &);
 
 }  // namespace ecs
