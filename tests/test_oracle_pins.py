@@ -531,3 +531,25 @@ def test_adjoint_gradient_vs_central_differences():
         km = k2.copy(); km[j, i] -= eps
         fd = (loss(kp)[0] - loss(km)[0]) / (2 * eps)
         assert abs(fd - grad[j, i]) <= 1e-5 * max(1e-12, abs(fd)) + 1e-10, (j, i, fd, grad[j, i])
+
+
+def test_stored_full_size_oracle_solution_fixture():
+    """tests/golden/oracle_large_coulomb_2049.json (written by the oracle-only
+    script beside it): the oracle's own solves of the 2049^2 benchmark system
+    converged (1e-8 and 1e-12 true residuals), the automatic |Re lambda0| is
+    max k^2 = 2(E + 1) = 6 (Sec. 5's rule, E = 2), and the sampled solution
+    vanishes on the Dirichlet boundary, is finite, and its samples stay below
+    the recorded maximum."""
+    with open(os.path.join(GOLDEN, "oracle_large_coulomb_2049.json")) as fh:
+        g = json.load(fh)
+    assert g["lam0"] == 6.0
+    a, b = g["fgmres_1e8"], g["solution_1e12"]["stats"]
+    assert a["status"] == 0 and a["rel_residual"] <= 1e-8 and b["status"] == 0 and b["rel_residual"] <= 1e-12
+    assert b["iterations"] > a["iterations"]
+    s = g["solution_1e12"]
+    m = 2048 // s["stride"] + 1
+    x = (np.array(s["re"]) + 1j * np.array(s["im"])).reshape(m, m)
+    assert np.all(np.isfinite(x))
+    assert np.all(x[0] == 0) and np.all(x[-1] == 0) and np.all(x[:, 0] == 0) and np.all(x[:, -1] == 0)
+    assert 0 < np.abs(x).max() <= s["max_abs"]
+
