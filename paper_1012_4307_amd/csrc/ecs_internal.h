@@ -125,6 +125,10 @@ inline RhsSet one_rhs() {
   r.count = 1;
   return r;
 }
+// launches for a map other than slot 0 alone use the kernels' multi-right-
+// hand-side instantiations (template flag MR); single launches use the others,
+// which never read the map
+inline bool multi_rhs(const RhsSet &rs) { return rs.count > 1 || rs.slot[0] != 0; }
 
 // XCD-aware tile order.  Workgroups are handed to the 8 XCDs of the chip in
 // round-robin order of their linear index, and each XCD has its own L2.  A 1D

@@ -282,10 +282,11 @@ __global__ __launch_bounds__(BS) void k_pairdot(const cplx<R> *__restrict__ x0, 
 
 // final reduction of pair dots and the Bi-CGSTAB scalar recurrence (one
 // block per right-hand side)
+template <bool MR>
 __global__ __launch_bounds__(BS) void k_bicg_final(const cplx<double> *__restrict__ partials, int nblocks,
                                                    int npairs, BicgScalars *S, int mode, RhsSet rs) {
   __shared__ cplx<double> lds[BS / 64];
-  {
+  if constexpr (MR) {
     const int64_t q = rhs_index(rs);
     partials += q * kRhsPartials;
     S += q;
@@ -300,11 +301,11 @@ __global__ __launch_bounds__(BS) void k_bicg_final(const cplx<double> *__restric
 }
 
 // p = r + beta (p - omega v)
-template <typename R>
+template <typename R, bool MR>
 __global__ __launch_bounds__(BS) void k_bicg_p(cplx<R> *__restrict__ p, const cplx<R> *__restrict__ r,
                                                const cplx<R> *__restrict__ v, int64_t n, const BicgScalars *S,
                                                RhsSet rs) {
-  {
+  if constexpr (MR) {
     const int64_t q = rhs_index(rs), sn = rhs_stride(n);
     p += q * sn;
     r += q * sn;
@@ -317,11 +318,11 @@ __global__ __launch_bounds__(BS) void k_bicg_p(cplx<R> *__restrict__ p, const cp
 }
 
 // s = r - alpha v
-template <typename R>
+template <typename R, bool MR>
 __global__ __launch_bounds__(BS) void k_bicg_s(cplx<R> *__restrict__ s, const cplx<R> *__restrict__ r,
                                                const cplx<R> *__restrict__ v, int64_t n, const BicgScalars *S,
                                                RhsSet rs) {
-  {
+  if constexpr (MR) {
     const int64_t q = rhs_index(rs), sn = rhs_stride(n);
     s += q * sn;
     r += q * sn;
@@ -335,14 +336,14 @@ __global__ __launch_bounds__(BS) void k_bicg_s(cplx<R> *__restrict__ s, const cp
 
 // x += alpha ph + omega sh ; r = s - omega t ; ||r||^2 and (r^, r) reduced by
 // the last block into est and the next step's beta
-template <typename R, typename RZ>
+template <typename R, typename RZ, bool MR>
 __global__ __launch_bounds__(BS) void k_bicg_xr(cplx<R> *__restrict__ x, const cplx<RZ> *__restrict__ ph,
                                                 const cplx<RZ> *__restrict__ sh, cplx<R> *__restrict__ r,
                                                 const cplx<R> *__restrict__ s, const cplx<R> *__restrict__ t,
                                                 const cplx<R> *__restrict__ rh, int64_t n, BicgScalars *S,
                                                 cplx<double> *partials, RhsSet rs) {
   __shared__ cplx<double> lds[BS / 64];
-  {
+  if constexpr (MR) {
     const int64_t q = rhs_index(rs), sn = rhs_stride(n);
     x += q * sn;
     ph += q * sn;
@@ -373,10 +374,10 @@ __global__ __launch_bounds__(BS) void k_bicg_xr(cplx<R> *__restrict__ x, const c
 }
 
 // ----------------------------------------------------------- utilities
-template <typename RI, typename RO>
+template <typename RI, typename RO, bool MR>
 __global__ __launch_bounds__(BS) void k_cast(const cplx<RI> *__restrict__ x, cplx<RO> *__restrict__ y, int64_t n,
                                              RhsSet rs) {
-  {
+  if constexpr (MR) {
     const int64_t q = rhs_index(rs) * rhs_stride(n);
     x += q;
     y += q;
@@ -551,35 +552,47 @@ void launch_pairdot(const cplx<R> *x0, const cplx<R> *y0, const cplx<R> *x1, con
                     cplx<double> *partials, BicgScalars *S, int mode, hipStream_t s) {
   int nb = red_blocks(n);
   launch_k((k_pairdot<R>), dim3(nb), dim3(BS), 0, s, x0, y0, x1, y1, npairs, n, partials);
-  launch_k(k_bicg_final, dim3(1), dim3(BS), 0, s, partials, nb, npairs, S, mode, one_rhs());
+  launch_k(k_bicg_final<false>, dim3(1), dim3(BS), 0, s, partials, nb, npairs, S, mode, one_rhs());
 }
 template <typename R>
 void launch_bicg_p(cplx<R> *p, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s,
                    const RhsSet &rs) {
-  launch_k((k_bicg_p<R>), dim3(grid_for(n), rs.count), dim3(BS), 0, s, p, r, v, n, S, rs);
+  if (multi_rhs(rs)) launch_k((k_bicg_p<R, true>), dim3(grid_for(n), rs.count), dim3(BS), 0, s, p, r, v, n, S, rs);
+  else launch_k((k_bicg_p<R, false>), dim3(grid_for(n)), dim3(BS), 0, s, p, r, v, n, S, rs);
 }
 template <typename R>
 void launch_bicg_s(cplx<R> *sv, const cplx<R> *r, const cplx<R> *v, int64_t n, const BicgScalars *S, hipStream_t s,
                    const RhsSet &rs) {
-  launch_k((k_bicg_s<R>), dim3(grid_for(n), rs.count), dim3(BS), 0, s, sv, r, v, n, S, rs);
+  if (multi_rhs(rs)) launch_k((k_bicg_s<R, true>), dim3(grid_for(n), rs.count), dim3(BS), 0, s, sv, r, v, n, S, rs);
+  else launch_k((k_bicg_s<R, false>), dim3(grid_for(n)), dim3(BS), 0, s, sv, r, v, n, S, rs);
 }
 template <typename R, typename RZ>
 void launch_bicg_xr(cplx<R> *x, const cplx<RZ> *ph, const cplx<RZ> *sh, cplx<R> *r, const cplx<R> *sv,
                     const cplx<R> *t, const cplx<R> *rh, int64_t n, cplx<double> *partials, BicgScalars *S,
                     hipStream_t s, const RhsSet &rs) {
   const int nb = red_blocks(n);
-  launch_k((k_bicg_xr<R, RZ>), dim3(nb, rs.count), dim3(BS), 0, s, x, ph, sh, r, sv, t, rh, n, S, partials, rs);
-  launch_k(k_bicg_final, dim3(1, rs.count), dim3(BS), 0, s, partials, nb, 2, S, (int)kBicgNormRho, rs);
+  if (multi_rhs(rs)) {
+    launch_k((k_bicg_xr<R, RZ, true>), dim3(nb, rs.count), dim3(BS), 0, s, x, ph, sh, r, sv, t, rh, n, S, partials,
+             rs);
+    launch_k(k_bicg_final<true>, dim3(1, rs.count), dim3(BS), 0, s, partials, nb, 2, S, (int)kBicgNormRho, rs);
+  } else {
+    launch_k((k_bicg_xr<R, RZ, false>), dim3(nb), dim3(BS), 0, s, x, ph, sh, r, sv, t, rh, n, S, partials, rs);
+    launch_k(k_bicg_final<false>, dim3(1), dim3(BS), 0, s, partials, nb, 2, S, (int)kBicgNormRho, rs);
+  }
 }
 
 void launch_bicg_final(const cplx<double> *partials, int nblocks, int npairs, BicgScalars *S, int mode,
                        hipStream_t s, const RhsSet &rs) {
-  launch_k(k_bicg_final, dim3(1, rs.count), dim3(BS), 0, s, partials, nblocks, npairs, S, mode, rs);
+  if (multi_rhs(rs))
+    launch_k(k_bicg_final<true>, dim3(1, rs.count), dim3(BS), 0, s, partials, nblocks, npairs, S, mode, rs);
+  else
+    launch_k(k_bicg_final<false>, dim3(1), dim3(BS), 0, s, partials, nblocks, npairs, S, mode, rs);
 }
 
 template <typename RI, typename RO>
 void launch_cast(const cplx<RI> *x, cplx<RO> *y, int64_t n, hipStream_t s, const RhsSet &rs) {
-  launch_k((k_cast<RI, RO>), dim3(grid_for(n), rs.count), dim3(BS), 0, s, x, y, n, rs);
+  if (multi_rhs(rs)) launch_k((k_cast<RI, RO, true>), dim3(grid_for(n), rs.count), dim3(BS), 0, s, x, y, n, rs);
+  else launch_k((k_cast<RI, RO, false>), dim3(grid_for(n)), dim3(BS), 0, s, x, y, n, rs);
 }
 void launch_cast_real(const double *x, float *y, int64_t n, hipStream_t s) {
   launch_k(k_cast_real, dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);

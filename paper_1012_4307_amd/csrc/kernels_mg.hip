@@ -317,14 +317,14 @@ __global__ __launch_bounds__(256) void k_prolong_jacobi(Grid<R> f, Grid<R> c, co
 // a wave read consecutive entries; b's unknowns are first staged in LDS.
 // Thread t writes the t-th unknown and, if node t is a boundary node, its zero.
 // One block of 1024 threads (nunk <= 2048 unknowns).
-template <typename R>
+template <typename R, bool MR>
 __global__ __launch_bounds__(1024) void k_coarse_solve(int nunk, const cplx<R> *__restrict__ minvT,
                                                        const int *__restrict__ unk, int n0, int n1, int n2,
                                                        const cplx<R> *__restrict__ b, cplx<R> *__restrict__ x,
                                                        RhsSet rs) {
   __shared__ cplx<R> sb[2048];
   const int nn = n0 * n1 * n2;
-  {
+  if constexpr (MR) {
     const int64_t q = rhs_index(rs) * rhs_stride(nn);  // one block per right-hand side
     b += q;
     x += q;
@@ -396,14 +396,14 @@ __global__ __launch_bounds__(256) void k_apply_dot(Grid<R> g, const cplx<RI> *__
 // Bi-CGSTAB dot products of k_apply_dot (kBicgAlpha / kBicgOmega), 0 = none.
 constexpr int SX = 62;
 
-template <typename R, typename RI, typename RO, int MODE, int SY>
+template <typename R, typename RI, typename RO, int MODE, int SY, bool MR = false>
 __global__ __launch_bounds__(256) void k_apply2d(Grid<R> g, const cplx<RI> *__restrict__ x, cplx<RO> *__restrict__ y,
                                                  const cplx<R> *__restrict__ d0, cplx<double> *partials, int tiles_x,
                                                  int tiles, RhsSet rs) {
   __shared__ cplx<double> lds[4];
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n0 = g.n0, n1 = g.n1;
-  {
+  if constexpr (MR) {
     const int64_t q = rhs_index(rs), sn = rhs_stride((int64_t)n0 * n1);
     x += q * sn;
     y += q * sn;
@@ -568,7 +568,10 @@ void launch_prolong_jacobi(const Grid<R> &fine, const Grid<R> &coarse, const cpl
 template <typename R>
 void launch_coarse_solve(int nunk, const cplx<R> *minv, const int *unk, int n0, int n1, int n2, const cplx<R> *b,
                          cplx<R> *x, hipStream_t s, const RhsSet &rs) {
-  launch_k((k_coarse_solve<R>), dim3(1, rs.count), dim3(1024), 0, s, nunk, minv, unk, n0, n1, n2, b, x, rs);
+  if (multi_rhs(rs))
+    launch_k((k_coarse_solve<R, true>), dim3(1, rs.count), dim3(1024), 0, s, nunk, minv, unk, n0, n1, n2, b, x, rs);
+  else
+    launch_k((k_coarse_solve<R, false>), dim3(1), dim3(1024), 0, s, nunk, minv, unk, n0, n1, n2, b, x, rs);
 }
 template <typename R, typename RI>
 void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cplx<R> *d0, int mode,
@@ -581,8 +584,15 @@ void launch_apply_dot(const Grid<R> &g, const cplx<RI> *x, cplx<R> *y, const cpl
     int tx, tiles, nb;
     strip_grid(g, sy, &tx, &tiles, &nb, rs.count > 1);
     const dim3 grid(nb, rs.count);
-    if (mode == kBicgAlpha)
+    const bool mr = multi_rhs(rs);
+    if (mode == kBicgAlpha && mr)
+      launch_k((k_apply2d<R, RI, R, kBicgAlpha, sy, true>), grid, dim3(256), 0, s, g, x, y, d0, partials, tx, tiles,
+               rs);
+    else if (mode == kBicgAlpha)
       launch_k((k_apply2d<R, RI, R, kBicgAlpha, sy>), grid, dim3(256), 0, s, g, x, y, d0, partials, tx, tiles, rs);
+    else if (mr)
+      launch_k((k_apply2d<R, RI, R, kBicgOmega, sy, true>), grid, dim3(256), 0, s, g, x, y, d0, partials, tx, tiles,
+               rs);
     else
       launch_k((k_apply2d<R, RI, R, kBicgOmega, sy>), grid, dim3(256), 0, s, g, x, y, d0, partials, tx, tiles, rs);
     launch_bicg_final(partials, nb, mode == kBicgAlpha ? 1 : 2, S, mode, s, rs);

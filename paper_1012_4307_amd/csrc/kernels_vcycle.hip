@@ -87,7 +87,7 @@ __device__ __forceinline__ cplx<R> sel(bool c, cplx<R> a, cplx<R> b) {
 // stage the Bi-CGSTAB vectors it is formed from instead (r, p, v or r, v),
 // form it per staged node and store it at the owned nodes (boundary nodes,
 // read as 0, get 0).
-template <typename R, int CY, int SRC>
+template <typename R, int CY, int SRC, bool MR>
 __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
                                                 const DownSrc<R> src, cplx<R> *__restrict__ rc, R omega,
                                                 int tiles_x, int tiles, RhsSet rs) {
@@ -104,8 +104,9 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
-  {
-    // this block's right-hand side (the formed-b variants run one only)
+  if constexpr (MR) {
+    // this block's right-hand side (a separate instantiation: the slot is a
+    // load the single right-hand side path does not wait for)
     const int64_t q = rhs_index(rs);
     b += q * rhs_stride((int64_t)f.n0 * f.n1);
     rc += q * rhs_stride((int64_t)c.n0 * c.n1);
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
 // on the tile reads red values on ring 1.  Column a = x0 - 4 + 2 lane is even,
 // so both columns of pair l interpolate from coarse column x0/2 - 2 + l
 // (= staged coarse column l).
-template <typename R, int TY>
+template <typename R, int TY, bool MR>
 __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R> *__restrict__ b,
                                               const cplx<R> *__restrict__ ec, cplx<R> *__restrict__ u_out, R omega,
                                               int tiles_x, int tiles, RhsSet rs) {
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
-  {
+  if constexpr (MR) {
     const int64_t q = rhs_index(rs), sf = rhs_stride((int64_t)f.n0 * f.n1);
     b += q * sf;
     u_out += q * sf;
@@ -491,12 +492,12 @@ __device__ __forceinline__ void tail_dense(int nu, int tpr, const M *mi, const c
   }
 }
 
-template <typename R>
+template <typename R, bool MR>
 __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a, RhsSet rs) {
   __shared__ TailLds<R> S;
   const int tid = threadIdx.x;
   // one workgroup per right-hand side (the kernel argument block is not written)
-  const int64_t rq = rhs_index(rs) * rhs_stride((int64_t)a.g[0].n0 * a.g[0].n1);
+  const int64_t rq = MR ? rhs_index(rs) * rhs_stride((int64_t)a.g[0].n0 * a.g[0].n1) : 0;
   const cplx<R> *const b0 = a.b0 + rq;
   cplx<R> *const u0 = a.u0 + rq;
   const R om = a.omega, om1 = R(1) - a.omega;
@@ -706,29 +707,36 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a, RhsSet rs) {
 // host (autotuned per grid size and dtype): coarse rows per down block in
 // {2, ..., 6, 8, 16} (16 only in FP32, whose tile fits the LDS), fine rows
 // per up block in {4, 8, 10, 12, 16, 32}.
-template <typename R, int SRC>
-void launch_down(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const DownSrc<R> &src, cplx<R> *rc,
-                 R omega, int rows, hipStream_t s, const RhsSet &rs) {
+template <typename R, int SRC, bool MR>
+void launch_down_mr(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const DownSrc<R> &src, cplx<R> *rc,
+                    R omega, int rows, hipStream_t s, const RhsSet &rs) {
   constexpr int CX = 61;
   const int tx = (coarse.n0 + CX - 1) / CX;
   const int tiles = tx * ((coarse.n1 + rows - 1) / rows);
   const dim3 grid(xcd_padded(tiles), rs.count), block(NT);
   switch (rows) {
-    case 2: launch_k((k_down_rb<R, 2, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
-    case 3: launch_k((k_down_rb<R, 3, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
-    case 4: launch_k((k_down_rb<R, 4, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
-    case 5: launch_k((k_down_rb<R, 5, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
-    case 6: launch_k((k_down_rb<R, 6, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
+    case 2: launch_k((k_down_rb<R, 2, SRC, MR>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
+    case 3: launch_k((k_down_rb<R, 3, SRC, MR>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
+    case 4: launch_k((k_down_rb<R, 4, SRC, MR>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
+    case 5: launch_k((k_down_rb<R, 5, SRC, MR>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
+    case 6: launch_k((k_down_rb<R, 6, SRC, MR>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs); break;
     case 16:
       if constexpr (sizeof(R) == 4) {
-        launch_k((k_down_rb<R, 16, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs);
+        launch_k((k_down_rb<R, 16, SRC, MR>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs);
         break;
       }
       [[fallthrough]];
     default:
-      launch_k((k_down_rb<R, 8, SRC>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs);
+      launch_k((k_down_rb<R, 8, SRC, MR>), grid, block, 0, s, fine, coarse, b, src, rc, omega, tx, tiles, rs);
       break;
   }
+}
+
+template <typename R, int SRC>
+void launch_down(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const DownSrc<R> &src, cplx<R> *rc,
+                 R omega, int rows, hipStream_t s, const RhsSet &rs) {
+  if (multi_rhs(rs)) launch_down_mr<R, SRC, true>(fine, coarse, b, src, rc, omega, rows, s, rs);
+  else launch_down_mr<R, SRC, false>(fine, coarse, b, src, rc, omega, rows, s, rs);
 }
 
 template <typename R>
@@ -744,26 +752,34 @@ void launch_down_rb_src(const Grid<R> &fine, const Grid<R> &coarse, const DownSr
   else launch_down<R, kDownSrcS>(fine, coarse, nullptr, src, rc, omega, rows, s, one_rhs());
 }
 
-template <typename R>
-void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *ec, cplx<R> *u_out,
+template <typename R, bool MR>
+void launch_up_mr(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *ec, cplx<R> *u_out,
                   R omega, int rows, hipStream_t s, const RhsSet &rs) {
   constexpr int TX = 120;
   const int tx = (fine.n0 + TX - 1) / TX;
   const int tiles = tx * ((fine.n1 + rows - 1) / rows);
   const dim3 grid(xcd_padded(tiles), rs.count), block(NT);
   switch (rows) {
-    case 4: launch_k((k_up_rb<R, 4>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
-    case 8: launch_k((k_up_rb<R, 8>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
-    case 10: launch_k((k_up_rb<R, 10>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
-    case 12: launch_k((k_up_rb<R, 12>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
-    case 32: launch_k((k_up_rb<R, 32>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
-    default: launch_k((k_up_rb<R, 16>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    case 4: launch_k((k_up_rb<R, 4, MR>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    case 8: launch_k((k_up_rb<R, 8, MR>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    case 10: launch_k((k_up_rb<R, 10, MR>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    case 12: launch_k((k_up_rb<R, 12, MR>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    case 32: launch_k((k_up_rb<R, 32, MR>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
+    default: launch_k((k_up_rb<R, 16, MR>), grid, block, 0, s, fine, coarse, b, ec, u_out, omega, tx, tiles, rs); break;
   }
 }
 
 template <typename R>
+void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, const cplx<R> *ec, cplx<R> *u_out,
+                  R omega, int rows, hipStream_t s, const RhsSet &rs) {
+  if (multi_rhs(rs)) launch_up_mr<R, true>(fine, coarse, b, ec, u_out, omega, rows, s, rs);
+  else launch_up_mr<R, false>(fine, coarse, b, ec, u_out, omega, rows, s, rs);
+}
+
+template <typename R>
 void launch_tail(const TailArgs<R> &a, hipStream_t s, const RhsSet &rs) {
-  launch_k((k_tail<R>), dim3(1, rs.count), dim3(TT), 0, s, a, rs);
+  if (multi_rhs(rs)) launch_k((k_tail<R, true>), dim3(1, rs.count), dim3(TT), 0, s, a, rs);
+  else launch_k((k_tail<R, false>), dim3(1, 1), dim3(TT), 0, s, a, rs);
 }
 
 template void launch_down_rb<double>(const Grid<double> &, const Grid<double> &, const cplx<double> *, cplx<double> *,

@@ -238,7 +238,7 @@ __device__ __forceinline__ void restrict_fw(const Grid<R> &c, const Region<R> &A
 // Block tile: C x CY nodes of level l + 2 at (I0, J0).  Mid region (level
 // l+1): origin (2 I0 - 3, 2 J0 - 3), (2C + 5) x (2CY + 5); fine region
 // (level l): origin twice that minus 3, (4C + 15) x (4CY + 15).
-template <typename R, int C, int CY>
+template <typename R, int C, int CY, bool MR>
 __global__ __launch_bounds__(NP) void k_down2_rb(Grid<R> f, Grid<R> m, Grid<R> c, const cplx<R> *__restrict__ b,
                                                  cplx<R> *__restrict__ t_f, cplx<R> *__restrict__ b_m,
                                                  cplx<R> *__restrict__ t_m, cplx<R> *__restrict__ rc, R omega,
@@ -250,8 +250,9 @@ __global__ __launch_bounds__(NP) void k_down2_rb(Grid<R> f, Grid<R> m, Grid<R> c
   __shared__ cplx<R> Aw[2 * (AW + AH)], Mw[2 * (MW + MH)];
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
-  {
-    const int64_t q = rhs_index(rs), sf = rhs_stride((int64_t)f.n0 * f.n1), sm = rhs_stride((int64_t)m.n0 * m.n1);
+  if constexpr (MR) {
+    const int64_t q = rhs_index(rs);
+    const int64_t sf = rhs_stride((int64_t)f.n0 * f.n1), sm = rhs_stride((int64_t)m.n0 * m.n1);
     b += q * sf;
     t_f += q * sf;
     b_m += q * sm;
@@ -350,7 +351,7 @@ __device__ void up_sweep(const Grid<R> &g, const Region<R> &A, const cplx<R> *ab
 // mid nodes E = (x0/2 - 1, y0/2 - 1), (TX/2 + 3) x (TY/2 + 3), whose final
 // values need the mid sweep over E plus a 2-node halo (region F), whose nodes
 // interpolate from coarse region G.
-template <typename R, int TX, int TY>
+template <typename R, int TX, int TY, bool MR>
 __global__ __launch_bounds__(NP) void k_up2_rb(Grid<R> f, Grid<R> m, Grid<R> c, const cplx<R> *__restrict__ b_f,
                                                const cplx<R> *__restrict__ t_f, const cplx<R> *__restrict__ b_m,
                                                const cplx<R> *__restrict__ t_m, const cplx<R> *__restrict__ ec,
@@ -366,8 +367,9 @@ __global__ __launch_bounds__(NP) void k_up2_rb(Grid<R> f, Grid<R> m, Grid<R> c, 
   __shared__ cplx<R> Aw[2 * (AW + AH)], Fw[2 * (FW + FH)];
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
-  {
-    const int64_t q = rhs_index(rs), sf = rhs_stride((int64_t)f.n0 * f.n1), sm = rhs_stride((int64_t)m.n0 * m.n1);
+  if constexpr (MR) {
+    const int64_t q = rhs_index(rs);
+    const int64_t sf = rhs_stride((int64_t)f.n0 * f.n1), sm = rhs_stride((int64_t)m.n0 * m.n1);
     b_f += q * sf;
     t_f += q * sf;
     u_out += q * sf;
@@ -425,8 +427,12 @@ void launch_down2_rb(const Grid<R> &f, const Grid<R> &m, const Grid<R> &c, const
   constexpr int C = 8, CY = sizeof(R) == 4 ? 4 : 2;
   const int tx = (c.n0 + C - 1) / C;
   const int tiles = tx * ((c.n1 + CY - 1) / CY);
-  launch_k((k_down2_rb<R, C, CY>), dim3(xcd_padded(tiles), rs.count), dim3(NP), 0, s, f, m, c, b, t_f, b_m, t_m,
-           rc, omega, tx, tiles, rs);
+  if (multi_rhs(rs))
+    launch_k((k_down2_rb<R, C, CY, true>), dim3(xcd_padded(tiles), rs.count), dim3(NP), 0, s, f, m, c, b, t_f, b_m,
+             t_m, rc, omega, tx, tiles, rs);
+  else
+    launch_k((k_down2_rb<R, C, CY, false>), dim3(xcd_padded(tiles)), dim3(NP), 0, s, f, m, c, b, t_f, b_m, t_m, rc,
+             omega, tx, tiles, rs);
 }
 
 template <typename R>
@@ -436,8 +442,12 @@ void launch_up2_rb(const Grid<R> &f, const Grid<R> &m, const Grid<R> &c, const c
   constexpr int TX = 32, TY = sizeof(R) == 4 ? 16 : 8;
   const int tx = (f.n0 + TX - 1) / TX;
   const int tiles = tx * ((f.n1 + TY - 1) / TY);
-  launch_k((k_up2_rb<R, TX, TY>), dim3(xcd_padded(tiles), rs.count), dim3(NP), 0, s, f, m, c, b_f, t_f, b_m, t_m,
-           ec, u_out, omega, tx, tiles, rs);
+  if (multi_rhs(rs))
+    launch_k((k_up2_rb<R, TX, TY, true>), dim3(xcd_padded(tiles), rs.count), dim3(NP), 0, s, f, m, c, b_f, t_f, b_m,
+             t_m, ec, u_out, omega, tx, tiles, rs);
+  else
+    launch_k((k_up2_rb<R, TX, TY, false>), dim3(xcd_padded(tiles)), dim3(NP), 0, s, f, m, c, b_f, t_f, b_m, t_m, ec,
+             u_out, omega, tx, tiles, rs);
 }
 
 template void launch_down2_rb<double>(const Grid<double> &, const Grid<double> &, const Grid<double> &,
