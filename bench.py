@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2049)
     ap.add_argument("--restart", type=int, default=40)
-    ap.add_argument("--inner", type=int, default=16, help="FP32 inner Bi-CGSTAB iterations per FGMRES step")
+    ap.add_argument("--inner", type=int, default=20, help="FP32 inner Bi-CGSTAB iterations per FGMRES step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-context", action="store_true", help="skip the context solves (FP32-cycle FGMRES, "
                                                                "FP64 Bi-CGSTAB)")
