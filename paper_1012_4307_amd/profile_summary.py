@@ -37,9 +37,11 @@ TAIL_MARKER = b"\n// -----------------------------------------------------------
 COPY_BYTES = 512 << 20   # the copy probe moves 512 MiB each way
 # class (as bench.py's timing classes) and kernel name pattern; the finest
 # grid of each is the one recorded
-CLASSES = (("up", r"k_up_rb<float, \d+>"), ("down_p", r"k_down_rb<float, \d+, 1>"),
-           ("down_s", r"k_down_rb<float, \d+, 2>"), ("down_f64", r"k_down_rb<double, \d+, 0>"),
-           ("up_f64", r"k_up_rb<double, \d+>"))
+# (the single right-hand side instantiations: a trailing ", false" where the
+# kernel also has a multi-right-hand-side form)
+CLASSES = (("up", r"k_up_rb<float, \d+(, false)?>"), ("down_p", r"k_down_rb<float, \d+, 1(, false)?>"),
+           ("down_s", r"k_down_rb<float, \d+, 2(, false)?>"), ("down_f64", r"k_down_rb<double, \d+, 0(, false)?>"),
+           ("up_f64", r"k_up_rb<double, \d+(, false)?>"))
 # algorithmic bytes per fine node: every input read once, every output written
 # once.  FP32 complex 8 B, real 4 B: up reads the coarse correction (a quarter
 # node), b, k^2 and writes u (5.5 reals = 22 B); the p-forming down kernel
