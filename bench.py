@@ -51,7 +51,8 @@ def parse():
                                                                "FP64 Bi-CGSTAB)")
     ap.add_argument("--vcycles", type=int, default=20, help="cycles timed for the V-cycle bandwidth")
     ap.add_argument("--config", default="mixed2049",
-                    choices=["mixed2049", "batched", "adjoint", "cube", "coulomb513", "small65", "paper_mp", "coupled"],
+                    choices=["mixed2049", "batched", "persistent_probe", "adjoint", "cube", "coulomb513", "small65",
+                             "paper_mp", "coupled"],
                     help="mixed2049 (default): the headline line; the others report the secondary workloads")
     ap.add_argument("--batch-count", type=int, default=96)
     ap.add_argument("--batch-streams", type=int, default=32, help="HIP streams the batched systems are spread over")

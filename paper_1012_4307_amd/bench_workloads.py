@@ -23,6 +23,14 @@ coupled     the coupled block system of Sec. 2 (4 soft-Coulomb channels on
             preconditioner, blocks solved by the batched Bi-CGSTAB driver to
             1e-3 (FP32 cycles, one stream per block), and with one cycle per
             block instead.
+persistent_probe
+            the two persistent organisations of the batched solve that the
+            library does not use, measured by the probes of
+            include/ecsmg_probe.h: the memory rate of red-black sweeps with one
+            workgroup per independent grid (257^2, 513^2, 1025^2; 1, 32, 256
+            grids at once), and the cost of a device-wide phase barrier among a
+            group of workgroups (8 to 256 workgroups, with and without 64 KiB
+            written per workgroup and phase).
 paper_mp    the model problems of Sec. 5 (Tables 1-4: MP1 k = 160 on 385^2,
             MP2 on 641^2, MP3 k = 2 on 641^2 and k = 4 on 897^2), each with the
             CSL, CSG and QD set-ups of its table: stand-alone multigrid on
@@ -337,6 +345,39 @@ def coupled(args):
                higher_is_better=False, runs=rows, dtype="f64 outer / f32 cycles", data="synthetic"))
 
 
+def persistent_probe(args):
+    import ctypes
+    from . import lib
+    L = lib()
+    L.ecs_probe_item_sweeps.argtypes = [ctypes.c_int] * 4 + [ctypes.POINTER(ctypes.c_double)]
+    L.ecs_probe_group_barrier.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_double)] * 2
+    sweeps, rows = 4, []
+    for n in (257, 513, 1025):
+        for g in (1, 32, 256):
+            ms = ctypes.c_double()
+            rc = L.ecs_probe_item_sweeps(n, g, g, sweeps, ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"ecs_probe_item_sweeps({n}, {g}) returned {rc}")
+            # per sweep and node: read u, b, k^2 once, write u once (56 B in FP64)
+            gbs = g * n * n * 56.0 * sweeps / (ms.value * 1e-3) / 1e9
+            rows.append(dict(n=n, workgroups=g, ms_per_sweep=round(ms.value / sweeps, 4), gbs=round(gbs, 1),
+                             gbs_per_workgroup=round(gbs / g, 2)))
+            print(f"item sweeps n={n} workgroups={g}: {gbs:.0f} GB/s", flush=True)
+    bars = []
+    for blocks in (8, 32, 64, 256):
+        for nbytes in (0, 65536):
+            ub, ul = ctypes.c_double(), ctypes.c_double()
+            rc = L.ecs_probe_group_barrier(blocks, 2000, nbytes, ctypes.byref(ub), ctypes.byref(ul))
+            if rc != 0:
+                raise RuntimeError(f"ecs_probe_group_barrier({blocks}, {nbytes}) returned {rc}")
+            bars.append(dict(workgroups=blocks, bytes_per_workgroup=nbytes, us_per_phase=round(ub.value, 3),
+                             us_per_phase_local=round(ul.value, 3), barrier_us=round(ub.value - ul.value, 3)))
+            print(f"group barrier {blocks} workgroups, {nbytes} B: {ub.value - ul.value:.2f} us", flush=True)
+    _emit(dict(metric="persistent batched-solve organisations: one-workgroup-per-grid sweep rate and phase "
+                      "barrier cost", unit="GB/s", value=max(r["gbs"] for r in rows), higher_is_better=True,
+               item_sweeps=rows, group_barrier=bars, sweep_bytes_per_node=56, dtype="f64", data="synthetic"))
+
+
 def run(args):
-    {"batched": batched, "adjoint": adjoint, "cube": cube, "coulomb513": coulomb513, "small65": small65,
+    {"batched": batched, "persistent_probe": persistent_probe, "adjoint": adjoint, "cube": cube, "coulomb513": coulomb513, "small65": small65,
      "paper_mp": paper_mp, "coupled": coupled}[args.config](args)

@@ -52,3 +52,30 @@ def test_null_context_is_rejected():
     assert lib.ecs_solve(None, None, None, None, None) == -1
     assert lib.ecs_last_error(None) == b"null context"
     lib.ecs_destroy(None)
+
+
+def test_probe_header_symbols_are_exported_and_check_arguments():
+    """The measurement probes (include/ecsmg_probe.h) are exported and refuse
+    out-of-range arguments before any device call."""
+    src = open(os.path.join(ROOT, "include", "ecsmg_probe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = sorted(set(re.findall(r"\b(ecs_[a-z0-9_]+)\s*\(", src)))
+    assert names == ["ecs_probe_group_barrier", "ecs_probe_item_sweeps"]
+    lib = E.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+    ms = ctypes.c_double()
+    f = lib.ecs_probe_item_sweeps
+    f.argtypes = [ctypes.c_int] * 4 + [ctypes.POINTER(ctypes.c_double)]
+    assert f(4, 1, 1, 1, ctypes.byref(ms)) == -1          # grid too small
+    assert f(65, 2, 3, 1, ctypes.byref(ms)) == -1         # more workgroups than grids
+    assert f(65, 1, 1, 65, ctypes.byref(ms)) == -1        # too many sweeps
+    assert f(4097, 4096, 1, 1, ctypes.byref(ms)) == -1    # more than 64 GiB
+    assert f(65, 1, 1, 1, None) == -1
+    g = lib.ecs_probe_group_barrier
+    g.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_double)] * 2
+    ub, ul = ctypes.c_double(), ctypes.c_double()
+    assert g(0, 10, 0, ctypes.byref(ub), ctypes.byref(ul)) == -1
+    assert g(8, 0, 0, ctypes.byref(ub), ctypes.byref(ul)) == -1
+    assert g(8, 10, (1 << 20) + 8, ctypes.byref(ub), ctypes.byref(ul)) == -1
+    assert g(8, 10, 0, None, ctypes.byref(ul)) == -1
