@@ -300,14 +300,16 @@ def main():
         "mixed": dict(seconds=round(value, 4), iterations=stmix["iterations"],
                       inner_iterations=stmix["inner_iterations"], vcycles=stmix["vcycles"],
                       rel_residual=stmix["rel_residual"], rel_diff_vs_fp64_solution=rel_diff,
-                      second_gram_schmidt_passes=stmix["reorthogonalisations"]),
+                      second_gram_schmidt_passes=stmix["reorthogonalisations"],
+                      inner_runs_cut_short=stmix["inner_breakdowns"]),
         "fp64": dict(seconds=round(float(np.median(t64)), 4), iterations=st64["iterations"],
                      vcycles=st64["vcycles"], rel_residual=st64["rel_residual"],
                      second_gram_schmidt_passes=st64["reorthogonalisations"]),
         "nested_fp64": dict(seconds=round(float(np.median(tn64)), 4), iterations=stn64["iterations"],
                             inner_iterations=stn64["inner_iterations"], vcycles=stn64["vcycles"],
                             rel_residual=stn64["rel_residual"],
-                            second_gram_schmidt_passes=stn64["reorthogonalisations"]),
+                            second_gram_schmidt_passes=stn64["reorthogonalisations"],
+                            inner_runs_cut_short=stn64["inner_breakdowns"]),
         "speedup_mixed_vs_fp64": round(float(np.median(t64)) / value, 3),
         "speedup_mixed_vs_nested_fp64": round(float(np.median(tn64)) / value, 3),
         "context_solves": context,

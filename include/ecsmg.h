@@ -133,6 +133,10 @@ typedef struct {
   double seconds;          /* host wall time inside the call                  */
   int status;              /* same value as returned                          */
   int64_t reorthogonalisations; /* second Gram-Schmidt passes run (GMRES)     */
+  int64_t inner_breakdowns;/* nested form: inner Bi-CGSTAB runs cut short by
+                              a zero or non-finite scalar (a breakdown, or an
+                              exactly converged residual); the iterate reached
+                              so far serves as that step's direction          */
 } ecs_stats;
 
 /* Create a problem on the calling thread's current HIP device.

@@ -69,7 +69,8 @@ class Tuning(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("vcycles", ctypes.c_int64),
                 ("inner_iterations", ctypes.c_int64), ("rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("status", ctypes.c_int), ("reorthogonalisations", ctypes.c_int64)]
+                ("seconds", ctypes.c_double), ("status", ctypes.c_int), ("reorthogonalisations", ctypes.c_int64),
+                ("inner_breakdowns", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

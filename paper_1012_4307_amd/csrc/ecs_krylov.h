@@ -33,6 +33,7 @@ struct BicgScalars {
   cplx<double> rho, alpha, omega, beta;
   double rnorm2, bnorm, est;
   int bad;
+  int breakdowns;  // restarts (kBicgInit) that found the previous run ended by a bad scalar
 };
 
 enum { kBicgAlpha = 1, kBicgOmega = 2, kBicgInit = 4, kBicgNormRho = 5 };

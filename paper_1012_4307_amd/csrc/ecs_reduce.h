@@ -63,6 +63,7 @@ __device__ inline void bicg_update(BicgScalars *S, int mode, cplx<double> d0, cp
       S->omega = (1.0 / d1.re) * d0;
       break;
     case kBicgInit:  // (re)start: rho = (r^, r) = ||r||^2, p = r on the first step
+      S->breakdowns += S->bad;
       S->rnorm2 = d0.re;
       S->est = sqrt(d0.re) / S->bnorm;
       S->rho = mk<double>(d0.re, 0);

@@ -1388,6 +1388,9 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
   if (d->inner > 0) {  // the inner iteration has no stopping test: unit reference norm
     const double unit = 1.0;
     HIP_OK(hipMemcpyAsync(&C->bs_in->bnorm, &unit, sizeof(double), hipMemcpyHostToDevice, s));
+    // bad and breakdowns (adjacent): inner runs cut short are counted as each
+    // new run starts
+    HIP_OK(hipMemsetAsync(&C->bs_in->bad, 0, 2 * sizeof(int), s));
   }
   if (!d->x_is_guess) launch_zero<double>(x, n, s);
   int it = 0;
@@ -1455,6 +1458,12 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
   }
   st->iterations = it;
   st->reorthogonalisations = reorth_passes(C, S, d->orth, it);
+  if (d->inner > 0) {
+    // the runs counted at their successors' starts, and the last run's flag
+    int v[2] = {0, -1};
+    if (read_bytes(C, &C->bs_in->bad, 2 * sizeof(int))) std::memcpy(v, C->pinned, sizeof v);
+    st->inner_breakdowns = v[1] < 0 ? -1 : v[0] + v[1];
+  }
   HIP_OK(hipGetLastError());
   return status;
 }

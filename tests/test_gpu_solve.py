@@ -124,9 +124,15 @@ def test_headline_mixed_nested_vs_fp64_oracle():
         err = relerr(x, xo)
         res = oracle_resid(P, x, b)
         print(f"rtol {rtol:g}: outer {st['iterations']} inner {st['inner_iterations']} "
-              f"relerr vs oracle {err:.3e} oracle residual {res:.3e}", flush=True)
+              f"relerr vs oracle {err:.3e} oracle residual {res:.3e} "
+              f"inner runs cut short {st['inner_breakdowns']}", flush=True)
         assert res <= 1.05 * rtol, (rtol, res)
         assert err < 1e-6, (rtol, err)
+        # every inner run is counted (none is cut short at the benchmark's
+        # tolerance on this family)
+        assert 0 <= st["inner_breakdowns"] <= st["iterations"], st
+        if rtol == 1e-8:
+            assert st["inner_breakdowns"] == 0, st
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
