@@ -156,6 +156,13 @@ def main():
     Sn64.solve(b)
     tn64, stn64, xn64, _ = timed_solves(Sn64, min(args.steps, 5))
     del Sn64
+    # the cycle's levels below the finest (every kernel of the chain, the tail
+    # included), timed in one more mixed solve outside the headline's runs
+    _, stc, _, ctim = timed_solves(Smix, 1, ("coarse",))
+    nlc, msc, _ = ctim["coarse"]
+    coarse_chain = dict(launches_timed=nlc, avg_launch_us=round(1e3 * msc / nlc, 2) if nlc else None,
+                        per_cycle_us=round(1e3 * msc * TIMED_ONE_IN / stc["vcycles"], 1),
+                        launches_per_cycle=round(nlc * TIMED_ONE_IN / stc["vcycles"], 2))
 
     context = {}
     if not args.no_context:
@@ -226,6 +233,10 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 2 * src.numel() / (ev0.elapsed_time(ev1) / 5 * 1e-3) / 1e9
     del src, dst
+    # the same rates as fractions of the copy probe (the practical HBM rate)
+    for vc in (vc64, vc32):
+        for key in [k for k in vc if k.endswith("_gbs")]:
+            vc[key[:-4] + "_frac_of_copy"] = round(vc[key] / copy_gbs, 4)
 
     kernels = {}
     for cls, (nl, ms, by) in ktim.items():
@@ -268,6 +279,7 @@ def main():
                     counters=None if traffic is None else dict(
                         hbm_bytes_per_launch=traffic, achieved=round(traffic / (raw_us * 1e-6) / 1e9, 1),
                         frac=round(traffic / (raw_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)),
+                    frac_of_copy_probe=round(achieved / copy_gbs, 4),
                     empty_kernel_us=round(overhead_us, 2),
                     achieved_net_of_empty=round(method_bytes / (net_us * 1e-6) / 1e9, 1), launches=nl,
                     timed_one_launch_in=TIMED_ONE_IN)
@@ -320,6 +332,7 @@ def main():
                    "vectors": "in the cycle's dtype (no conversion passes)"},
         "copy_probe_gbs": round(copy_gbs, 1),
         "kernels_in_timed_region": kernels,
+        "coarse_chain": coarse_chain,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
