@@ -9,6 +9,9 @@ namespace ecs {
 constexpr int kMaxRestart = 64;
 // reduction kernels use at most this many blocks (partial buffers are sized for it)
 constexpr int kRedBlocks = 2048;
+// steps of the nested Bi-CGSTAB whose preconditioned directions are kept for
+// the deferred x update (a longer inner run updates x every kDeferSteps steps)
+constexpr int kDeferSteps = 24;
 
 // Scalars of one GMRES / FGMRES solve, kept in device memory.
 struct GmresScalars {
@@ -83,6 +86,17 @@ template <typename R, typename RZ>
 void launch_bicg_xr(cplx<R> *x, const cplx<RZ> *ph, const cplx<RZ> *sh, cplx<R> *r, const cplx<R> *sv,
                     const cplx<R> *t, const cplx<R> *rh, int64_t n, cplx<double> *partials, BicgScalars *S,
                     hipStream_t s, const RhsSet &rs = one_rhs());
+// The nested Bi-CGSTAB with its x update deferred: r = s - omega t, the
+// same reductions as launch_bicg_xr, and (alpha, omega) of the step stored at
+// coef[0..1]; later x += sum_i alpha_i p^_i + omega_i s^_i over `count`
+// stored steps (ld elements apart), in step order, each step the one-step
+// update's expression.
+template <typename R>
+void launch_bicg_r(cplx<R> *r, const cplx<R> *sv, const cplx<R> *t, const cplx<R> *rh, int64_t n,
+                   cplx<double> *partials, BicgScalars *S, cplx<double> *coef, hipStream_t s);
+template <typename R>
+void launch_bicg_xdefer(cplx<R> *x, const cplx<R> *ph, const cplx<R> *sh, int64_t ld, int count,
+                        const cplx<double> *coef, int64_t n, hipStream_t s);
 // y = A x with a fused dot product: kBicgAlpha -> (d0, y) gives alpha;
 // kBicgOmega -> (y, d0) and (y, y) give omega (multigrid side, kernels_mg.hip)
 void launch_bicg_final(const cplx<double> *partials, int nblocks, int npairs, BicgScalars *S, int mode,

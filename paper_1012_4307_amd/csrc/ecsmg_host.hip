@@ -352,6 +352,10 @@ struct KrylovBufs {
   // second p buffer (the fused update writes p beside the old one)
   void *fr = nullptr, *frh = nullptr, *fp = nullptr, *fv = nullptr, *fs = nullptr, *ft = nullptr, *fph = nullptr,
        *fsh = nullptr, *fp2 = nullptr;
+  // its deferred x update: fph / fsh hold fdefer steps' p^ and s^ (ld apart),
+  // fcoef their (alpha, omega)
+  int fdefer = 0;
+  cplx<double> *fcoef = nullptr;
   cplx<double> *a1 = nullptr, *a2 = nullptr;  // adjoint scaling buffers
   cplx<double> *bz = nullptr;                 // right-hand side with its boundary entries zeroed
   int64_t ld = 0;
@@ -424,8 +428,10 @@ size_t plan_krylov(const ecs_ctx *C, const ecs_solve_desc *d, char *base, Krylov
       K->fv = cv.take<char>(n * zs);
       K->fs = cv.take<char>(n * zs);
       K->ft = cv.take<char>(n * zs);
-      K->fph = cv.take<char>(n * zs);
-      K->fsh = cv.take<char>(n * zs);
+      K->fdefer = std::min(d->inner, kDeferSteps);
+      K->fph = cv.take<char>((size_t)K->ld * K->fdefer * zs);
+      K->fsh = cv.take<char>((size_t)K->ld * K->fdefer * zs);
+      K->fcoef = cv.take<cplx<double>>(2 * (size_t)K->fdefer);
       K->fp2 = cv.take<char>(n * zs);
     }
   }
@@ -1279,8 +1285,8 @@ void inner_bicgstab(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *v, cplx
   BicgScalars *S = C->bs_in;
   cplx<R> *fr = reinterpret_cast<cplx<R> *>(K.fr), *frh = reinterpret_cast<cplx<R> *>(K.frh);
   cplx<R> *fv = reinterpret_cast<cplx<R> *>(K.fv), *fs = reinterpret_cast<cplx<R> *>(K.fs);
-  cplx<R> *ft = reinterpret_cast<cplx<R> *>(K.ft), *fph = reinterpret_cast<cplx<R> *>(K.fph);
-  cplx<R> *fsh = reinterpret_cast<cplx<R> *>(K.fsh);
+  cplx<R> *ft = reinterpret_cast<cplx<R> *>(K.ft);
+  cplx<R> *const ph0 = reinterpret_cast<cplx<R> *>(K.fph), *const sh0 = reinterpret_cast<cplx<R> *>(K.fsh);
   if constexpr (sizeof(R) == 4) launch_cast<double, float>(v, fr, n, s);
   else (void)hipMemcpyAsync(fr, v, n * sizeof(cplx<R>), hipMemcpyDeviceToDevice, s);
   (void)hipMemcpyAsync(frh, fr, n * sizeof(cplx<R>), hipMemcpyDeviceToDevice, s);
@@ -1293,7 +1299,12 @@ void inner_bicgstab(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *v, cplx
   // blocks read the old p around their tiles) and s; the same values either way
   const bool fuse = sizeof(R) == 4 && fused_updates(C);
   cplx<R> *p_old = reinterpret_cast<cplx<R> *>(K.fp), *p_new = reinterpret_cast<cplx<R> *>(K.fp2);
+  // x = sum of alpha_i p^_i + omega_i s^_i: each step keeps its p^, s^ and
+  // scalars, and x is updated once per K.fdefer steps (the same values as
+  // a one-step update, in half its traffic per step)
   for (int it = 0; it < iters; it++) {
+    const int slot = it % K.fdefer;
+    cplx<R> *fph = ph0 + (int64_t)slot * K.ld, *fsh = sh0 + (int64_t)slot * K.ld;
     if (fuse) {
       const DownSrc<R> sp{kDownSrcP, fr, p_old, fv, p_new, S};
       vcycle_fused<R>(C, p_new, fph, &sp);
@@ -1311,7 +1322,8 @@ void inner_bicgstab(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *v, cplx
       vcycle<R>(C, fs, fsh);
     }
     launch_apply_dot<R, R>(gA, fsh, ft, fs, kBicgOmega, C->partials, S, s);
-    launch_bicg_xr<R, R>(x, fph, fsh, fr, fs, ft, frh, n, C->partials, S, s);
+    launch_bicg_r<R>(fr, fs, ft, frh, n, C->partials, S, K.fcoef + 2 * slot, s);
+    if (slot == K.fdefer - 1 || it == iters - 1) launch_bicg_xdefer<R>(x, ph0, sh0, K.ld, slot + 1, K.fcoef, n, s);
   }
 }
 

@@ -373,6 +373,67 @@ __global__ __launch_bounds__(BS) void k_bicg_xr(cplx<R> *__restrict__ x, const c
   if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = a1;
 }
 
+// The nested Bi-CGSTAB's r update without x: r = s - omega t with the same
+// dot products, and this step's (alpha, omega) kept in coef[0..1] for the
+// deferred x update below (the preconditioned directions p^, s^ of the step
+// stay in memory until then).
+template <typename R>
+__global__ __launch_bounds__(BS) void k_bicg_r(cplx<R> *__restrict__ r, const cplx<R> *__restrict__ s,
+                                               const cplx<R> *__restrict__ t, const cplx<R> *__restrict__ rh,
+                                               int64_t n, const BicgScalars *S, cplx<double> *partials,
+                                               cplx<double> *coef) {
+  __shared__ cplx<double> lds[BS / 64];
+  const cplx<R> omega = cvt<R>(S->omega);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    coef[0] = S->alpha;
+    coef[1] = S->omega;
+  }
+  double nrm = 0;
+  cplx<double> rr = mk<double>(0, 0);
+  for (int64_t q = (int64_t)blockIdx.x * BS + threadIdx.x; q < n; q += (int64_t)gridDim.x * BS) {
+    const cplx<R> rq = s[q] - omega * t[q];
+    r[q] = rq;
+    const cplx<double> rd = cvt<double>(rq);
+    nrm += abs2(rd);
+    rr = rr + conjg(cvt<double>(rh[q])) * rd;
+  }
+  cplx<double> a0 = block_sum(mk<double>(nrm, 0), lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = a0;
+  __syncthreads();
+  cplx<double> a1 = block_sum(rr, lds);
+  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = a1;
+}
+
+// The deferred x update of `count` steps: x += alpha_i p^_i + omega_i s^_i,
+// i = 0 .. count - 1 in order, each step the same expression as the one-step
+// update (so x is the same), p^_i and s^_i ld elements apart.  The loads of
+// a group of steps are all issued before the first is added.
+template <typename R>
+__global__ __launch_bounds__(BS) void k_bicg_xdefer(cplx<R> *__restrict__ x, const cplx<R> *__restrict__ ph,
+                                                    const cplx<R> *__restrict__ sh, int64_t ld, int count,
+                                                    const cplx<double> *__restrict__ coef, int64_t n) {
+  constexpr int G = 4;
+  for (int64_t q = (int64_t)blockIdx.x * BS + threadIdx.x; q < n; q += (int64_t)gridDim.x * BS) {
+    cplx<R> acc = x[q];
+    for (int i0 = 0; i0 < count; i0 += G) {
+      cplx<R> pv[G], sv[G];
+#pragma unroll
+      for (int g = 0; g < G; g++) {
+        const int i = i0 + g < count ? i0 + g : i0;
+        pv[g] = ph[(int64_t)i * ld + q];
+        sv[g] = sh[(int64_t)i * ld + q];
+      }
+#pragma unroll
+      for (int g = 0; g < G; g++) {
+        if (i0 + g >= count) break;
+        const cplx<R> alpha = cvt<R>(coef[2 * (i0 + g)]), omega = cvt<R>(coef[2 * (i0 + g) + 1]);
+        acc = acc + alpha * pv[g] + omega * sv[g];
+      }
+    }
+    x[q] = acc;
+  }
+}
+
 // ----------------------------------------------------------- utilities
 template <typename RI, typename RO, bool MR>
 __global__ __launch_bounds__(BS) void k_cast(const cplx<RI> *__restrict__ x, cplx<RO> *__restrict__ y, int64_t n,
@@ -580,6 +641,28 @@ void launch_bicg_xr(cplx<R> *x, const cplx<RZ> *ph, const cplx<RZ> *sh, cplx<R> 
     launch_k(k_bicg_final<false>, dim3(1), dim3(BS), 0, s, partials, nb, 2, S, (int)kBicgNormRho, rs);
   }
 }
+
+template <typename R>
+void launch_bicg_r(cplx<R> *r, const cplx<R> *sv, const cplx<R> *t, const cplx<R> *rh, int64_t n,
+                   cplx<double> *partials, BicgScalars *S, cplx<double> *coef, hipStream_t s) {
+  const int nb = red_blocks(n);
+  launch_k((k_bicg_r<R>), dim3(nb), dim3(BS), 0, s, r, sv, t, rh, n, (const BicgScalars *)S, partials, coef);
+  launch_k(k_bicg_final<false>, dim3(1), dim3(BS), 0, s, partials, nb, 2, S, (int)kBicgNormRho, one_rhs());
+}
+template <typename R>
+void launch_bicg_xdefer(cplx<R> *x, const cplx<R> *ph, const cplx<R> *sh, int64_t ld, int count,
+                        const cplx<double> *coef, int64_t n, hipStream_t s) {
+  launch_k((k_bicg_xdefer<R>), dim3(grid_for(n)), dim3(BS), 0, s, x, ph, sh, ld, count, coef, n);
+}
+template void launch_bicg_r<float>(cplx<float> *, const cplx<float> *, const cplx<float> *, const cplx<float> *,
+                                   int64_t, cplx<double> *, BicgScalars *, cplx<double> *, hipStream_t);
+template void launch_bicg_r<double>(cplx<double> *, const cplx<double> *, const cplx<double> *,
+                                    const cplx<double> *, int64_t, cplx<double> *, BicgScalars *, cplx<double> *,
+                                    hipStream_t);
+template void launch_bicg_xdefer<float>(cplx<float> *, const cplx<float> *, const cplx<float> *, int64_t, int,
+                                        const cplx<double> *, int64_t, hipStream_t);
+template void launch_bicg_xdefer<double>(cplx<double> *, const cplx<double> *, const cplx<double> *, int64_t, int,
+                                         const cplx<double> *, int64_t, hipStream_t);
 
 void launch_bicg_final(const cplx<double> *partials, int nblocks, int npairs, BicgScalars *S, int mode,
                        hipStream_t s, const RhsSet &rs) {

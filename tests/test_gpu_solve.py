@@ -86,16 +86,18 @@ def test_coulomb_513():
 
 
 def test_mixed_fgmres_vs_fp64_oracle():
-    """Mixed form (FP32 cycle inside FP64 FGMRES(40), with 0 or 2 nested FP32
-    Bi-CGSTAB iterations) and the FP64 cycle (plain, and with 4 nested FP64
-    Bi-CGSTAB iterations) on the benchmark operator family at a reduced size
-    (257^2, h = 0.25): both sides at 1e-12, relative error <= 1e-6."""
+    """Mixed form (FP32 cycle inside FP64 FGMRES(40), with 0, 2 or 30 nested
+    FP32 Bi-CGSTAB iterations) and the FP64 cycle (plain, and with 4 or 30
+    nested FP64 Bi-CGSTAB iterations) on the benchmark operator family at a
+    reduced size (257^2, h = 0.25): both sides at 1e-12, relative error
+    <= 1e-6.  30 inner iterations update the inner iterate twice (after 24
+    steps and at the end: the deferred update's two groups)."""
     w = W.large_coulomb(n=257, coarsest=9)
     P = oracle_for(w)
     xo, sto = P.solve(w.rhs[0], "fgmres", 40, 1e-12, 20000)
     assert sto["status"] == 0
     kr = E.Krylov(method="fgmres", restart=40, rtol=1e-12, maxit=20000)
-    for dt, inner in (("f32", 0), ("f32", 2), ("f64", 0), ("f64", 4)):
+    for dt, inner in (("f32", 0), ("f32", 2), ("f32", 30), ("f64", 0), ("f64", 4), ("f64", 30)):
         S = gpu_for(w, dt, krylov=E.Krylov(method="fgmres", restart=40, rtol=1e-12, maxit=20000, inner=inner))
         x, st = S.solve(to_gpu(w.rhs[0]))
         assert st["status"] == 0, (dt, inner, st)
