@@ -309,8 +309,13 @@ ecs_status ecs_timing_read(ecs_ctx *ctx, int kclass, int64_t *launches, double *
  * class 9 for the call only. */
 ecs_status ecs_timing_calibrate(ecs_ctx *ctx, int launches);
 
-/* Launch schedule of the fused 2D V(1,1) red-black cycle (performance only;
- * results do not depend on it):
+/* Launch schedule of the fused 2D V(1,1) red-black cycle.  It chooses which
+ * kind of kernel runs each level (one level per kernel, two levels per
+ * kernel, the single-workgroup tail) and their tile heights; the method's
+ * arithmetic is the same under every schedule, but kernels of different kinds
+ * order some floating-point operations differently, so the cycle's result
+ * can change at the level of rounding (in FP32 enough to move a nested
+ * solve's outer iteration count by a few percent):
  *   down_rows   coarse rows per block of the fused pre-smoothing/restriction
  *               kernel on grids above small_grid: 2 to 6, 8 (16 in FP32)
  *   up_rows     fine rows per block of the fused prolongation/post-smoothing

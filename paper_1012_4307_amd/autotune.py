@@ -18,7 +18,9 @@ objectives:
 Results are cached in a JSON file keyed by GPU architecture, grid, dtype and
 objective (``$ECSMG_TUNING_CACHE``, default ``~/.cache/ecsmg/tuning.json``),
 so a batch of systems of the same size pays the search once.  The schedule
-only changes performance: the arithmetic of every node is the same.
+does not change the method's arithmetic; which kernel kind runs a level can
+change the rounding of the cycle (kernels order some floating-point operations
+differently), so the objective is time per cycle, not time per solve.
 """
 from __future__ import annotations
 

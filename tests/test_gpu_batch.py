@@ -148,7 +148,7 @@ def test_autotune_group_one_schedule_for_the_batch(tmp_path, monkeypatch):
     """The throughput tuner for batches: one schedule from the candidate list,
     applied to every solver of the group, cached; solvers of another size are
     refused; the batched solve under that schedule still equals the single
-    solves (a schedule changes no arithmetic)."""
+    solves made under the same schedule."""
     import torch
     from paper_1012_4307_amd import autotune
     monkeypatch.setenv("ECSMG_TUNING_CACHE", str(tmp_path / "tune.json"))
@@ -227,3 +227,17 @@ def test_side_stream_solver_is_ordered_with_the_callers_stream():
         b2.copy_(ref)
         x1, st = S1.solve(b2)
         assert st["status"] == 0 and torch.equal(x1, x0)
+    # larger Krylov settings make the side-stream solver reallocate its
+    # workspace from the caller's stream pool while that stream is still
+    # busy with memory it then frees: the set-up in the new workspace waits
+    # for the caller's stream, so the solve equals the caller-stream solver's
+    big = E.Krylov(method="fgmres", restart=40, rtol=1e-8, maxit=20000)
+    xb0, _ = S0.solve(ref, krylov=big)
+    scratch = torch.randn(64 << 20, device="cuda", dtype=torch.float64)
+    _ = a @ a
+    scratch.mul_(2.0)
+    del scratch
+    b3 = torch.zeros_like(ref)
+    b3.copy_(ref)
+    xb1, st = S1.solve(b3, krylov=big)
+    assert st["status"] == 0 and torch.equal(xb1, xb0)
