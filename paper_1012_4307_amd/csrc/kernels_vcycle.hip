@@ -187,23 +187,28 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
 #pragma unroll
     for (int r = 0; r < RPW; r++) {
       const int ly = wv + 4 * r, j = gy0 + ly;
-      if (ly < 3 || ly >= 3 + 2 * CY || j >= n1) continue;
-      cplx<R> *row = src.out + (int64_t)j * n0;
-      if (owna) row[ia] = ared ? bR[r] : bB[r];
-      if (ownb) row[ib] = ared ? bB[r] : bR[r];
+      if (ly >= 3 && ly < 3 + 2 * CY && j < n1) {
+        cplx<R> *row = src.out + (int64_t)j * n0;
+        if (owna) row[ia] = ared ? bR[r] : bB[r];
+        if (ownb) row[ib] = ared ? bB[r] : bR[r];
+      }
     }
   }
-  // inverse diagonals; red relaxation from zero: omega b / D
+  // inverse diagonals; red relaxation from zero: omega b / D.  Row
+  // conditions depend on the wave (uniform) and are tested apart from the
+  // lane conditions, so the compiler branches on them instead of carrying a
+  // per-lane exit state through the unrolled row loops.
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
-    if (ly >= WY) break;
-    const int j = gy0 + ly;
-    const bool yin = j >= 1 && j <= n1 - 2;
-    dR[r] = (yin && inR) ? inv_cycle(xmR + xpR + cym[r] + cyp[r] + (kR[r] * f.beta + f.c)) : zero_c<R>();
-    dB[r] = (yin && inBk) ? inv_cycle(xmB + xpB + cym[r] + cyp[r] + (kB[r] * f.beta + f.c)) : zero_c<R>();
-    sR[ly][lane] = omega * (bR[r] * dR[r]);
-    sB[ly][lane] = zero_c<R>();
+    if (ly < WY) {
+      const int j = gy0 + ly;
+      const bool yin = j >= 1 && j <= n1 - 2;
+      dR[r] = (yin && inR) ? inv_cycle(xmR + xpR + cym[r] + cyp[r] + (kR[r] * f.beta + f.c)) : zero_c<R>();
+      dB[r] = (yin && inBk) ? inv_cycle(xmB + xpB + cym[r] + cyp[r] + (kB[r] * f.beta + f.c)) : zero_c<R>();
+      sR[ly][lane] = omega * (bR[r] * dR[r]);
+      sB[ly][lane] = zero_c<R>();
+    }
   }
   __syncthreads();
   // black relaxation and the black residual (1 - w)(b + o).  The black node's
@@ -222,13 +227,15 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     resB[r] = tB[r] = zero_c<R>();
-    if (ly >= WY) break;
-    if (ly < 1 || ly > WY - 2 || !pin) continue;
-    const cplx<R> tb =
-        bB[r] + (wBo * sR[ly][lane] + wBn * sR[ly][ps] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane]);
-    tB[r] = omega * (tb * dB[r]);
-    resB[r] = om1 * tb;
-    sB[ly][lane] = tB[r];
+    if (ly >= 1 && ly <= WY - 2) {
+      if (pin) {
+        const cplx<R> tb =
+            bB[r] + (wBo * sR[ly][lane] + wBn * sR[ly][ps] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane]);
+        tB[r] = omega * (tb * dB[r]);
+        resB[r] = om1 * tb;
+        sB[ly][lane] = tB[r];
+      }
+    }
   }
   __syncthreads();
   // red residual (1 - w) b + o from the relaxed black neighbours: own black
@@ -242,15 +249,18 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
-    if (ly >= WY) break;
-    const int j = gy0 + ly;
-    const bool yin = j >= 1 && j <= n1 - 2;
-    cplx<R> resR = zero_c<R>();
-    if (yin && inR && qin && ly >= 1 && ly <= WY - 2)
-      resR = om1 * bR[r] +
-             (wRo * sB[ly][lane] + wRn * sB[ly][pq] + cym[r] * sB[ly - 1][lane] + cyp[r] * sB[ly + 1][lane]);
-    rR[ly][lane] = resR;
-    rB[ly][lane] = (yin && inBk) ? resB[r] : zero_c<R>();
+    if (ly < WY) {
+      const int j = gy0 + ly;
+      const bool yin = j >= 1 && j <= n1 - 2;
+      cplx<R> resR = zero_c<R>();
+      if (yin && ly >= 1 && ly <= WY - 2) {
+        if (inR && qin)
+          resR = om1 * bR[r] +
+                 (wRo * sB[ly][lane] + wRn * sB[ly][pq] + cym[r] * sB[ly - 1][lane] + cyp[r] * sB[ly + 1][lane]);
+      }
+      rR[ly][lane] = resR;
+      rB[ly][lane] = (yin && inBk) ? resB[r] : zero_c<R>();
+    }
   }
   __syncthreads();
   // full weighting onto the owned coarse nodes: lane = coarse column.  The
@@ -347,16 +357,20 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
   }
   // inverse diagonals and the down pass's zero-guess red relaxation
   // t = w b / D (0 off the interior)
+  // Row conditions depend on the wave (uniform) and are tested apart from the
+  // lane conditions, so the compiler branches on them instead of carrying a
+  // per-lane exit state through the unrolled row loops.
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
-    if (ly >= WY) break;
-    const int j = gy0 + ly;
-    const bool yin = j >= 1 && j <= n1 - 2;
-    dR[r] = (yin && inR) ? inv_cycle(xmR + xpR + cym[r] + cyp[r] + (kR[r] * f.beta + f.c)) : zero_c<R>();
-    dB[r] = (yin && inBk) ? inv_cycle(xmB + xpB + cym[r] + cyp[r] + (kB[r] * f.beta + f.c)) : zero_c<R>();
-    vR[r] = omega * (bR[r] * dR[r]);
-    sR[ly][lane] = vR[r];
+    if (ly < WY) {
+      const int j = gy0 + ly;
+      const bool yin = j >= 1 && j <= n1 - 2;
+      dR[r] = (yin && inR) ? inv_cycle(xmR + xpR + cym[r] + cyp[r] + (kR[r] * f.beta + f.c)) : zero_c<R>();
+      dB[r] = (yin && inBk) ? inv_cycle(xmB + xpB + cym[r] + cyp[r] + (kB[r] * f.beta + f.c)) : zero_c<R>();
+      vR[r] = omega * (bR[r] * dR[r]);
+      sR[ly][lane] = vR[r];
+    }
   }
   __syncthreads();
   // the down pass's black relaxation t = w (b + o) / D on rings 2 and
@@ -374,29 +388,29 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
     vB[r] = zero_c<R>();
-    if (ly >= WY) break;
-    if (ly < 1 || ly > WY - 2) continue;  // ring 3: red t only
-    const int j = gy0 + ly;
-    const bool yin = j >= 1 && j <= n1 - 2;
-    if (pin) {
-      const cplx<R> tb =
-          bB[r] + (wBo * sR[ly][lane] + wBn * sR[ly][psc] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane]);
-      vB[r] = omega * (tb * dB[r]);
-    }
-    if (yin) {
-      const int cj = (j >> 1) - cy0;
-      cplx<R> pa, pb;
-      if ((j & 1) == 0) {
-        pa = se[cj][lane];
-        pb = R(0.5) * (se[cj][lane] + se[cj][lane + 1]);
-      } else {
-        pa = R(0.5) * (se[cj][lane] + se[cj + 1][lane]);
-        pb = R(0.25) * (se[cj][lane] + se[cj][lane + 1] + se[cj + 1][lane] + se[cj + 1][lane + 1]);
+    if (ly >= 1 && ly <= WY - 2) {  // ring 3: red t only
+      const int j = gy0 + ly;
+      const bool yin = j >= 1 && j <= n1 - 2;
+      if (pin) {
+        const cplx<R> tb =
+            bB[r] + (wBo * sR[ly][lane] + wBn * sR[ly][psc] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane]);
+        vB[r] = omega * (tb * dB[r]);
       }
-      if (inR) vR[r] = vR[r] + (ared ? pa : pb);
-      if (inBk) vB[r] = vB[r] + (ared ? pb : pa);
+      if (yin) {
+        const int cj = (j >> 1) - cy0;
+        cplx<R> pa, pb;
+        if ((j & 1) == 0) {
+          pa = se[cj][lane];
+          pb = R(0.5) * (se[cj][lane] + se[cj][lane + 1]);
+        } else {
+          pa = R(0.5) * (se[cj][lane] + se[cj + 1][lane]);
+          pb = R(0.25) * (se[cj][lane] + se[cj][lane + 1] + se[cj + 1][lane] + se[cj + 1][lane + 1]);
+        }
+        if (inR) vR[r] = vR[r] + (ared ? pa : pb);
+        if (inBk) vB[r] = vB[r] + (ared ? pb : pa);
+      }
+      sB[ly][lane] = vB[r];
     }
-    sB[ly][lane] = vB[r];
   }
   __syncthreads();
   // red relaxation on the tile plus a one-node ring.  The red node's black
@@ -409,12 +423,15 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
-    if (ly >= WY) break;
     const int j = gy0 + ly;
-    if (ly < 2 || ly > WY - 3 || !qin || !inR || j < 1 || j > n1 - 2) continue;
-    const cplx<R> o = wRo * sB[ly][lane] + wRn * sB[ly][pq] + cym[r] * sB[ly - 1][lane] + cyp[r] * sB[ly + 1][lane];
-    vR[r] = om1 * vR[r] + omega * ((bR[r] + o) * dR[r]);
-    sR[ly][lane] = vR[r];
+    if (ly >= 2 && ly <= WY - 3 && j >= 1 && j <= n1 - 2) {
+      if (qin && inR) {
+        const cplx<R> o =
+            wRo * sB[ly][lane] + wRn * sB[ly][pq] + cym[r] * sB[ly - 1][lane] + cyp[r] * sB[ly + 1][lane];
+        vR[r] = om1 * vR[r] + omega * ((bR[r] + o) * dR[r]);
+        sR[ly][lane] = vR[r];
+      }
+    }
   }
   __syncthreads();
   // black relaxation on the owned tile (pairs 2..61, rows 3..TY+2); write
@@ -425,18 +442,18 @@ __global__ __launch_bounds__(NT) void k_up_rb(Grid<R> f, Grid<R> c, const cplx<R
 #pragma unroll
   for (int r = 0; r < RPW; r++) {
     const int ly = wv + 4 * r;
-    if (ly >= WY) break;
     const int j = gy0 + ly;
-    if (ly < 3 || ly >= TY + 3 || j >= n1) continue;
-    cplx<R> outB = vB[r];
-    if (own_x && inBk && j >= 1 && j <= n1 - 2) {
-      const cplx<R> o =
-          wBo * sR[ly][lane] + wBn * sR[ly][psc] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane];
-      outB = om1 * outB + omega * ((bB[r] + o) * dB[r]);
+    if (ly >= 3 && ly < TY + 3 && j < n1) {
+      cplx<R> outB = vB[r];
+      if (own_x && inBk && j >= 1 && j <= n1 - 2) {
+        const cplx<R> o =
+            wBo * sR[ly][lane] + wBn * sR[ly][psc] + cym[r] * sR[ly - 1][lane] + cyp[r] * sR[ly + 1][lane];
+        outB = om1 * outB + omega * ((bB[r] + o) * dB[r]);
+      }
+      const uint32_t qo = row_off<cplx<R>>(j - y0, n0);
+      st_c(ro, osR + qo, vR[r]);
+      st_c(ro, osB + qo, outB);
     }
-    const uint32_t qo = row_off<cplx<R>>(j - y0, n0);
-    st_c(ro, osR + qo, vR[r]);
-    st_c(ro, osB + qo, outB);
   }
 }
 
