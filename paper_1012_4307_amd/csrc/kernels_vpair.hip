@@ -53,20 +53,21 @@ template <typename R>
 struct Region {
   int ox, oy, w, h;
   float invw, invh2;  // 1 / w, 1 / ceil(w / 2)
-  // the level's 1D weights over the region's columns and rows (LDS)
-  cplx<R> *xm, *xp, *ym, *yp;
+  // the level's 1D weights over the region's columns and rows, in LDS from
+  // wt: xm at [0, w), xp at [w, 2w), ym at [2w, 2w + h), yp after them.  One
+  // base and integer offsets (four separate pointers, selected between at
+  // run time, were kept in scratch memory and read through flat accesses).
+  cplx<R> *wt;
+  __device__ __forceinline__ cplx<R> xm(int x) const { return wt[x]; }
+  __device__ __forceinline__ cplx<R> xp(int x) const { return wt[w + x]; }
+  __device__ __forceinline__ cplx<R> ym(int y) const { return wt[2 * w + y]; }
+  __device__ __forceinline__ cplx<R> yp(int y) const { return wt[2 * w + h + y]; }
 };
 
 template <typename R>
 __device__ __forceinline__ Region<R> make_region(int ox, int oy, int w, int h, cplx<R> *wts) {
   Region<R> g;
-  g.xm = g.xp = g.ym = g.yp = nullptr;
-  if (wts) {
-    g.xm = wts;
-    g.xp = wts + w;
-    g.ym = wts + 2 * w;
-    g.yp = wts + 2 * w + h;
-  }
+  g.wt = wts;
   g.ox = ox;
   g.oy = oy;
   g.w = w;
@@ -110,11 +111,11 @@ __device__ __forceinline__ void write_weights(const Region<R> &A, const WeightRe
   const int q = threadIdx.x;
   const cplx<R> m = w.in ? w.m : zc<R>(), p = w.in ? w.p : zc<R>();
   if (q < A.w) {
-    A.xm[q] = m;
-    A.xp[q] = p;
+    A.wt[q] = m;
+    A.wt[A.w + q] = p;
   } else if (q < A.w + A.h) {
-    A.ym[q - A.w] = m;
-    A.yp[q - A.w] = p;
+    A.wt[A.w + q] = m;              // ym at 2w + (q - w)
+    A.wt[A.w + A.h + q] = p;        // yp at 2w + h + (q - w)
   }
 }
 
@@ -183,8 +184,8 @@ __device__ void down_sweep(const Grid<R> &g, const Region<R> &A, const cplx<R> *
     const int i = A.ox + x;
     if (x >= 1 && x <= W - 2 && y >= 1 && y <= A.h - 2 && interior(i, j, n0, n1)) {
       const int p = y * W + x;
-      const cplx<R> tb = ab[p] + (A.xm[x] * at[p - 1] + A.xp[x] * at[p + 1] + A.ym[y] * at[p - W] +
-                                  A.yp[y] * at[p + W]);
+      const cplx<R> tb = ab[p] + (A.xm(x) * at[p - 1] + A.xp(x) * at[p + 1] + A.ym(y) * at[p - W] +
+                                  A.yp(y) * at[p + W]);
       at[p] = omega * (tb * ad[p]);
       ar[p] = om1 * tb;
     }
@@ -199,8 +200,8 @@ __device__ void down_sweep(const Grid<R> &g, const Region<R> &A, const cplx<R> *
     const int i = A.ox + x;
     if (x >= 1 && x <= W - 2 && y >= 1 && y <= A.h - 2 && interior(i, j, n0, n1)) {
       const int p = y * W + x;
-      ar[p] = om1 * ab[p] + (A.xm[x] * at[p - 1] + A.xp[x] * at[p + 1] + A.ym[y] * at[p - W] +
-                             A.yp[y] * at[p + W]);
+      ar[p] = om1 * ab[p] + (A.xm(x) * at[p - 1] + A.xp(x) * at[p + 1] + A.ym(y) * at[p - W] +
+                             A.yp(y) * at[p + W]);
     }
     if (y >= p0 && y < p1 && j < n1) {
       const int xa = 2 * h;
@@ -331,7 +332,7 @@ __device__ void up_sweep(const Grid<R> &g, const Region<R> &A, const cplx<R> *ab
                                        : (x >= o0 && x < o1 && y >= p0 && y < p1);
       if (ring_ok && interior(i, j, n0, n1)) {
         const int p = y * W + x;
-        const cplx<R> o = A.xm[x] * av[p - 1] + A.xp[x] * av[p + 1] + A.ym[y] * av[p - W] + A.yp[y] * av[p + W];
+        const cplx<R> o = A.xm(x) * av[p - 1] + A.xp(x) * av[p + 1] + A.ym(y) * av[p - W] + A.yp(y) * av[p + W];
         av[p] = om1 * av[p] + omega * ((ab[p] + o) * ad[p]);
       }
     }
