@@ -14,10 +14,11 @@ Bi-CGSTAB around the complex-FP32 V-cycle (Arnoldi, Hessenberg least squares
 and the true residual stay FP64 on the GPU).  Reported beside it: the plain
 FP64 solve (FGMRES(40), FP64 cycle) timed the same way, the FP32-cycle-only
 FGMRES(40), FP64 Bi-CGSTAB, V-cycle bandwidth, per-kernel timings of the
-dominant kernel measured with HIP events inside the timed region, and the
-CPU oracle on a bounded sample.  Prints one JSON line.
+dominant kernel measured with HIP events inside the timed region (and, as a
+cross-check, from an in-process kernel trace of one more solve), and the CPU
+oracle on a bounded sample.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-trace]
 """
 from __future__ import annotations
 
@@ -50,6 +51,8 @@ def parse():
     ap.add_argument("--no-context", action="store_true", help="skip the context solves (FP32-cycle FGMRES, "
                                                                "FP64 Bi-CGSTAB)")
     ap.add_argument("--vcycles", type=int, default=20, help="cycles timed for the V-cycle bandwidth")
+    ap.add_argument("--no-trace", action="store_true",
+                    help="skip the in-process kernel trace of one more mixed solve (for runs under rocprofv3)")
     ap.add_argument("--config", default="mixed2049",
                     choices=["mixed2049", "batched", "persistent_probe", "adjoint", "cube", "coulomb513", "small65",
                              "paper_mp", "coupled"],
@@ -86,6 +89,44 @@ def vcycle_algorithmic_bytes(n, nlev, real_bytes, model="method"):
     nodes = level_nodes(n, nlev)
     per = PASS_REALS[model]["down"] + PASS_REALS[model]["up"]
     return sum(nodes[:-1]) * per * real_bytes
+
+
+def trace_dominant_us(run, cls, PS):
+    """Average duration (us) of the finest-grid launches of kernel class `cls`
+    in a kernel trace of run(), or None when the class has no pattern or the
+    tracer records nothing."""
+    import collections
+    import re
+    import tempfile
+    import torch
+    from torch.profiler import ProfilerActivity, profile
+    pats = dict(PS.CLASSES)
+    if cls not in pats:
+        return None
+    with profile(activities=[ProfilerActivity.CUDA]) as prof:
+        run()
+        torch.cuda.synchronize()
+    fd, path = tempfile.mkstemp(suffix=".json")
+    os.close(fd)
+    try:
+        prof.export_chrome_trace(path)
+        with open(path) as f:
+            events = json.load(f).get("traceEvents", [])
+    finally:
+        os.remove(path)
+    agg = collections.defaultdict(list)
+    for e in events:
+        if e.get("ph") != "X" or e.get("cat") != "kernel":
+            continue
+        name = PS.short_name(e.get("name", ""))
+        if not re.fullmatch(pats[cls], name):
+            continue
+        g = e.get("args", {}).get("grid", [0, 0, 0])
+        agg[int(g[0]) * int(g[1]) * int(g[2])].append(float(e["dur"]))
+    if not agg:
+        return None
+    durs = agg[max(agg)]
+    return sum(durs) / len(durs)
 
 
 def main():
@@ -283,6 +324,21 @@ def main():
                     empty_kernel_us=round(overhead_us, 2),
                     achieved_net_of_empty=round(method_bytes / (net_us * 1e-6) / 1e9, 1), launches=nl,
                     timed_one_launch_in=TIMED_ONE_IN)
+
+    # cross-check of the dominant kernel's duration: an in-process kernel trace
+    # (the ROCm tracer behind torch.profiler) of one more mixed solve.  Its
+    # durations are the kernels' own execution, as in rocprofv3's kernel
+    # trace; a launch timed with HIP events also spans the dispatch of the
+    # kernel and the completion of its stop event.
+    if not args.no_trace:
+        tr_us = trace_dominant_us(lambda: Smix.solve(b), dom, PS)
+        if tr_us:
+            roofline["trace"] = dict(
+                avg_launch_us=round(tr_us, 2), achieved=round(method_bytes / (tr_us * 1e-6) / 1e9, 1),
+                frac=round(method_bytes / (tr_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                kernel_model_frac=round(kernel_bytes / (tr_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                source="in-process kernel trace (torch.profiler) of one more mixed solve: the dominant class's "
+                       "finest-grid launches")
 
     cpu = None
     if not args.no_cpu:
