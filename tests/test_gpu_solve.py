@@ -165,6 +165,26 @@ def test_arnoldi_orthogonalisation_vs_oracle_mgs(dt):
     assert 0 <= its["cgs2_selective"][1] <= its["cgs2_selective"][0]
 
 
+def test_mixed_solve_beyond_the_benchmark_grid():
+    """The benchmark's solver configuration on a grid four times larger:
+    4097^2 nodes (h = 0.25, [-512, 512]^2, 10 levels to the 9^2 coarsest,
+    16.8 M unknowns), so every kernel's indexing, tiling and reduction grid
+    runs past the sizes the benchmark uses: the mixed solve reaches 1e-8 by
+    the oracle's own operator, with no inner run cut short."""
+    w = W.large_coulomb(n=4097)
+    assert w.nlev == 10
+    P = oracle_for(w)
+    kr = E.Krylov(method="fgmres", restart=40, rtol=1e-8, maxit=400, inner=20)
+    S = gpu_for(w, "f32", krylov=kr)
+    b = w.rhs[0]
+    x, st = S.solve(to_gpu(b))
+    assert st["status"] == 0, st
+    res = oracle_resid(P, to_np(x), b)
+    print(f"4097^2: outer {st['iterations']} inner {st['inner_iterations']} oracle residual {res:.3e}", flush=True)
+    assert res <= 1.05e-8, res
+    assert st["inner_breakdowns"] == 0, st
+
+
 def test_full_size_solutions_vs_stored_oracle_samples():
     """The benchmark itself at full size (2049^2, h = 0.25): the mixed solve
     (FGMRES(40) around 20 nested FP32 Bi-CGSTAB iterations) and the FP64
