@@ -95,13 +95,10 @@ def trace_dominant_us(run, cls, PS):
     """Average duration (us) of the finest-grid launches of kernel class `cls`
     in a kernel trace of run(), or None when the class has no pattern or the
     tracer records nothing."""
-    import collections
-    import re
     import tempfile
     import torch
     from torch.profiler import ProfilerActivity, profile
-    pats = dict(PS.CLASSES)
-    if cls not in pats:
+    if cls not in dict(PS.CLASSES):
         return None
     with profile(activities=[ProfilerActivity.CUDA]) as prof:
         run()
@@ -114,19 +111,7 @@ def trace_dominant_us(run, cls, PS):
             events = json.load(f).get("traceEvents", [])
     finally:
         os.remove(path)
-    agg = collections.defaultdict(list)
-    for e in events:
-        if e.get("ph") != "X" or e.get("cat") != "kernel":
-            continue
-        name = PS.short_name(e.get("name", ""))
-        if not re.fullmatch(pats[cls], name):
-            continue
-        g = e.get("args", {}).get("grid", [0, 0, 0])
-        agg[int(g[0]) * int(g[1]) * int(g[2])].append(float(e["dur"]))
-    if not agg:
-        return None
-    durs = agg[max(agg)]
-    return sum(durs) / len(durs)
+    return PS.trace_class_avg(events, cls)
 
 
 def main():

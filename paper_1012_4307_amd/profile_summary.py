@@ -70,6 +70,28 @@ def short_name(name: str) -> str:
     return re.split(r"[(]", nm)[0]
 
 
+def trace_class_avg(events, cls: str):
+    """Average duration (the trace's unit) of the finest-grid launches of the
+    timing class `cls` among chrome-trace events (a kernel event: ph "X",
+    cat "kernel", args.grid in workgroups), or None when the class has no
+    pattern here or no launch of it is among the events."""
+    pats = dict(CLASSES)
+    if cls not in pats:
+        return None
+    agg = collections.defaultdict(list)
+    for e in events:
+        if e.get("ph") != "X" or e.get("cat") != "kernel":
+            continue
+        if not re.fullmatch(pats[cls], short_name(e.get("name", ""))):
+            continue
+        g = e.get("args", {}).get("grid", [0, 0, 0])
+        agg[int(g[0]) * int(g[1]) * int(g[2])].append(float(e["dur"]))
+    if not agg:
+        return None
+    durs = agg[max(agg)]
+    return sum(durs) / len(durs)
+
+
 def stats(trace_csv: str, out_txt: str, cmd: str, top: int = 40) -> None:
     agg = collections.defaultdict(list)
     with open(trace_csv) as f:

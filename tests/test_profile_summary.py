@@ -60,3 +60,23 @@ def test_stats_table(tmp_path):
     assert "k_tail<float>" in text and "2 dispatches" in text
     row = next(ln for ln in text.splitlines() if ln.startswith("k_tail"))
     assert row.split()[1:4] == ["1024", "2", "4.00"]
+
+
+def test_trace_class_average_takes_the_finest_grid_of_the_class():
+    """The bench's in-process trace cross-check: kernel events of the class
+    (with or without the single right-hand-side template flag) on the largest
+    grid are averaged; other grids, other kernels, runtime events and classes
+    without a pattern are ignored."""
+    def ev(name, grid, dur, cat="kernel", ph="X"):
+        return {"ph": ph, "cat": cat, "name": f"void ecs::(anonymous namespace)::{name}(ecs::Grid<float>, int)",
+                "dur": dur, "args": {"grid": [grid, 1, 1], "block": [256, 1, 1]}}
+    events = [ev("k_up_rb<float, 8, false>", 4632, 25.0), ev("k_up_rb<float, 8, false>", 4632, 27.0),
+              ev("k_up_rb<float, 8, false>", 1168, 10.0),          # the 1025^2 level
+              ev("k_up_rb<float, 8>", 4632, 26.0),                 # the form without the flag
+              ev("k_up_rb<double, 8, false>", 9999, 40.0),         # another class
+              ev("k_up_rb<float, 8, false>", 9999, 99.0, cat="cuda_runtime"),
+              ev("k_up_rb<float, 8, false>", 9999, 99.0, ph="i")]
+    assert PS.trace_class_avg(events, "up") == 26.0
+    assert PS.trace_class_avg(events, "up_f64") == 40.0
+    assert PS.trace_class_avg(events, "down_p") is None
+    assert PS.trace_class_avg(events, "mdot") is None
