@@ -180,8 +180,9 @@ ecs_status ecs_set_workspace(ecs_ctx *ctx, void *dev, size_t bytes);
 /* Solve A x = b (Sec. 5).  b, x: complex128 device arrays. */
 ecs_status ecs_solve(ecs_ctx *ctx, const ecs_solve_desc *desc, const void *b_dev, void *x_dev, ecs_stats *stats);
 
-/* For callers that cannot allocate device memory (code under HIP graph
- * capture, serving loops, harnesses that forbid hipMalloc): ecs_solve with
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc; the solve itself waits on the host between Krylov
+ * steps, so it is not for use inside a graph capture): ecs_solve with
  * the Krylov vectors in the library's static device scratch instead of the
  * workspace.  Same arguments, method, results and statuses as ecs_solve; the
  * call itself allocates nothing (no hipMalloc/hipFree, no graph, no event):
