@@ -322,8 +322,11 @@ ecs_status ecs_timing_calibrate(ecs_ctx *ctx, int launches);
  *   up_rows     fine rows per block of the fused prolongation/post-smoothing
  *               kernel on grids above small_grid: 4, 8, 10, 12, 16 or 32
  *   small_grid  grids with at most this many nodes per axis use 2 / 4 rows
- *   tail_nodes  levels with at most this many nodes per axis (3..33) run in
- *               the single-workgroup kernel that ends the cycle
+ *   tail_nodes  levels with at most this many nodes per axis run in the
+ *               single-workgroup kernel that ends the cycle: 3..65; above 33
+ *               it applies to FP32 cycles only (their wide tail holds up to
+ *               5696 nodes, e.g. 65^2 down to a 9^2 coarsest), FP64 cycles
+ *               and general cycles use min(tail_nodes, 33)
  *   pair_grid   levels above the tail with at most this many nodes per axis
  *               run two per kernel (pairs counted from the tail up); 0: none
  *   fuse_updates  1: the FP32 Bi-CGSTAB inside FGMRES (desc->inner > 0) forms

@@ -48,7 +48,8 @@ def _key(solver) -> str:
 
 def candidates(dtype: str):
     downs = (2, 4, 6, 8, 16) if dtype == "f32" else (2, 4, 6, 8)
-    for d, u, sg, tn, pg in itertools.product(downs, (4, 8, 16), (257, 513), (17, 33), (0, 129, 513)):
+    tails = (17, 33, 65) if dtype == "f32" else (17, 33)   # FP32 cycles have a wide tail up to 65^2
+    for d, u, sg, tn, pg in itertools.product(downs, (4, 8, 16), (257, 513), tails, (0, 129, 513)):
         yield dict(down_rows=d, up_rows=u, small_grid=sg, tail_nodes=tn, pair_grid=pg, fuse_updates=1)
 
 

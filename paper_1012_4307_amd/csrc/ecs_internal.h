@@ -241,6 +241,12 @@ constexpr int kTailMaxLevels = 8;
 constexpr int kTailNodes = 33;
 constexpr int kTailCap = 1536;
 constexpr int kTailMinv = 2401;  // coarsest inverse entries staged in LDS (49 unknowns)
+// FP32 cycles also have a wide tail: levels of up to kTailWideNodes nodes per
+// axis, kTailWideCap nodes in all (a 65^2 level down to a 9^2 coarsest: 5684),
+// with at most kTailWideWeights 1D weights per axis over its levels
+constexpr int kTailWideNodes = 65;
+constexpr int kTailWideCap = 5696;
+constexpr int kTailWideWeights = 132;
 template <typename R>
 struct TailArgs {
   int nl;                            // levels in the tail, the last one the coarsest

@@ -930,12 +930,18 @@ FusedPlan fused_plan(const ecs_ctx *C) {
   const ecs_tuning &T = C->tune;
   FusedPlan P{};
   // first level handled by the tail: the coarsest levels that are small
+  // (FP32 cycles: up to 65 nodes per axis in the wide tail; FP64: up to 33)
+  const bool wide = C->prec.vcycle_dtype == ECS_F32;
+  const int tn = wide ? T.tail_nodes : std::min(T.tail_nodes, kTailNodes);
+  const int64_t cap = wide ? kTailWideCap : kTailCap;
   int lt = lc;
-  int64_t tail_nn = C->hl[lc].nn;
-  while (lt > 0 && C->hl[lt - 1].n[0] <= T.tail_nodes && C->hl[lt - 1].n[1] <= T.tail_nodes &&
-         lc - (lt - 1) + 1 <= kTailMaxLevels && tail_nn + C->hl[lt - 1].nn <= kTailCap) {
+  int64_t tail_nn = C->hl[lc].nn, tail_w = std::max(C->hl[lc].n[0], C->hl[lc].n[1]);
+  while (lt > 0 && C->hl[lt - 1].n[0] <= tn && C->hl[lt - 1].n[1] <= tn && lc - (lt - 1) + 1 <= kTailMaxLevels &&
+         tail_nn + C->hl[lt - 1].nn <= cap &&
+         tail_w + std::max(C->hl[lt - 1].n[0], C->hl[lt - 1].n[1]) <= (wide ? kTailWideWeights : 128)) {
     lt--;
     tail_nn += C->hl[lt].nn;
+    tail_w += std::max(C->hl[lt].n[0], C->hl[lt].n[1]);
   }
   P.lt = lt;
   // the levels above the tail with at most pair_grid nodes per axis run two
@@ -1192,8 +1198,8 @@ void ensure_sched(ecs_ctx *C) {
   int lt = -1;
   if (C->sfirst >= 0) {
     lt = lc;
-    while (lt - 1 >= C->sfirst && C->hl[lt - 1].n[0] <= C->tune.tail_nodes &&
-           C->hl[lt - 1].n[1] <= C->tune.tail_nodes)
+    const int tn = std::min(C->tune.tail_nodes, kTailNodes);  // the schedule tail holds up to 33^2 levels
+    while (lt - 1 >= C->sfirst && C->hl[lt - 1].n[0] <= tn && C->hl[lt - 1].n[1] <= tn)
       lt--;
     if (lt == lc) lt = -1;
   }
@@ -2606,7 +2612,8 @@ ecs_status ecs_set_tuning(ecs_ctx *C, const ecs_tuning *t) {
   const bool up_ok = t->up_rows == 4 || t->up_rows == 8 || t->up_rows == 10 || t->up_rows == 12 || t->up_rows == 16 ||
                      t->up_rows == 32;
   if (!down_ok || !up_ok) return fail(C, ECS_EINVAL, "unsupported tile height");
-  if (t->tail_nodes < 3 || t->tail_nodes > kTailNodes) return fail(C, ECS_EINVAL, "tail_nodes must be in [3, 33]");
+  if (t->tail_nodes < 3 || t->tail_nodes > kTailWideNodes)
+    return fail(C, ECS_EINVAL, "tail_nodes must be in [3, 65]");
   if (t->small_grid < 3) return fail(C, ECS_EINVAL, "small_grid must be >= 3");
   if (t->pair_grid < 0) return fail(C, ECS_EINVAL, "pair_grid must be >= 0");
   if (t->fuse_updates != 0 && t->fuse_updates != 1) return fail(C, ECS_EINVAL, "fuse_updates must be 0 or 1");

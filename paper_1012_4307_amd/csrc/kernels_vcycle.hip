@@ -718,6 +718,204 @@ __global__ __launch_bounds__(TT) void k_tail(TailArgs<R> a, RhsSet rs) {
   }
 }
 
+// ------------------------------------------------------------ wide tail
+// The same cycle as k_tail (FP32) from a level of up to 65^2 nodes.  To fit
+// a workgroup's 160 KiB of LDS a node keeps its right-hand side, iterate,
+// residual and k^2 (28 B) and its inverse diagonal is formed where it is used,
+// from the LDS weights and k^2 by k_tail's set-up expression (the same value);
+// the coarsest inverse is read from memory.  The set-up loads the weights
+// (wave k: level k's, two entries per lane), k^2 of every node and the first
+// level's right-hand side; the first level's zero-guess red relaxation is a
+// phase of its own.
+struct TailLdsWide {
+  cplx<float> xm[kTailWideWeights], xp[kTailWideWeights], ym[kTailWideWeights], yp[kTailWideWeights];
+  cplx<float> b[kTailWideCap], t[kTailWideCap], w[kTailWideCap];
+  float k[kTailWideCap];
+};
+static_assert(sizeof(TailLdsWide) <= 163840, "the wide tail's vectors fit a workgroup's LDS");
+
+template <bool MR>
+__global__ __launch_bounds__(TT) void k_tail_wide(TailArgs<float> a, RhsSet rs) {
+  __shared__ TailLdsWide S;
+  const int tid = threadIdx.x;
+  const int64_t rq = MR ? rhs_index(rs) * rhs_stride((int64_t)a.g[0].n0 * a.g[0].n1) : 0;
+  const cplx<float> *const b0 = a.b0 + rq;
+  cplx<float> *const u0 = a.u0 + rq;
+  const float om = a.omega, om1 = 1.0f - a.omega;
+  const int last = a.nl - 1;
+  // inverse diagonal of node p = (i, j) of level k (k uniform)
+  auto dinv = [&](int k, int i, int j, int p) {
+    const Grid<float> &g = a.g[k];
+    const int wo = a.woff[k];
+    return inv_c(S.xm[wo + i] + S.xp[wo + i] + S.ym[wo + j] + S.yp[wo + j] + (S.k[a.noff[k] + p] * g.beta + g.c));
+  };
+  {
+    const int ln = tid & 63;
+    const int kw = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (kw < a.nl) {
+      const Grid<float> &gw = a.g[kw];
+      const int wo = a.woff[kw], nw = a.woff[kw + 1] - wo;
+      for (int q = ln; q < nw; q += 64) {
+        const int q0 = q < gw.n0 ? q : gw.n0 - 1, q1 = q < gw.n1 ? q : gw.n1 - 1;
+        S.xm[wo + q] = gw.cm0[q0];
+        S.xp[wo + q] = gw.cp0[q0];
+        S.ym[wo + q] = gw.cm1[q1];
+        S.yp[wo + q] = gw.cp1[q1];
+      }
+    }
+    // nodes: slot sl of thread tid is padded index P = tid + sl TT (waves
+    // never straddle levels, so a wave's level is uniform)
+    constexpr int kSlots = (kTailWideCap + kTailMaxLevels * 63 + TT - 1) / TT;
+    float kv[kSlots];
+    cplx<float> bv[kSlots];
+    int lv[kSlots], pv[kSlots];
+#pragma unroll
+    for (int sl = 0; sl < kSlots; sl++) {
+      const int P = tid + sl * TT;
+      int k = 0;
+      for (int q = 1; q < a.nl; q++) k = P >= a.poff[q] ? q : k;
+      k = __builtin_amdgcn_readfirstlane(k);
+      const Grid<float> &g = a.g[k];
+      const int nn = g.n0 * g.n1;
+      const int p0 = P - a.poff[k], p = p0 < nn ? p0 : nn - 1;
+      lv[sl] = P < a.poff[a.nl] && p0 < nn ? k : -1;
+      pv[sl] = p;
+      kv[sl] = g.k2[p];
+      bv[sl] = b0[k == 0 ? p : 0];
+    }
+#pragma unroll
+    for (int sl = 0; sl < kSlots; sl++) {
+      const int k = lv[sl];
+      if (k < 0) continue;
+      const int kk = __builtin_amdgcn_readfirstlane(k);
+      const Grid<float> &g = a.g[kk];
+      const int p = pv[sl], j = (int)(((float)p + 0.5f) * (1.0f / (float)g.n0)), i = p - j * g.n0;
+      const int P = a.noff[kk] + p;
+      S.k[P] = kv[sl];
+      if (kk == 0) S.b[P] = (i >= 1 && i <= g.n0 - 2 && j >= 1 && j <= g.n1 - 2) ? bv[sl] : zero_c<float>();
+    }
+  }
+  __syncthreads();
+  {
+    // the first level's zero-guess red relaxation t = w b / D (0 elsewhere)
+    const Grid<float> &g = a.g[0];
+    const int n0 = g.n0, nn = n0 * g.n1;
+    const float inv0 = 1.0f / (float)n0;
+    for (int p = tid; p < nn; p += TT) {
+      const int j = (int)(((float)p + 0.5f) * inv0), i = p - j * n0;
+      const bool in = i >= 1 && i <= n0 - 2 && j >= 1 && j <= g.n1 - 2;
+      S.t[p] = (in && ((i + j) & 1) == 0) ? om * (S.b[p] * dinv(0, i, j, p)) : zero_c<float>();
+    }
+  }
+  __syncthreads();
+
+  // down: black relaxation, red residual, restriction (with the next level's
+  // zero-guess red relaxation), as in k_tail
+  for (int k = 0; k < last; k++) {
+    const Grid<float> &g = a.g[k];
+    const int n0 = g.n0, n1 = g.n1, no = a.noff[k], wo = a.woff[k];
+    const int H = (n0 + 1) >> 1, np = n1 * H;
+    const float invH = 1.0f / (float)H;
+    const cplx<float> *xm = S.xm + wo, *xp = S.xp + wo, *ym = S.ym + wo, *yp = S.yp + wo;
+    cplx<float> *b = S.b + no, *t = S.t + no, *w = S.w + no;
+    for (int q = tid; q < np; q += TT) {
+      const int j = (int)(((float)q + 0.5f) * invH), i = 2 * (q - j * H) + ((j + 1) & 1);  // black
+      if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
+        const int p = j * n0 + i;
+        const cplx<float> tb = b[p] + (xm[i] * t[p - 1] + xp[i] * t[p + 1] + ym[j] * t[p - n0] + yp[j] * t[p + n0]);
+        t[p] = om * (tb * dinv(k, i, j, p));
+        w[p] = om1 * tb;
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < np; q += TT) {
+      const int j = (int)(((float)q + 0.5f) * invH), i = 2 * (q - j * H) + (j & 1);  // red
+      if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
+        const int p = j * n0 + i;
+        w[p] = om1 * b[p] + (xm[i] * t[p - 1] + xp[i] * t[p + 1] + ym[j] * t[p - n0] + yp[j] * t[p + n0]);
+      }
+    }
+    __syncthreads();
+    const Grid<float> &gc = a.g[k + 1];
+    const int c0 = gc.n0, nc = c0 * gc.n1, nco = a.noff[k + 1];
+    const float inv0 = 1.0f / (float)c0;
+    for (int q = tid; q < nc; q += TT) {
+      const int J = (int)(((float)q + 0.5f) * inv0), I = q - J * c0;
+      cplx<float> acc = zero_c<float>(), tv = zero_c<float>();
+      if (I >= 1 && I <= c0 - 2 && J >= 1 && J <= gc.n1 - 2) {
+        const cplx<float> *r0 = w + (2 * J) * n0 + 2 * I;
+        acc = 0.25f * r0[0] + 0.125f * (r0[-1] + r0[1] + r0[-n0] + r0[n0]) +
+              0.0625f * (r0[-n0 - 1] + r0[-n0 + 1] + r0[n0 - 1] + r0[n0 + 1]);
+        if (((I + J) & 1) == 0) tv = om * (acc * dinv(k + 1, I, J, q));
+      }
+      S.b[nco + q] = acc;
+      S.t[nco + q] = tv;
+    }
+    __syncthreads();
+  }
+
+  // dense solve on the coarsest level (inverse from memory); boundary zeros
+  {
+    const Grid<float> &g = a.g[last];
+    const int nn = g.n0 * g.n1, no = a.noff[last];
+    const float inv0 = 1.0f / (float)g.n0;
+    for (int p = tid; p < nn; p += TT) {
+      const int j = (int)(((float)p + 0.5f) * inv0), i = p - j * g.n0;
+      if (i == 0 || i == g.n0 - 1 || j == 0 || j == g.n1 - 1) S.w[no + p] = zero_c<float>();
+    }
+    tail_dense(a.nunk, a.tpr, a.minvT, S.b + no, S.w + no, g.n0);
+    __syncthreads();
+  }
+
+  // up: prolongation + correction, then the red-black post-sweep, as in k_tail
+  for (int k = last - 1; k >= 0; k--) {
+    const Grid<float> &g = a.g[k];
+    const int n0 = g.n0, n1 = g.n1, no = a.noff[k], wo = a.woff[k];
+    const int H = (n0 + 1) >> 1, np = n1 * H;
+    const float invH = 1.0f / (float)H;
+    const int c0 = a.g[k + 1].n0;
+    const cplx<float> *xm = S.xm + wo, *xp = S.xp + wo, *ym = S.ym + wo, *yp = S.yp + wo;
+    const cplx<float> *b = S.b + no, *t = S.t + no, *e = S.w + a.noff[k + 1];
+    cplx<float> *w = S.w + no;
+    for (int q = tid; q < np; q += TT) {
+      const int j = (int)(((float)q + 0.5f) * invH), i0 = 2 * (q - j * H);
+      const bool yin = j >= 1 && j <= n1 - 2;
+      const cplx<float> *e0 = e + (j >> 1) * c0 + (i0 >> 1);
+      cplx<float> pa = zero_c<float>(), pb = zero_c<float>();
+      if (yin) {
+        if ((j & 1) == 0) {
+          pa = e0[0];
+          pb = 0.5f * (e0[0] + e0[1]);
+        } else {
+          pa = 0.5f * (e0[0] + e0[c0]);
+          pb = 0.25f * (e0[0] + e0[1] + e0[c0] + e0[c0 + 1]);
+        }
+      }
+      const int p = j * n0 + i0;
+      w[p] = (yin && i0 >= 1 && i0 <= n0 - 2) ? t[p] + pa : zero_c<float>();
+      if (i0 + 1 < n0) w[p + 1] = (yin && i0 + 1 <= n0 - 2) ? t[p + 1] + pb : zero_c<float>();
+    }
+    __syncthreads();
+    for (int colour = 0; colour < 2; colour++) {
+      for (int q = tid; q < np; q += TT) {
+        const int j = (int)(((float)q + 0.5f) * invH), h2 = 2 * (q - j * H);
+        const int i = h2 + ((j + colour) & 1);
+        const int p = j * n0 + i;
+        if (i >= 1 && i <= n0 - 2 && j >= 1 && j <= n1 - 2) {
+          const cplx<float> o = xm[i] * w[p - 1] + xp[i] * w[p + 1] + ym[j] * w[p - n0] + yp[j] * w[p + n0];
+          w[p] = om1 * w[p] + om * ((b[p] + o) * dinv(k, i, j, p));
+        }
+        if (k == 0 && colour == 1) {
+          const int pp = j * n0 + h2;
+          u0[pp] = w[pp];
+          if (h2 + 1 < n0) u0[pp + 1] = w[pp + 1];
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 }  // namespace
 
 // The tile height of the fused kernels is a launch parameter chosen by the
@@ -795,6 +993,14 @@ void launch_up_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, 
 
 template <typename R>
 void launch_tail(const TailArgs<R> &a, hipStream_t s, const RhsSet &rs) {
+  if constexpr (sizeof(R) == 4) {
+    // beyond k_tail's capacity (or a level wider than one wave): the wide tail
+    if (a.noff[a.nl] > kTailCap || a.g[0].n0 > 64 || a.g[0].n1 > 64) {
+      if (multi_rhs(rs)) launch_k((k_tail_wide<true>), dim3(1, rs.count), dim3(TT), 0, s, a, rs);
+      else launch_k((k_tail_wide<false>), dim3(1, 1), dim3(TT), 0, s, a, rs);
+      return;
+    }
+  }
   if (multi_rhs(rs)) launch_k((k_tail<R, true>), dim3(1, rs.count), dim3(TT), 0, s, a, rs);
   else launch_k((k_tail<R, false>), dim3(1, 1), dim3(TT), 0, s, a, rs);
 }

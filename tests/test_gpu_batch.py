@@ -106,6 +106,33 @@ def test_multi_rhs_groups_equal_single_solves(dt):
     assert rc == -2 and "nrhs = 8" in E.lib().ecs_last_error(S._h).decode()
 
 
+def test_batch_wide_tail_equals_single_solves():
+    """FP32 cycles with the wide tail (a 65^2 level and below in one
+    workgroup): the batched solve of three right-hand sides together equals
+    the single solves bit for bit, and the residuals meet the tolerance by the
+    oracle's operator."""
+    import torch
+    w = W.coulomb(E=2.5, n=257)
+    rng = np.random.default_rng(91)
+    rhs = [W.random_complex(w.shape, rng) for _ in range(3)]
+    kr = E.Krylov(method="bicgstab", rtol=1e-8, maxit=5000)
+    S = gpu_for(w, "f32", krylov=kr)
+    S.set_tuning(tail_nodes=65)
+    B = torch.stack([to_gpu(b) for b in rhs])
+    xs, stats = E.batch_solve([S], [B], kr)
+    torch.cuda.synchronize()
+    assert stats[0]["status"] == 0, stats
+    P = oracle_for(w)
+    for r, b in enumerate(rhs):
+        x1, _ = S.solve(to_gpu(b), krylov=kr)
+        torch.cuda.synchronize()
+        assert torch.equal(xs[0][r], x1), r
+        res = np.linalg.norm((b - P.apply(to_np(xs[0][r])))[1:-1, 1:-1]) / np.linalg.norm(b[1:-1, 1:-1])
+        assert res <= 1.05e-8, (r, res)
+    with pytest.raises(E.EcsError):
+        S.set_tuning(tail_nodes=66)
+
+
 def test_batch_edge_cases():
     """A zero right-hand side yields x = 0; an empty system list is a no-op."""
     import torch

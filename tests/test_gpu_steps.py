@@ -130,12 +130,17 @@ def test_vcycle_tail_schedules(dt):
     """The single-workgroup tail over every admissible range of coarse levels:
     the whole cycle (33^2 grid), the dense solve alone, and coarsest grids of
     9, 4, 225 and 49 unknowns (64, 64, 4 and 16 threads per row of the dense
-    solve), against the oracle's cycle."""
+    solve), against the oracle's cycle.  FP32 cycles also run the wide tail:
+    from a 65^2 level, the whole cycle of a 65^2 grid, and from a ragged 49^2
+    level."""
     rng = np.random.default_rng(12)
     runs = [(W.coulomb(E=1.0, n=33), (33, 17, 9, 5, 3)),
             (ragged_workload(), (3, 4, 7, 13, 25)),
             (ragged_workload(n=129, coarsest=17), (17, 33)),
             (W.coulomb(E=2.0, n=129, coarsest=9), (9, 17, 33))]
+    if dt == "f32":
+        runs += [(W.coulomb(E=2.0, n=257, coarsest=9), (65,)), (W.coulomb(E=1.0, n=65, coarsest=9), (65,)),
+                 (ragged_workload(n=193, coarsest=7), (49, 65))]
     for w, tails in runs:
         P = oracle_for(w)
         S = gpu_for(w, dt)
