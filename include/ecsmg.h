@@ -60,7 +60,7 @@ enum { ECS_SMOOTH_JACOBI = 0, ECS_SMOOTH_RBGS = 1 };
 enum { ECS_KRYLOV_GMRES = 0, ECS_KRYLOV_FGMRES = 1, ECS_KRYLOV_BICGSTAB = 2 };
 enum { ECS_OP_A = 0, ECS_OP_AT = 1, ECS_OP_M = 2 };
 /* Gram-Schmidt of the GMRES / FGMRES Arnoldi step (see ecs_solve_desc) */
-enum { ECS_ORTH_CGS2_SELECTIVE = 0, ECS_ORTH_CGS2 = 1, ECS_ORTH_CGS1 = 2 };
+enum { ECS_ORTH_DCGS2 = 0, ECS_ORTH_CGS2 = 1, ECS_ORTH_CGS1 = 2, ECS_ORTH_CGS2_SELECTIVE = 3 };
 
 /* Preconditioner M and the multigrid cycle that approximately inverts it
  * (Sec. 4.2, Algorithm 1; operators of Sec. 5):
@@ -104,10 +104,16 @@ typedef struct {
  * history: optional host array of history_len doubles receiving the
  * estimated relative residual after each iteration.
  * orth: the Arnoldi step's Gram-Schmidt (GMRES, FGMRES; Hermitian inner
- * products): classical Gram-Schmidt with a second pass -- always
+ * products): classical Gram-Schmidt with a second pass -- delayed by one step
+ * (ECS_ORTH_DCGS2, the default 0: the newest basis vector is
+ * reorthogonalised in the same two passes over the basis that orthogonalise
+ * the next direction, so every vector gets two passes for the memory traffic
+ * of one; the rotated Hessenberg column is not corrected for the delayed
+ * pass, a change of the size of the first pass's rounding error, and the
+ * preconditioner sees the vector before its second pass), always
  * (ECS_ORTH_CGS2), when the first pass leaves less than 1/sqrt(2) of the new
- * vector's norm (ECS_ORTH_CGS2_SELECTIVE, the default 0: the criterion of
- * Daniel, Gragg, Kaufman and Stewart), or never (ECS_ORTH_CGS1).
+ * vector's norm (ECS_ORTH_CGS2_SELECTIVE: the criterion of Daniel, Gragg,
+ * Kaufman and Stewart), or never (ECS_ORTH_CGS1).
  * nrhs: Bi-CGSTAB right-hand sides of one system at once in ecs_batch_solve
  * (1..8; 0: up to 8), and in ecs_workspace_size the batched solve's storage
  * for that many (0 there sizes a single solve only); other calls ignore it. */

@@ -31,7 +31,7 @@ DIRICHLET, ECS = 0, 1
 PREC = {"none": 0, "laplace": 1, "csl": 2, "csg": 3, "qd": 4}
 SMOOTHER = {"jacobi": 0, "rbgs": 1}
 KRYLOV = {"gmres": 0, "fgmres": 1, "bicgstab": 2}
-ORTH = {"cgs2_selective": 0, "cgs2": 1, "cgs1": 2}
+ORTH = {"dcgs2": 0, "cgs2": 1, "cgs1": 2, "cgs2_selective": 3}
 OP = {"A": 0, "AT": 1, "M": 2}
 STATUS = {0: "ok", 1: "not_converged", -1: "einval", -2: "enomem", -3: "edevice", -4: "ebreakdown", -5: "estate"}
 TIMER = {"smooth": 0, "mdot": 1, "apply_A": 2, "coarse": 3, "mupdate": 4, "restrict": 5, "prolong": 6, "down": 7,
@@ -219,7 +219,7 @@ class Krylov:
     rtol: float = 1e-8
     maxit: int = 2000
     inner: int = 0             # nested Bi-CGSTAB iterations (cycle dtype) per FGMRES step
-    orth: str = "cgs2_selective"   # Arnoldi Gram-Schmidt: cgs2_selective | cgs2 | cgs1
+    orth: str = "dcgs2"        # Arnoldi Gram-Schmidt: dcgs2 | cgs2_selective | cgs2 | cgs1
     nrhs: int = 0              # Bi-CGSTAB workspace for the batched solve: right-hand sides at once (0: none)
 
     def to_c(self, x_is_guess=False, history=None):

@@ -163,8 +163,8 @@ def adjoint(args):
     x = W.real_nodes(n, -10.0, 10.0)
     inner = np.flatnonzero((np.abs(x) <= 8))
     # 50 random interior nodes (|x|, |y| <= 8) at eps = 1e-6; and 5 nodes
-    # among those whose gradient is within 1e-2 of the largest at eps = 1e-6
-    # and 1e-3.  With gradients ~1e-7 and the loss known to ~1e-15 from
+    # among those whose gradient is at least 1e-2 times the largest, at
+    # eps = 1e-6 and 1e-3.  With gradients ~1e-7 and the loss known to ~1e-15 from
     # 1e-12 solves, eps = 1e-6 leaves ~1e-3 relative noise in the quotient;
     # eps = 1e-3 brings it below 1e-5 while the truncation error stays
     # O((eps / k^2)^2) ~ 1e-8
@@ -206,9 +206,18 @@ def cube(args):
     f = torch.from_numpy(w.rhs[0]).to("cuda")
     S.solve(f)
     (x, st), secs = _timed(lambda: S.solve(f))
+    # the same solve with the other Arnoldi variants
+    others = {}
+    for orth in ("cgs2_selective", "cgs1"):
+        k1 = Krylov(method="fgmres", restart=30, rtol=1e-8, maxit=5000, orth=orth)
+        S.solve(f, krylov=k1)
+        (_, st1), secs1 = _timed(lambda: S.solve(f, krylov=k1))
+        others[orth] = dict(seconds=round(secs1, 4), iterations=st1["iterations"],
+                            second_passes=st1["reorthogonalisations"], rel_residual=st1["rel_residual"])
     _emit(dict(metric="3D 129^3 ECS Helmholtz solve to 1e-8 (k = 12, QD, V(1,1) RB-GS, FGMRES(30))", unit="s",
                value=round(secs, 4), higher_is_better=False, iterations=st["iterations"], vcycles=st["vcycles"],
-               rel_residual=st["rel_residual"], status=st["status"], dtype="f64", data="synthetic"))
+               second_passes=st["reorthogonalisations"], rel_residual=st["rel_residual"], status=st["status"],
+               other_arnoldi=others, dtype="f64", data="synthetic"))
 
 
 def coulomb513(args):
@@ -332,15 +341,20 @@ def coupled(args):
     b = torch.from_numpy(rhs).to("cuda")
     outer = Krylov(method="fgmres", restart=30, rtol=1e-8, maxit=500)
     inner = Krylov(method="bicgstab", rtol=1e-3, maxit=100)
+    outer_sel = Krylov(method="fgmres", restart=30, rtol=1e-8, maxit=500, orth="cgs2_selective")
+    outer_cgs1 = Krylov(method="fgmres", restart=30, rtol=1e-8, maxit=500, orth="cgs1")
     rows = {}
-    for mode in ("batched_bicgstab_1e-3", "one_cycle_per_block"):
-        only = mode == "one_cycle_per_block"
-        coupled_solve(solvers, kc, b, outer=outer, inner=inner, cycles_only=only)
-        (x, st), secs = _timed(lambda: coupled_solve(solvers, kc, b, outer=outer, inner=inner, cycles_only=only))
+    for mode in ("batched_bicgstab_1e-3", "one_cycle_per_block", "one_cycle_per_block_cgs2_selective",
+                 "one_cycle_per_block_cgs1"):
+        only = mode.startswith("one_cycle_per_block")
+        ko = outer_cgs1 if mode.endswith("cgs1") else outer_sel if mode.endswith("selective") else outer
+        coupled_solve(solvers, kc, b, outer=ko, inner=inner, cycles_only=only)
+        (x, st), secs = _timed(lambda: coupled_solve(solvers, kc, b, outer=ko, inner=inner, cycles_only=only))
         rows[mode] = dict(seconds=round(secs, 4), outer_iterations=st["iterations"],
                           inner_iterations=st["inner_iterations"], vcycles=st["vcycles"],
-                          rel_residual=st["rel_residual"], status=st["status_name"])
-    best = min(r["seconds"] for r in rows.values())
+                          second_passes=st.get("reorthogonalisations"), rel_residual=st["rel_residual"],
+                          status=st["status_name"])
+    best = min(r["seconds"] for m, r in rows.items() if not m.endswith(("cgs1", "selective")))
     _emit(dict(metric=f"coupled block system, {nb} channels on {n}^2, FGMRES(30) to 1e-8", unit="s", value=best,
                higher_is_better=False, runs=rows, dtype="f64 outer / f32 cycles", data="synthetic"))
 

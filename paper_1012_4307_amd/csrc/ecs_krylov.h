@@ -28,6 +28,7 @@ struct GmresScalars {
   cplx<double> cs[kMaxRestart], sn[kMaxRestart];
   cplx<double> y[kMaxRestart];
   cplx<double> h2[kMaxRestart + 1];                    // second Gram-Schmidt pass
+  cplx<double> d2[2 * kMaxRestart + 2];                // products of the delayed second pass
   cplx<double> H[(kMaxRestart + 1) * kMaxRestart];     // column-major Hessenberg, ld = m+1
 };
 
@@ -55,6 +56,14 @@ void launch_reduce_cols(const cplx<double> *partials, int64_t n, int ncols, cplx
 // w <- w - sum_c V_c h_c ; partials[block] = block's share of ||w||^2
 void launch_mupdate_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w,
                             int64_t n, cplx<double> *partials, hipStream_t s, const int *gate = nullptr);
+// delayed second pass (DCGS2): partials of [V_0..V_{ncols-1}, x]^H x and
+// [V_0..V_{ncols-1}, x]^H w (2 ncols + 2 columns, layout in kernels_blas.hip)
+void launch_mdot2_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *x,
+                          const cplx<double> *w, int64_t n, cplx<double> *partials, hipStream_t s);
+// x's second pass and w's first from the reduced products d; partials of
+// ||w||^2; hcol[0..ncols] = w's Hessenberg column
+void launch_mupdate2_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *d, cplx<double> *x,
+                             cplx<double> *w, int64_t n, cplx<double> *partials, cplx<double> *hcol, hipStream_t s);
 // S->reorth = (||w'||^2 = S->nrm2 < eta2 ||w||^2 = H(j+1, j)); counts it
 void launch_reorth_gate(GmresScalars *S, int j, int m, double eta2, hipStream_t s);
 template <typename R>

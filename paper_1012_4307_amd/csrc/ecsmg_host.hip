@@ -315,7 +315,7 @@ size_t plan_layout(ecs_ctx *C, Carver &cv) {
   C->spack64 = cv.take<cplx<double>>(kSchedPack);
   if (f32) C->spack32 = cv.take<cplx<float>>(kSchedPack);
   C->sprog = cv.take<uint32_t>(4 * kSchedProgCap);
-  C->partials = cv.take<cplx<double>>((size_t)kRedBlocks * (kMaxRestart + 2));
+  C->partials = cv.take<cplx<double>>((size_t)kRedBlocks * (2 * kMaxRestart + 2));
   C->dscal = cv.take<double>(kRedBlocks + 8);
   C->gs = cv.take<GmresScalars>(1);
   C->bs = cv.take<BicgScalars>(kMaxRhs);  // one per right-hand side slot of the batched solve
@@ -1341,9 +1341,34 @@ void inner_bicgstab(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *v, cplx
 // after the first pass (ECS_ORTH_CGS2_SELECTIVE, decided on the device: the
 // gated kernels of the second pass exit at once otherwise).  w is the basis
 // column V_{j+1}, so one more multi-dot column gives ||w||^2.
-void orthogonalise(ecs_ctx *C, const cplx<double> *V, int64_t ld, int j, cplx<double> *w, int64_t n,
+// ECS_ORTH_DCGS2 delays the second pass by one step (Gram-Schmidt with
+// delayed reorthogonalisation): v_j enters step j after one pass and its
+// normalisation, and its second pass shares the multi-dot and the update pass
+// with w's first, so the two passes cost what one does.  The corrections
+// H(0..j-1, j-1) += h_{j,j-1} s and h_{j,j-1} *= nu of the column already
+// rotated are left out; they are of the size of the first pass's rounding
+// error (|s| = O(eps ||w|| / ||w'||)), so the least-squares problem and its
+// residual estimate change only at that level (the stopping test and every
+// restart use the true residual).  z_j = M^{-1} v_j is taken before v_j's
+// second pass: FGMRES accepts any z_j, and for GMRES the mismatch is of the
+// same size.
+void orthogonalise(ecs_ctx *C, cplx<double> *V, int64_t ld, int j, cplx<double> *w, int64_t n,
                    cplx<double> *partials, GmresScalars *S, int m, int orth, hipStream_t s) {
   cplx<double> *h = S->H + (int64_t)j * (m + 1);
+  if (orth == ECS_ORTH_DCGS2) {
+    cplx<double> *vj = V + (int64_t)j * ld;
+    {
+      TimedScope ts(C, kTMdot, (double)n * 16 * (j + 2));  // read v_0..v_{j-1}, v_j, w
+      launch_mdot2_partial(V, ld, j, vj, w, n, partials, s);
+    }
+    launch_reduce_cols(partials, n, 2 * j + 2, S->d2, s);
+    {
+      TimedScope ts(C, kTMupdate, (double)n * 16 * (j + (j > 0 ? 4 : 3)));  // read v_0..v_j, w; write v_j, w
+      launch_mupdate2_partial(V, ld, j, S->d2, vj, w, n, partials, h, s);
+    }
+    launch_reduce_cols(partials, n, 1, &S->nrm2, s);
+    return;
+  }
   const bool sel = orth == ECS_ORTH_CGS2_SELECTIVE;
   const int nc = j + 1 + (sel ? 1 : 0);
   {
@@ -1370,10 +1395,12 @@ void orthogonalise(ecs_ctx *C, const cplx<double> *V, int64_t ld, int j, cplx<do
 }
 
 // second Gram-Schmidt passes of a solve: counted on the device when selective
-// (read through the context's pinned buffer on its stream)
-int64_t reorth_passes(ecs_ctx *C, GmresScalars *S, int orth, int64_t iterations) {
+// (read through the context's pinned buffer on its stream); with the delayed
+// pass every step but the first of a cycle reorthogonalises its basis vector
+int64_t reorth_passes(ecs_ctx *C, GmresScalars *S, int orth, int64_t iterations, int64_t later_steps) {
   if (orth == ECS_ORTH_CGS1) return 0;
   if (orth == ECS_ORTH_CGS2) return iterations;
+  if (orth == ECS_ORTH_DCGS2) return later_steps;
   int cnt = -1;
   if (read_bytes(C, &S->reorth_count, sizeof(int))) std::memcpy(&cnt, C->pinned, sizeof(int));
   return cnt;
@@ -1412,6 +1439,7 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
   }
   if (!d->x_is_guess) launch_zero<double>(x, n, s);
   int it = 0;
+  int64_t later_steps = 0;
   ecs_status status = ECS_NOT_CONVERGED;
   for (;;) {
     {
@@ -1444,6 +1472,7 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
         launch_apply<double, RZ, double>(grid_A(C), zj, w, s);
       }
       orthogonalise(C, K.V, ld, j, w, n, C->partials, S, m, d->orth, s);
+      later_steps += j > 0;
       launch_gmres_givens(S, j, m, s);
       launch_scale_dev(w, n, &S->inv, s);
       it++;
@@ -1475,7 +1504,7 @@ ecs_status gmres(ecs_ctx *C, const ecs_solve_desc *d, const KrylovBufs &K, const
     st->restarts++;
   }
   st->iterations = it;
-  st->reorthogonalisations = reorth_passes(C, S, d->orth, it);
+  st->reorthogonalisations = reorth_passes(C, S, d->orth, it, later_steps);
   if (d->inner > 0) {
     // the runs counted at their successors' starts, and the last run's flag
     int v[2] = {0, -1};
@@ -1917,7 +1946,7 @@ size_t plan_coupled(int nb, int64_t nn, int m, char *base, CoupledBufs *B) {
   B->V = cv.take<cplx<double>>((size_t)(m + 1) * B->ld);
   B->Z = cv.take<cplx<double>>((size_t)m * B->ld);
   B->S = cv.take<GmresScalars>(1);
-  B->partials = cv.take<cplx<double>>((size_t)kRedBlocks * (kMaxRestart + 2));
+  B->partials = cv.take<cplx<double>>((size_t)kRedBlocks * (2 * kMaxRestart + 2));
   return cv.off;
 }
 
@@ -1944,7 +1973,7 @@ ecs_status coupled_check(int nb, ecs_ctx *const *ctx, const ecs_solve_desc *oute
   if (outer->krylov != ECS_KRYLOV_FGMRES) return fail(ctx[0], ECS_EINVAL, "the outer method is FGMRES");
   if (outer->restart < 1 || outer->restart > kMaxRestart) return fail(ctx[0], ECS_EINVAL, "restart must be in [1, 64]");
   if (!(outer->rtol > 0) || outer->maxit < 0) return fail(ctx[0], ECS_EINVAL, "rtol must be > 0 and maxit >= 0");
-  if (outer->orth < ECS_ORTH_CGS2_SELECTIVE || outer->orth > ECS_ORTH_CGS1)
+  if (outer->orth < ECS_ORTH_DCGS2 || outer->orth > ECS_ORTH_CGS2_SELECTIVE)
     return fail(ctx[0], ECS_EINVAL, "unknown orthogonalisation");
   if (inner && (inner->krylov != ECS_KRYLOV_BICGSTAB || !(inner->rtol > 0) || inner->maxit < 1))
     return fail(ctx[0], ECS_EINVAL, "the block solves use Bi-CGSTAB with rtol > 0, maxit >= 1");
@@ -1983,6 +2012,7 @@ ecs_status coupled_fgmres(int nb, ecs_ctx *const *ctx, const double *k2c, const 
   std::vector<int> ones(nb, 1);
   std::vector<const ecs_solve_desc *> inner_descs(nb, inner);
   int it = 0;
+  int64_t later_steps = 0;
   ecs_status status = ECS_NOT_CONVERGED;
   for (;;) {
     coupled_apply(nb, ctx, k2c, x, B.V, B.bz, s);  // r = b - A x
@@ -2033,6 +2063,7 @@ ecs_status coupled_fgmres(int nb, ecs_ctx *const *ctx, const double *k2c, const 
       }
       coupled_apply(nb, ctx, k2c, zj, w, nullptr, s);
       orthogonalise(C, B.V, ld, j, w, N, B.partials, S, m, d->orth, s);
+      later_steps += j > 0;
       launch_gmres_givens(S, j, m, s);
       launch_scale_dev(w, N, &S->inv, s);
       it++;
@@ -2055,7 +2086,7 @@ ecs_status coupled_fgmres(int nb, ecs_ctx *const *ctx, const double *k2c, const 
     st->restarts++;
   }
   st->iterations = it;
-  st->reorthogonalisations = reorth_passes(C, S, d->orth, it);
+  st->reorthogonalisations = reorth_passes(C, S, d->orth, it, later_steps);
   HIP_OK(hipStreamSynchronize(s));
   HIP_OK(hipGetLastError());
   return status;
@@ -2082,7 +2113,7 @@ ecs_status solve_impl(ecs_ctx *C, const ecs_solve_desc *d, const cplx<double> *b
   if (d->restart < 1 || d->restart > kMaxRestart) return fail(C, ECS_EINVAL, "restart must be in [1, 64]");
   if (!(d->rtol > 0) || d->maxit < 0) return fail(C, ECS_EINVAL, "rtol must be > 0 and maxit >= 0");
   if (d->krylov < 0 || d->krylov > 2) return fail(C, ECS_EINVAL, "unknown Krylov method");
-  if (d->orth < ECS_ORTH_CGS2_SELECTIVE || d->orth > ECS_ORTH_CGS1)
+  if (d->orth < ECS_ORTH_DCGS2 || d->orth > ECS_ORTH_CGS2_SELECTIVE)
     return fail(C, ECS_EINVAL, "unknown orthogonalisation");
   if (d->inner > 0 && d->krylov != ECS_KRYLOV_FGMRES) return fail(C, ECS_EINVAL, "inner iterations need FGMRES");
   if (d->inner > 0 && C->prec.kind == ECS_PREC_NONE) return fail(C, ECS_EINVAL, "inner iterations need a cycle");

@@ -140,6 +140,178 @@ __global__ __launch_bounds__(BS) void k_mupdate(const cplx<double> *__restrict__
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// ------------------------------------- delayed second pass (DCGS2)
+// The newest basis vector x = v_j has had one Gram-Schmidt pass (and its
+// normalisation) when the next direction w = A z_j arrives; its second pass
+// is taken together with w's first: one multi-dot of the columns
+// V_0..V_{ncols-1} and x itself against both x and w, then one update pass
+// over the same columns for both vectors.
+//   partial columns c < ncols:        sum conj(V_c) x      (s_c)
+//                   c = ncols:        sum conj(x) x        (alpha)
+//                   ncols + 1 + c:    sum conj(V_c) w      (g_c)
+//                   2 ncols + 1:      sum conj(x) w        (beta)
+// Same tiling and fixed summation order as the one-vector multi-dot.
+__global__ __launch_bounds__(BS) void k_mdot2(const cplx<double> *__restrict__ V, int64_t ldv, int ncols,
+                                              const cplx<double> *__restrict__ x, const cplx<double> *__restrict__ w,
+                                              int64_t n, cplx<double> *partials) {
+  constexpr int LDA = 2 * kMaxRestart + 2;
+  __shared__ cplx<double> acc[BS / 64][LDA];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nout = 2 * ncols + 2;
+  for (int c = threadIdx.x; c < (BS / 64) * LDA; c += BS) acc[c / LDA][c % LDA] = mk<double>(0, 0);
+  __syncthreads();
+  const int64_t tile = (int64_t)BS * EPT;
+  for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
+    cplx<double> xv[EPT], wv[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const int64_t p = base + e * BS + threadIdx.x;
+      xv[e] = p < n ? x[p] : mk<double>(0, 0);
+      wv[e] = p < n ? w[p] : mk<double>(0, 0);
+    }
+    for (int c0 = 0; c0 < ncols; c0 += CG) {
+      cplx<double> sx[CG], sw[CG];
+#pragma unroll
+      for (int g = 0; g < CG; g++) {
+        sx[g] = mk<double>(0, 0);
+        sw[g] = mk<double>(0, 0);
+        if (c0 + g < ncols) {
+          const cplx<double> *vc = V + (int64_t)(c0 + g) * ldv;
+#pragma unroll
+          for (int e = 0; e < EPT; e++) {
+            const int64_t p = base + e * BS + threadIdx.x;
+            if (p < n) {
+              const cplx<double> cv = conjg(vc[p]);
+              sx[g] = sx[g] + cv * xv[e];
+              sw[g] = sw[g] + cv * wv[e];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < CG; g++) {
+        if (c0 + g < ncols) {
+          double xr = wave_sum(sx[g].re), xi = wave_sum(sx[g].im);
+          double wr = wave_sum(sw[g].re), wi = wave_sum(sw[g].im);
+          if (lane == 0) {
+            acc[wid][c0 + g] = acc[wid][c0 + g] + mk<double>(xr, xi);
+            acc[wid][ncols + 1 + c0 + g] = acc[wid][ncols + 1 + c0 + g] + mk<double>(wr, wi);
+          }
+        }
+      }
+    }
+    // the vector x as a column: alpha = (x, x), beta = (x, w)
+    cplx<double> sa = mk<double>(0, 0), sb = mk<double>(0, 0);
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      sa = sa + conjg(xv[e]) * xv[e];
+      sb = sb + conjg(xv[e]) * wv[e];
+    }
+    double ar = wave_sum(sa.re), br = wave_sum(sb.re), bi = wave_sum(sb.im);
+    if (lane == 0) {
+      acc[wid][ncols] = acc[wid][ncols] + mk<double>(ar, 0);
+      acc[wid][2 * ncols + 1] = acc[wid][2 * ncols + 1] + mk<double>(br, bi);
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < nout; c += BS) {
+    cplx<double> t = mk<double>(0, 0);
+    for (int q = 0; q < BS / 64; q++) t = t + acc[q][c];
+    partials[(int64_t)c * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Coefficients of the delayed pass from the reduced products d (layout of
+// k_mdot2) -- every block derives the same values in the same order:
+//   nu = sqrt(alpha - sum |s_c|^2)     norm of x after its second pass
+//   h  = (beta - sum conj(s_c) g_c) / nu = (x after the pass, w)
+// With no earlier columns (the first step of a cycle, x = r / ||r|| exactly)
+// nu = 1.  Should alpha - sum |s|^2 not be positive (x numerically inside the
+// span of the basis) the second pass of x is skipped (s = 0, nu = 1).
+// Coefficients stored in k[0] = (1 / nu, pass ? 1 : 0), k[1] = h.
+__device__ inline void dcgs2_coef(const cplx<double> *d, int ncols, cplx<double> *k) {
+  double ss = 0;
+  cplx<double> sg = mk<double>(0, 0);
+  for (int c = 0; c < ncols; c++) {
+    ss += abs2(d[c]);
+    sg = sg + conjg(d[c]) * d[ncols + 1 + c];
+  }
+  const double nu2 = d[ncols].re - ss;
+  const bool pass = ncols > 0 && nu2 > 0 && !isinf(nu2);
+  const double inv_nu = pass ? 1.0 / sqrt(nu2) : 1.0;
+  k[0] = mk<double>(inv_nu, pass ? 1.0 : 0.0);
+  k[1] = pass ? inv_nu * (d[2 * ncols + 1] - sg) : d[2 * ncols + 1];
+}
+
+// The update pass of the delayed step (ncols columns before x):
+//   x <- (x - sum_c V_c s_c) / nu           (x's second pass; skipped for ncols = 0)
+//   w <- w - sum_c V_c g_c - h x            (w's first pass against V and the new x)
+// partials[block] = the block's share of ||w||^2; block 0 stores the
+// Hessenberg column H(0..ncols, j) = (g_0, ..., g_{ncols-1}, h).
+__global__ __launch_bounds__(BS) void k_mupdate2(const cplx<double> *__restrict__ V, int64_t ldv, int ncols,
+                                                 const cplx<double> *__restrict__ d, cplx<double> *__restrict__ x,
+                                                 cplx<double> *__restrict__ w, int64_t n, cplx<double> *partials,
+                                                 cplx<double> *hcol) {
+  __shared__ cplx<double> ss[kMaxRestart], gs[kMaxRestart];
+  __shared__ cplx<double> lds[BS / 64];
+  __shared__ cplx<double> kc[2];
+  for (int c = threadIdx.x; c < ncols; c += BS) {
+    ss[c] = d[c];
+    gs[c] = d[ncols + 1 + c];
+  }
+  if (threadIdx.x == 0) dcgs2_coef(d, ncols, kc);
+  __syncthreads();
+  const double inv_nu = kc[0].re;
+  const bool pass = kc[0].im != 0;
+  const cplx<double> hx = kc[1];
+  if (blockIdx.x == 0) {
+    if ((int)threadIdx.x < ncols) hcol[threadIdx.x] = gs[threadIdx.x];
+    else if ((int)threadIdx.x == ncols) hcol[ncols] = kc[1];
+  }
+  double nrm = 0;
+  const int64_t tile = (int64_t)BS * EPT;
+  for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
+    cplx<double> xv[EPT], wv[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const int64_t p = base + e * BS + threadIdx.x;
+      xv[e] = p < n ? x[p] : mk<double>(0, 0);
+      wv[e] = p < n ? w[p] : mk<double>(0, 0);
+    }
+    for (int c0 = 0; c0 < ncols; c0 += CG) {
+#pragma unroll
+      for (int g = 0; g < CG; g++) {
+        if (c0 + g < ncols) {
+          const cplx<double> *vc = V + (int64_t)(c0 + g) * ldv;
+          const cplx<double> sc = pass ? ss[c0 + g] : mk<double>(0, 0), gc = gs[c0 + g];
+#pragma unroll
+          for (int e = 0; e < EPT; e++) {
+            const int64_t p = base + e * BS + threadIdx.x;
+            if (p < n) {
+              const cplx<double> v = vc[p];
+              xv[e] = xv[e] - v * sc;
+              wv[e] = wv[e] - v * gc;
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const int64_t p = base + e * BS + threadIdx.x;
+      if (p < n) {
+        const cplx<double> xn = inv_nu * xv[e];
+        wv[e] = wv[e] - xn * hx;
+        if (pass) x[p] = xn;
+        w[p] = wv[e];
+        nrm += abs2(wv[e]);
+      }
+    }
+  }
+  cplx<double> s = block_sum(mk<double>(nrm, 0), lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
 template <typename R>
 __global__ __launch_bounds__(BS) void k_nrm2sq(const cplx<R> *__restrict__ x, int64_t n, cplx<double> *partials) {
   __shared__ cplx<double> lds[BS / 64];
@@ -572,6 +744,16 @@ void launch_reduce_cols(const cplx<double> *partials, int64_t n, int ncols, cplx
 void launch_mupdate_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *h, cplx<double> *w,
                             int64_t n, cplx<double> *partials, hipStream_t s, const int *gate) {
   launch_k(k_mupdate, dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, h, w, n, partials, gate);
+}
+
+void launch_mdot2_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *x,
+                          const cplx<double> *w, int64_t n, cplx<double> *partials, hipStream_t s) {
+  launch_k(k_mdot2, dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, x, w, n, partials);
+}
+
+void launch_mupdate2_partial(const cplx<double> *V, int64_t ldv, int ncols, const cplx<double> *d, cplx<double> *x,
+                             cplx<double> *w, int64_t n, cplx<double> *partials, cplx<double> *hcol, hipStream_t s) {
+  launch_k(k_mupdate2, dim3(red_blocks(n)), dim3(BS), 0, s, V, ldv, ncols, d, x, w, n, partials, hcol);
 }
 
 void launch_reorth_gate(GmresScalars *S, int j, int m, double eta2, hipStream_t s) {

@@ -55,19 +55,22 @@ def test_coupled_operator_w_symmetric():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("mode", ["batched", "cycles"])
+@pytest.mark.parametrize("mode", ["batched", "cycles", "cycles_dcgs2"])
 def test_coupled_solve_matches_dense(mode):
     """3 coupled channels on 33^2: the GPU solve at a tight tolerance against
-    the dense direct solution; a random right-hand side in every channel."""
+    the dense direct solution; a random right-hand side in every channel
+    (the outer Arnoldi with the selective or the delayed second pass)."""
     import paper_1012_4307_amd as E
     blocks, k2c, rhs = W.coupled_blocks(nb=3, n=33)
     rng = np.random.default_rng(8)
     b = np.stack([W.random_complex(blocks[0].shape, rng) for _ in range(3)])
     xd = oracle.coupled_solve_dense(_problems(blocks), k2c, b)
     Ss = [gpu_for(w, "f64") for w in blocks]
-    outer = E.Krylov(method="fgmres", restart=30, rtol=1e-11, maxit=400)
+    outer = E.Krylov(method="fgmres", restart=30, rtol=1e-11, maxit=400,
+                     orth="dcgs2" if mode.endswith("dcgs2") else "cgs2_selective")
     inner = E.Krylov(method="bicgstab", rtol=1e-4, maxit=200)
-    x, st = E.coupled_solve(Ss, to_gpu(k2c), to_gpu(b), outer=outer, inner=inner, cycles_only=(mode == "cycles"))
+    x, st = E.coupled_solve(Ss, to_gpu(k2c), to_gpu(b), outer=outer, inner=inner,
+                            cycles_only=mode.startswith("cycles"))
     print(mode, st)
     assert st["status"] == 0 and st["rel_residual"] <= 1e-11
     assert relerr(to_np(x), xd) < 1e-8
