@@ -358,6 +358,16 @@ def test_status_paths():
     with pytest.raises(E.EcsError) as ei:
         S.solve(to_gpu(w.rhs[0]), krylov=E.Krylov(method="gmres", restart=500))
     assert ei.value.status == -1
+    # an orthogonalisation code outside the enumeration is refused before any work
+    import ctypes
+    d = E.Krylov(method="fgmres").to_c()
+    b = to_gpu(w.rhs[0])
+    x = torch.zeros_like(b)
+    for bad_orth in (-1, 4):
+        d.orth = bad_orth
+        st = E.Stats()
+        assert E.lib().ecs_solve(S._h, ctypes.byref(d), E._ptr(b), E._ptr(x), ctypes.byref(st)) == -1
+    assert int(torch.count_nonzero(x)) == 0
 
 
 def test_adjoint_solve_and_gradient():
