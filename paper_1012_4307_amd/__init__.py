@@ -32,6 +32,16 @@ PREC = {"none": 0, "laplace": 1, "csl": 2, "csg": 3, "qd": 4}
 SMOOTHER = {"jacobi": 0, "rbgs": 1}
 KRYLOV = {"gmres": 0, "fgmres": 1, "bicgstab": 2}
 ORTH = {"dcgs2": 0, "cgs2": 1, "cgs1": 2, "cgs2_selective": 3}
+
+
+def _code(table, name, what):
+    """The ABI code of an option name; ValueError naming the choices otherwise."""
+    try:
+        return table[name]
+    except KeyError:
+        raise ValueError(f"unknown {what} {name!r}: one of {', '.join(sorted(table))}") from None
+
+
 OP = {"A": 0, "AT": 1, "M": 2}
 STATUS = {0: "ok", 1: "not_converged", -1: "einval", -2: "enomem", -3: "edevice", -4: "ebreakdown", -5: "estate"}
 TIMER = {"smooth": 0, "mdot": 1, "apply_A": 2, "coarse": 3, "mupdate": 4, "restrict": 5, "prolong": 6, "down": 7,
@@ -207,8 +217,9 @@ class Precond:
     vcycle_dtype: str = "f64"          # f64 | f32
 
     def to_c(self):
-        return PrecDesc(PREC[self.kind], self.beta1, self.beta2, self.theta_alpha, self.re_lambda0,
-                        SMOOTHER[self.smoother], self.omega, self.nu1, self.nu2, self.gamma_f, self.gamma_c,
+        return PrecDesc(_code(PREC, self.kind, "preconditioner kind"), self.beta1, self.beta2, self.theta_alpha,
+                        self.re_lambda0, _code(SMOOTHER, self.smoother, "smoother"), self.omega, self.nu1,
+                        self.nu2, self.gamma_f, self.gamma_c,
                         self.coarsest_nodes, F32 if self.vcycle_dtype == "f32" else F64)
 
 
@@ -223,8 +234,9 @@ class Krylov:
     nrhs: int = 0              # Bi-CGSTAB workspace for the batched solve: right-hand sides at once (0: none)
 
     def to_c(self, x_is_guess=False, history=None):
-        d = SolveDesc(KRYLOV[self.method], self.restart, self.rtol, self.maxit, 1 if x_is_guess else 0, self.inner,
-                      None, 0, ORTH[self.orth], self.nrhs)
+        d = SolveDesc(_code(KRYLOV, self.method, "Krylov method"), self.restart, self.rtol, self.maxit,
+                      1 if x_is_guess else 0, self.inner, None, 0, _code(ORTH, self.orth, "orthogonalisation"),
+                      self.nrhs)
         if history is not None:
             d.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             d.history_len = history.size

@@ -59,3 +59,17 @@ def test_batch_solve_validates_every_rhs():
         E.batch_solve([S0], [cpu], [kr, kr])               # one Krylov per system
     with pytest.raises(ValueError):
         E.batch_solve([S0], [cpu], E.Krylov(method="gmres"))
+
+
+def test_option_names_are_checked():
+    """Unknown option names raise ValueError naming the choices (no library
+    call is made to build a descriptor)."""
+    with pytest.raises(ValueError, match="orthogonalisation"):
+        E.Krylov(method="fgmres", orth="mgs").to_c()
+    with pytest.raises(ValueError, match="Krylov method"):
+        E.Krylov(method="cg").to_c()
+    with pytest.raises(ValueError, match="smoother"):
+        E.Precond(smoother="gs").to_c()
+    with pytest.raises(ValueError, match="preconditioner kind"):
+        E.Precond(kind="ilu").to_c()
+    assert E.Krylov().to_c().orth == E.ORTH["dcgs2"] == 0
