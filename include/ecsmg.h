@@ -138,7 +138,9 @@ typedef struct {
   double rel_residual;     /* true ||b - A x|| / ||b|| at exit (FP64)         */
   double seconds;          /* host wall time inside the call                  */
   int status;              /* same value as returned                          */
-  int64_t reorthogonalisations; /* second Gram-Schmidt passes run (GMRES)     */
+  int64_t reorthogonalisations; /* second Gram-Schmidt passes run (GMRES; with
+                              the delayed pass: every step but each restart
+                              cycle's first)                                  */
   int64_t inner_breakdowns;/* nested form: inner Bi-CGSTAB runs cut short by
                               a zero or non-finite scalar (a breakdown, or an
                               exactly converged residual); the iterate reached
