@@ -203,7 +203,7 @@ template <typename R>
 void launch_down_rb(const Grid<R> &fine, const Grid<R> &coarse, const cplx<R> *b, cplx<R> *rc, R omega, int rows,
                     hipStream_t s, const RhsSet &rs = one_rhs());
 // The down kernel can form its right-hand side while staging it, from the
-// vectors of a Bi-CGSTAB step (FP32 only): kDownSrcP b = r + beta (p - omega v),
+// vectors of a Bi-CGSTAB step: kDownSrcP b = r + beta (p - omega v),
 // kDownSrcS b = r - alpha v (the step's scalars read from S), each with the
 // expression of the separate update kernels, so the values are the same.  The
 // formed vector is stored at every node of the grid (out must not alias r, p

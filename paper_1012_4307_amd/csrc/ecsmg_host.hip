@@ -176,6 +176,9 @@ struct ecs_ctx {
 
   // launch schedule of the fused V(1,1) cycle (autotuned per grid and dtype)
   ecs_tuning tune{4, 8, 513, 33, 129, 1};
+  // FP64 Bi-CGSTAB with its p update inside the cycle: which of p / p2 holds
+  // the current direction (reset at every restart)
+  int bicg_pflip = 0;
 
   // coarse end of the general cycle in one workgroup (2D): packed weights and
   // inverse diagonals of the levels that may form it (levels sfirst .. coarsest,
@@ -348,6 +351,7 @@ struct KrylovBufs {
   void *tz = nullptr;         // n, cycle dtype
   cplx<double> *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *tt = nullptr;
   void *ph = nullptr, *sh = nullptr;
+  cplx<double> *p2 = nullptr;  // FP64 cycle: second p buffer for the update inside the cycle
   // nested Bi-CGSTAB of the FGMRES preconditioner, in the cycle's dtype; fp2:
   // second p buffer (the fused update writes p beside the old one)
   void *fr = nullptr, *frh = nullptr, *fp = nullptr, *fv = nullptr, *fs = nullptr, *ft = nullptr, *fph = nullptr,
@@ -397,6 +401,14 @@ size_t plan_batch(const ecs_ctx *C, int slots, char *base, KrylovBufs *K) {
   return cv.off;
 }
 
+// The outer FP64 Bi-CGSTAB forms p and s inside the cycle (bicg_enqueue_step) up to 1025^2 finest
+// nodes, where a launch is short enough that the two it saves count: measured
+// 2-3% faster at 513^2 and 1025^2.  At 2049^2 the fused FP64 kernels (121
+// VGPRs for p against 84 for the plain down kernel) lose occupancy on a level
+// that is bandwidth-bound: 1-2% slower for every tile height, so the separate
+// update kernels stay there.
+constexpr int64_t kFuse64MaxNodes = int64_t(1025) * 1025;
+
 size_t plan_krylov(const ecs_ctx *C, const ecs_solve_desc *d, char *base, KrylovBufs *K) {
   Carver cv(base);
   const int64_t n = nn_of(C);
@@ -416,6 +428,8 @@ size_t plan_krylov(const ecs_ctx *C, const ecs_solve_desc *d, char *base, Krylov
     K->tt = cv.take<cplx<double>>(n);
     K->ph = cv.take<char>(n * zs);
     K->sh = cv.take<char>(n * zs);
+    // its second p buffer (kFuse64MaxNodes above)
+    if (C->prec.vcycle_dtype == ECS_F64 && n <= kFuse64MaxNodes) K->p2 = cv.take<cplx<double>>(n);
   } else {
     const int m = d->restart;
     K->V = cv.take<cplx<double>>((size_t)K->ld * (m + 1));
@@ -952,9 +966,10 @@ FusedPlan fused_plan(const ecs_ctx *C) {
   return P;
 }
 
-// The inner FP32 Bi-CGSTAB can form each cycle's right-hand side (its p and
-// s updates) inside the finest level's down kernel when that level has one
-// and the cycle is launched eagerly.
+// A Bi-CGSTAB (the nested FP32 one, or the outer one with the FP64 cycle) can
+// form each cycle's right-hand side (its p and s updates) inside the finest
+// level's down kernel when that level has one and the cycle is launched
+// eagerly.
 bool fused_updates(const ecs_ctx *C) {
   if (!C->tune.fuse_updates || !fused_vcycle(C) || C->graph_mode == ECS_GRAPHS_ALWAYS) return false;
   const FusedPlan P = fused_plan(C);
@@ -999,17 +1014,15 @@ void vcycle_fused(ecs_ctx *C, const cplx<R> *b0, cplx<R> *u0, const DownSrc<R> *
   auto small = [&](int l) { return C->hl[l].n[0] <= T.small_grid && C->hl[l].n[1] <= T.small_grid; };
   for (int l = 0; l < lt;) {
     const cplx<R> *b = l == 0 ? b0 : B.b[l];
-    if constexpr (sizeof(R) == 4) {
-      if (l == 0 && src) {
-        // reads the vectors b is formed from (r, p, v or r, v) and k^2;
-        // writes b and the coarse residual
-        const bool pm = src->mode == kDownSrcP;
-        TimedScope ts(C, pm ? kTDownP : kTDownS, (double)C->hl[0].nn * sizeof(R) * (pm ? 9.5 : 7.5));
-        launch_down_rb_src<R>(grid_M<R>(C, 0), grid_M<R>(C, 1), *src, B.b[1], om, small(0) ? 2 : T.down_rows,
-                              C->stream);
-        l++;
-        continue;
-      }
+    if (l == 0 && src) {
+      // reads the vectors b is formed from (r, p, v or r, v) and k^2;
+      // writes b and the coarse residual
+      const bool pm = src->mode == kDownSrcP;
+      TimedScope ts(C, pm ? kTDownP : kTDownS, (double)C->hl[0].nn * sizeof(R) * (pm ? 9.5 : 7.5));
+      launch_down_rb_src<R>(grid_M<R>(C, 0), grid_M<R>(C, 1), *src, B.b[1], om, small(0) ? 2 : T.down_rows,
+                            C->stream);
+      l++;
+      continue;
     }
     if (pair_start[l]) {
       // reads b, k^2 of both levels; writes u of both, b of level l+1, the
@@ -1538,11 +1551,16 @@ void bicg_enqueue_restart(ecs_ctx *C, const KrylovBufs &K, const cplx<double> *b
   (void)hipMemcpyAsync(K.rh, K.r, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, s);
   launch_zero<double>(K.p, n, s);
   launch_zero<double>(K.v, n, s);
+  C->bicg_pflip = 0;
 }
 
 // one iteration: p = r + beta (p - omega v); ph = M^{-1} p; v = A ph -> alpha;
 // s = r - alpha v; sh = M^{-1} s; t = A sh -> omega; x += alpha ph + omega sh;
-// r = s - omega t -> est and the next beta
+// r = s - omega t -> est and the next beta.  With the FP64 cycle the p and s
+// updates can run inside the finest down kernel (as in the nested FP32
+// Bi-CGSTAB): the same values, two launches and two vector passes fewer; p
+// then alternates between two buffers (blocks read the old p around their
+// tiles while others write the new one).
 template <typename RZ>
 void bicg_enqueue_step(ecs_ctx *C, const KrylovBufs &K, cplx<double> *x) {
   const int64_t n = nn_of(C);
@@ -1550,14 +1568,32 @@ void bicg_enqueue_step(ecs_ctx *C, const KrylovBufs &K, cplx<double> *x) {
   BicgScalars *S = C->bs;
   cplx<RZ> *ph = reinterpret_cast<cplx<RZ> *>(K.ph);
   cplx<RZ> *sh = reinterpret_cast<cplx<RZ> *>(K.sh);
-  launch_bicg_p<double>(K.p, K.r, K.v, n, S, s);
-  precond<RZ>(C, K.p, ph);
+  bool fuse = false;
+  if constexpr (sizeof(RZ) == 8) fuse = K.p2 && fused_updates(C);
+  if (fuse) {
+    if constexpr (sizeof(RZ) == 8) {
+      cplx<double> *p_old = C->bicg_pflip ? K.p2 : K.p, *p_new = C->bicg_pflip ? K.p : K.p2;
+      const DownSrc<double> sp{kDownSrcP, K.r, p_old, K.v, p_new, S};
+      vcycle_fused<double>(C, p_new, ph, &sp);
+      C->bicg_pflip ^= 1;
+    }
+  } else {
+    launch_bicg_p<double>(K.p, K.r, K.v, n, S, s);
+    precond<RZ>(C, K.p, ph);
+  }
   {
     TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 40));
     launch_apply_dot<double, RZ>(grid_A(C), ph, K.v, K.rh, kBicgAlpha, C->partials, S, s);
   }
-  launch_bicg_s<double>(K.s, K.r, K.v, n, S, s);
-  precond<RZ>(C, K.s, sh);
+  if (fuse) {
+    if constexpr (sizeof(RZ) == 8) {
+      const DownSrc<double> ss{kDownSrcS, K.r, nullptr, K.v, K.s, S};
+      vcycle_fused<double>(C, K.s, sh, &ss);
+    }
+  } else {
+    launch_bicg_s<double>(K.s, K.r, K.v, n, S, s);
+    precond<RZ>(C, K.s, sh);
+  }
   {
     TimedScope ts(C, kTApply, (double)n * (2 * sizeof(RZ) + 40));
     launch_apply_dot<double, RZ>(grid_A(C), sh, K.tt, K.s, kBicgOmega, C->partials, S, s);

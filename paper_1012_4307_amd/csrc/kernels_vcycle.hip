@@ -189,8 +189,12 @@ __global__ __launch_bounds__(NT) void k_down_rb(Grid<R> f, Grid<R> c, const cplx
       const int ly = wv + 4 * r, j = gy0 + ly;
       if (ly >= 3 && ly < 3 + 2 * CY && j < n1) {
         cplx<R> *row = src.out + (int64_t)j * n0;
-        if (owna) row[ia] = ared ? bR[r] : bB[r];
-        if (ownb) row[ib] = ared ? bB[r] : bR[r];
+        // component selects: a select of the structs goes through scratch
+        // memory in FP64
+        const cplx<R> va = mk<R>(ared ? bR[r].re : bB[r].re, ared ? bR[r].im : bB[r].im);
+        const cplx<R> vb = mk<R>(ared ? bB[r].re : bR[r].re, ared ? bB[r].im : bR[r].im);
+        if (owna) row[ia] = va;
+        if (ownb) row[ib] = vb;
       }
     }
   }
@@ -1013,6 +1017,8 @@ template void launch_up_rb<double>(const Grid<double> &, const Grid<double> &, c
                                    const cplx<double> *, cplx<double> *, double, int, hipStream_t, const RhsSet &);
 template void launch_down_rb_src<float>(const Grid<float> &, const Grid<float> &, const DownSrc<float> &, cplx<float> *,
                                         float, int, hipStream_t);
+template void launch_down_rb_src<double>(const Grid<double> &, const Grid<double> &, const DownSrc<double> &,
+                                         cplx<double> *, double, int, hipStream_t);
 template void launch_tail<double>(const TailArgs<double> &, hipStream_t, const RhsSet &);
 template void launch_tail<float>(const TailArgs<float> &, hipStream_t, const RhsSet &);
 template void launch_up_rb<float>(const Grid<float> &, const Grid<float> &, const cplx<float> *, const cplx<float> *,

@@ -321,6 +321,49 @@ def test_nested_updates_fused_equal_separate(case):
         S.set_tuning(fuse_updates=2)
 
 
+@pytest.mark.parametrize("case", ["coulomb257", "ragged193"])
+def test_outer_bicgstab_updates_fused_equal_separate(case):
+    """FP64 Bi-CGSTAB with the FP64 cycle: the p and s updates formed inside
+    the finest down kernel give the same solve as the separate update
+    kernels (same iteration count and restarts, equal iterates); also with
+    graph launches, which switch the fusion off."""
+    import torch
+    w = W.coulomb(E=2.0, n=257) if case == "coulomb257" else ragged_workload(n=193, coarsest=7)
+    kr = E.Krylov(method="bicgstab", rtol=1e-11, maxit=5000)
+    S = gpu_for(w, "f64", krylov=kr)
+    b = to_gpu(w.rhs[0])
+    nn = w.shape[0] * w.shape[1]
+    out = {}
+    for label, fuse, graphs in (("separate", 0, "auto"), ("fused", 1, "auto"), ("graphs", 1, True)):
+        S.set_tuning(fuse_updates=fuse)
+        S.set_graphs(graphs)
+        timed = label != "graphs"
+        for cls in ("down", "down_p", "down_s"):
+            S.timing(cls, timed)
+        x, st = S.solve(b)
+        assert st["status"] == 0, (label, st)
+        out[label] = (x.clone(), st["iterations"], st["restarts"])
+        if timed:
+            got = {cls: S.timing_read(cls) for cls in ("down", "down_p", "down_s")}
+            it = st["iterations"]
+            if fuse:
+                assert got["down_p"][0] == it and got["down_s"][0] == it, got
+                assert got["down_p"][2] == it * nn * 8 * 9.5 and got["down_s"][2] == it * nn * 8 * 7.5
+                assert got["down"][0] == 0, got
+            else:
+                assert got["down"][0] == 2 * it and got["down_p"][0] == got["down_s"][0] == 0, got
+            for cls in ("down", "down_p", "down_s"):
+                S.timing(cls, False)
+    S.set_graphs("auto")
+    x0, it0, rs0 = out["separate"]
+    for label in ("fused", "graphs"):
+        x1, it1, rs1 = out[label]
+        assert (it1, rs1) == (it0, rs0), label
+        assert torch.equal(x1, x0), (label, relerr(to_np(x1), to_np(x0)))
+    P = oracle_for(w)
+    assert oracle_resid(P, to_np(x0), w.rhs[0]) <= 1.05e-11
+
+
 def test_nested_updates_fused_full_size():
     """The same at the benchmark's size and launch configuration (2049^2,
     h = 0.25, 9 levels, 16 inner iterations), over two outer FGMRES(40)
