@@ -68,14 +68,16 @@ def test_delayed_second_pass_tight(method, dt):
     from the corrected basis."""
     w = ragged_workload(n=65, coarsest=5)
     P = oracle_for(w)
-    kr = E.Krylov(method=method, restart=30, rtol=1e-12, maxit=3000, orth="dcgs2")
-    S = gpu_for(w, dt, krylov=kr)
     b = w.rhs[0]
-    x, st = S.solve(to_gpu(b))
-    assert st["status"] == 0, st
     xo, _ = P.solve(b, "fgmres", 30, 1e-13, 5000)
-    assert relerr(to_np(x), xo) < 1e-9
-    assert oracle_resid(P, to_np(x), b) <= 1.05e-12
+    # restart 64: the largest basis (130 product columns per step)
+    for m in (30, 64):
+        kr = E.Krylov(method=method, restart=m, rtol=1e-12, maxit=3000, orth="dcgs2")
+        S = gpu_for(w, dt, krylov=kr)
+        x, st = S.solve(to_gpu(b))
+        assert st["status"] == 0, (m, st)
+        assert relerr(to_np(x), xo) < 1e-9, m
+        assert oracle_resid(P, to_np(x), b) <= 1.05e-12, m
 
 
 @pytest.mark.parametrize("E_", [0.5, 1.0, 2.0, 4.0])
