@@ -299,10 +299,11 @@ ecs_status ecs_level_info(ecs_ctx *ctx, int level, int *nlevels, int64_t *nodes)
  *   2 FP64 operator A (matvec)          7 finest-level fused down kernel
  *   3 coarse-level cycle kernels        8 finest-level fused up kernel
  *   4 Arnoldi orthogonal update          9 empty kernel (ecs_timing_calibrate)
- *  10 finest-level fused down kernel forming the nested Bi-CGSTAB's p
- *  11 finest-level fused down kernel forming the nested Bi-CGSTAB's s
- *     (classes 10 and 11 run instead of 7 in the nested FP32 Bi-CGSTAB when
- *     ecs_tuning.fuse_updates applies)
+ *  10 finest-level fused down kernel forming a Bi-CGSTAB's p
+ *  11 finest-level fused down kernel forming a Bi-CGSTAB's s
+ *     (classes 10 and 11 run instead of 7 in the nested FP32 Bi-CGSTAB, and
+ *     in the outer Bi-CGSTAB with the FP64 cycle up to 1025^2 finest nodes,
+ *     when ecs_tuning.fuse_updates applies)
  * A timed duration runs from the dispatch of the kernel to its completion.
  * ecs_timing_read synchronises the stream and returns the number of timed
  * launches, their summed duration in ms and their summed algorithmic bytes
@@ -337,11 +338,13 @@ ecs_status ecs_timing_calibrate(ecs_ctx *ctx, int launches);
  *               and general cycles use min(tail_nodes, 33)
  *   pair_grid   levels above the tail with at most this many nodes per axis
  *               run two per kernel (pairs counted from the tail up); 0: none
- *   fuse_updates  1: the FP32 Bi-CGSTAB inside FGMRES (desc->inner > 0) forms
- *               its p and s updates inside the finest level's down kernel
- *               when that level has its own down kernel and the cycle is not
- *               launched as a graph (ECS_GRAPHS_ALWAYS), with the same values
- *               as the separate update kernels; 0: separate update kernels
+ *   fuse_updates  1: the FP32 Bi-CGSTAB inside FGMRES (desc->inner > 0), and
+ *               the Bi-CGSTAB solve with the FP64 cycle on grids of at most
+ *               1025^2 nodes, form their p and s updates inside the finest
+ *               level's down kernel when that level has its own down kernel
+ *               and the cycle is not launched as a graph
+ *               (ECS_GRAPHS_ALWAYS), with the same values as the separate
+ *               update kernels; 0: separate update kernels
  * Defaults {4, 8, 513, 33, 129, 1}; a project autotuner picks the tile
  * heights per grid size and dtype by timing cycles.  Other values:
  * ECS_EINVAL. */

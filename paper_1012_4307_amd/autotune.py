@@ -30,8 +30,8 @@ import os
 import time
 from typing import Dict
 
-# fuse_updates does not change a cycle (only how the nested FP32 Bi-CGSTAB
-# feeds it) and keeps its default
+# fuse_updates does not change a cycle (only how a Bi-CGSTAB feeds it) and
+# keeps its default
 DEFAULT = dict(down_rows=4, up_rows=8, small_grid=513, tail_nodes=33, pair_grid=129, fuse_updates=1)
 
 
