@@ -8,9 +8,41 @@ namespace ecs {
 
 constexpr int kRedThreads = 256;  // 4 waves of 64
 
+// The wave's sum in every lane: the butterfly v += v[lane ^ o], o = 32, 16,
+// ..., 1, with each exchange done in registers rather than through the LDS
+// crossbar -- lanes ^ 32 and ^ 16 by the permlane swaps (each returns both
+// halves of the swapped pair: a lane takes the half that came from the other
+// side), ^ 8 by a row rotation by 8 (exact within a 16-lane row), and ^ 4, 2,
+// 1 by rotations by 4, 2, 1: after the ^ 8 step every value repeats with
+// period 8 within its row (then 4, then 2), so a lane's rotation partner
+// holds the same value as its xor partner.  Every addition has the same
+// operands in the same order as the plain butterfly, so the sums are equal
+// bit for bit.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_xor32(double v) {
+  const bool low = (__lane_id() & 32) == 0;
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double(low ? hi[1] : hi[0], low ? lo[1] : lo[0]);
+}
+__device__ __forceinline__ double lane_xor16(double v) {
+  const bool even = (__lane_id() & 16) == 0;
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double(even ? hi[1] : hi[0], even ? lo[1] : lo[0]);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v += lane_xor32(v);
+  v += lane_xor16(v);
+  v += dpp_move<0x128>(v);  // row_ror:8
+  v += dpp_move<0x124>(v);  // row_ror:4
+  v += dpp_move<0x122>(v);  // row_ror:2
+  v += dpp_move<0x121>(v);  // row_ror:1
   return v;
 }
 
