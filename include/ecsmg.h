@@ -251,7 +251,8 @@ ecs_status ecs_vcycle_native(ecs_ctx *ctx, const void *v_dev, void *z_dev);
  *        (ecs_workspace_size with inner, nrhs = 1).
  *   stats: iterations = outer iterations, inner_iterations and vcycles summed
  *        over all block solves.  Outer work runs on ctx[0]'s stream; the call
- *        returns after every stream involved has finished. */
+ *        returns after every stream involved has finished.
+ * Returns ECS_EINVAL (message on ctx[0]) for nb outside 1..8 or a NULL outer. */
 ecs_status ecs_coupled_workspace_size(int nb, ecs_ctx *const *ctx, const ecs_solve_desc *outer, size_t *bytes);
 ecs_status ecs_coupled_solve(int nb, ecs_ctx *const *ctx, const double *k2c, const ecs_solve_desc *outer,
                              const ecs_solve_desc *inner, void *workspace, size_t ws_bytes, const void *b_dev,

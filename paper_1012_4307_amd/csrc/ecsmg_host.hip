@@ -1996,7 +1996,10 @@ void coupled_apply(int nb, ecs_ctx *const *ctx, const double *k2c, const cplx<do
 }
 
 ecs_status coupled_check(int nb, ecs_ctx *const *ctx, const ecs_solve_desc *outer, const ecs_solve_desc *inner) {
-  if (nb < 1 || nb > kMaxBlocks || !ctx || !outer) return ECS_EINVAL;
+  if (nb < 1 || nb > kMaxBlocks || !ctx || !outer)
+    return fail(ctx && nb >= 1 ? ctx[0] : nullptr, ECS_EINVAL,
+                "coupled solve: nb = " + std::to_string(nb) + " blocks (1 to " + std::to_string(kMaxBlocks) +
+                    ") and an outer descriptor are required");
   for (int i = 0; i < nb; i++) {
     if (!ctx[i]) return ECS_EINVAL;
     ecs_status st = check_ready(ctx[i]);

@@ -121,3 +121,38 @@ def test_coupled_residual_recomputed_by_oracle():
     bz[:, :, 0] = bz[:, :, -1] = 0
     assert np.linalg.norm(np.stack(r)) <= 1.05e-8 * np.linalg.norm(bz)
     assert all(np.abs(xn[i]).max() > 1e-6 * np.abs(xn[0]).max() for i in range(1, 4))
+
+
+@pytest.mark.gpu
+def test_coupled_eight_channels_and_the_limit():
+    """The largest coupled system the library takes, 8 channels on 33^2
+    (energies 4.0 down to 0.5): the true residual recomputed by the oracle's
+    block operators and the coupling meets the tolerance.  A ninth block is
+    refused with a message before any launch."""
+    import paper_1012_4307_amd as E
+    blocks, k2c, rhs = W.coupled_blocks(nb=9, n=33, E=4.0)
+    Ss = [gpu_for(w, "f64") for w in blocks]
+    outer = E.Krylov(method="fgmres", restart=30, rtol=1e-9, maxit=400)
+    inner = E.Krylov(method="bicgstab", rtol=1e-4, maxit=200)
+    with pytest.raises(E.EcsError, match="nb = 9"):
+        E.coupled_solve(Ss, to_gpu(k2c), to_gpu(rhs), outer=outer, inner=inner)
+    nb = 8
+    k8 = np.ascontiguousarray(k2c[:nb, :nb])
+    x, st = E.coupled_solve(Ss[:nb], to_gpu(k8), to_gpu(rhs[:nb]), outer=outer, inner=inner)
+    assert st["status"] == 0, st
+    xn = to_np(x)
+    Ps = _problems(blocks[:nb])
+    r = []
+    for i in range(nb):
+        ri = rhs[i] - Ps[i].apply(xn[i])
+        for j in range(nb):
+            if j != i:
+                ri = ri + k8[i, j] * xn[j]
+        ri[0, :] = ri[-1, :] = 0
+        ri[:, 0] = ri[:, -1] = 0
+        r.append(ri)
+    bz = rhs[:nb].copy()
+    bz[:, 0, :] = bz[:, -1, :] = 0
+    bz[:, :, 0] = bz[:, :, -1] = 0
+    assert np.linalg.norm(np.stack(r)) <= 1.05e-9 * np.linalg.norm(bz)
+    assert all(np.abs(xn[i]).max() > 0 for i in range(1, nb))
