@@ -400,9 +400,10 @@ def test_status_paths():
     assert st["status"] == 1 and st["iterations"] == 2
     with pytest.raises(ValueError):
         S.solve(to_gpu(w.rhs[0]).to(torch.complex64))
-    with pytest.raises(E.EcsError) as ei:
-        S.solve(to_gpu(w.rhs[0]), krylov=E.Krylov(method="gmres", restart=500))
-    assert ei.value.status == -1
+    for bad_restart in (0, 65, 500):  # the basis holds 1 to 64 vectors
+        with pytest.raises(E.EcsError, match="restart") as ei:
+            S.solve(to_gpu(w.rhs[0]), krylov=E.Krylov(method="gmres", restart=bad_restart))
+        assert ei.value.status == -1
     # an orthogonalisation code outside the enumeration is refused before any work
     import ctypes
     d = E.Krylov(method="fgmres").to_c()
