@@ -366,6 +366,38 @@ def test_outer_bicgstab_updates_fused_equal_separate(case):
     assert oracle_resid(P, to_np(x0), w.rhs[0]) <= 1.05e-11
 
 
+def test_outer_bicgstab_fusion_size_limit():
+    """The FP64 Bi-CGSTAB forms p and s inside the cycle up to 1025^2 finest
+    nodes: at 1025^2 (its largest grid, 12 iterations) the fused kernels run and
+    the iterates equal the separate kernels' bit for bit; at 2049^2 the same
+    setting runs the separate update kernels."""
+    import torch
+    kr = E.Krylov(method="bicgstab", rtol=1e-30, maxit=12)
+    for n, fused_expected in ((1025, True), (2049, False)):
+        w = W.large_coulomb(n=n, coarsest=9)
+        S = gpu_for(w, "f64", krylov=kr)
+        b = to_gpu(w.rhs[0])
+        out = {}
+        for fuse in ((0, 1) if fused_expected else (1,)):
+            S.set_tuning(fuse_updates=fuse)
+            for cls in ("down", "down_p", "down_s"):
+                S.timing(cls, True)
+            x, st = S.solve(b)
+            assert st["status"] == 1 and st["iterations"] == 12, (n, fuse, st)
+            got = {cls: S.timing_read(cls)[0] for cls in ("down", "down_p", "down_s")}
+            for cls in ("down", "down_p", "down_s"):
+                S.timing(cls, False)
+            if fuse and fused_expected:
+                assert got == {"down": 0, "down_p": 12, "down_s": 12}, (n, got)
+            else:
+                assert got == {"down": 24, "down_p": 0, "down_s": 0}, (n, fuse, got)
+            out[fuse] = (x.clone(), st["restarts"])
+        if fused_expected:
+            assert out[0][1] == out[1][1]
+            assert torch.equal(out[0][0], out[1][0]), relerr(to_np(out[1][0]), to_np(out[0][0]))
+        del S
+
+
 def test_nested_updates_fused_full_size():
     """The same at the benchmark's size and launch configuration (2049^2,
     h = 0.25, 9 levels, 16 inner iterations), over two outer FGMRES(40)
