@@ -156,7 +156,7 @@ def traffic(fetch_csv: str, write_csv: str, out_txt: str, out_json: str, cmd_fet
         f.write("\n".join(lines) + "\n")
     with open(out_json, "w") as f:
         json.dump(dict(sources_digest=sources_digest(), fetch_scale=fetch_scale, write_scale=write_scale,
-                       kernels=kernels), f, indent=1)
+                       kernels=kernels, commands=dict(fetch=cmd_fetch, write=cmd_write)), f, indent=1)
         f.write("\n")
 
 

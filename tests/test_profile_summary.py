@@ -38,6 +38,7 @@ def test_traffic_scales_by_copy_probe_and_takes_finest_grid(tmp_path):
     rec = json.loads((tmp_path / "t.json").read_text())
     assert abs(rec["fetch_scale"] - 2.0) < 1e-12 and abs(rec["write_scale"] - 1.0) < 1e-12
     assert rec["sources_digest"] == PS.sources_digest()
+    assert rec["commands"] == {"fetch": "cf", "write": "cw"}
     for q, (cls, name) in enumerate(NAMES.items()):
         k = rec["kernels"][cls]
         assert k["kernel"] == name and k["grid_threads"] == 500000 + q
